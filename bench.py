@@ -1,0 +1,196 @@
+"""Throughput benchmark: REANN energy + force + virial evaluations on one MI355X.
+
+One step = one full evaluation of the workload (neighbour-list reuse check, T message-
+passing layers forward, the hand-written backward for forces and virial) with the
+positions already resident in HBM.  Default workload: the 100,800-atom FCC Cu-like
+crystal, r_c = 6 A with a 1 A skin, T = 3, L = 2, K = 12, 3x128 SiLU atomic NNs, FP32.
+
+Prints ONE JSON line (rank 0).  Per-kernel durations come from HIP events recorded by
+the library on the evaluation stream during the timed steps; the roofline entry is
+for the kernel phase with the largest share of the step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "energy+force atom-steps/s at T=3 on 1 MI355X vs FP64 oracle; serve p50/p99"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"fp32_vector": 157.3, "fp64_vector": 78.6, "fp32_mfma": 157.3, "bf16_mfma": 2500.0,
+               "fp8_mfma": 5000.0, "fp64_mfma": 78.6}
+
+
+def describe(name, w):
+    m = w["model"]
+    return ("%s: %d atoms, r_c=%g A + %g A skin, T=%d, L=%d, K=%d, %dx%d SiLU atomic NNs, decomp %s"
+            % (name, len(w["system"]["pos"]), m.r_c, w["skin"], w["T"], m.L, m.K, m.n_hidden, m.hidden,
+               "x".join(map(str, w["decomp"]))))
+
+
+def work_model(w, n_local_pairs, n_in_cutoff, prec):
+    """Algorithmic bytes and flops per launch of each kernel phase (per MP layer)."""
+    m, n = w["model"], len(w["system"]["pos"])
+    K, L = m.K, m.L
+    NL = (L + 1) * (L + 2) * (L + 3) // 6
+    F, H, nh = m.F, m.hidden, m.n_hidden
+    rs = 8 if prec == "fp64" else 4
+    out = {}
+    # edge forward: list indices, own position, own message, written S; S += w*A per in-cutoff edge
+    out["edge_fwd"] = dict(bytes=4 * n_local_pairs + n * (24 + rs * K + rs * NL * K),
+                           flops=2 * NL * K * n_in_cutoff)
+    # edge backward: + Sbar read, cbar and force written; P, Q and cbar contractions per edge
+    out["edge_bwd"] = dict(bytes=4 * n_local_pairs + n * (24 + rs * K + 2 * rs * NL * K + rs * K + rs * 3),
+                           flops=6 * NL * K * n_in_cutoff)
+    macs_msg = F * H + (nh - 1) * H * H + H * K
+    macs_en = F * H + (nh - 1) * H * H + H
+    out["nn"] = dict(flops_per_atom_msg=2 * macs_msg, flops_per_atom_en=2 * macs_en)
+    return out
+
+
+def cpu_baseline(workload_name, T, max_seconds=30.0):
+    """The FP64 oracle timed on this host on the same workload (one full evaluation)."""
+    import oracle
+    import synth
+    oracle.build(force=False)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = int(min(cores, 16))
+    w = synth.workload(workload_name)
+    s = w["system"]
+    n = len(s["pos"])
+    sample = "full %s system, one energy+force+virial evaluation" % workload_name
+    # bound the CPU work: on hosts far slower than expected fall back to an FCC sub-box of
+    # the same lattice, density and model
+    if workload_name == "cu100800" and threads < 4:
+        s = synth.systems.fcc_crystal((12, 12, 12))
+        n = len(s["pos"])
+        sample = "12x12x12-cell sub-box (6,912 atoms) of the same crystal and model"
+    t0 = time.perf_counter()
+    oracle.evaluate(w["model"], s, T=T, skin=w["skin"], threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="atom-steps/s", cores=threads, kind="oracle", sample=sample,
+                seconds=round(dt, 3))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cu100800")
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16", "fp8"])
+    ap.add_argument("--T", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the subdomain exchange is "
+              "emulated inside one device); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2505_06711_amd as rn
+
+    w = synth.workload(a.workload)
+    if a.T is not None:
+        w["T"] = a.T
+    s, m, T = w["system"], w["model"], w["T"]
+    n = len(s["pos"])
+    print("bench: %s precision=%s steps=%d warmup=%d" % (describe(a.workload, w), a.precision, a.steps, a.warmup),
+          file=sys.stderr, flush=True)
+    ctx = rn.Context(0, torch.cuda.current_stream())
+    model = rn.Model(m)
+    plan = rn.Plan(ctx, model, s, T=T, precision=a.precision, decomp=w["decomp"], skin=w["skin"])
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
+    E = torch.zeros((), dtype=torch.float64, device="cuda")
+    F = torch.zeros_like(pos)
+    W = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.forward(pos, E)
+        plan.backward(F, virial=W)
+
+    t_build = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t_build
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.timing()                     # reset accumulators
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(a.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    tim = plan.timing()
+    plan.set_timing(False)
+    ms_per_step = gpu_ms / a.steps
+    value = n * a.steps / (gpu_ms / 1e3)
+
+    nl = rn.build_neighbors(ctx, s, m.r_c, w["skin"], w["decomp"]).info()
+    n_local_pairs = nl["n_local_pairs"]
+    # in-cutoff directed edges of the locals: the list without skin
+    n_in_cutoff = rn.build_neighbors(ctx, s, m.r_c, 0.0, w["decomp"]).info()["n_local_pairs"]
+    wk = work_model(w, n_local_pairs, n_in_cutoff, a.precision)
+
+    steps_t = max(1, tim["steps"])
+    ms = {k: v / steps_t for k, v in tim["ms"].items()}
+    dominant = max(("edge_fwd", "edge_bwd", "nn_fwd", "nn_bwd"), key=lambda k: ms[k])
+    la = tim["launches"]
+    if dominant in ("edge_fwd", "edge_bwd"):
+        per_launch_ms = tim["ms"][dominant] / max(1, la[dominant])
+        flops = wk[dominant]["flops"]
+        byts = wk[dominant]["bytes"]
+        t_alu = flops / (PEAK_TFLOPS["fp32_vector" if a.precision != "fp64" else "fp64_vector"] * 1e12)
+        t_hbm = byts / (HBM_PEAK_GBS * 1e9)
+        if t_alu >= t_hbm:
+            peak = PEAK_TFLOPS["fp32_vector" if a.precision != "fp64" else "fp64_vector"]
+            achieved = flops / (per_launch_ms * 1e-3) / 1e12
+            roof = dict(bound="alu", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                        frac=round(achieved / peak, 4), traffic=None)
+        else:
+            achieved = byts / (per_launch_ms * 1e-3) / 1e9
+            roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+        roof.update(kernel=dominant, per_launch_ms=round(per_launch_ms, 4), launches=la[dominant],
+                    algorithmic_flops=flops, algorithmic_bytes=byts)
+    else:
+        # atomic NN phase: dense layers (forward: T NNs; backward: T VJPs)
+        nnf = wk["nn"]
+        flops_step = n * ((T - 1) * nnf["flops_per_atom_msg"] + nnf["flops_per_atom_en"])
+        achieved = flops_step / (ms[dominant] * 1e-3) / 1e12
+        key = {"fp64": "fp64_mfma", "fp32": "fp32_mfma", "bf16": "bf16_mfma", "fp8": "fp8_mfma"}[a.precision]
+        roof = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK_TFLOPS[key], unit="TFLOP/s",
+                    frac=round(achieved / PEAK_TFLOPS[key], 4), traffic=None, kernel=dominant,
+                    phase_ms_per_step=round(ms[dominant], 4))
+
+    out = dict(metric=METRIC, value=round(value, 1), unit="atom-steps/s", n_gpus=1, steps=a.steps,
+               warmup=a.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype={"fp64": "f64", "fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[a.precision],
+               data="synthetic",
+               config=dict(workload=describe(a.workload, w), precision=a.precision, n_atoms=n,
+                           ghosts=nl["n_ghosts"], list_pairs=n_local_pairs, in_cutoff_edges=n_in_cutoff,
+                           first_step_s=round(t_build, 3), wall_s=round(wall, 3)),
+               phase_ms_per_step={k: round(v, 4) for k, v in ms.items()},
+               roofline=roof)
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.workload, T)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,245 @@
+/*
+ * reann.h -- C ABI of the MI355X (gfx950) REANN message-passing energy/force library.
+ *
+ * The library evaluates the REANN potential of Xia & Jiang, "Efficient
+ * Parallelization of Message Passing Neural Networks":
+ *   Sec. 2.1, Eq. (1)   embedded atom densities rho_i from orbital sums over the
+ *                       neighbours inside r_c, squared with the l!/(lx!ly!lz!) weights;
+ *   Sec. 2.1, Eq. (2)   message update c_i^t = M^{t-1}_{s_i}(rho_i^{t-1}), 1 <= t <= T-1;
+ *   Sec. 2.1            atomic energies from the last atomic NN, E = sum_i E_i;
+ *   Sec. 2.2            one neighbour list (cutoff r_c + skin) reused by every layer;
+ *                       spatial subdomains whose ghost atoms receive their owners'
+ *                       messages once per layer, emulated inside one GPU;
+ *   Sec. 2.2, Eqs. (3)-(5)  forces by the chain rule, with the ghost atoms' message
+ *                       adjoints (vector-Jacobian products) and forces reduced onto
+ *                       their owners.
+ * The problem statement (positions, species, periodic cell, r_c, T and weights in;
+ * energy, forces and virial out) follows the paper's setting of periodic MD boxes
+ * decomposed into subdomains (Sec. 2.2).
+ *
+ * Conventions for every call:
+ *  - Units: Angstrom, eV, eV/Angstrom, fs.  Positions are Cartesian, FP64, [n][3] row-major.
+ *  - cell[9] holds the three lattice vectors as rows; only orthorhombic cells are
+ *    supported (off-diagonal entries must be 0, else REANN_E_UNSUPPORTED).
+ *    pbc[3] != 0 marks a periodic axis.  Non-periodic axes must not be split.
+ *  - Every array argument is caller-owned.  Inputs are copied before the call returns;
+ *    outputs are written only when the call returns REANN_OK.  Handles are library-owned;
+ *    every _free / _destroy accepts NULL.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device memory
+ *    of the context's GPU.
+ *  - No C++ exception crosses this boundary.  On failure the call returns a negative
+ *    status and reann_last_error() describes it.
+ *  - A context, nlist or plan must not be used by two threads at once.  reann_submit and
+ *    reann_poll are thread-safe.
+ *  - Plans and neighbour lists keep a pointer to their context and must be freed before it.
+ */
+#ifndef REANN_H
+#define REANN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t reann_status;
+#define REANN_OK 0
+#define REANN_PENDING 1
+#define REANN_E_INVALID (-1)        /* NULL, n <= 0, T out of range, r_c mismatch, bad species, NaN, ... */
+#define REANN_E_UNSUPPORTED (-2)    /* non-orthorhombic cell, (L, K) without a compiled kernel, ...     */
+#define REANN_E_NOMEM (-3)          /* host or device allocation failed                                */
+#define REANN_E_CAPACITY (-4)       /* request larger than a server's HBM budget                       */
+#define REANN_E_DEVICE (-5)         /* HIP runtime error                                               */
+#define REANN_E_UNKNOWN_TICKET (-6)
+#define REANN_E_STATE (-7)          /* call out of order (e.g. backward before forward)               */
+
+/* Arithmetic of the evaluation.  FP64: every step in double.  FP32: edge passes,
+   densities and atomic NNs in float, positions and displacements formed in double,
+   energy and virial sums in double.  BF16 / FP8: as FP32 but the atomic-NN matrix
+   products take bfloat16 / OCP e4m3 operands (per-tensor scale) with float accumulation. */
+#define REANN_FP64 0
+#define REANN_FP32 1
+#define REANN_BF16 2
+#define REANN_FP8 3
+
+typedef struct reann_model reann_model;
+typedef struct reann_ctx reann_ctx;
+typedef struct reann_nlist reann_nlist;
+typedef struct reann_plan reann_plan;
+typedef struct reann_server reann_server;
+
+/* Thread-local description of the last error on this thread; valid until the next call. */
+const char *reann_last_error(void);
+
+/* ------------------------------------------------------------------ model --
+ * Model parameters (Sec. 2.1).  All arrays are host FP64 and copied.
+ *   centres[K], alphas[K]   primitive Gaussians R_m(r) = exp(-alphas[m] (r - centres[m])^2)
+ *   c0[n_species][K]        layer-0 orbital coefficients per element (dc^0/dr = 0)
+ *   angular part            A(d) = (s dx)^lx (s dy)^ly (s dz)^lz, s = ang_scale, l <= L
+ *   cutoff                  f_c(r) = (cos(pi r/r_c)/2 + 1/2)^2 for r < r_c, 0 beyond
+ *   features                rho[l,(a,b)], a <= b, F = (L+1) K (K+1)/2, order l, a, b
+ *   atomic NN dims          [F, hidden x n_hidden, out]: hidden layers z = W h + b, h = SiLU(z);
+ *                           linear output.  Each NN is stored as W_1 [d1][d0] (row-major),
+ *                           b_1 [d1], W_2, b_2, ...
+ *   msg                     (T_max - 1) * n_species message NNs (out = K), ordered t-major
+ *   en                      n_species energy NNs (out = 1); E_i = energy_scale * NN(rho_i^{T-1})
+ * Supported (L, K): (2, 8), (2, 12), (1, 4), (2, 4); n_hidden 1..4; hidden <= 256. */
+typedef struct {
+    int32_t n_species, L, K, T_max, n_hidden, hidden;
+    double r_c, ang_scale, energy_scale;
+    const double *centres, *alphas, *c0, *msg, *en;
+} reann_model_desc;
+
+reann_status reann_model_create(const reann_model_desc *desc, reann_model **out);
+void reann_model_free(reann_model *m);
+
+/* ---------------------------------------------------------------- context --
+ * A context binds the library to one GPU and one HIP stream.  hip_stream may be NULL
+ * (the library then creates a stream of default priority).  Device memory the
+ * context needs is allocated on first use and kept until reann_ctx_free. */
+reann_status reann_ctx_create(int32_t device, void *hip_stream, reann_ctx **out);
+void reann_ctx_free(reann_ctx *ctx);
+
+/* Options of an evaluation.  Zero-initialised = FP32, whole system, no skin. */
+typedef struct {
+    int32_t precision;   /* REANN_FP64 / FP32 / BF16 / FP8                                 */
+    int32_t decomp[3];   /* subdomains per axis; {0,0,0} or {1,1,1} = whole system          */
+    double skin;         /* neighbour-list skin (A); the list is rebuilt when an atom has
+                            moved more than skin/2 since the last build                    */
+} reann_opts;
+
+/* ------------------------------------------------------------- neighbours --
+ * reann_build_neighbors: neighbour list of every atom for cutoff r_c + skin (Sec. 2.2:
+ * one list, reused by every MP layer), built on the GPU through the subdomain split
+ * `decomp` (NULL = whole system).  The pair set is every copy (j, shift) of atom j
+ * displaced by integer lattice vectors, (j, shift) != (i, 0), with
+ *   d = (w_j + shift*L) - w_i,  fma(dz,dz, fma(dy,dy, dx*dx)) < (r_c+skin)^2   (FP64),
+ * where w is the position wrapped into [0, L) on periodic axes by
+ *   w = x - floor(x/L)*L, then +L if negative, then -L if >= L.
+ * pos: host [n][3].  The result stays on the device; export it with reann_nlist_export. */
+reann_status reann_build_neighbors(reann_ctx *ctx, const double *pos, int64_t n, const double cell[9],
+                                   const int32_t pbc[3], double r_c, double skin, const int32_t decomp[3],
+                                   reann_nlist **out);
+
+/* Two-call export of the list in canonical order: each atom's row sorted by (j, shift).
+   First call with row == NULL to get *n_pairs; then pass row[n+1], j[n_pairs],
+   shift[n_pairs][3] (all host). */
+reann_status reann_nlist_export(const reann_nlist *nl, int64_t *n_pairs, int64_t *row, int64_t *j,
+                                int32_t *shift);
+
+/* Sizes of a built list (each output may be NULL): atoms, ghost/image copies, stored pairs
+   (rows of locals plus the rows of ghosts that the backward reads), pairs in the rows of
+   the locals (the list proper). */
+reann_status reann_nlist_info(const reann_nlist *nl, int64_t *n_atoms, int64_t *n_ghosts, int64_t *n_pairs,
+                              int64_t *n_local_pairs);
+void reann_nlist_free(reann_nlist *nl);
+
+/* ----------------------------------------------------------- evaluation --
+ * reann_energy_forces: one energy + force + virial evaluation (host pointers).
+ *   pos[n][3], species[n] (0 <= s < n_species), r_c must equal the model's r_c,
+ *   1 <= T <= model T_max.  opt may be NULL (FP32, whole system, skin 0).
+ *   energy: host scalar (eV); forces: host [n][3] (eV/A) or NULL; virial: host [9] or NULL,
+ *   W_ab = sum over directed edges of d_a f_b with f = -dE/dd (eV).
+ * The context caches the plan of the last system: calling again with the same n, species,
+ * cell, pbc, T and opts reuses it, and reuses the neighbour list while no atom has moved
+ * more than skin/2. */
+reann_status reann_energy_forces(reann_ctx *ctx, const reann_model *m, const double *pos, const int32_t *species,
+                                 int64_t n, const double cell[9], const int32_t pbc[3], double r_c, int32_t T,
+                                 const reann_opts *opt, double *energy, double *forces, double *virial);
+
+/* Device-pointer path (used by the PyTorch autograd binding).  A plan fixes the system
+ * (n, species, cell, pbc), the model, T and the options.  species is host [n].
+ *   reann_plan_forward:  d_pos device FP64 [n][3]; writes d_energy (device FP64 scalar) and,
+ *                        if not NULL, d_atom_energy (device FP64 [n]).  Enqueued on hip_stream
+ *                        (NULL = HIP's null stream, which is also PyTorch's default stream);
+ *                        synchronises that stream once per call for the skin check, and
+ *                        rebuilds the neighbour list when an atom has moved more than skin/2.
+ *   reann_plan_backward: gradient of E w.r.t. positions after a forward: d_grad_energy is a
+ *                        device FP64 scalar g (NULL = 1); writes d_forces = -g dE/dx (device FP64
+ *                        [n][3]) and, if not NULL, d_virial = g W (device FP64 [9]).  Enqueued
+ *                        on hip_stream (NULL = null stream).  REANN_E_STATE if no forward
+ *                        preceded it. */
+reann_status reann_plan_create(reann_ctx *ctx, const reann_model *m, const int32_t *species, int64_t n,
+                               const double cell[9], const int32_t pbc[3], int32_t T, const reann_opts *opt,
+                               reann_plan **out);
+reann_status reann_plan_forward(reann_plan *p, const double *d_pos, double *d_energy, double *d_atom_energy,
+                                void *hip_stream);
+reann_status reann_plan_backward(reann_plan *p, const double *d_grad_energy, double *d_forces, double *d_virial,
+                                 void *hip_stream);
+void reann_plan_free(reann_plan *p);
+
+/* Intermediate values of the last forward, for layer-by-layer checks, copied to host in
+ * the caller's atom order:  what = 0: orbital sums S^t [n][NL][K] (NL = (L+1)(L+2)(L+3)/6,
+ * components ordered by l, then lx descending, then ly descending); 1: messages c^t [n][K];
+ * 2: atomic energies [n] (t ignored).  Synchronises the stream. */
+reann_status reann_plan_get(reann_plan *p, int32_t what, int32_t t, double *host_out);
+
+/* Kernel time per phase, measured with HIP events recorded on the evaluation stream at
+ * phase boundaries while timing is enabled (reann_plan_set_timing), accumulated over every
+ * forward+backward since the previous reann_plan_timing call:
+ *   [0] neighbour build, [1] edge forward, [2] density + atomic NN forward, [3] ghost exchange,
+ *   [4] atomic NN backward + density adjoint, [5] edge backward, [6] other (refresh, seeds,
+ *   reductions, output).
+ * ms7: host [7] milliseconds; launches7 (host [7] or NULL): kernel launches counted for the
+ * phases that time a single kernel type ([0] builds, [1] edge-forward and [5] edge-backward
+ * launches); steps (or NULL): backward passes covered.  Synchronises on the last event and
+ * resets the accumulators. */
+reann_status reann_plan_set_timing(reann_plan *p, int32_t enable);
+reann_status reann_plan_timing(reann_plan *p, double *ms7, int64_t *launches7, int64_t *steps);
+
+/* ---------------------------------------------------------------- serving --
+ * Continuous-batching server: many independent systems stay resident on the device
+ * (positions, velocities, neighbour lists, features); requests that arrive while others
+ * run are admitted as batch slots and HBM budget free up.
+ *   hbm_budget_bytes  device memory the resident systems may use (0 = 3/4 of free memory);
+ *                     reann_system_add returns REANN_E_CAPACITY for a system that can never fit.
+ *   max_batch_atoms   atoms evaluated together in one batched step (0 = 262144).
+ *   precision, T, skin as in reann_opts.  use_graph != 0 replays a captured HIP graph for the
+ *   batched step when the batch shape repeats. */
+typedef struct {
+    int64_t hbm_budget_bytes;
+    int64_t max_batch_atoms;
+    int32_t precision;
+    int32_t T;
+    double skin;
+    int32_t use_graph;
+    int32_t device;
+} reann_server_opts;
+
+#define REANN_REQ_EVAL 0      /* evaluate E, F, W at the given positions (pos required)        */
+#define REANN_REQ_VV_STEP 1   /* one velocity-Verlet step of dt_fs (pos ignored), then E, F, W  */
+
+typedef struct {
+    uint64_t sys_id;
+    int32_t kind;
+    double dt_fs;
+    const double *pos;        /* host [n][3] for REANN_REQ_EVAL, copied by reann_submit */
+} reann_request;
+
+typedef struct {
+    double energy;
+    double virial[9];
+    double *forces;           /* caller-owned host [n][3], or NULL to skip                   */
+    double *positions;        /* caller-owned host [n][3], or NULL: positions after the step */
+    int64_t t_submit_ns, t_done_ns;   /* CLOCK_MONOTONIC                                    */
+    reann_status status;      /* status of the request itself                              */
+} reann_result;
+
+reann_status reann_server_create(const reann_model *m, const reann_server_opts *opt, reann_server **out);
+/* masses: host [n_species] in amu, used by REANN_REQ_VV_STEP (NULL = no dynamics). */
+reann_status reann_server_set_masses(reann_server *s, const double *masses_amu);
+reann_status reann_system_add(reann_server *s, const int32_t *species, int64_t n, const double cell[9],
+                              const int32_t pbc[3], const double *pos, const double *vel, uint64_t *sys_id);
+reann_status reann_submit(reann_server *s, const reann_request *req, uint64_t *ticket);
+/* Non-blocking: REANN_PENDING while running, REANN_OK when res is filled (the ticket is then
+   released), or a negative status. */
+reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res);
+/* Statistics: [0] batches run, [1] requests completed, [2] atoms evaluated, [3] graph replays,
+   [4] admissions deferred for HBM budget, [5] resident bytes. */
+reann_status reann_server_stats(reann_server *s, int64_t *stats6);
+void reann_server_destroy(reann_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REANN_H */

@@ -1,0 +1,346 @@
+"""ctypes binding of ``libreann.so`` (declared in include/reann.h).
+
+Argument marshalling only: every step of the evaluation runs in the library's HIP
+kernels.  Importing fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libreann.so")
+
+FP64, FP32, BF16, FP8 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp8": FP8}
+REQ_EVAL, REQ_VV_STEP = 0, 1
+OK, PENDING = 0, 1
+
+
+class ReannError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("reann status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _ModelDesc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("L", C.c_int32), ("K", C.c_int32), ("T_max", C.c_int32),
+                ("n_hidden", C.c_int32), ("hidden", C.c_int32), ("r_c", C.c_double),
+                ("ang_scale", C.c_double), ("energy_scale", C.c_double),
+                ("centres", C.c_void_p), ("alphas", C.c_void_p), ("c0", C.c_void_p),
+                ("msg", C.c_void_p), ("en", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("decomp", C.c_int32 * 3), ("skin", C.c_double)]
+
+
+class _ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_batch_atoms", C.c_int64), ("precision", C.c_int32),
+                ("T", C.c_int32), ("skin", C.c_double), ("use_graph", C.c_int32), ("device", C.c_int32)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("sys_id", C.c_uint64), ("kind", C.c_int32), ("dt_fs", C.c_double), ("pos", C.c_void_p)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("energy", C.c_double), ("virial", C.c_double * 9), ("forces", C.c_void_p),
+                ("positions", C.c_void_p), ("t_submit_ns", C.c_int64), ("t_done_ns", C.c_int64),
+                ("status", C.c_int32)]
+
+
+_vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+_SIGS = {
+    "reann_last_error": (C.c_char_p, []),
+    "reann_model_create": (_i32, [C.POINTER(_ModelDesc), C.POINTER(_vp)]),
+    "reann_model_free": (None, [_vp]),
+    "reann_ctx_create": (_i32, [_i32, _vp, C.POINTER(_vp)]),
+    "reann_ctx_free": (None, [_vp]),
+    "reann_build_neighbors": (_i32, [_vp, _vp, _i64, _vp, _vp, _d, _d, _vp, C.POINTER(_vp)]),
+    "reann_nlist_export": (_i32, [_vp, C.POINTER(_i64), _vp, _vp, _vp]),
+    "reann_nlist_info": (_i32, [_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
+    "reann_nlist_free": (None, [_vp]),
+    "reann_energy_forces": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _d, _i32, C.POINTER(_Opts), _vp, _vp, _vp]),
+    "reann_plan_create": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _i32, C.POINTER(_Opts), C.POINTER(_vp)]),
+    "reann_plan_forward": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "reann_plan_backward": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "reann_plan_free": (None, [_vp]),
+    "reann_plan_get": (_i32, [_vp, _i32, _i32, _vp]),
+    "reann_plan_set_timing": (_i32, [_vp, _i32]),
+    "reann_plan_timing": (_i32, [_vp, _vp, _vp, C.POINTER(_i64)]),
+    "reann_server_create": (_i32, [_vp, C.POINTER(_ServerOpts), C.POINTER(_vp)]),
+    "reann_server_set_masses": (_i32, [_vp, _vp]),
+    "reann_system_add": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, C.POINTER(C.c_uint64)]),
+    "reann_submit": (_i32, [_vp, C.POINTER(_Request), C.POINTER(C.c_uint64)]),
+    "reann_poll": (_i32, [_vp, C.c_uint64, C.POINTER(_Result)]),
+    "reann_server_stats": (_i32, [_vp, _vp]),
+    "reann_server_destroy": (None, [_vp]),
+}
+
+_lib = None
+
+# Live handles, released at interpreter exit in dependency order (plans, lists and
+# servers before the contexts and models they use) while the HIP runtime is still up.
+_LIVE = {k: weakref.WeakSet() for k in ("plan", "nlist", "server", "ctx", "model")}
+
+
+def _release_all():
+    for kind in ("plan", "nlist", "server", "ctx", "model"):
+        for obj in list(_LIVE[kind]):
+            obj.close()
+
+
+atexit.register(_release_all)
+
+
+def load():
+    """Load libreann.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libreann.so is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+                              "or `python paper_2505_06711_amd/build.py`")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(status: int) -> int:
+    if status < 0:
+        raise ReannError(status, load().reann_last_error().decode())
+    return status
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a.reshape(shape) if shape is not None else a
+
+
+def _i32a(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _opts(precision="fp32", decomp=(1, 1, 1), skin=0.0) -> _Opts:
+    o = _Opts()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    for a in range(3):
+        o.decomp[a] = int(decomp[a])
+    o.skin = float(skin)
+    return o
+
+
+class Model:
+    """Device-ready model parameters (``reann_model``)."""
+
+    def __init__(self, params):
+        """``params``: a synth.models.ModelParams-like object."""
+        lib = load()
+        self.params = params
+        self._keep = [_f64(params.centres), _f64(params.alphas), _f64(params.c0),
+                      _f64(params.msg_blob if params.msg_blob.size else np.zeros(1)), _f64(params.energy_blob)]
+        d = _ModelDesc(params.n_species, params.L, params.K, params.T_max, params.n_hidden, params.hidden,
+                       params.r_c, params.ang_scale, params.energy_scale, *[_p(a) for a in self._keep])
+        h = _vp()
+        check(lib.reann_model_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.r_c = params.r_c
+        self.T_max = params.T_max
+        self.K, self.L = params.K, params.L
+        _LIVE["model"].add(self)
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.reann_model_free(self.handle)
+        self.handle = None
+
+    __del__ = close
+
+
+class Context:
+    """One GPU and one HIP stream (``reann_ctx``).  ``stream``: an int handle, a
+    torch.cuda.Stream, or None for a library-created stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = load()
+        if stream is not None and hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        h = _vp()
+        check(lib.reann_ctx_create(int(device), stream, C.byref(h)))
+        self.handle = h
+        self.device = device
+        _LIVE["ctx"].add(self)
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            for kind in ("plan", "nlist", "server"):      # dependants first
+                for obj in list(_LIVE[kind]):
+                    if getattr(obj, "ctx", None) is self:
+                        obj.close()
+            _lib.reann_ctx_free(self.handle)
+        self.handle = None
+
+    __del__ = close
+
+
+class NeighborList:
+    def __init__(self, handle, ctx=None):
+        self.handle = handle
+        self.ctx = ctx
+        _LIVE["nlist"].add(self)
+
+    def info(self):
+        a, g, p, q = _i64(), _i64(), _i64(), _i64()
+        check(load().reann_nlist_info(self.handle, C.byref(a), C.byref(g), C.byref(p), C.byref(q)))
+        return dict(n_atoms=a.value, n_ghosts=g.value, n_pairs=p.value, n_local_pairs=q.value)
+
+    def export(self):
+        """(row[n+1], j[n_pairs], shift[n_pairs, 3]) in canonical (j, shift) row order."""
+        lib = load()
+        cnt = _i64()
+        check(lib.reann_nlist_export(self.handle, C.byref(cnt), None, None, None))
+        n = self.info()["n_atoms"]
+        row = np.zeros(n + 1, np.int64)
+        j = np.zeros(max(cnt.value, 1), np.int64)
+        sh = np.zeros((max(cnt.value, 1), 3), np.int32)
+        check(lib.reann_nlist_export(self.handle, C.byref(cnt), _p(row), _p(j), _p(sh)))
+        return row, j[:cnt.value], sh[:cnt.value]
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.reann_nlist_free(self.handle)
+        self.handle = None
+
+    __del__ = close
+
+
+def build_neighbors(ctx: Context, system: dict, r_c: float, skin: float = 0.0, decomp=(1, 1, 1)) -> NeighborList:
+    pos = _f64(system["pos"])
+    cell = _f64(system["cell"], (9,))
+    pbc = _i32a(system["pbc"])
+    dec = _i32a(decomp)
+    h = _vp()
+    check(load().reann_build_neighbors(ctx.handle, _p(pos), pos.shape[0], _p(cell), _p(pbc), float(r_c), float(skin),
+                                       _p(dec), C.byref(h)))
+    return NeighborList(h, ctx)
+
+
+def energy_forces(ctx: Context, model: Model, system: dict, T: int, precision="fp32", decomp=(1, 1, 1),
+                  skin: float = 0.0, forces: bool = True):
+    """Host-pointer evaluation: returns (E, F[n,3] or None, W[3,3] or None)."""
+    pos = _f64(system["pos"])
+    spec = _i32a(system["species"])
+    cell = _f64(system["cell"], (9,))
+    pbc = _i32a(system["pbc"])
+    n = pos.shape[0]
+    E = np.zeros(1)
+    F = np.zeros((n, 3)) if forces else None
+    W = np.zeros(9) if forces else None
+    o = _opts(precision, decomp, skin)
+    check(load().reann_energy_forces(ctx.handle, model.handle, _p(pos), _p(spec), n, _p(cell), _p(pbc),
+                                     float(model.r_c), int(T), C.byref(o), _p(E), _p(F), _p(W)))
+    return float(E[0]), F, (W.reshape(3, 3) if forces else None)
+
+
+class Plan:
+    """Device-pointer evaluation of one system (``reann_plan``).  Tensors are torch
+    tensors on the context's GPU; the stream defaults to torch's current stream."""
+
+    def __init__(self, ctx: Context, model: Model, system: dict, T: int, precision="fp32", decomp=(1, 1, 1),
+                 skin: float = 0.0):
+        lib = load()
+        self.ctx, self.model = ctx, model
+        spec = _i32a(system["species"])
+        cell = _f64(system["cell"], (9,))
+        pbc = _i32a(system["pbc"])
+        self.n = spec.shape[0]
+        self.T = T
+        o = _opts(precision, decomp, skin)
+        h = _vp()
+        check(lib.reann_plan_create(ctx.handle, model.handle, _p(spec), self.n, _p(cell), _p(pbc), int(T),
+                                    C.byref(o), C.byref(h)))
+        self.handle = h
+        self.L, self.K = model.L, model.K
+        _LIVE["plan"].add(self)
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        if stream is None:
+            return torch.cuda.current_stream().cuda_stream
+        return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+    def forward(self, pos, energy, atom_energy=None, stream=None):
+        """pos: float64 [n,3] device tensor; energy: float64 [] device tensor (written)."""
+        _require_device_f64(pos, (self.n, 3))
+        _require_device_f64(energy, ())
+        ae = None
+        if atom_energy is not None:
+            _require_device_f64(atom_energy, (self.n,))
+            ae = atom_energy.data_ptr()
+        check(load().reann_plan_forward(self.handle, pos.data_ptr(), energy.data_ptr(), ae, self._stream(stream)))
+
+    def backward(self, forces, grad_energy=None, virial=None, stream=None):
+        """forces: float64 [n,3] device tensor receiving -g dE/dx; grad_energy: float64 []
+        device tensor g or None (= 1); virial: float64 [3,3] device tensor or None."""
+        _require_device_f64(forces, (self.n, 3))
+        g = None
+        if grad_energy is not None:
+            _require_device_f64(grad_energy, ())
+            g = grad_energy.data_ptr()
+        w = None
+        if virial is not None:
+            _require_device_f64(virial, (3, 3))
+            w = virial.data_ptr()
+        check(load().reann_plan_backward(self.handle, g, forces.data_ptr(), w, self._stream(stream)))
+
+    def get(self, what: str, t: int = 0) -> np.ndarray:
+        """Intermediates of the last forward in caller atom order: 'S' [n,NL,K], 'c' [n,K],
+        'atom_energy' [n]."""
+        NL = (self.L + 1) * (self.L + 2) * (self.L + 3) // 6
+        code, shape = {"S": (0, (self.n, NL, self.K)), "c": (1, (self.n, self.K)),
+                       "atom_energy": (2, (self.n,))}[what]
+        out = np.zeros(shape)
+        check(load().reann_plan_get(self.handle, code, int(t), _p(out)))
+        return out
+
+    def set_timing(self, on: bool = True):
+        check(load().reann_plan_set_timing(self.handle, int(bool(on))))
+
+    PHASES = ("nlist", "edge_fwd", "nn_fwd", "ghost", "nn_bwd", "edge_bwd", "other")
+
+    def timing(self) -> dict:
+        """Per-phase kernel milliseconds accumulated since the last call (see reann.h)."""
+        ms = np.zeros(7)
+        la = np.zeros(7, np.int64)
+        steps = _i64()
+        check(load().reann_plan_timing(self.handle, _p(ms), _p(la), C.byref(steps)))
+        return dict(ms=dict(zip(self.PHASES, ms.tolist())), launches=dict(zip(self.PHASES, la.tolist())),
+                    steps=steps.value)
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.reann_plan_free(self.handle)
+        self.handle = None
+
+    __del__ = close
+
+
+def _require_device_f64(t, shape):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 device tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (tuple(shape), tuple(t.shape)))

@@ -1,0 +1,344 @@
+// C ABI entry points.  Every call converts library exceptions into a status code and a
+// thread-local message; no exception crosses the boundary.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "runtime.hpp"
+
+using namespace reann;
+
+static thread_local std::string g_last_error;
+
+static reann_status set_err(reann_status code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class F> static reann_status guarded(F &&f) {
+    try {
+        f();
+        g_last_error.clear();
+        return REANN_OK;
+    } catch (const Error &e) {
+        return set_err(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return set_err(REANN_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return set_err(REANN_E_DEVICE, e.what());
+    } catch (...) {
+        return set_err(REANN_E_DEVICE, "unknown error");
+    }
+}
+
+#define REQUIRE(cond, msg) \
+    do { if (!(cond)) fail(REANN_E_INVALID, msg); } while (0)
+
+static void check_cell(const double *cell, const int32_t *pbc) {
+    REQUIRE(cell && pbc, "cell and pbc are required");
+    for (int k = 0; k < 9; ++k) REQUIRE(std::isfinite(cell[k]), "cell has a non-finite entry");
+}
+
+static void check_positions(const double *pos, int64_t n) {
+    for (int64_t i = 0; i < 3 * n; ++i) REQUIRE(std::isfinite(pos[i]), "positions contain NaN or Inf");
+}
+
+extern "C" {
+
+const char *reann_last_error(void) { return g_last_error.c_str(); }
+
+reann_status reann_model_create(const reann_model_desc *d, reann_model **out) {
+    return guarded([&] {
+        REQUIRE(d && out, "NULL argument");
+        REQUIRE(d->n_species >= 1 && d->n_species <= 64, "n_species must be in [1, 64]");
+        REQUIRE(d->L >= 0 && d->K >= 1, "bad L or K");
+        const bool lk_ok = (d->L == 2 && (d->K == 8 || d->K == 12 || d->K == 4)) || (d->L == 1 && d->K == 4);
+        if (!lk_ok) fail(REANN_E_UNSUPPORTED, "no kernels compiled for this (L, K)");
+        REQUIRE(d->T_max >= 1 && d->T_max <= 16, "T_max must be in [1, 16]");
+        REQUIRE(d->n_hidden >= 1 && d->n_hidden <= 4, "n_hidden must be in [1, 4]");
+        REQUIRE(d->hidden >= 1 && d->hidden <= 256, "hidden must be in [1, 256]");
+        REQUIRE(d->r_c > 0 && std::isfinite(d->r_c), "r_c must be > 0");
+        REQUIRE(std::isfinite(d->ang_scale) && std::isfinite(d->energy_scale), "non-finite scale");
+        REQUIRE(d->centres && d->alphas && d->c0 && d->en, "NULL parameter array");
+        REQUIRE(d->T_max == 1 || d->msg, "message NN parameters required for T_max > 1");
+        auto *m = new reann_model();
+        Model &M = m->impl;
+        M.n_species = d->n_species; M.L = d->L; M.K = d->K; M.T_max = d->T_max;
+        M.nh = d->n_hidden; M.H = d->hidden;
+        M.F = n_feat(d->L, d->K); M.NL = n_lambda(d->L);
+        M.r_c = d->r_c; M.ang_scale = d->ang_scale; M.energy_scale = d->energy_scale;
+        M.centres.assign(d->centres, d->centres + d->K);
+        M.alphas.assign(d->alphas, d->alphas + d->K);
+        M.c0.assign(d->c0, d->c0 + (size_t)d->n_species * d->K);
+        M.msg_nn = nn_layout(M.F, M.H, M.nh, M.K);
+        M.en_nn = nn_layout(M.F, M.H, M.nh, 1);
+        const size_t nmsg = (size_t)(d->T_max - 1) * d->n_species * M.msg_nn.size;
+        const size_t nen = (size_t)d->n_species * M.en_nn.size;
+        if (nmsg) M.msg.assign(d->msg, d->msg + nmsg);
+        M.en.assign(d->en, d->en + nen);
+        for (double v : M.msg) if (!std::isfinite(v)) { delete m; fail(REANN_E_INVALID, "non-finite weight"); }
+        for (double v : M.en) if (!std::isfinite(v)) { delete m; fail(REANN_E_INVALID, "non-finite weight"); }
+        *out = m;
+    });
+}
+
+void reann_model_free(reann_model *m) { delete m; }
+
+reann_status reann_ctx_create(int32_t device, void *hip_stream, reann_ctx **out) {
+    return guarded([&] {
+        REQUIRE(out, "NULL argument");
+        int nd = 0;
+        HIP_OK(hipGetDeviceCount(&nd));
+        REQUIRE(device >= 0 && device < nd, "device index out of range");
+        HIP_OK(hipSetDevice(device));
+        auto *c = new reann_ctx();
+        c->impl.device = device;
+        if (hip_stream) {
+            c->impl.stream = (hipStream_t)hip_stream;
+        } else {
+            hipError_t e = hipStreamCreateWithFlags(&c->impl.stream, hipStreamNonBlocking);
+            if (e != hipSuccess) { delete c; HIP_OK(e); }
+            c->impl.own_stream = true;
+        }
+        *out = c;
+    });
+}
+
+void reann_ctx_free(reann_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->impl.device);
+    (void)hipStreamSynchronize(c->impl.stream);
+    c->impl.cached.reset();
+    if (c->impl.own_stream) (void)hipStreamDestroy(c->impl.stream);
+    delete c;
+}
+
+// ------------------------------------------------------------------ nlist --
+
+struct reann_nlist {
+    Plan plan;   // geometry and neighbour list only; no model attached
+};
+
+reann_status reann_build_neighbors(reann_ctx *ctx, const double *pos, int64_t n, const double cell[9],
+                                   const int32_t pbc[3], double r_c, double skin, const int32_t decomp[3],
+                                   reann_nlist **out) {
+    return guarded([&] {
+        REQUIRE(ctx && pos && out, "NULL argument");
+        REQUIRE(n > 0, "n must be > 0");
+        REQUIRE(r_c > 0 && std::isfinite(r_c), "r_c must be > 0");
+        REQUIRE(skin >= 0 && std::isfinite(skin), "skin must be >= 0");
+        check_cell(cell, pbc);
+        check_positions(pos, n);
+        HIP_OK(hipSetDevice(ctx->impl.device));
+        auto *nl = new reann_nlist();
+        try {
+            Plan &p = nl->plan;
+            p.ctx = &ctx->impl;
+            p.n = n;
+            int32_t P[3] = {1, 1, 1};
+            if (decomp)
+                for (int a = 0; a < 3; ++a) P[a] = decomp[a] > 0 ? decomp[a] : 1;
+            geom_init(p.g, cell, pbc, P, r_c, skin);
+            hipStream_t st = ctx->impl.stream;
+            DevBuf dpos;
+            dpos.ensure(n * 24);
+            HIP_OK(hipMemcpyAsync(dpos.p, pos, n * 24, hipMemcpyHostToDevice, st));
+            int32_t *ds = p.d_species.resize(n);
+            zero(st, ds, n * 4);
+            build_nlist(st, dpos.as<double>(), ds, n, 1, p.g, r_c, skin, p.nl, p.ns);
+            p.built = true;
+        } catch (...) {
+            delete nl;
+            throw;
+        }
+        *out = nl;
+    });
+}
+
+reann_status reann_nlist_info(const reann_nlist *nl, int64_t *n_atoms, int64_t *n_ghosts, int64_t *n_pairs,
+                              int64_t *n_local_pairs) {
+    return guarded([&] {
+        REQUIRE(nl, "NULL list");
+        if (n_atoms) *n_atoms = nl->plan.nl.n;
+        if (n_ghosts) *n_ghosts = nl->plan.nl.n_gh;
+        if (n_pairs) *n_pairs = nl->plan.nl.n_pairs;
+        if (n_local_pairs) *n_local_pairs = nl->plan.nl.n_local_pairs;
+    });
+}
+
+reann_status reann_nlist_export(const reann_nlist *nlh, int64_t *n_pairs, int64_t *row, int64_t *j, int32_t *shift) {
+    return guarded([&] {
+        REQUIRE(nlh && n_pairs, "NULL argument");
+        const NList &nl = nlh->plan.nl;
+        const int64_t n = nl.n;
+        if (!row) { *n_pairs = nl.n_local_pairs; return; }
+        REQUIRE(j && shift, "NULL output array");
+        HIP_OK(hipDeviceSynchronize());
+        std::vector<int64_t> r(n + 1);
+        std::vector<int32_t> col(std::max<int64_t>(nl.n_local_pairs, 1)), perm(n),
+            owner(std::max<int64_t>(nl.n_gh, 1)), sh(std::max<int64_t>(nl.n_gh, 1) * 3);
+        HIP_OK(hipMemcpy(r.data(), nl.row.ptr(), (n + 1) * 8, hipMemcpyDeviceToHost));
+        if (nl.n_local_pairs) HIP_OK(hipMemcpy(col.data(), nl.col.ptr(), nl.n_local_pairs * 4, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(perm.data(), nl.perm.ptr(), n * 4, hipMemcpyDeviceToHost));
+        if (nl.n_gh) {
+            HIP_OK(hipMemcpy(owner.data(), nl.gh_owner.ptr(), nl.n_gh * 4, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(sh.data(), nl.gh_shift.ptr(), nl.n_gh * 12, hipMemcpyDeviceToHost));
+        }
+        std::vector<int32_t> inv(n);
+        for (int64_t i = 0; i < n; ++i) inv[perm[i]] = (int32_t)i;
+        struct E { int64_t j; int32_t s[3]; };
+        int64_t o = 0;
+        row[0] = 0;
+        std::vector<E> buf;
+        for (int64_t u = 0; u < n; ++u) {
+            const int64_t x = inv[u];
+            buf.clear();
+            for (int64_t k = r[x]; k < r[x + 1]; ++k) {
+                const int64_t e = col[k];
+                E v;
+                if (e < n) { v.j = perm[e]; v.s[0] = v.s[1] = v.s[2] = 0; }
+                else {
+                    const int64_t g = e - n;
+                    v.j = perm[owner[g]];
+                    for (int a = 0; a < 3; ++a) v.s[a] = sh[3 * g + a];
+                }
+                buf.push_back(v);
+            }
+            std::sort(buf.begin(), buf.end(), [](const E &a, const E &b) {
+                if (a.j != b.j) return a.j < b.j;
+                for (int q = 0; q < 3; ++q) if (a.s[q] != b.s[q]) return a.s[q] < b.s[q];
+                return false;
+            });
+            for (const E &v : buf) {
+                j[o] = v.j;
+                for (int a = 0; a < 3; ++a) shift[3 * o + a] = v.s[a];
+                ++o;
+            }
+            row[u + 1] = o;
+        }
+        *n_pairs = o;
+    });
+}
+
+void reann_nlist_free(reann_nlist *nl) { delete nl; }
+
+// ------------------------------------------------------------- evaluation --
+
+static void check_eval_args(const reann_model *m, const double *pos, const int32_t *species, int64_t n,
+                            const double *cell, const int32_t *pbc, int32_t T, const reann_opts *opt) {
+    REQUIRE(m && species, "NULL argument");
+    REQUIRE(n > 0, "n must be > 0");
+    check_cell(cell, pbc);
+    if (pos) check_positions(pos, n);
+    REQUIRE(T >= 1 && T <= m->impl.T_max, "T must be in [1, T_max]");
+    for (int64_t i = 0; i < n; ++i)
+        REQUIRE(species[i] >= 0 && species[i] < m->impl.n_species, "species out of range");
+    if (opt) {
+        REQUIRE(opt->skin >= 0 && std::isfinite(opt->skin), "skin must be >= 0");
+        if (opt->precision != REANN_FP64 && opt->precision != REANN_FP32 && opt->precision != REANN_BF16 &&
+            opt->precision != REANN_FP8)
+            fail(REANN_E_INVALID, "unknown precision");
+    }
+}
+
+reann_status reann_energy_forces(reann_ctx *ctx, const reann_model *m, const double *pos, const int32_t *species,
+                                 int64_t n, const double cell[9], const int32_t pbc[3], double r_c, int32_t T,
+                                 const reann_opts *opt, double *energy, double *forces, double *virial) {
+    return guarded([&] {
+        REQUIRE(ctx && pos && energy, "NULL argument");
+        check_eval_args(m, pos, species, n, cell, pbc, T, opt);
+        REQUIRE(r_c == m->impl.r_c, "r_c must equal the model's cutoff");
+        Ctx &c = ctx->impl;
+        HIP_OK(hipSetDevice(c.device));
+        if (!c.cached || !c.cached->same_system(&m->impl, species, n, cell, pbc, T, opt)) {
+            c.cached.reset();
+            auto p = std::make_unique<Plan>();
+            p->init(&c, const_cast<Model *>(&m->impl), species, n, cell, pbc, T, opt);
+            c.cached = std::move(p);
+        }
+        Plan &p = *c.cached;
+        hipStream_t st = c.stream;
+        double *dpos = static_cast<double *>(c.pos.ensure(n * 24));
+        double *dF = static_cast<double *>(c.forces.ensure(n * 24));
+        double *dsc = static_cast<double *>(c.scal.ensure(16 * 8));
+        HIP_OK(hipMemcpyAsync(dpos, pos, n * 24, hipMemcpyHostToDevice, st));
+        p.forward(dpos, dsc, nullptr, st);
+        if (forces || virial) p.backward(nullptr, dF, dsc + 1, st);
+        double h[10];
+        HIP_OK(hipMemcpyAsync(h, dsc, 10 * 8, hipMemcpyDeviceToHost, st));
+        if (forces) HIP_OK(hipMemcpyAsync(forces, dF, n * 24, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        *energy = h[0];
+        if (virial) std::memcpy(virial, h + 1, 9 * 8);
+    });
+}
+
+reann_status reann_plan_create(reann_ctx *ctx, const reann_model *m, const int32_t *species, int64_t n,
+                               const double cell[9], const int32_t pbc[3], int32_t T, const reann_opts *opt,
+                               reann_plan **out) {
+    return guarded([&] {
+        REQUIRE(ctx && out, "NULL argument");
+        check_eval_args(m, nullptr, species, n, cell, pbc, T, opt);
+        HIP_OK(hipSetDevice(ctx->impl.device));
+        auto *p = new reann_plan();
+        try {
+            p->impl.init(&ctx->impl, const_cast<Model *>(&m->impl), species, n, cell, pbc, T, opt);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+    });
+}
+
+reann_status reann_plan_forward(reann_plan *p, const double *d_pos, double *d_energy, double *d_atom_energy,
+                                void *hip_stream) {
+    return guarded([&] {
+        REQUIRE(p && d_pos && d_energy, "NULL argument");
+        HIP_OK(hipSetDevice(p->impl.ctx->device));
+        p->impl.forward(d_pos, d_energy, d_atom_energy, (hipStream_t)hip_stream);
+    });
+}
+
+reann_status reann_plan_backward(reann_plan *p, const double *d_grad_energy, double *d_forces, double *d_virial,
+                                 void *hip_stream) {
+    return guarded([&] {
+        REQUIRE(p && d_forces, "NULL argument");
+        HIP_OK(hipSetDevice(p->impl.ctx->device));
+        p->impl.backward(d_grad_energy, d_forces, d_virial, (hipStream_t)hip_stream);
+    });
+}
+
+reann_status reann_plan_get(reann_plan *p, int32_t what, int32_t t, double *host_out) {
+    return guarded([&] {
+        REQUIRE(p && host_out, "NULL argument");
+        HIP_OK(hipSetDevice(p->impl.ctx->device));
+        p->impl.get(what, t, host_out);
+    });
+}
+
+reann_status reann_plan_set_timing(reann_plan *p, int32_t enable) {
+    return guarded([&] {
+        REQUIRE(p, "NULL argument");
+        p->impl.timing = enable != 0;
+    });
+}
+
+reann_status reann_plan_timing(reann_plan *p, double *ms7, int64_t *launches7, int64_t *steps) {
+    return guarded([&] {
+        REQUIRE(p && ms7, "NULL argument");
+        HIP_OK(hipSetDevice(p->impl.ctx->device));
+        const int64_t s = p->impl.collect_timing(ms7, launches7);
+        if (steps) *steps = s;
+    });
+}
+
+void reann_plan_free(reann_plan *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->impl.ctx->device);
+    (void)hipStreamSynchronize(p->impl.ctx->stream);
+    delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Runtime plumbing shared by the library's translation units: status codes carried by
+// exceptions inside the library (never across the C ABI), device buffers, launch checks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "reann.h"
+
+namespace reann {
+
+struct Error : std::runtime_error {
+    reann_status code;
+    Error(reann_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(reann_status c, const std::string &m) { throw Error(c, m); }
+
+inline void hip_check(hipError_t e, const char *what, const char *file, int line) {
+    if (e != hipSuccess) {
+        char buf[512];
+        std::snprintf(buf, sizeof buf, "%s failed at %s:%d: %s", what, file, line, hipGetErrorString(e));
+        if (e == hipErrorOutOfMemory) throw Error(REANN_E_NOMEM, buf);
+        throw Error(REANN_E_DEVICE, buf);
+    }
+}
+#define HIP_OK(x) ::reann::hip_check((x), #x, __FILE__, __LINE__)
+#define LAUNCH_OK(name) ::reann::hip_check(hipGetLastError(), name, __FILE__, __LINE__)
+
+// Owning device allocation that only grows.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void *ensure(size_t n) {
+        if (n == 0) n = 256;
+        if (n > bytes) {
+            release();
+            HIP_OK(hipMalloc(&p, n));
+            bytes = n;
+        }
+        return p;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+template <class T> struct DArr {
+    DevBuf b;
+    size_t n = 0;
+    T *resize(size_t count) {
+        b.ensure(count * sizeof(T));
+        n = count;
+        return b.as<T>();
+    }
+    T *ptr() const { return b.as<T>(); }
+    size_t bytes() const { return b.bytes; }
+};
+
+inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+// Parameters of the (L, K) pairs the kernels are compiled for.
+constexpr int n_lambda(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
+constexpr int n_feat(int L, int K) { return (L + 1) * K * (K + 1) / 2; }
+
+}  // namespace reann

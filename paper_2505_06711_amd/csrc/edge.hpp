@@ -1,0 +1,44 @@
+// Edge passes of one MP layer (Sec. 2.1 Eq. (1) inner sum, and its adjoint, Eqs. (3)-(5))
+// plus the per-layer ghost exchange (Sec. 2.2): gather of messages, reduction of adjoints.
+#pragma once
+
+#include "common.hpp"
+
+namespace reann {
+
+struct EdgeConsts {
+    double centres[16];
+    double alphas[16];
+    double r_c;
+    double rc2;       // r_c^2 in FP64: in-cutoff test of a list entry
+    double ang_scale;
+};
+
+struct EdgeArgs {
+    int64_t n, n_ext;
+    const int64_t *row;
+    const int32_t *col;
+    const double *px, *py, *pz;
+};
+
+// S[i][lambda][m] for the n local rows.  c: messages of all ext atoms, [n_ext][K].
+void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const EdgeConsts &ec, const void *c,
+                  void *S);
+
+// Atomics-free adjoint over every ext row (locals: all neighbours; ghosts: local neighbours).
+//   Sbar [n][NL][K] (locals), c [n_ext][K]; F [n_ext][3] is accumulated (+=);
+//   cbar [n_ext][K] is overwritten when want_cbar; Wpart receives one FP64 [9] per block.
+// Returns the number of blocks (rows of Wpart).
+int edge_backward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const EdgeConsts &ec, const void *c,
+                  const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart);
+int edge_backward_blocks(int64_t n_ext);
+
+// c[n + g][:] = c[owner[g]][:]
+void ghost_gather(hipStream_t st, bool fp64, int64_t n, int64_t n_gh, int K, const int32_t *owner, void *c);
+// v[o][:] += sum over ghost copies g of o of v[n + g][:], in increasing g
+void ghost_reduce(hipStream_t st, bool fp64, int64_t n, int width, const int32_t *copy_ptr, const int32_t *copy_idx,
+                  void *v);
+// c^0 of every ext atom from its species
+void init_messages(hipStream_t st, bool fp64, int64_t n_ext, int K, const int8_t *spec, const void *c0, void *c);
+
+}  // namespace reann

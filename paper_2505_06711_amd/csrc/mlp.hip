@@ -1,0 +1,286 @@
+// Density contraction, dense layers of the atomic NNs and the small reductions around them.
+//
+// Density (Sec. 2.1, Eq. (1) with the pairwise features that give the stated
+// (L+1) K (K+1)/2 count): rho[l,(a,b)] = sum_{|lambda|=l} w_lambda S[lambda][a] S[lambda][b].
+// Atomic NN (Eq. (2)): hidden layers Linear + SiLU, linear output, one NN per element.
+#include "mlp.hpp"
+
+namespace reann {
+
+__device__ inline float d_expm(float x) { return expf(x); }
+__device__ inline double d_expm(double x) { return exp(x); }
+
+template <typename R> __device__ inline R silu(R z) { return z / (R(1) + d_expm(-z)); }
+template <typename R> __device__ inline R dsilu(R z) {
+    const R sg = R(1) / (R(1) + d_expm(-z));
+    return sg * (R(1) + z * (R(1) - sg));
+}
+
+// ------------------------------------------------------------------ density --
+
+// one thread per (i, l, a): writes rho[l, (a, b)] for b = a..K-1
+template <typename R>
+__global__ void k_density(int64_t n, int L, int K, DensityConsts dc, const R *__restrict__ S, R *__restrict__ rho) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = (L + 1) * K;
+    if (t >= n * per) return;
+    const int64_t i = t / per;
+    const int la = (int)(t % per), l = la / K, a = la % K;
+    const int NL = dc.lstart[L + 1], P = K * (K + 1) / 2, F = (L + 1) * P;
+    const R *Si = S + i * NL * K;
+    R *out = rho + i * F + l * P + a * K - a * (a - 1) / 2;
+    for (int b = a; b < K; ++b) {
+        R s = R(0);
+        for (int k = dc.lstart[l]; k < dc.lstart[l + 1]; ++k) s += R(dc.w[k]) * Si[k * K + a] * Si[k * K + b];
+        out[b - a] = s;
+    }
+}
+
+// one thread per (i, lambda, a)
+template <typename R>
+__global__ void k_density_vjp(int64_t n, int L, int K, DensityConsts dc, const R *__restrict__ S,
+                              const R *__restrict__ rb, R *__restrict__ Sbar) {
+    const int NL = dc.lstart[L + 1];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * NL * K) return;
+    const int64_t i = t / (NL * K);
+    const int k = (int)((t / K) % NL), a = (int)(t % K);
+    int l = 0;
+    while (dc.lstart[l + 1] <= k) ++l;
+    const int P = K * (K + 1) / 2, F = (L + 1) * P;
+    const R *Si = S + i * NL * K + k * K;
+    const R *rbi = rb + i * F + l * P;
+    R s = R(0);
+    for (int b = 0; b < K; ++b) {
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        const R coef = rbi[lo * K - lo * (lo - 1) / 2 + (hi - lo)];
+        s += (a == b ? R(2) : R(1)) * coef * Si[b];
+    }
+    Sbar[t] = R(dc.w[k]) * s;
+}
+
+void density(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S, void *rho) {
+    const int64_t tot = n * (L + 1) * K;
+    if (tot == 0) return;
+    if (fp64) hipLaunchKernelGGL(k_density<double>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const double *)S, (double *)rho);
+    else hipLaunchKernelGGL(k_density<float>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const float *)S, (float *)rho);
+    LAUNCH_OK("k_density");
+}
+
+void density_vjp(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S,
+                 const void *rhobar, void *Sbar) {
+    const int64_t tot = n * dc.lstart[L + 1] * K;
+    if (tot == 0) return;
+    if (fp64) hipLaunchKernelGGL(k_density_vjp<double>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const double *)S, (const double *)rhobar, (double *)Sbar);
+    else hipLaunchKernelGGL(k_density_vjp<float>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const float *)S, (const float *)rhobar, (float *)Sbar);
+    LAUNCH_OK("k_density_vjp");
+}
+
+// -------------------------------------------------------------- dense layer --
+
+constexpr int TM = 64, TN = 64, TK = 16;
+
+template <typename R, int EPI, bool TRANS>
+__global__ __launch_bounds__(256) void k_dense(int64_t rows, int in, int out, const R *__restrict__ A, int lda,
+                                               const R *__restrict__ W, const R *__restrict__ bias, R *__restrict__ Z,
+                                               int ldz, R *__restrict__ C, int ldc) {
+    __shared__ R As[TK][TM + 1];
+    __shared__ R Ws[TK][TN + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int64_t r0 = (int64_t)blockIdx.x * TM;
+    const int o0 = blockIdx.y * TN;
+    R acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = R(0);
+    for (int k0 = 0; k0 < in; k0 += TK) {
+        for (int e = threadIdx.x; e < TM * TK; e += 256) {
+            const int rr = e / TK, kk = e % TK;
+            const int64_t r = r0 + rr;
+            const int k = k0 + kk;
+            As[kk][rr] = (r < rows && k < in) ? A[r * lda + k] : R(0);
+        }
+        for (int e = threadIdx.x; e < TN * TK; e += 256) {
+            int oo, kk;
+            if (TRANS) { oo = e / TK; kk = e % TK; }
+            else { kk = e / TN; oo = e % TN; }
+            const int o = o0 + oo, k = k0 + kk;
+            R v = R(0);
+            if (o < out && k < in) v = TRANS ? W[(int64_t)o * in + k] : W[(int64_t)k * out + o];
+            Ws[kk][oo] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+            R a[4], w[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) a[p] = As[kk][ty + 16 * p];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[q] = Ws[kk][tx + 16 * q];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * w[q];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int64_t r = r0 + ty + 16 * p;
+        if (r >= rows) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = o0 + tx + 16 * q;
+            if (o >= out) continue;
+            R v = acc[p][q];
+            if (EPI == EPI_BIAS_SILU) {
+                v += bias[o];
+                Z[r * ldz + o] = v;
+                v = silu(v);
+            } else if (EPI == EPI_BIAS) {
+                v += bias[o];
+            } else if (EPI == EPI_DSILU) {
+                v *= dsilu(Z[r * ldz + o]);
+            }
+            C[r * ldc + o] = v;
+        }
+    }
+}
+
+template <typename R>
+static void dense_t(hipStream_t st, Epi epi, bool trans, int64_t rows, int in, int out, const R *A, int lda, const R *W,
+                    const R *b, R *Z, int ldz, R *C, int ldc) {
+    if (rows <= 0) return;
+    dim3 grid((unsigned)((rows + TM - 1) / TM), (unsigned)((out + TN - 1) / TN));
+#define L_(E, T) hipLaunchKernelGGL((k_dense<R, E, T>), grid, dim3(256), 0, st, rows, in, out, A, lda, W, b, Z, ldz, C, ldc)
+    if (trans) {
+        switch (epi) {
+        case EPI_BIAS_SILU: L_(EPI_BIAS_SILU, true); break;
+        case EPI_BIAS: L_(EPI_BIAS, true); break;
+        case EPI_DSILU: L_(EPI_DSILU, true); break;
+        default: L_(EPI_NONE, true); break;
+        }
+    } else {
+        switch (epi) {
+        case EPI_BIAS_SILU: L_(EPI_BIAS_SILU, false); break;
+        case EPI_BIAS: L_(EPI_BIAS, false); break;
+        case EPI_DSILU: L_(EPI_DSILU, false); break;
+        default: L_(EPI_NONE, false); break;
+        }
+    }
+#undef L_
+    LAUNCH_OK("k_dense");
+}
+
+void dense(hipStream_t st, bool fp64, Epi epi, bool trans_w, int64_t rows, int in, int out, const void *A, int lda,
+           const void *W, const void *b, void *Z, int ldz, void *C, int ldc) {
+    if (fp64)
+        dense_t<double>(st, epi, trans_w, rows, in, out, (const double *)A, lda, (const double *)W, (const double *)b,
+                        (double *)Z, ldz, (double *)C, ldc);
+    else
+        dense_t<float>(st, epi, trans_w, rows, in, out, (const float *)A, lda, (const float *)W, (const float *)b,
+                       (float *)Z, ldz, (float *)C, ldc);
+}
+
+// ------------------------------------------------------------- reductions --
+
+constexpr int kRedBlock = 256;
+
+template <typename R>
+__global__ void k_energy(int64_t n, double scale, const R *__restrict__ y, const int32_t *__restrict__ perm,
+                         double *__restrict__ Eat, double *__restrict__ part) {
+    __shared__ double sm[kRedBlock];
+    const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+    double e = 0.0;
+    if (i < n) {
+        e = scale * (double)y[i];
+        if (Eat) Eat[perm[i]] = e;
+    }
+    sm[threadIdx.x] = e;
+    __syncthreads();
+    for (int h = kRedBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const void *y, const int32_t *perm,
+                    double *Eat_user, double *partials) {
+    const int nb = grid_for(n, kRedBlock);
+    if (fp64) hipLaunchKernelGGL(k_energy<double>, dim3(nb), dim3(kRedBlock), 0, st, n, scale, (const double *)y, perm, Eat_user, partials);
+    else hipLaunchKernelGGL(k_energy<float>, dim3(nb), dim3(kRedBlock), 0, st, n, scale, (const float *)y, perm, Eat_user, partials);
+    LAUNCH_OK("k_energy");
+    return nb;
+}
+
+__global__ void k_sum_rows(const double *__restrict__ part, int nb, int width, double *__restrict__ out, int acc) {
+    // one block; thread q < width sums column q over the rows in a fixed tree order
+    __shared__ double sm[256];
+    for (int q = 0; q < width; ++q) {
+        double s = 0.0;
+        for (int r = threadIdx.x; r < nb; r += blockDim.x) s += part[(int64_t)r * width + q];
+        sm[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[q] = acc ? out[q] + sm[0] : sm[0];
+        __syncthreads();
+    }
+}
+
+void sum_rows(hipStream_t st, const double *partials, int nb, int width, double *out, bool accumulate) {
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, partials, nb, width, out, accumulate ? 1 : 0);
+    LAUNCH_OK("k_sum_rows");
+}
+
+template <typename R>
+__global__ void k_seed(int64_t n, double scale, const double *__restrict__ g, R *__restrict__ ybar) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ybar[i] = R(scale * (g ? *g : 1.0));
+}
+
+void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const double *g, void *ybar) {
+    if (fp64) hipLaunchKernelGGL(k_seed<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, scale, g, (double *)ybar);
+    else hipLaunchKernelGGL(k_seed<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, scale, g, (float *)ybar);
+    LAUNCH_OK("k_seed");
+}
+
+template <typename R>
+__global__ void k_forces_out(int64_t n, const R *__restrict__ F, const int32_t *__restrict__ perm,
+                             const double *__restrict__ g, double *__restrict__ out, const double *__restrict__ W,
+                             double *__restrict__ Wout) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double gs = g ? *g : 1.0;
+    if (t < n * 3) {
+        const int64_t i = t / 3, a = t % 3;
+        out[(int64_t)perm[i] * 3 + a] = gs * (double)F[t];
+    }
+    if (Wout && t < 9) Wout[t] = gs * W[t];
+}
+
+void forces_out(hipStream_t st, bool fp64, int64_t n, const void *F, const int32_t *perm, const double *g,
+                double *forces_user, const double *W, double *virial_out) {
+    const int64_t tot = n * 3 > 9 ? n * 3 : 9;
+    if (fp64) hipLaunchKernelGGL(k_forces_out<double>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, (const double *)F, perm, g, forces_user, W, virial_out);
+    else hipLaunchKernelGGL(k_forces_out<float>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, (const float *)F, perm, g, forces_user, W, virial_out);
+    LAUNCH_OK("k_forces_out");
+}
+
+__global__ void k_zero(uint32_t *__restrict__ p, int64_t nwords) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nwords) p[t] = 0u;
+}
+
+// A fill kernel rather than hipMemsetAsync, so the step can be captured in a HIP graph.
+void zero(hipStream_t st, void *p, size_t bytes) {
+    const int64_t nw = (int64_t)((bytes + 3) / 4);
+    if (nw == 0) return;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(nw, 256)), dim3(256), 0, st, (uint32_t *)p, nw);
+    LAUNCH_OK("k_zero");
+}
+
+}  // namespace reann

@@ -1,0 +1,42 @@
+// Atomic neural networks (Sec. 2.1, Eq. (2) and the energy readout) and the density
+// contraction of Eq. (1) that feeds them, with their vector-Jacobian products.
+#pragma once
+
+#include "common.hpp"
+
+namespace reann {
+
+struct DensityConsts {
+    double w[35];    // multinomial weight l!/(lx! ly! lz!) per Cartesian component
+    int lstart[6];   // first component of each l (lstart[L+1] = NL)
+};
+
+// rho[i][f], f = (l, a, b >= a), from S[i][NL][K]; rows [0, n).
+void density(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S, void *rho);
+// Sbar[i][lambda][a] from rhobar[i][F] and S (overwrites Sbar).
+void density_vjp(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S,
+                 const void *rhobar, void *Sbar);
+
+enum Epi { EPI_BIAS_SILU = 0, EPI_BIAS = 1, EPI_DSILU = 2, EPI_NONE = 3 };
+
+// Dense layer over `rows` rows (row-major, leading dims lda / ldc):
+//   trans_w = true : C = A W^T (+ epilogue), W [out][in]   (forward)
+//   trans_w = false: C = A W   (+ epilogue), W [in][out]   (vector-Jacobian product)
+// EPI_BIAS_SILU: Z = acc + b (stored to Z), C = SiLU(Z);  EPI_BIAS: C = acc + b;
+// EPI_DSILU: C = acc * SiLU'(Z) with Z read;  EPI_NONE: C = acc.
+void dense(hipStream_t st, bool fp64, Epi epi, bool trans_w, int64_t rows, int in, int out, const void *A, int lda,
+           const void *W, const void *b, void *Z, int ldz, void *C, int ldc);
+
+// Eat[perm[i]] = scale * y[i] (FP64), and per-block partial sums of Eat in local order.
+int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const void *y, const int32_t *perm,
+                    double *Eat_user, double *partials);
+// out[0] = sum of partials[0..nb) (single block, fixed order); if accumulate, out[q] += ...
+void sum_rows(hipStream_t st, const double *partials, int nb, int width, double *out, bool accumulate);
+// ybar[i] = scale * g  (g = device scalar or NULL = 1)
+void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const double *g, void *ybar);
+// forces_user[perm[i]][a] = gscale * F[i][a]; virial_out[q] = gscale * W[q]
+void forces_out(hipStream_t st, bool fp64, int64_t n, const void *F, const int32_t *perm, const double *g,
+                double *forces_user, const double *W, double *virial_out);
+void zero(hipStream_t st, void *p, size_t bytes);
+
+}  // namespace reann

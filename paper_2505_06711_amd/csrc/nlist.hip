@@ -1,0 +1,642 @@
+// GPU neighbour-list build for the subdomain-extended system.
+//
+// Every FP64 position operation here is written without contraction so that the pair
+// predicate is exactly  d = y_j - w_i,  fma(dz,dz, fma(dy,dy, dx*dx)) < (r_c+skin)^2,
+// with w the wrapped position and y = w + shift*L the copy position.
+#include "nlist.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+#pragma clang fp contract(off)
+
+namespace reann {
+
+// ------------------------------------------------------------------ geometry --
+
+void geom_init(Geom &g, const double cell[9], const int32_t pbc[3], const int32_t P[3], double r_c, double skin) {
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (a != b && cell[3 * a + b] != 0.0) fail(REANN_E_UNSUPPORTED, "only orthorhombic cells are supported");
+    g.ndom = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.L[a] = cell[4 * a];
+        g.per[a] = pbc[a] ? 1 : 0;
+        g.P[a] = P ? (P[a] > 0 ? P[a] : 1) : 1;
+        if (g.P[a] > kMaxSplit) fail(REANN_E_UNSUPPORTED, "at most 16 subdomains per axis");
+        if (!g.per[a] && g.P[a] != 1) fail(REANN_E_INVALID, "a non-periodic axis cannot be split");
+        if (g.per[a] && !(g.L[a] > 0.0 && std::isfinite(g.L[a]))) fail(REANN_E_INVALID, "periodic cell length must be > 0");
+        g.ndom *= g.P[a];
+        if (g.per[a]) {
+            double h = g.L[a] / g.P[a];
+            for (int k = 0; k < g.P[a]; ++k) {
+                g.lo[a][k] = k * h;
+                g.hi[a][k] = (k == g.P[a] - 1) ? g.L[a] : (k + 1) * h;
+            }
+        } else {
+            g.lo[a][0] = -INFINITY;
+            g.hi[a][0] = INFINITY;
+        }
+    }
+    g.rcut = r_c + skin;
+    g.rc2 = g.rcut * g.rcut;
+    g.shell = g.rcut + 1e-6;
+    for (int a = 0; a < 3; ++a) g.nm[a] = g.per[a] ? (int)std::floor(g.shell / g.L[a]) + 1 : 0;
+}
+
+__device__ inline double wrap_coord(double x, double L, int &qe) {
+    double q = floor(x / L);
+    double t = q * L;
+    double w = x - t;
+    int k = (int)q;
+    if (w < 0.0) { w = w + L; k -= 1; }
+    if (w >= L) { w = w - L; k += 1; }
+    qe = k;
+    return w;
+}
+
+// Domains along axis a whose shell contains coordinate y: bitmask (P <= 16).
+__device__ inline unsigned axis_domains(const Geom &g, int a, double y) {
+    if (!g.per[a]) return 1u;
+    unsigned m = 0;
+    for (int k = 0; k < g.P[a]; ++k)
+        if (y >= g.lo[a][k] - g.shell && y < g.hi[a][k] + g.shell) m |= 1u << k;
+    return m;
+}
+
+__global__ void k_wrap_count(Geom g, int64_t n, const double *__restrict__ pos, double *__restrict__ w,
+                             int32_t *__restrict__ q, int32_t *__restrict__ dom, int64_t *__restrict__ gcount,
+                             int32_t *__restrict__ bad) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int c[3];
+    double wu[3];
+    bool finite = true;
+    for (int a = 0; a < 3; ++a) finite = finite && isfinite(pos[3 * u + a]) && fabs(pos[3 * u + a]) < 1e9;
+    if (!finite) {
+        // flagged for the host; the atom gets no copies so every offset stays in range
+        atomicOr(bad, 1);
+        for (int a = 0; a < 3; ++a) { w[3 * u + a] = 0.0; q[3 * u + a] = 0; }
+        dom[u] = 0;
+        gcount[u] = 0;
+        return;
+    }
+    for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * u + a];
+        int qe = 0;
+        double ww = g.per[a] ? wrap_coord(x, g.L[a], qe) : x;
+        wu[a] = ww;
+        w[3 * u + a] = ww;
+        q[3 * u + a] = qe;
+        c[a] = 0;
+        for (int k = 0; k < g.P[a]; ++k)
+            if (ww >= g.lo[a][k] && ww < g.hi[a][k]) c[a] = k;
+    }
+    dom[u] = (c[0] * g.P[1] + c[1]) * g.P[2] + c[2];
+    int64_t cnt = 0;
+    for (int s0 = -g.nm[0]; s0 <= g.nm[0]; ++s0)
+        for (int s1 = -g.nm[1]; s1 <= g.nm[1]; ++s1)
+            for (int s2 = -g.nm[2]; s2 <= g.nm[2]; ++s2) {
+                int s[3] = {s0, s1, s2};
+                unsigned m[3];
+                for (int a = 0; a < 3; ++a) {
+                    double y = g.per[a] ? wu[a] + (double)s[a] * g.L[a] : wu[a];
+                    m[a] = axis_domains(g, a, y);
+                }
+                int k = __popc(m[0]) * __popc(m[1]) * __popc(m[2]);
+                if (s0 == 0 && s1 == 0 && s2 == 0) k -= 1;   // the atom itself in its own subdomain
+                cnt += k;
+            }
+    gcount[u] = cnt;
+}
+
+__global__ void k_ghost_gen(Geom g, int64_t n, const double *__restrict__ w, const int32_t *__restrict__ dom,
+                            const int64_t *__restrict__ goff, int32_t *__restrict__ g_owner, int32_t *__restrict__ g_shift,
+                            int32_t *__restrict__ g_dom, double *__restrict__ g_pos) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int64_t o = goff[u];
+    if (goff[u + 1] == o) return;   // no copies (also the case of a flagged atom)
+    double wu[3] = {w[3 * u], w[3 * u + 1], w[3 * u + 2]};
+    int own = dom[u];
+    for (int s0 = -g.nm[0]; s0 <= g.nm[0]; ++s0)
+        for (int s1 = -g.nm[1]; s1 <= g.nm[1]; ++s1)
+            for (int s2 = -g.nm[2]; s2 <= g.nm[2]; ++s2) {
+                int s[3] = {s0, s1, s2};
+                unsigned m[3];
+                double y[3];
+                for (int a = 0; a < 3; ++a) {
+                    y[a] = g.per[a] ? wu[a] + (double)s[a] * g.L[a] : wu[a];
+                    m[a] = axis_domains(g, a, y[a]);
+                }
+                for (int k0 = 0; k0 < g.P[0]; ++k0) {
+                    if (!(m[0] >> k0 & 1u)) continue;
+                    for (int k1 = 0; k1 < g.P[1]; ++k1) {
+                        if (!(m[1] >> k1 & 1u)) continue;
+                        for (int k2 = 0; k2 < g.P[2]; ++k2) {
+                            if (!(m[2] >> k2 & 1u)) continue;
+                            int p = (k0 * g.P[1] + k1) * g.P[2] + k2;
+                            if (s0 == 0 && s1 == 0 && s2 == 0 && p == own) continue;
+                            g_owner[o] = (int32_t)u;
+                            g_shift[3 * o] = s0; g_shift[3 * o + 1] = s1; g_shift[3 * o + 2] = s2;
+                            g_dom[o] = p;
+                            g_pos[3 * o] = y[0]; g_pos[3 * o + 1] = y[1]; g_pos[3 * o + 2] = y[2];
+                            ++o;
+                        }
+                    }
+                }
+            }
+}
+
+struct Bins {
+    double mn[3], bs[3];
+    int nb[3];
+    int64_t nbin;
+};
+
+__device__ inline int bin_of(const Bins &b, const double *y) {
+    int c[3];
+    for (int a = 0; a < 3; ++a) {
+        int k = (int)((y[a] - b.mn[a]) / b.bs[a]);
+        c[a] = k < 0 ? 0 : (k >= b.nb[a] ? b.nb[a] - 1 : k);
+    }
+    return (c[0] * b.nb[1] + c[1]) * b.nb[2] + c[2];
+}
+
+// Key of a pre-ext element: locals (slot = species) then ghosts (slot = n_species).
+__global__ void k_keys(Bins b, int ndom, int n_species, int64_t n, int64_t n_gh, const double *__restrict__ w,
+                       const int32_t *__restrict__ dom, const int32_t *__restrict__ species, const double *__restrict__ g_pos,
+                       const int32_t *__restrict__ g_dom, int64_t *__restrict__ key, int32_t *__restrict__ count) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n + n_gh) return;
+    int slot, p;
+    int bn;
+    if (e < n) {
+        slot = species[e]; p = dom[e]; bn = bin_of(b, w + 3 * e);
+    } else {
+        int64_t gi = e - n;
+        slot = n_species; p = g_dom[gi]; bn = bin_of(b, g_pos + 3 * gi);
+    }
+    int64_t k = ((int64_t)slot * ndom + p) * b.nbin + bn;
+    key[e] = k;
+    atomicAdd(&count[k], 1);
+}
+
+__global__ void k_i32_to_i64(const int32_t *__restrict__ a, int64_t *__restrict__ b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+__global__ void k_scatter(int64_t m, const int64_t *__restrict__ key, const int64_t *__restrict__ kstart,
+                          int32_t *__restrict__ cursor, int32_t *__restrict__ order) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    int64_t k = key[e];
+    int64_t pos = kstart[k] + atomicAdd(&cursor[k], 1);
+    order[pos] = (int32_t)e;
+}
+
+// Sort each segment [start[k], start[k+1]) ascending (insertion sort; segments are small).
+__global__ void k_sort_segments(int64_t nseg, const int64_t *__restrict__ start, int32_t *__restrict__ v) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nseg) return;
+    int64_t a = start[k], e = start[k + 1];
+    for (int64_t i = a + 1; i < e; ++i) {
+        int32_t x = v[i];
+        int64_t j = i - 1;
+        while (j >= a && v[j] > x) { v[j + 1] = v[j]; --j; }
+        v[j + 1] = x;
+    }
+}
+
+__global__ void k_sort_segments32(int64_t nseg, const int32_t *__restrict__ start, int32_t *__restrict__ v) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nseg) return;
+    int32_t a = start[k], e = start[k + 1];
+    for (int32_t i = a + 1; i < e; ++i) {
+        int32_t x = v[i];
+        int32_t j = i - 1;
+        while (j >= a && v[j] > x) { v[j + 1] = v[j]; --j; }
+        v[j + 1] = x;
+    }
+}
+
+__global__ void k_build_ext(Bins b, int64_t n, int64_t n_ext, const int32_t *__restrict__ order,
+                            const double *__restrict__ w, const int32_t *__restrict__ dom, const int32_t *__restrict__ species,
+                            const double *__restrict__ g_pos, const int32_t *__restrict__ g_dom,
+                            const int32_t *__restrict__ g_owner_user, const int32_t *__restrict__ g_shift_in,
+                            int32_t *__restrict__ perm, int32_t *__restrict__ inv_perm, double *__restrict__ pext,
+                            int32_t *__restrict__ dom_ext, int32_t *__restrict__ bin_ext, int8_t *__restrict__ spec_ext,
+                            int32_t *__restrict__ gh_owner_user, int32_t *__restrict__ gh_shift) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n_ext) return;
+    int64_t pre = order[x];
+    const double *y;
+    if (pre < n) {
+        perm[x] = (int32_t)pre;
+        inv_perm[pre] = (int32_t)x;
+        y = w + 3 * pre;
+        dom_ext[x] = dom[pre];
+        spec_ext[x] = (int8_t)species[pre];
+    } else {
+        int64_t gi = pre - n, go = x - n;
+        y = g_pos + 3 * gi;
+        dom_ext[x] = g_dom[gi];
+        int32_t ou = g_owner_user[gi];
+        gh_owner_user[go] = ou;
+        spec_ext[x] = (int8_t)species[ou];
+        for (int a = 0; a < 3; ++a) gh_shift[3 * go + a] = g_shift_in[3 * gi + a];
+    }
+    pext[x] = y[0];
+    pext[n_ext + x] = y[1];
+    pext[2 * n_ext + x] = y[2];
+    bin_ext[x] = bin_of(b, y);
+}
+
+__global__ void k_ghost_owner(int64_t n_gh, const int32_t *__restrict__ owner_user, const int32_t *__restrict__ inv_perm,
+                              int32_t *__restrict__ owner) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n_gh) owner[g] = inv_perm[owner_user[g]];
+}
+
+// Candidate scan over the 27 bins around atom x of its subdomain.  Locals see every
+// ext atom of the subdomain; ghosts see only locals.
+template <bool FILL>
+__global__ void k_rows(Bins b, Geom g, int n_species, int64_t n, int64_t n_ext, const double *__restrict__ pext,
+                       const int32_t *__restrict__ dom_ext, const int32_t *__restrict__ bin_ext,
+                       const int64_t *__restrict__ kstart, int64_t *__restrict__ rowcnt, const int64_t *__restrict__ row,
+                       int32_t *__restrict__ col) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n_ext) return;
+    const double xi = pext[x], yi = pext[n_ext + x], zi = pext[2 * n_ext + x];
+    const int p = dom_ext[x];
+    const int bx = bin_ext[x];
+    const int c2 = bx % b.nb[2], c1 = (bx / b.nb[2]) % b.nb[1], c0 = bx / (b.nb[2] * b.nb[1]);
+    const int nslot = (x < n) ? n_species + 1 : n_species;
+    int64_t cnt = 0, o = FILL ? row[x] : 0;
+    for (int d0 = -1; d0 <= 1; ++d0) {
+        int a0 = c0 + d0;
+        if (a0 < 0 || a0 >= b.nb[0]) continue;
+        for (int d1 = -1; d1 <= 1; ++d1) {
+            int a1 = c1 + d1;
+            if (a1 < 0 || a1 >= b.nb[1]) continue;
+            for (int d2 = -1; d2 <= 1; ++d2) {
+                int a2 = c2 + d2;
+                if (a2 < 0 || a2 >= b.nb[2]) continue;
+                int64_t bn = ((int64_t)a0 * b.nb[1] + a1) * b.nb[2] + a2;
+                for (int slot = 0; slot < nslot; ++slot) {
+                    int64_t k = ((int64_t)slot * g.ndom + p) * b.nbin + bn;
+                    for (int64_t e = kstart[k]; e < kstart[k + 1]; ++e) {
+                        if (e == x) continue;
+                        double dx = pext[e] - xi, dy = pext[n_ext + e] - yi, dz = pext[2 * n_ext + e] - zi;
+                        double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                        if (d2 < g.rc2) {
+                            if (FILL) col[o++] = (int32_t)e;
+                            else ++cnt;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (!FILL) rowcnt[x] = cnt;
+}
+
+__global__ void k_copy_count(int64_t n_gh, const int32_t *__restrict__ owner, int32_t *__restrict__ cnt) {
+    int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi < n_gh) atomicAdd(&cnt[owner[gi]], 1);
+}
+
+__global__ void k_copy_fill(int64_t n_gh, const int32_t *__restrict__ owner, const int64_t *__restrict__ start,
+                            int32_t *__restrict__ cursor, int32_t *__restrict__ idx) {
+    int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= n_gh) return;
+    int32_t o = owner[gi];
+    idx[start[o] + atomicAdd(&cursor[o], 1)] = (int32_t)gi;
+}
+
+__global__ void k_i64_to_i32(const int64_t *__restrict__ a, int32_t *__restrict__ b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (int32_t)a[i];
+}
+
+__global__ void k_minmax(int64_t n, const double *__restrict__ w, double *__restrict__ out) {
+    // single block: deterministic min/max of the three coordinates
+    __shared__ double smin[3][256], smax[3][256];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+        for (int a = 0; a < 3; ++a) {
+            double v = w[3 * i + a];
+            mn[a] = fmin(mn[a], v);
+            mx[a] = fmax(mx[a], v);
+        }
+    for (int a = 0; a < 3; ++a) { smin[a][threadIdx.x] = mn[a]; smax[a][threadIdx.x] = mx[a]; }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < 3; ++a) {
+                smin[a][threadIdx.x] = fmin(smin[a][threadIdx.x], smin[a][threadIdx.x + s]);
+                smax[a][threadIdx.x] = fmax(smax[a][threadIdx.x], smax[a][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) { out[a] = smin[a][0]; out[3 + a] = smax[a][0]; }
+}
+
+__global__ void k_xref(int64_t n, const double *__restrict__ pos, const int32_t *__restrict__ perm,
+                       double *__restrict__ xref) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t u = perm[i];
+    for (int a = 0; a < 3; ++a) xref[3 * i + a] = pos[3 * u + a];
+}
+
+// ---------------------------------------------------------------------- scan --
+
+__global__ void k_scan_block(int64_t *__restrict__ d, int64_t n, int64_t *__restrict__ sums) {
+    __shared__ int64_t s[1024];
+    int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    int64_t v = i < n ? d[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t t = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) d[i] = s[threadIdx.x] - v;   // exclusive
+    if (threadIdx.x == 1023) sums[blockIdx.x] = s[1023];
+}
+
+__global__ void k_scan_add(int64_t *__restrict__ d, int64_t n, const int64_t *__restrict__ sums) {
+    int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (i < n) d[i] += sums[blockIdx.x];
+}
+
+static void scan_rec(hipStream_t st, int64_t *d, int64_t n, int64_t *tmp) {
+    int64_t nb = (n + 1023) / 1024;
+    int64_t *sums = tmp;
+    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(1024), 0, st, d, n, sums);
+    LAUNCH_OK("k_scan_block");
+    if (nb > 1) {
+        scan_rec(st, sums, nb, tmp + nb + 1);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(1024), 0, st, d, n, sums);
+        LAUNCH_OK("k_scan_add");
+    }
+}
+
+// d holds n counts in [0, n); on return d[0..n] are exclusive offsets, d[n] = total.
+int64_t scan_exclusive_i64(hipStream_t st, int64_t *d, int64_t n, DevBuf &tmp) {
+    // last element + its count = total: scan n+1 values where d[n] was set to 0 by the caller
+    int64_t m = n + 1;
+    int64_t need = 0, k = m;
+    while (k > 1) { k = (k + 1023) / 1024; need += k + 1; }
+    int64_t *t = static_cast<int64_t *>(tmp.ensure((size_t)(need + 16) * sizeof(int64_t)));
+    scan_rec(st, d, m, t);
+    int64_t total = 0;
+    HIP_OK(hipMemcpyAsync(&total, d + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return total;
+}
+
+// --------------------------------------------------------------------- build --
+
+void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, int64_t n, int n_species,
+                 const Geom &g, double r_c, double skin, NList &nl, NListScratch &s) {
+    if (n <= 0) fail(REANN_E_INVALID, "n must be > 0");
+    if (n >= (int64_t)1 << 30) fail(REANN_E_UNSUPPORTED, "too many atoms");
+    const int B = 256;
+    nl.g = g;
+    nl.n = n;
+    nl.n_species = n_species;
+    nl.skin = skin;
+    nl.r_c = r_c;
+    double *w = static_cast<double *>(s.a.ensure(n * 3 * sizeof(double)));
+    int32_t *q = nl.q.resize(n * 3);
+    int32_t *dom = static_cast<int32_t *>(s.b.ensure(n * sizeof(int32_t)));
+    int64_t *goff = static_cast<int64_t *>(s.c.ensure((n + 1) * sizeof(int64_t)));
+    int32_t *bad = static_cast<int32_t *>(s.i.ensure(64));
+    HIP_OK(hipMemsetAsync(goff + n, 0, sizeof(int64_t), st));
+    HIP_OK(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_wrap_count, dim3(grid_for(n, B)), dim3(B), 0, st, g, n, d_pos, w, q, dom, goff, bad);
+    LAUNCH_OK("k_wrap_count");
+    int32_t hbad = 0;
+    HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int64_t n_gh = scan_exclusive_i64(st, goff, n, s.m);   // synchronises
+    if (hbad) fail(REANN_E_INVALID, "positions contain NaN, Inf or |x| >= 1e9");
+    if (n + n_gh >= ((int64_t)1 << 31) - 1) fail(REANN_E_UNSUPPORTED, "extended system too large");
+    nl.n_gh = n_gh;
+    nl.n_ext = n + n_gh;
+    const int64_t n_ext = nl.n_ext;
+    int32_t *g_owner = static_cast<int32_t *>(s.d.ensure((n_gh + 1) * sizeof(int32_t)));
+    int32_t *g_shift = static_cast<int32_t *>(s.e.ensure((n_gh + 1) * 3 * sizeof(int32_t)));
+    int32_t *g_dom = static_cast<int32_t *>(s.f.ensure((n_gh + 1) * sizeof(int32_t)));
+    double *g_pos = static_cast<double *>(s.g.ensure((n_gh + 1) * 3 * sizeof(double)));
+    hipLaunchKernelGGL(k_ghost_gen, dim3(grid_for(n, B)), dim3(B), 0, st, g, n, w, dom, goff, g_owner, g_shift, g_dom,
+                       g_pos);
+    LAUNCH_OK("k_ghost_gen");
+
+    // spatial bins of size >= r_c + skin over the region holding every copy
+    Bins b{};
+    double bb[6];
+    {
+        double *d_mm = static_cast<double *>(s.h.ensure(6 * sizeof(double)));
+        hipLaunchKernelGGL(k_minmax, dim3(1), dim3(256), 0, st, n, w, d_mm);
+        LAUNCH_OK("k_minmax");
+        HIP_OK(hipMemcpyAsync(bb, d_mm, sizeof bb, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
+    b.nbin = 1;
+    for (int a = 0; a < 3; ++a) {
+        double lo = g.per[a] ? -g.shell : bb[a];
+        double hi = g.per[a] ? g.L[a] + g.shell : bb[3 + a];
+        double ext = hi - lo;
+        if (!(ext >= 0.0 && ext < 1e8)) fail(REANN_E_INVALID, "system extent out of range");
+        int nb = (int)std::floor(ext / (g.rcut * 1.000000001));
+        nb = std::max(1, std::min(nb, 1024));
+        b.nb[a] = nb;
+        b.mn[a] = lo;
+        b.bs[a] = nb > 1 ? ext / nb : 1.0;
+        b.nbin *= nb;
+    }
+    const int64_t nkeys = (int64_t)(n_species + 1) * g.ndom * b.nbin;
+    if (nkeys > ((int64_t)1 << 28)) fail(REANN_E_UNSUPPORTED, "bin table too large");
+
+    int64_t *key = static_cast<int64_t *>(s.h.ensure(n_ext * sizeof(int64_t)));
+    int32_t *cnt32 = static_cast<int32_t *>(s.i.ensure((nkeys + 1) * sizeof(int32_t)));
+    int64_t *kstart = static_cast<int64_t *>(s.j.ensure((nkeys + 1) * sizeof(int64_t)));
+    HIP_OK(hipMemsetAsync(cnt32, 0, (nkeys + 1) * sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n_ext, B)), dim3(B), 0, st, b, g.ndom, n_species, n, n_gh, w, dom,
+                       d_species, g_pos, g_dom, key, cnt32);
+    LAUNCH_OK("k_keys");
+    hipLaunchKernelGGL(k_i32_to_i64, dim3(grid_for(nkeys + 1, B)), dim3(B), 0, st, cnt32, kstart, nkeys + 1);
+    LAUNCH_OK("k_i32_to_i64");
+    int64_t tot = scan_exclusive_i64(st, kstart, nkeys, s.m);
+    if (tot != n_ext) fail(REANN_E_DEVICE, "neighbour build: key count mismatch");
+    int32_t *order = static_cast<int32_t *>(s.k.ensure(n_ext * sizeof(int32_t)));
+    HIP_OK(hipMemsetAsync(cnt32, 0, (nkeys + 1) * sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_ext, B)), dim3(B), 0, st, n_ext, key, kstart, cnt32, order);
+    LAUNCH_OK("k_scatter");
+    hipLaunchKernelGGL(k_sort_segments, dim3(grid_for(nkeys, B)), dim3(B), 0, st, nkeys, kstart, order);
+    LAUNCH_OK("k_sort_segments");
+
+    // species segments of the locals
+    {
+        nl.seg.assign(n_species + 1, 0);
+        for (int sp = 0; sp <= n_species; ++sp) {
+            int64_t v = 0;
+            HIP_OK(hipMemcpyAsync(&v, kstart + (int64_t)sp * g.ndom * b.nbin, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            nl.seg[sp] = v;
+        }
+        if (nl.seg[n_species] != n) fail(REANN_E_DEVICE, "neighbour build: species segments mismatch");
+    }
+
+    int32_t *perm = nl.perm.resize(n);
+    int32_t *inv_perm = nl.inv_perm.resize(n);
+    double *pext = static_cast<double *>(s.l.ensure(3 * n_ext * sizeof(double)));
+    DevBuf dext, bext, gou;
+    int32_t *d_dom_ext = static_cast<int32_t *>(dext.ensure(n_ext * sizeof(int32_t)));
+    int32_t *d_bin_ext = static_cast<int32_t *>(bext.ensure(n_ext * sizeof(int32_t)));
+    int32_t *gh_owner_user = static_cast<int32_t *>(gou.ensure((n_gh + 1) * sizeof(int32_t)));
+    int8_t *spec_ext = nl.spec_ext.resize(n_ext);
+    int32_t *gh_shift = nl.gh_shift.resize((n_gh + 1) * 3);
+    hipLaunchKernelGGL(k_build_ext, dim3(grid_for(n_ext, B)), dim3(B), 0, st, b, n, n_ext, order, w, dom, d_species,
+                       g_pos, g_dom, g_owner, g_shift, perm, inv_perm, pext, d_dom_ext, d_bin_ext, spec_ext,
+                       gh_owner_user, gh_shift);
+    LAUNCH_OK("k_build_ext");
+    int32_t *gh_owner = nl.gh_owner.resize(n_gh + 1);
+    if (n_gh > 0) {
+        hipLaunchKernelGGL(k_ghost_owner, dim3(grid_for(n_gh, B)), dim3(B), 0, st, n_gh, gh_owner_user, inv_perm,
+                           gh_owner);
+        LAUNCH_OK("k_ghost_owner");
+    }
+
+    // rows: count, scan, fill
+    int64_t *row = nl.row.resize(n_ext + 1);
+    HIP_OK(hipMemsetAsync(row + n_ext, 0, sizeof(int64_t), st));
+    hipLaunchKernelGGL(k_rows<false>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, n, n_ext, pext,
+                       d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr);
+    LAUNCH_OK("k_rows<count>");
+    int64_t n_pairs = scan_exclusive_i64(st, row, n_ext, s.m);
+    if (n_pairs >= ((int64_t)1 << 31) - 1) fail(REANN_E_UNSUPPORTED, "too many neighbour pairs");
+    nl.n_pairs = n_pairs;
+    HIP_OK(hipMemcpyAsync(&nl.n_local_pairs, row + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    int32_t *col = nl.col.resize(n_pairs + 1);
+    hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, n, n_ext, pext,
+                       d_dom_ext, d_bin_ext, kstart, nullptr, row, col);
+    LAUNCH_OK("k_rows<fill>");
+
+    // owner -> ghost copies
+    int32_t *copy_ptr = nl.copy_ptr.resize(n + 1);
+    int32_t *copy_idx = nl.copy_idx.resize(n_gh + 1);
+    {
+        int32_t *c32 = static_cast<int32_t *>(s.i.ensure((n + 1) * sizeof(int32_t)));
+        int64_t *c64 = static_cast<int64_t *>(s.j.ensure((n + 1) * sizeof(int64_t)));
+        HIP_OK(hipMemsetAsync(c32, 0, (n + 1) * sizeof(int32_t), st));
+        if (n_gh > 0) {
+            hipLaunchKernelGGL(k_copy_count, dim3(grid_for(n_gh, B)), dim3(B), 0, st, n_gh, gh_owner, c32);
+            LAUNCH_OK("k_copy_count");
+        }
+        hipLaunchKernelGGL(k_i32_to_i64, dim3(grid_for(n + 1, B)), dim3(B), 0, st, c32, c64, n + 1);
+        LAUNCH_OK("k_i32_to_i64");
+        scan_exclusive_i64(st, c64, n, s.m);
+        hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for(n + 1, B)), dim3(B), 0, st, c64, copy_ptr, n + 1);
+        LAUNCH_OK("k_i64_to_i32");
+        if (n_gh > 0) {
+            HIP_OK(hipMemsetAsync(c32, 0, (n + 1) * sizeof(int32_t), st));
+            hipLaunchKernelGGL(k_copy_fill, dim3(grid_for(n_gh, B)), dim3(B), 0, st, n_gh, gh_owner, c64, c32, copy_idx);
+            LAUNCH_OK("k_copy_fill");
+            hipLaunchKernelGGL(k_sort_segments32, dim3(grid_for(n, B)), dim3(B), 0, st, n, copy_ptr, copy_idx);
+            LAUNCH_OK("k_sort_segments32");
+        }
+    }
+    double *xref = nl.xref.resize(n * 3);
+    hipLaunchKernelGGL(k_xref, dim3(grid_for(n, B)), dim3(B), 0, st, n, d_pos, perm, xref);
+    LAUNCH_OK("k_xref");
+    HIP_OK(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------ per-step work --
+
+__global__ void k_refresh(Geom g, int64_t n, int64_t n_ext, const double *__restrict__ pos, const int32_t *__restrict__ perm,
+                          const int32_t *__restrict__ q, const int32_t *__restrict__ gh_owner,
+                          const int32_t *__restrict__ gh_shift, double *__restrict__ px, double *__restrict__ py,
+                          double *__restrict__ pz) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n_ext) return;
+    int64_t i = x < n ? x : gh_owner[x - n];
+    int64_t u = perm[i];
+    double w[3];
+    for (int a = 0; a < 3; ++a) {
+        double v = pos[3 * u + a];
+        if (g.per[a]) {
+            double t = (double)q[3 * u + a] * g.L[a];   // q is stored per caller index
+            v = v - t;
+        }
+        w[a] = v;
+    }
+    if (x >= n) {
+        int64_t gi = x - n;
+        for (int a = 0; a < 3; ++a)
+            if (g.per[a]) w[a] = w[a] + (double)gh_shift[3 * gi + a] * g.L[a];
+    }
+    px[x] = w[0];
+    py[x] = w[1];
+    pz[x] = w[2];
+}
+
+void refresh_positions(hipStream_t st, const NList &nl, const double *d_pos, double *px, double *py, double *pz) {
+    hipLaunchKernelGGL(k_refresh, dim3(grid_for(nl.n_ext, 256)), dim3(256), 0, st, nl.g, nl.n, nl.n_ext, d_pos,
+                       nl.perm.ptr(), nl.q.ptr(), nl.gh_owner.ptr(), nl.gh_shift.ptr(), px, py, pz);
+    LAUNCH_OK("k_refresh");
+}
+
+__device__ inline double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// Per-block maxima of |x_i - xref_i|^2 (NaN counts as too far), then one block combines them.
+__global__ void k_maxdisp_part(int64_t n, const double *__restrict__ pos, const int32_t *__restrict__ perm,
+                               const double *__restrict__ xref, double *__restrict__ part) {
+    __shared__ double sm[256];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = perm[i];
+        const double dx = pos[3 * u] - xref[3 * i], dy = pos[3 * u + 1] - xref[3 * i + 1],
+                     dz = pos[3 * u + 2] - xref[3 * i + 2];
+        m = nan_max(m, dx * dx + dy * dy + dz * dz);
+    }
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = nan_max(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_maxdisp_final(int nb, const double *__restrict__ part, double *__restrict__ out) {
+    __shared__ double sm[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) m = nan_max(m, part[i]);
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = nan_max(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sm[0];
+}
+
+// d_out must hold 1 + 1024 doubles (result, then per-block partials).
+void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_out) {
+    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nl.n + 255) / 256));
+    hipLaunchKernelGGL(k_maxdisp_part, dim3(nb), dim3(256), 0, st, nl.n, d_pos, nl.perm.ptr(), nl.xref.ptr(),
+                       d_out + 1);
+    LAUNCH_OK("k_maxdisp_part");
+    hipLaunchKernelGGL(k_maxdisp_final, dim3(1), dim3(256), 0, st, nb, d_out + 1, d_out);
+    LAUNCH_OK("k_maxdisp_final");
+}
+
+}  // namespace reann

@@ -1,0 +1,375 @@
+// Evaluation of one system: neighbour list (rebuilt by the skin rule), T message-passing
+// layers forward, then the hand-written reverse sweep for forces and virial.
+//
+// Forward (Sec. 2.1, Eqs. (1)-(2)): for t = 0..T-1 the edge pass gives S^t of the locals;
+// for t < T-1 the message NN of each element gives c^{t+1} of the locals and the ghost
+// copies receive their owners' values (the per-layer exchange of Sec. 2.2); the energy NN
+// of S^{T-1}'s densities gives E_i, summed in FP64.
+// Backward (Sec. 2.2, Eqs. (3)-(5)): Sbar^{T-1} from the energy NN's VJP; for t = T-1..0
+// the edge adjoint adds forces and virial and, for t >= 1, the message adjoints cbar^t of
+// every ext atom, which are summed onto their owners (the reverse exchange) and pulled
+// through the message NN of layer t-1 to give Sbar^{t-1}.  dc^0/dr = 0 ends the sweep.
+#include <cmath>
+#include <cstring>
+
+#include "runtime.hpp"
+
+namespace reann {
+
+NNLayout nn_layout(int F, int H, int nh, int out) {
+    NNLayout l;
+    int prev = F;
+    int64_t o = 0;
+    for (int k = 0; k <= nh; ++k) {
+        const int d = (k == nh) ? out : H;
+        l.w_off.push_back(o); o += (int64_t)d * prev;
+        l.b_off.push_back(o); o += d;
+        l.din.push_back(prev);
+        l.dout.push_back(d);
+        prev = d;
+    }
+    l.size = o;
+    return l;
+}
+
+static void upload(DevBuf &b, const std::vector<double> &v, bool to_float, hipStream_t st) {
+    const size_t n = v.size() ? v.size() : 1;
+    if (to_float) {
+        std::vector<float> f(n, 0.f);
+        for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+        b.ensure(n * 4);
+        HIP_OK(hipMemcpyAsync(b.p, f.data(), n * 4, hipMemcpyHostToDevice, st));
+        HIP_OK(hipStreamSynchronize(st));
+    } else {
+        b.ensure(n * 8);
+        if (v.size()) HIP_OK(hipMemcpyAsync(b.p, v.data(), v.size() * 8, hipMemcpyHostToDevice, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
+}
+
+DeviceWeights &Model::weights(int device, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = dev.find(device);
+    if (it != dev.end()) return *it->second;
+    auto w = std::make_unique<DeviceWeights>();
+    upload(w->msg64, msg, false, st);
+    upload(w->en64, en, false, st);
+    upload(w->c064, c0, false, st);
+    upload(w->msg32, msg, true, st);
+    upload(w->en32, en, true, st);
+    upload(w->c032, c0, true, st);
+    auto &ref = *w;
+    dev[device] = std::move(w);
+    return ref;
+}
+
+EdgeConsts Model::edge_consts() const {
+    EdgeConsts e{};
+    for (int m = 0; m < K; ++m) { e.centres[m] = centres[m]; e.alphas[m] = alphas[m]; }
+    e.r_c = r_c;
+    e.rc2 = r_c * r_c;
+    e.ang_scale = ang_scale;
+    return e;
+}
+
+DensityConsts Model::density_consts() const {
+    DensityConsts d{};
+    auto fact = [](int v) { double f = 1; for (int k = 2; k <= v; ++k) f *= k; return f; };
+    int k = 0;
+    for (int l = 0; l <= L; ++l) {
+        d.lstart[l] = k;
+        for (int lx = l; lx >= 0; --lx)
+            for (int ly = l - lx; ly >= 0; --ly) {
+                const int lz = l - lx - ly;
+                d.w[k++] = fact(l) / (fact(lx) * fact(ly) * fact(lz));
+            }
+    }
+    d.lstart[L + 1] = k;
+    return d;
+}
+
+// -------------------------------------------------------------------- plan --
+
+Plan::~Plan() {
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const double cell_[9], const int32_t pbc_[3],
+                int TT, const reann_opts *opt) {
+    ctx = c_;
+    m = mm;
+    if (nn <= 0) fail(REANN_E_INVALID, "n must be > 0");
+    if (TT < 1 || TT > m->T_max) fail(REANN_E_INVALID, "T must be in [1, T_max]");
+    T = TT;
+    prec = opt ? opt->precision : REANN_FP32;
+    if (prec != REANN_FP64 && prec != REANN_FP32)
+        fail(REANN_E_UNSUPPORTED, "precision not available in this build");
+    fp64 = prec == REANN_FP64;
+    rs = fp64 ? 8 : 4;
+    skin = opt ? opt->skin : 0.0;
+    if (!(skin >= 0.0) || !std::isfinite(skin)) fail(REANN_E_INVALID, "skin must be >= 0");
+    for (int a = 0; a < 3; ++a) P[a] = (opt && opt->decomp[a] > 0) ? opt->decomp[a] : 1;
+    std::memcpy(cell, cell_, sizeof cell);
+    std::memcpy(pbc, pbc_, sizeof pbc);
+    geom_init(g, cell, pbc, P, m->r_c, skin);
+    n = nn;
+    species.assign(spec, spec + nn);
+    for (int64_t i = 0; i < n; ++i)
+        if (species[i] < 0 || species[i] >= m->n_species) fail(REANN_E_INVALID, "species out of range");
+    hipStream_t st = ctx->stream;
+    int32_t *ds = d_species.resize(n);
+    HIP_OK(hipMemcpyAsync(ds, species.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+    m->weights(ctx->device, st);
+}
+
+bool Plan::same_system(const Model *mm, const int32_t *spec, int64_t nn, const double cell_[9], const int32_t pbc_[3],
+                       int TT, const reann_opts *opt) const {
+    if (mm != m || nn != n || TT != T) return false;
+    const int pr = opt ? opt->precision : REANN_FP32;
+    const double sk = opt ? opt->skin : 0.0;
+    if (pr != prec || sk != skin) return false;
+    for (int a = 0; a < 3; ++a) {
+        const int pa = (opt && opt->decomp[a] > 0) ? opt->decomp[a] : 1;
+        if (pa != P[a] || (pbc_[a] != 0) != (pbc[a] != 0)) return false;
+    }
+    if (std::memcmp(cell_, cell, sizeof cell) != 0) return false;
+    return std::memcmp(spec, species.data(), nn * sizeof(int32_t)) == 0;
+}
+
+void Plan::mark(hipStream_t st, int phase, int nlaunch) {
+    if (!timing) return;
+    if (nev == ev.size()) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        ev.push_back(e);
+        ev_phase.push_back(-1);
+    }
+    HIP_OK(hipEventRecord(ev[nev], st));
+    ev_phase[nev] = phase;
+    if (phase >= 0 && phase < 7) launches[phase] += nlaunch;
+    ++nev;
+}
+
+int64_t Plan::collect_timing(double *ms7, int64_t *launches7) {
+    for (int q = 0; q < 7; ++q) ms7[q] = 0.0;
+    if (nev > 0) HIP_OK(hipEventSynchronize(ev[nev - 1]));
+    for (size_t i = 1; i < nev; ++i) {
+        const int ph = ev_phase[i];
+        if (ph < 0 || ph >= 7) continue;
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
+        ms7[ph] += ms;
+    }
+    if (launches7)
+        for (int q = 0; q < 7; ++q) launches7[q] = launches[q];
+    const int64_t steps = timed_steps;
+    nev = 0;
+    timed_steps = 0;
+    for (int q = 0; q < 7; ++q) launches[q] = 0;
+    return steps;
+}
+
+void Plan::alloc_buffers() {
+    const int K = m->K, NL = m->NL, F = m->F, H = m->H, nh = m->nh;
+    const int64_t ne = nl.n_ext;
+    px.ensure(ne * 8); py.ensure(ne * 8); pz.ensure(ne * 8);
+    c.ensure((size_t)T * ne * K * rs);
+    S.ensure((size_t)T * n * NL * K * rs);
+    rho.ensure((size_t)T * n * F * rs);
+    Z.ensure((size_t)T * nh * n * H * rs);
+    Hh.ensure((size_t)T * nh * n * H * rs);
+    y.ensure((size_t)n * K * rs);
+    ybar.ensure((size_t)n * rs);
+    Eat.ensure((size_t)n * 8);
+    Epart.ensure((size_t)(grid_for(n, 256) + 1) * 8);
+    Sbar.ensure((size_t)n * NL * K * rs);
+    rhobar.ensure((size_t)n * F * rs);
+    const int wmax = F > H ? F : H;
+    gA.ensure((size_t)n * wmax * rs);
+    gB.ensure((size_t)n * wmax * rs);
+    cbar.ensure((size_t)ne * K * rs);
+    this->F.ensure((size_t)ne * 3 * rs);
+    Wpart.ensure((size_t)(edge_backward_blocks(ne) + 1) * 9 * 8);
+    Wacc.ensure(16 * 8);
+    disp.ensure(1025 * 8);
+}
+
+void Plan::ensure_list(const double *d_pos, hipStream_t st) {
+    bool rebuild = !built;
+    if (built) {
+        double d2 = 0;
+        max_displacement2(st, nl, d_pos, disp.as<double>());
+        HIP_OK(hipMemcpyAsync(&d2, disp.p, 8, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        const double half = 0.5 * skin;
+        if (!(d2 <= half * half)) rebuild = true;
+    }
+    if (rebuild) {
+        build_nlist(st, d_pos, d_species.ptr(), n, m->n_species, g, m->r_c, skin, nl, ns);
+        built = true;
+        ++rebuilds;
+        alloc_buffers();
+    }
+}
+
+void Plan::nn_forward(hipStream_t st, int t, bool energy) {
+    DeviceWeights &w = m->weights(ctx->device, st);
+    const NNLayout &lay = energy ? m->en_nn : m->msg_nn;
+    const char *blob = energy ? (fp64 ? w.en64.as<char>() : w.en32.as<char>())
+                              : (fp64 ? w.msg64.as<char>() : w.msg32.as<char>());
+    const int F = m->F, H = m->H, nh = m->nh, K = m->K;
+    for (int s = 0; s < m->n_species; ++s) {
+        const int64_t a = nl.seg[s], rows = nl.seg[s + 1] - nl.seg[s];
+        if (rows <= 0) continue;
+        const int64_t nn_index = energy ? s : (int64_t)t * m->n_species + s;
+        const char *p = blob + (size_t)nn_index * lay.size * rs;
+        const char *A = rhoptr(t) + (size_t)a * F * rs;
+        int lda = F;
+        for (int k = 0; k < nh; ++k) {
+            char *Zk = Zptr(t, k) + (size_t)a * H * rs;
+            char *Hk = Hptr(t, k) + (size_t)a * H * rs;
+            dense(st, fp64, EPI_BIAS_SILU, true, rows, lay.din[k], H, A, lda, p + lay.w_off[k] * rs,
+                  p + lay.b_off[k] * rs, Zk, H, Hk, H);
+            A = Hk;
+            lda = H;
+        }
+        char *out = energy ? y.as<char>() + (size_t)a * rs : cptr(t + 1) + (size_t)a * K * rs;
+        const int dout = energy ? 1 : K;
+        dense(st, fp64, EPI_BIAS, true, rows, H, dout, A, lda, p + lay.w_off[nh] * rs, p + lay.b_off[nh] * rs,
+              nullptr, 0, out, dout);
+    }
+}
+
+// VJP of the NN applied at layer t (energy NN if `energy`), from output adjoint gout
+// [n][ldg] to Sbar (through rho^t and S^t).
+void Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) {
+    DeviceWeights &w = m->weights(ctx->device, st);
+    const NNLayout &lay = energy ? m->en_nn : m->msg_nn;
+    const char *blob = energy ? (fp64 ? w.en64.as<char>() : w.en32.as<char>())
+                              : (fp64 ? w.msg64.as<char>() : w.msg32.as<char>());
+    const int F = m->F, H = m->H, nh = m->nh;
+    for (int s = 0; s < m->n_species; ++s) {
+        const int64_t a = nl.seg[s], rows = nl.seg[s + 1] - nl.seg[s];
+        if (rows <= 0) continue;
+        const int64_t nn_index = energy ? s : (int64_t)t * m->n_species + s;
+        const char *p = blob + (size_t)nn_index * lay.size * rs;
+        // output layer: zbar_{nh-1} = (gout W_out) * silu'(Z_{nh-1})
+        const char *gin = gout + (size_t)a * ldg * rs;
+        int ldin = ldg;
+        char *bufs[2] = {gA.as<char>(), gB.as<char>()};
+        int cur = 0;
+        for (int k = nh; k >= 1; --k) {
+            char *dst = bufs[cur] + (size_t)a * H * rs;
+            const char *Zk = Zptr(t, k - 1) + (size_t)a * H * rs;
+            dense(st, fp64, EPI_DSILU, false, rows, lay.dout[k], lay.din[k], gin, ldin, p + lay.w_off[k] * rs,
+                  nullptr, (void *)Zk, H, dst, H);
+            gin = dst;
+            ldin = H;
+            cur ^= 1;
+        }
+        char *rb = rhobar.as<char>() + (size_t)a * F * rs;
+        dense(st, fp64, EPI_NONE, false, rows, lay.dout[0], F, gin, ldin, p + lay.w_off[0] * rs, nullptr, nullptr, 0,
+              rb, F);
+    }
+    density_vjp(st, fp64, m->L, m->K, n, m->density_consts(), Sptr(t), rhobar.p, Sbar.p);
+}
+
+void Plan::forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st) {
+    mark(st, -1);
+    const int64_t rb0 = rebuilds;
+    ensure_list(d_pos, st);
+    mark(st, 0, rebuilds != rb0 ? 1 : 0);
+    const int K = m->K;
+    DeviceWeights &w = m->weights(ctx->device, st);
+    refresh_positions(st, nl, d_pos, px.as<double>(), py.as<double>(), pz.as<double>());
+    init_messages(st, fp64, nl.n_ext, K, nl.spec_ext.ptr(), fp64 ? w.c064.p : w.c032.p, cptr(0));
+    EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), px.as<double>(), py.as<double>(), pz.as<double>()};
+    const EdgeConsts ec = m->edge_consts();
+    const DensityConsts dc = m->density_consts();
+    mark(st, 6);
+    for (int t = 0; t < T; ++t) {
+        edge_forward(st, fp64, m->L, K, ea, ec, cptr(t), Sptr(t));
+        mark(st, 1, 1);
+        density(st, fp64, m->L, K, n, dc, Sptr(t), rhoptr(t));
+        if (t < T - 1) {
+            nn_forward(st, t, false);
+            mark(st, 2);
+            ghost_gather(st, fp64, n, nl.n_gh, K, nl.gh_owner.ptr(), cptr(t + 1));
+            mark(st, 3);
+        }
+    }
+    nn_forward(st, T - 1, true);
+    mark(st, 2);
+    const int nb = energy_finalize(st, fp64, n, m->energy_scale, y.p, nl.perm.ptr(), d_atom_energy, Epart.as<double>());
+    sum_rows(st, Epart.as<double>(), nb, 1, d_energy, false);
+    mark(st, 6);
+    have_forward = true;
+}
+
+void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipStream_t st) {
+    if (!have_forward) fail(REANN_E_STATE, "backward called before forward");
+    const int K = m->K;
+    EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), px.as<double>(), py.as<double>(), pz.as<double>()};
+    const EdgeConsts ec = m->edge_consts();
+    mark(st, -1);
+    fill_energy_seed(st, fp64, n, m->energy_scale, d_g, ybar.p);
+    nn_vjp(st, T - 1, true, ybar.as<char>(), 1);
+    mark(st, 4);
+    zero(st, this->F.p, (size_t)nl.n_ext * 3 * rs);
+    zero(st, Wacc.p, 9 * 8);
+    mark(st, 6);
+    for (int t = T - 1; t >= 0; --t) {
+        const int nb = edge_backward(st, fp64, m->L, K, ea, ec, cptr(t), Sbar.p, t > 0, this->F.p, cbar.p,
+                                     Wpart.as<double>());
+        sum_rows(st, Wpart.as<double>(), nb, 9, Wacc.as<double>(), true);
+        mark(st, 5, 1);
+        if (t > 0) {
+            ghost_reduce(st, fp64, n, K, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), cbar.p);
+            mark(st, 3);
+            nn_vjp(st, t - 1, false, cbar.as<char>(), K);
+            mark(st, 4);
+        }
+    }
+    ghost_reduce(st, fp64, n, 3, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), this->F.p);
+    mark(st, 3);
+    // the seed carried g; forces are -dE/dx already scaled
+    forces_out(st, fp64, n, this->F.p, nl.perm.ptr(), nullptr, d_forces, Wacc.as<double>(), d_virial);
+    mark(st, 6);
+    if (timing) ++timed_steps;
+}
+
+void Plan::get(int what, int t, double *host) {
+    if (!have_forward) fail(REANN_E_STATE, "no forward has run");
+    HIP_OK(hipDeviceSynchronize());   // the forward may have run on a caller's stream
+    const int K = m->K, NL = m->NL;
+    std::vector<int32_t> perm(n);
+    HIP_OK(hipMemcpy(perm.data(), nl.perm.ptr(), n * 4, hipMemcpyDeviceToHost));
+    if (what == 2) {
+        std::vector<double> y_(n);
+        if (fp64) HIP_OK(hipMemcpy(y_.data(), y.p, n * 8, hipMemcpyDeviceToHost));
+        else {
+            std::vector<float> f(n);
+            HIP_OK(hipMemcpy(f.data(), y.p, n * 4, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) y_[i] = f[i];
+        }
+        for (int64_t i = 0; i < n; ++i) host[perm[i]] = m->energy_scale * y_[i];
+        return;
+    }
+    if (t < 0 || t >= T) fail(REANN_E_INVALID, "layer out of range");
+    const int width = what == 0 ? NL * K : K;
+    const char *src = what == 0 ? Sptr(t) : cptr(t);
+    if (what != 0 && what != 1) fail(REANN_E_INVALID, "unknown quantity");
+    std::vector<double> v((size_t)n * width);
+    if (fp64) HIP_OK(hipMemcpy(v.data(), src, (size_t)n * width * 8, hipMemcpyDeviceToHost));
+    else {
+        std::vector<float> f((size_t)n * width);
+        HIP_OK(hipMemcpy(f.data(), src, (size_t)n * width * 4, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < f.size(); ++i) v[i] = f[i];
+    }
+    for (int64_t i = 0; i < n; ++i)
+        std::memcpy(host + (size_t)perm[i] * width, v.data() + (size_t)i * width, width * 8);
+}
+
+}  // namespace reann

@@ -1,0 +1,110 @@
+// Runtime objects behind the C ABI: model parameters on the device, a context (device +
+// stream), and a plan that evaluates one system (neighbour list, layer buffers, kernels).
+#pragma once
+
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include "edge.hpp"
+#include "mlp.hpp"
+#include "nlist.hpp"
+
+struct reann_model;
+struct reann_ctx;
+struct reann_plan;
+
+namespace reann {
+
+// One atomic NN inside a flat parameter blob: offsets of W_k and b_k (k = 0 .. nh).
+struct NNLayout {
+    std::vector<int64_t> w_off, b_off;
+    std::vector<int> din, dout;
+    int64_t size = 0;
+};
+NNLayout nn_layout(int F, int H, int nh, int out);
+
+struct DeviceWeights {
+    DevBuf msg64, en64, c064, msg32, en32, c032;
+};
+
+struct Model {
+    int n_species, L, K, T_max, nh, H, F, NL;
+    double r_c, ang_scale, energy_scale;
+    std::vector<double> centres, alphas, c0, msg, en;
+    NNLayout msg_nn, en_nn;
+    std::mutex mu;
+    std::map<int, std::unique_ptr<DeviceWeights>> dev;
+    // device copy of the weights for `device` (created on first use)
+    DeviceWeights &weights(int device, hipStream_t st);
+    EdgeConsts edge_consts() const;
+    DensityConsts density_consts() const;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::unique_ptr<struct Plan> cached;   // plan of the last host-API system
+    const Model *cached_model = nullptr;
+    DevBuf pos, forces, scal;
+};
+
+struct Plan {
+    Ctx *ctx = nullptr;
+    Model *m = nullptr;
+    int T = 1, prec = REANN_FP32;
+    bool fp64 = false;
+    size_t rs = 4;   // bytes of the working type
+    Geom g{};
+    int32_t P[3] = {1, 1, 1};
+    double skin = 0, cell[9]{};
+    int32_t pbc[3]{};
+    int64_t n = 0;
+    std::vector<int32_t> species;
+    DArr<int32_t> d_species;
+    NList nl;
+    NListScratch ns;
+    bool built = false;
+    int64_t rebuilds = 0;
+    // layer buffers
+    DevBuf px, py, pz, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, Wacc, disp, one;
+    bool have_forward = false;
+    bool timing = false;
+    // events recorded at phase boundaries while timing is on; intervals are attributed to
+    // the phase named by the event that closes them (phase -1: not attributed)
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_phase;
+    size_t nev = 0;
+    int64_t timed_steps = 0;
+    int64_t launches[7]{};
+
+    ~Plan();
+    void init(Ctx *c, Model *mm, const int32_t *spec, int64_t nn, const double cell_[9], const int32_t pbc_[3], int TT,
+              const reann_opts *opt);
+    bool same_system(const Model *mm, const int32_t *spec, int64_t nn, const double cell_[9], const int32_t pbc_[3],
+                     int TT, const reann_opts *opt) const;
+    void forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st);
+    void backward(const double *d_g, double *d_forces, double *d_virial, hipStream_t st);
+    void get(int what, int t, double *host);
+    // per-phase kernel time (ms) accumulated since the last call; returns the step count
+    int64_t collect_timing(double *ms7, int64_t *launches7);
+
+  private:
+    void ensure_list(const double *d_pos, hipStream_t st);
+    void alloc_buffers();
+    char *cptr(int t) const { return c.as<char>() + (size_t)t * nl.n_ext * m->K * rs; }
+    char *Sptr(int t) const { return S.as<char>() + (size_t)t * n * m->NL * m->K * rs; }
+    char *rhoptr(int t) const { return rho.as<char>() + (size_t)t * n * m->F * rs; }
+    char *Zptr(int t, int k) const { return Z.as<char>() + ((size_t)t * m->nh + k) * n * m->H * rs; }
+    char *Hptr(int t, int k) const { return Hh.as<char>() + ((size_t)t * m->nh + k) * n * m->H * rs; }
+    void nn_forward(hipStream_t st, int t, bool energy);
+    void nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg);
+    void mark(hipStream_t st, int phase, int nlaunch = 0);
+};
+
+}  // namespace reann
+
+struct reann_model { reann::Model impl; };
+struct reann_ctx { reann::Ctx impl; };
+struct reann_plan { reann::Plan impl; };

@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances:
+  neighbour lists      bit-exact sets in canonical (i, owner, shift) order
+  FP64 path            |dE| <= 1e-12 * max(|E|, sum|E_i|); forces and virial <= 1e-10 (relative to max)
+  FP32 path            |dE| <= 1e-6  * max(|E|, sum|E_i|); force RMSE <= 1e-5 * force RMS
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from synth import models, systems
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def rn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_06711_amd as rn
+    return rn
+
+
+@pytest.fixture(scope="module")
+def ctx(rn):
+    return rn.Context(0)
+
+
+def rel_energy(E, ref):
+    return abs(E - ref["energy"]) / max(abs(ref["energy"]), np.abs(ref["atom_energy"]).sum())
+
+
+def rel_force_rmse(F, ref):
+    return np.sqrt(((F - ref["forces"]) ** 2).mean()) / np.sqrt((ref["forces"] ** 2).mean())
+
+
+def canon(row, j, sh):
+    return [(i, int(j[k]), *map(int, sh[k])) for i in range(len(row) - 1) for k in range(row[i], row[i + 1])]
+
+
+def tiny_box(seed=2):
+    rng = np.random.default_rng(seed)
+    return dict(pos=rng.uniform(-1, 5, (7, 3)), species=np.zeros(7, np.int32), cell=np.diag([4.0, 3.3, 5.1]),
+                pbc=np.ones(3, np.int32), elements=["Cu"])
+
+
+NLIST_CASES = {
+    "water_rc5": (lambda: systems.water_box(seed=1), 5.0, 0.0, (1, 1, 1)),
+    "water_rc5_skin1_2x2x2": (lambda: systems.water_box(seed=1), 5.0, 1.0, (2, 2, 2)),
+    "tiny_box_images": (tiny_box, 3.2, 0.5, (1, 1, 1)),
+    "slab": (lambda: dict(systems.water_box(seed=3), pbc=np.array([1, 1, 0], np.int32)), 4.5, 0.0, (1, 1, 1)),
+    "cu_skin_3x2x1": (lambda: systems.fcc_crystal((4, 4, 3), seed=5), 6.0, 1.0, (3, 2, 1)),
+}
+
+
+@pytest.mark.parametrize("case", list(NLIST_CASES))
+def test_neighbor_list_bit_exact(rn, ctx, oracle_lib, case):
+    make, r_c, skin, dec = NLIST_CASES[case]
+    s = make()
+    print("case", case, flush=True)
+    got = rn.build_neighbors(ctx, s, r_c, skin, dec).export()
+    want = oracle_lib.neighbors(s, r_c + skin, dec)
+    for a, b in zip(got, want):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_neighbor_list_full_cu100800(rn, ctx, oracle_lib):
+    w = synth.workload("cu100800")
+    s = w["system"]
+    nl = rn.build_neighbors(ctx, s, w["model"].r_c, w["skin"])
+    got = nl.export()
+    want = oracle_lib.neighbors(s, w["model"].r_c + w["skin"])
+    for a, b in zip(got, want):
+        np.testing.assert_array_equal(a, b)
+    info = nl.info()
+    assert info["n_atoms"] == 100800
+
+
+def _eval(rn, ctx, m, s, T, prec, skin=0.0, decomp=(1, 1, 1)):
+    model = rn.Model(m)
+    return rn.energy_forces(ctx, model, s, T=T, precision=prec, skin=skin, decomp=decomp)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3])
+@pytest.mark.parametrize("decomp", [(1, 1, 1), (2, 2, 2), (3, 2, 1)])
+def test_fp64_matches_oracle_water(rn, ctx, oracle_lib, T, decomp):
+    s = systems.water_box(seed=30)
+    m = models.water_model(T_max=3, seed=30, energy_scale=1.3)
+    ref = oracle_lib.evaluate(m, s, T=T, skin=0.5)
+    E, F, W = _eval(rn, ctx, m, s, T, "fp64", skin=0.5, decomp=decomp)
+    assert rel_energy(E, ref) <= 1e-12
+    assert np.abs(F - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max()
+    assert np.abs(W - ref["virial"]).max() <= 1e-10 * np.abs(ref["virial"]).max()
+
+
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_fp32_matches_oracle_water(rn, ctx, oracle_lib, T):
+    s = systems.water_box(seed=31)
+    m = models.water_model(T_max=3, seed=31)
+    ref = oracle_lib.evaluate(m, s, T=T)
+    E, F, W = _eval(rn, ctx, m, s, T, "fp32")
+    assert rel_energy(E, ref) <= 1e-6
+    assert rel_force_rmse(F, ref) <= 1e-5
+    assert np.abs(W - ref["virial"]).max() <= 1e-5 * np.abs(ref["virial"]).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cu_small_with_skin(rn, ctx, oracle_lib, prec):
+    s = systems.fcc_crystal((5, 5, 4), seed=32)
+    m = models.cu_model(T_max=3, seed=32)
+    ref = oracle_lib.evaluate(m, s, T=3, skin=1.0)
+    E, F, W = _eval(rn, ctx, m, s, 3, prec, skin=1.0)
+    if prec == "fp64":
+        assert rel_energy(E, ref) <= 1e-12
+        assert np.abs(F - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max()
+    else:
+        assert rel_energy(E, ref) <= 1e-6
+        assert rel_force_rmse(F, ref) <= 1e-5
+
+
+def test_layer_intermediates_fp64(rn, ctx, oracle_lib):
+    """Orbital sums S^t, messages c^t and atomic energies, layer by layer."""
+    import torch
+    s = systems.water_box(seed=33)
+    m = models.water_model(T_max=3, seed=33)
+    ref = oracle_lib.evaluate(m, s, T=3, forces=False, want_S=True, want_c=True)
+    model = rn.Model(m)
+    plan = rn.Plan(ctx, model, s, T=3, precision="fp64", decomp=(2, 1, 1))
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
+    e = torch.zeros((), dtype=torch.float64, device="cuda")
+    plan.forward(pos, e)
+    for t in range(3):
+        np.testing.assert_allclose(plan.get("S", t), ref["S"][t], rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(plan.get("c", t), ref["c"][t], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(plan.get("atom_energy"), ref["atom_energy"], rtol=1e-11, atol=1e-12)
+
+
+def test_open_cluster_and_mixed_pbc(rn, ctx, oracle_lib):
+    rng = np.random.default_rng(34)
+    pts = []
+    while len(pts) < 40:
+        p = rng.uniform(0, 9, 3)
+        if all(np.linalg.norm(p - q) > 1.5 for q in pts):
+            pts.append(p)
+    s = dict(pos=np.array(pts), species=rng.integers(0, 2, 40).astype(np.int32), cell=np.eye(3) * 9.0,
+             pbc=np.array([1, 0, 1], np.int32), elements=["H", "O"])
+    m = models.water_model(T_max=2, seed=34)
+    ref = oracle_lib.evaluate(m, s, T=2, skin=0.3)
+    E, F, W = _eval(rn, ctx, m, s, 2, "fp64", skin=0.3)
+    assert rel_energy(E, ref) <= 1e-12
+    assert np.abs(F - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_positions_outside_the_box(rn, ctx, oracle_lib, prec):
+    """Positions several box lengths outside [0, L) are wrapped; the result is the
+    oracle's, and equal to that of the translated system."""
+    s = systems.fcc_crystal((4, 4, 4), seed=40)
+    m = models.cu_model(T_max=3, seed=40)
+    shifted = dict(s, pos=s["pos"] + np.array([3.3, -7.1, 20.2]) * np.diag(s["cell"]) / 2.7)
+    ref = oracle_lib.evaluate(m, s, T=3, skin=1.0)
+    E, F, W = _eval(rn, ctx, m, shifted, 3, prec, skin=1.0)
+    tol_e, tol_f = (1e-12, 1e-10) if prec == "fp64" else (1e-6, 1e-5)
+    assert rel_energy(E, ref) <= tol_e
+    assert rel_force_rmse(F, ref) <= tol_f
+
+
+def test_decomposed_equals_whole_gpu_fp64(rn, ctx):
+    s = systems.water_box(grid=(6, 6, 6), spacing=synth.workloads.WATER_SPACING, seed=35)
+    m = models.water_model(T_max=4, seed=35)
+    a = _eval(rn, ctx, m, s, 4, "fp64", skin=1.0)
+    b = _eval(rn, ctx, m, s, 4, "fp64", skin=1.0, decomp=(2, 2, 2))
+    assert abs(a[0] - b[0]) <= 1e-12 * abs(a[0])
+    assert np.abs(a[1] - b[1]).max() <= 1e-10 * np.abs(a[1]).max()
+
+
+def test_repeat_runs_bitwise_equal(rn, ctx):
+    s = systems.fcc_crystal((5, 5, 5), seed=36)
+    m = models.cu_model(T_max=3, seed=36)
+    model = rn.Model(m)
+    a = rn.energy_forces(ctx, model, s, T=3, precision="fp32", skin=1.0)
+    b = rn.energy_forces(ctx, model, s, T=3, precision="fp32", skin=1.0)
+    assert a[0] == b[0]
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_skin_reuse_and_rebuild(rn, ctx, oracle_lib):
+    """Moving atoms less than skin/2 reuses the list, more than that rebuilds it; either way
+    the result is the oracle's at the new positions."""
+    s = systems.fcc_crystal((4, 4, 4), seed=37)
+    m = models.cu_model(T_max=3, seed=37)
+    model = rn.Model(m)
+    rng = np.random.default_rng(0)
+    for step, amp in enumerate([0.0, 0.1, 0.2, 0.9]):
+        s2 = dict(s, pos=s["pos"] + rng.normal(scale=amp / 3, size=s["pos"].shape) if amp else s["pos"])
+        E, F, W = rn.energy_forces(ctx, model, s2, T=3, precision="fp64", skin=1.0)
+        ref = oracle_lib.evaluate(m, s2, T=3, skin=1.0)
+        assert rel_energy(E, ref) <= 1e-12, step
+        assert np.abs(F - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max(), step
+
+
+def test_autograd_matches_oracle_forces(rn, ctx, oracle_lib):
+    import torch
+    from paper_2505_06711_amd.autograd import reann_energy
+    s = systems.water_box(seed=38)
+    m = models.water_model(T_max=3, seed=38)
+    ref = oracle_lib.evaluate(m, s, T=3)
+    model = rn.Model(m)
+    plan = rn.Plan(ctx, model, s, T=3, precision="fp64")
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda", requires_grad=True)
+    e = reann_energy(pos, plan)
+    (2.5 * e).backward()
+    torch.cuda.synchronize()
+    assert abs(float(e) - ref["energy"]) <= 1e-12 * np.abs(ref["atom_energy"]).sum()
+    np.testing.assert_allclose(-pos.grad.cpu().numpy() / 2.5, ref["forces"], rtol=0, atol=1e-10 * np.abs(ref["forces"]).max())
+
+
+def test_autograd_finite_differences_fp64(rn, ctx):
+    """d E / d x from the library's adjoint against central differences of its own FP64 energy."""
+    import torch
+    from paper_2505_06711_amd.autograd import reann_energy
+    s = systems.fcc_crystal((3, 3, 3), seed=39)
+    m = models.cu_model(T_max=3, seed=39)
+    model = rn.Model(m)
+    plan = rn.Plan(ctx, model, s, T=3, precision="fp64", skin=1.0)
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda", requires_grad=True)
+    reann_energy(pos, plan).backward()
+    g = pos.grad.cpu().numpy()
+    h = 1e-5
+    for (i, a) in [(0, 0), (7, 1), (50, 2), (100, 0)]:
+        vals = []
+        for sgn in (1, -1):
+            p = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
+            p[i, a] += sgn * h
+            vals.append(float(reann_energy(p, plan)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert g[i, a] == pytest.approx(fd, rel=1e-6, abs=1e-7)
+
+
+def _golden(name, T):
+    path = os.path.join(HERE, "golden", "%s_T%d.json" % (name, T))
+    if not os.path.exists(path):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_cu100800_full_size_against_oracle_golden(rn, ctx, prec):
+    """Full 100,800-atom Cu workload against the oracle's stored values (written by
+    tests/golden/make_golden.py, which calls only the oracle)."""
+    from tests.golden.make_golden import positions_digest
+    g = _golden("cu100800", 3)
+    w = synth.workload("cu100800")
+    s, m = w["system"], w["model"]
+    assert positions_digest(s["pos"]) == g["positions_sha256"]
+    model = rn.Model(m)
+    plan = rn.Plan(ctx, model, s, T=3, precision=prec, skin=w["skin"])
+    import torch
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
+    e = torch.zeros((), dtype=torch.float64, device="cuda")
+    ae = torch.zeros(len(s["pos"]), dtype=torch.float64, device="cuda")
+    F = torch.zeros_like(pos)
+    W = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    plan.forward(pos, e, ae)
+    plan.backward(F, virial=W)
+    torch.cuda.synchronize()
+    E = float(e)
+    den = max(abs(g["energy"]), g["sum_abs_atom_energy"])
+    idx = np.array(g["sample_index"])
+    Fs = F.cpu().numpy()[idx]
+    Fref = np.array(g["sample_forces"]).reshape(-1, 3)
+    frms = g["force_rms"]
+    tol_e, tol_f = (1e-12, 1e-10) if prec == "fp64" else (1e-6, 1e-5)
+    print(prec, "E", E, "ref", g["energy"], "relE", abs(E - g["energy"]) / den, flush=True)
+    assert abs(E - g["energy"]) / den <= tol_e
+    assert np.sqrt(((Fs - Fref) ** 2).mean()) / frms <= tol_f
+    np.testing.assert_allclose(ae.cpu().numpy()[idx], g["sample_atom_energy"], rtol=0,
+                               atol=(tol_f * 10) * np.abs(g["sample_atom_energy"]).max())
+    Wref = np.array(g["virial"]).reshape(3, 3)
+    assert np.abs(W.cpu().numpy() - Wref).max() <= tol_f * np.abs(Wref).max()
