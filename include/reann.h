@@ -31,7 +31,8 @@
  *    status and reann_last_error() describes it.
  *  - A context, nlist or plan must not be used by two threads at once.  reann_submit and
  *    reann_poll are thread-safe.
- *  - Plans and neighbour lists keep a pointer to their context and must be freed before it.
+ *  - Plans and neighbour lists keep their context alive: reann_ctx_free releases the context
+ *    once the last plan or list created on it has been freed.
  */
 #ifndef REANN_H
 #define REANN_H

@@ -84,18 +84,22 @@ _SIGS = {
 
 _lib = None
 
-# Live handles, released at interpreter exit in dependency order (plans, lists and
-# servers before the contexts and models they use) while the HIP runtime is still up.
+# Handles still alive when the interpreter exits are not freed one by one: teardown order
+# is arbitrary and the process exit returns every device allocation anyway, so after this
+# point close() makes no library call.
 _LIVE = {k: weakref.WeakSet() for k in ("plan", "nlist", "server", "ctx", "model")}
+_SHUTDOWN = [False]
 
 
-def _release_all():
-    for kind in ("plan", "nlist", "server", "ctx", "model"):
-        for obj in list(_LIVE[kind]):
-            obj.close()
+def _mark_shutdown():
+    _SHUTDOWN[0] = True
 
 
-atexit.register(_release_all)
+atexit.register(_mark_shutdown)
+
+
+def _can_free(obj) -> bool:
+    return bool(getattr(obj, "handle", None)) and _lib is not None and not _SHUTDOWN[0]
 
 
 def load():
@@ -162,7 +166,7 @@ class Model:
         _LIVE["model"].add(self)
 
     def close(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if _can_free(self):
             _lib.reann_model_free(self.handle)
         self.handle = None
 
@@ -184,12 +188,8 @@ class Context:
         _LIVE["ctx"].add(self)
 
     def close(self):
-        if getattr(self, "handle", None) and _lib is not None:
-            for kind in ("plan", "nlist", "server"):      # dependants first
-                for obj in list(_LIVE[kind]):
-                    if getattr(obj, "ctx", None) is self:
-                        obj.close()
-            _lib.reann_ctx_free(self.handle)
+        if _can_free(self):
+            _lib.reann_ctx_free(self.handle)   # the library keeps it until its plans/lists are freed
         self.handle = None
 
     __del__ = close
@@ -219,7 +219,7 @@ class NeighborList:
         return row, j[:cnt.value], sh[:cnt.value]
 
     def close(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if _can_free(self):
             _lib.reann_nlist_free(self.handle)
         self.handle = None
 
@@ -331,7 +331,7 @@ class Plan:
                     steps=steps.value)
 
     def close(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if _can_free(self):
             _lib.reann_plan_free(self.handle)
         self.handle = None
 

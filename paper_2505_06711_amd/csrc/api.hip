@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "runtime.hpp"
@@ -43,6 +44,31 @@ static void check_cell(const double *cell, const int32_t *pbc) {
 static void check_positions(const double *pos, int64_t n) {
     for (int64_t i = 0; i < 3 * n; ++i) REQUIRE(std::isfinite(pos[i]), "positions contain NaN or Inf");
 }
+
+static std::mutex g_ctx_mu;
+
+static void ctx_destroy(reann_ctx *c) {
+    (void)hipSetDevice(c->impl.device);
+    (void)hipStreamSynchronize(c->impl.stream);
+    c->impl.cached.reset();
+    if (c->impl.own_stream) (void)hipStreamDestroy(c->impl.stream);
+    delete c;
+}
+
+namespace reann {
+void ctx_acquire(Ctx *c) {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    ++c->users;
+}
+void ctx_release(Ctx *c) {
+    bool destroy = false;
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        destroy = --c->users == 0 && c->released;
+    }
+    if (destroy) ctx_destroy(reinterpret_cast<reann_ctx *>(c));
+}
+}  // namespace reann
 
 extern "C" {
 
@@ -105,19 +131,26 @@ reann_status reann_ctx_create(int32_t device, void *hip_stream, reann_ctx **out)
     });
 }
 
+
 void reann_ctx_free(reann_ctx *c) {
     if (!c) return;
-    (void)hipSetDevice(c->impl.device);
-    (void)hipStreamSynchronize(c->impl.stream);
-    c->impl.cached.reset();
-    if (c->impl.own_stream) (void)hipStreamDestroy(c->impl.stream);
-    delete c;
+    bool destroy = false;
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        c->impl.released = true;
+        destroy = c->impl.users == 0;
+    }
+    if (destroy) ctx_destroy(c);
 }
 
 // ------------------------------------------------------------------ nlist --
 
 struct reann_nlist {
     Plan plan;   // geometry and neighbour list only; no model attached
+    Ctx *owner = nullptr;
+    ~reann_nlist() {
+        if (owner) ctx_release(owner);
+    }
 };
 
 reann_status reann_build_neighbors(reann_ctx *ctx, const double *pos, int64_t n, const double cell[9],
@@ -132,6 +165,8 @@ reann_status reann_build_neighbors(reann_ctx *ctx, const double *pos, int64_t n,
         check_positions(pos, n);
         HIP_OK(hipSetDevice(ctx->impl.device));
         auto *nl = new reann_nlist();
+        ctx_acquire(&ctx->impl);
+        nl->owner = &ctx->impl;
         try {
             Plan &p = nl->plan;
             p.ctx = &ctx->impl;
@@ -288,6 +323,7 @@ reann_status reann_plan_create(reann_ctx *ctx, const reann_model *m, const int32
             delete p;
             throw;
         }
+        ctx_acquire(&ctx->impl);
         *out = p;
     });
 }
@@ -336,9 +372,11 @@ reann_status reann_plan_timing(reann_plan *p, double *ms7, int64_t *launches7, i
 
 void reann_plan_free(reann_plan *p) {
     if (!p) return;
-    (void)hipSetDevice(p->impl.ctx->device);
-    (void)hipStreamSynchronize(p->impl.ctx->stream);
+    Ctx *c = p->impl.ctx;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();   // its work may sit on any stream the caller passed
     delete p;
+    ctx_release(c);
 }
 
 }  // extern "C"

@@ -8,9 +8,11 @@
 //   g_ij = d/dd [ f_c sum_lambda A_lambda(d) sum_m Sbar_i[lambda][m] c_j[m] R_m(r) ],
 // contributing +g_ij to F_i, -g_ij to F_j, -d (x) g_ij to the virial and
 //   f_c R_m sum_lambda Sbar_i[lambda][m] A_lambda(d)  to  cbar_j[m] = dE/dc_j[m].
-// No atomics: every ext row k gathers what lands on k -- as centre (its own edges) and
-// as neighbour (the edges j->k of its local neighbours j, whose Sbar it reads).  Each
-// edge is therefore evaluated at both ends; results are deterministic.
+// No atomics: every ext row k gathers what lands on k -- as centre (its own edges, one
+// kernel) and as neighbour (the edges j->k of its local neighbours j, whose Sbar it
+// reads, a second kernel).  Each edge is evaluated at both ends; sums over a row's
+// edges are taken across the 32 lanes of a half-wave in a fixed order, so results are
+// deterministic.
 #include "edge.hpp"
 
 namespace reann {
@@ -63,8 +65,37 @@ __device__ inline void angular(R ux, R uy, R uz, R s, R *A, R (*dA)[3]) {
     }
 }
 
+// In-cutoff compaction of the (r_c + skin) list for the current positions: each row's
+// in-cutoff local neighbours are packed at the front of its slot range and its in-cutoff
+// ghost neighbours at the back (reverse order).  Every later pass of the step reads only
+// these entries.
+__global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, int32_t *__restrict__ nloc,
+                          int32_t *__restrict__ ngh) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.n_ext) return;
+    const double xi = a.px[x], yi = a.py[x], zi = a.pz[x];
+    const int64_t lo = a.row[x], hi = a.row[x + 1];
+    int64_t front = lo, back = hi;
+    for (int64_t k = lo; k < hi; ++k) {
+        const int32_t j = a.col[k];
+        const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
+        if (dx * dx + dy * dy + dz * dz < rc2) {
+            if (j < a.n) col2[front++] = j;
+            else col2[--back] = j;
+        }
+    }
+    nloc[x] = (int32_t)(front - lo);
+    ngh[x] = (int32_t)(hi - back);
+}
+
+// e-th in-cutoff neighbour of row x (locals first, then ghosts)
+__device__ inline int64_t cut_slot(const CutList &cl, int64_t x, int e) {
+    const int nl = cl.nloc[x];
+    return e < nl ? cl.row[x] + e : cl.row[x + 1] - cl.ngh[x] + (e - nl);
+}
+
 template <int L, int K, typename R>
-__global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, EdgeConsts ec, const R *__restrict__ c,
+__global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeConsts ec, const R *__restrict__ c,
                                                   R *__restrict__ S) {
     constexpr int NL = n_lambda(L);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -77,11 +108,11 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, EdgeConsts ec, con
     const double xi = a.px[i], yi = a.py[i], zi = a.pz[i];
     const R inv_rc = R(1.0 / ec.r_c);
     const R s = R(ec.ang_scale);
-    for (int64_t k = a.row[i]; k < a.row[i + 1]; ++k) {
-        const int64_t j = a.col[k];
+    const int cnt = cl.nloc[i] + cl.ngh[i];
+    for (int e = 0; e < cnt; ++e) {
+        const int64_t j = cl.col[cut_slot(cl, i, e)];
         const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
         const double d2 = dx * dx + dy * dy + dz * dz;
-        if (d2 >= ec.rc2) continue;
         const R r = d_sqrt(R(d2));
         const R u = R(0.5) * d_cospi(r * inv_rc) + R(0.5);
         const R fc = u * u;
@@ -103,137 +134,186 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, EdgeConsts ec, con
         for (int m = 0; m < K; ++m) out[l * K + m] = acc[l][m];
 }
 
-constexpr int kBwdBlock = 128;
+// Per-edge radial/cutoff factors shared by both adjoint roles.
+template <int K, typename R> struct EdgeGeo {
+    R r, ex, ey, ez, fc, dfc;
+    R Rm[K], dRm[K];
+};
 
-template <int L, int K, typename R, bool CBAR>
-__global__ __launch_bounds__(kBwdBlock) void k_edge_bwd(EdgeArgs a, EdgeConsts ec, const R *__restrict__ c,
-                                                        const R *__restrict__ Sbar, R *__restrict__ F,
-                                                        R *__restrict__ cbar, double *__restrict__ Wpart) {
+template <int K, typename R>
+__device__ inline void edge_geo(const EdgeConsts &ec, double dx, double dy, double dz, EdgeGeo<K, R> &g) {
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    g.r = d_sqrt(R(d2));
+    const R rinv = R(1) / g.r;
+    const R t = g.r * R(1.0 / ec.r_c);
+    const R u = R(0.5) * d_cospi(t) + R(0.5);
+    g.fc = u * u;
+    g.dfc = -u * R(M_PI / ec.r_c) * d_sinpi(t);
+    g.ex = R(dx) * rinv; g.ey = R(dy) * rinv; g.ez = R(dz) * rinv;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        const R xm = g.r - R(ec.centres[m]);
+        const R al = R(ec.alphas[m]);
+        g.Rm[m] = d_exp(-al * xm * xm);
+        g.dRm[m] = R(-2) * al * xm * g.Rm[m];
+    }
+}
+
+template <typename R> __device__ inline R hw_sum(R v) {   // sum over the 32 lanes of a half-wave
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+    return v;
+}
+
+constexpr int kRowsPerBlock = 8;   // 256 threads = 8 half-waves, one row each
+
+// Centre role: for local row k and each in-cutoff neighbour j (edge k -> j),
+//   g = d/dd [ f_c sum_lambda A_lambda(d) sum_m Sbar_k[lambda][m] c_j[m] R_m(r) ]
+// adds +g to F_k and -d (x) g to the virial.  Sbar_k is staged in LDS and read by all
+// 32 lanes of its half-wave; lanes take the row's edges in turn.
+template <int L, int K, typename R>
+__global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, EdgeConsts ec, const R *__restrict__ c,
+                                                    const R *__restrict__ Sbar, R *__restrict__ F,
+                                                    double *__restrict__ Wpart) {
     constexpr int NL = n_lambda(L);
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ R sS[kRowsPerBlock][NL * K];
+    __shared__ double sW[kRowsPerBlock][9];
+    const int hw = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock;
+    for (int t = threadIdx.x; t < kRowsPerBlock * NL * K; t += 256) {
+        const int64_t rr = row0 + t / (NL * K);
+        sS[t / (NL * K)][t % (NL * K)] = rr < a.n ? Sbar[row0 * NL * K + t] : R(0);
+    }
+    __syncthreads();
+    const int64_t x = row0 + hw;
+    R f0 = R(0), f1 = R(0), f2 = R(0);
     double W[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) W[q] = 0.0;
-    if (x < a.n_ext) {
-        const bool loc = x < a.n;
-        R sb[NL][K];
-#pragma unroll
-        for (int l = 0; l < NL; ++l)
-#pragma unroll
-            for (int m = 0; m < K; ++m) sb[l][m] = loc ? Sbar[x * NL * K + l * K + m] : R(0);
-        R ck[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m) ck[m] = c[x * K + m];
-        R f[3] = {R(0), R(0), R(0)};
-        R cb[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m) cb[m] = R(0);
+    if (x < a.n) {
         const double xi = a.px[x], yi = a.py[x], zi = a.pz[x];
-        const R inv_rc = R(1.0 / ec.r_c);
         const R s = R(ec.ang_scale);
-        const R pi_rc = R(M_PI / ec.r_c);
-        for (int64_t k = a.row[x]; k < a.row[x + 1]; ++k) {
-            const int64_t j = a.col[k];
-            const bool jloc = j < a.n;
+        const R *sb = sS[hw];
+        const int cnt = cl.nloc[x] + cl.ngh[x];
+        for (int e = lane; e < cnt; e += 32) {
+            // keep Sbar_k in LDS: without this the compiler hoists all NL*K reads out of
+            // the loop into registers, which caps occupancy
+            asm volatile("" ::: "memory");
+            const int64_t j = cl.col[cut_slot(cl, x, e)];
             const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            if (d2 >= ec.rc2) continue;
-            const R r = d_sqrt(R(d2));
-            const R rinv = R(1) / r;
-            const R t = r * inv_rc;
-            const R u = R(0.5) * d_cospi(t) + R(0.5);
-            const R fc = u * u;
-            const R dfc = -u * pi_rc * d_sinpi(t);
-            R Rm[K], dRm[K];
+            EdgeGeo<K, R> g;
+            edge_geo<K, R>(ec, dx, dy, dz, g);
+            R A[NL], dA[NL][3];
+            angular<L, R, true>(R(ec.ang_scale * dx), R(ec.ang_scale * dy), R(ec.ang_scale * dz), s, A, dA);
+            const R *cj = c + j * K;
+            R u[K], v[K];
+#pragma unroll
+            for (int m = 0; m < K; ++m) { const R cm = cj[m]; u[m] = cm * g.Rm[m]; v[m] = cm * g.dRm[m]; }
+            R gx = R(0), gy = R(0), gz = R(0), sAP = R(0), sAQ = R(0);
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                R P = R(0), Q = R(0);
+#pragma unroll
+                for (int m = 0; m < K; ++m) { const R w = sb[l * K + m]; P += w * u[m]; Q += w * v[m]; }
+                gx += P * dA[l][0]; gy += P * dA[l][1]; gz += P * dA[l][2];
+                sAP += A[l] * P; sAQ += A[l] * Q;
+            }
+            const R rad = g.dfc * sAP + g.fc * sAQ;
+            gx = g.fc * gx + rad * g.ex; gy = g.fc * gy + rad * g.ey; gz = g.fc * gz + rad * g.ez;
+            f0 += gx; f1 += gy; f2 += gz;
+            const double gd[3] = {double(gx), double(gy), double(gz)}, dd[3] = {dx, dy, dz};
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) W[3 * p + q] -= dd[p] * gd[q];
+        }
+    }
+    f0 = hw_sum(f0); f1 = hw_sum(f1); f2 = hw_sum(f2);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) W[q] = hw_sum(W[q]);
+    if (lane == 0) {
+        if (x < a.n) { F[3 * x] += f0; F[3 * x + 1] += f1; F[3 * x + 2] += f2; }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sW[hw][q] = W[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double t = 0.0;
+        for (int h = 0; h < kRowsPerBlock; ++h) t += sW[h][threadIdx.x];
+        Wpart[(int64_t)blockIdx.x * 9 + threadIdx.x] = t;
+    }
+}
+
+// Neighbour role: for ext row k (local or ghost) and each in-cutoff *local* neighbour j,
+// the edge j -> k (centre j, displacement -d) gives
+//   g' = d/dd' [ f_c sum_lambda A_lambda(-d) sum_m Sbar_j[lambda][m] c_k[m] R_m(r) ]
+// which adds -g' to F_k, and f_c R_m sum_lambda Sbar_j[lambda][m] A_lambda(-d) to cbar_k[m].
+template <int L, int K, typename R, bool CBAR>
+__global__ __launch_bounds__(256) void k_adj_neighbour(EdgeArgs a, CutList cl, EdgeConsts ec,
+                                                       const R *__restrict__ c, const R *__restrict__ Sbar,
+                                                       R *__restrict__ F, R *__restrict__ cbar) {
+    constexpr int NL = n_lambda(L);
+    const int hw = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    const int64_t x = (int64_t)blockIdx.x * kRowsPerBlock + hw;
+    if (x >= a.n_ext) return;   // whole half-wave leaves together
+    R ck[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) ck[m] = c[x * K + m];
+    R f0 = R(0), f1 = R(0), f2 = R(0);
+    R cb[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) cb[m] = R(0);
+    const double xi = a.px[x], yi = a.py[x], zi = a.pz[x];
+    const R s = R(ec.ang_scale);
+    const int cnt = cl.nloc[x];
+    const int64_t lo = cl.row[x];
+    for (int e = lane; e < cnt; e += 32) {
+        const int64_t j = cl.col[lo + e];
+        const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
+        EdgeGeo<K, R> g;
+        edge_geo<K, R>(ec, dx, dy, dz, g);
+        R A[NL], dA[NL][3];
+        angular<L, R, true>(R(-ec.ang_scale * dx), R(-ec.ang_scale * dy), R(-ec.ang_scale * dz), s, A, dA);
+        const R *sbj = Sbar + j * NL * K;
+        R u[K], v[K], cacc[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m) { u[m] = ck[m] * g.Rm[m]; v[m] = ck[m] * g.dRm[m]; cacc[m] = R(0); }
+        R gx = R(0), gy = R(0), gz = R(0), sAP = R(0), sAQ = R(0);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            R P = R(0), Q = R(0);
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const R xm = r - R(ec.centres[m]);
-                const R al = R(ec.alphas[m]);
-                Rm[m] = d_exp(-al * xm * xm);
-                dRm[m] = R(-2) * al * xm * Rm[m];
+                const R w = sbj[l * K + m];
+                P += w * u[m];
+                Q += w * v[m];
+                if constexpr (CBAR) cacc[m] += w * A[l];
             }
-            const R ex = R(dx) * rinv, ey = R(dy) * rinv, ez = R(dz) * rinv;   // unit vector k -> j
-            const R ux = R(ec.ang_scale * dx), uy = R(ec.ang_scale * dy), uz = R(ec.ang_scale * dz);
-            if (loc) {   // edge x -> j, x the centre
-                R A[NL], dA[NL][3];
-                angular<L, R, true>(ux, uy, uz, s, A, dA);
-                const R *cj = c + j * K;
-                R w[K], v[K];
-#pragma unroll
-                for (int m = 0; m < K; ++m) { w[m] = cj[m] * Rm[m]; v[m] = cj[m] * dRm[m]; }
-                R g0 = R(0), g1 = R(0), g2 = R(0), sAP = R(0), sAQ = R(0);
-#pragma unroll
-                for (int l = 0; l < NL; ++l) {
-                    R P = R(0), Q = R(0);
-#pragma unroll
-                    for (int m = 0; m < K; ++m) { P += sb[l][m] * w[m]; Q += sb[l][m] * v[m]; }
-                    g0 += P * dA[l][0]; g1 += P * dA[l][1]; g2 += P * dA[l][2];
-                    sAP += A[l] * P; sAQ += A[l] * Q;
-                }
-                const R rad = dfc * sAP + fc * sAQ;
-                const R gx = fc * g0 + rad * ex, gy = fc * g1 + rad * ey, gz = fc * g2 + rad * ez;
-                f[0] += gx; f[1] += gy; f[2] += gz;
-                const double gd[3] = {double(gx), double(gy), double(gz)};
-                const double dd[3] = {dx, dy, dz};
-#pragma unroll
-                for (int p = 0; p < 3; ++p)
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) W[3 * p + q] -= dd[p] * gd[q];
-            }
-            if (jloc) {   // edge j -> x, j the centre: displacement -d
-                R A[NL], dA[NL][3];
-                angular<L, R, true>(-ux, -uy, -uz, s, A, dA);
-                const R *sbj = Sbar + j * NL * K;
-                R w[K], v[K];
-#pragma unroll
-                for (int m = 0; m < K; ++m) { w[m] = ck[m] * Rm[m]; v[m] = ck[m] * dRm[m]; }
-                R g0 = R(0), g1 = R(0), g2 = R(0), sAP = R(0), sAQ = R(0);
-                R cacc[K];
-#pragma unroll
-                for (int m = 0; m < K; ++m) cacc[m] = R(0);
-#pragma unroll
-                for (int l = 0; l < NL; ++l) {
-                    R P = R(0), Q = R(0);
-#pragma unroll
-                    for (int m = 0; m < K; ++m) {
-                        const R sv = sbj[l * K + m];
-                        P += sv * w[m];
-                        Q += sv * v[m];
-                        if constexpr (CBAR) cacc[m] += sv * A[l];
-                    }
-                    g0 += P * dA[l][0]; g1 += P * dA[l][1]; g2 += P * dA[l][2];
-                    sAP += A[l] * P; sAQ += A[l] * Q;
-                }
-                const R rad = dfc * sAP + fc * sAQ;
-                // the unit vector of this edge is -e
-                f[0] -= fc * g0 - rad * ex;
-                f[1] -= fc * g1 - rad * ey;
-                f[2] -= fc * g2 - rad * ez;
-                if constexpr (CBAR) {
-#pragma unroll
-                    for (int m = 0; m < K; ++m) cb[m] += fc * Rm[m] * cacc[m];
-                }
-            }
+            gx += P * dA[l][0]; gy += P * dA[l][1]; gz += P * dA[l][2];
+            sAP += A[l] * P; sAQ += A[l] * Q;
         }
-        F[3 * x] += f[0];
-        F[3 * x + 1] += f[1];
-        F[3 * x + 2] += f[2];
+        const R rad = g.dfc * sAP + g.fc * sAQ;
+        // unit vector of the edge j -> k is -e
+        f0 += g.fc * gx - rad * g.ex;
+        f1 += g.fc * gy - rad * g.ey;
+        f2 += g.fc * gz - rad * g.ez;
+        if constexpr (CBAR) {
+#pragma unroll
+            for (int m = 0; m < K; ++m) cb[m] += g.fc * g.Rm[m] * cacc[m];
+        }
+    }
+    f0 = hw_sum(f0); f1 = hw_sum(f1); f2 = hw_sum(f2);
+    if constexpr (CBAR) {
+#pragma unroll
+        for (int m = 0; m < K; ++m) cb[m] = hw_sum(cb[m]);
+    }
+    if (lane == 0) {
+        F[3 * x] -= f0; F[3 * x + 1] -= f1; F[3 * x + 2] -= f2;
         if constexpr (CBAR) {
 #pragma unroll
             for (int m = 0; m < K; ++m) cbar[x * K + m] = cb[m];
         }
     }
-    __shared__ double sw[9][kBwdBlock];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) sw[q][threadIdx.x] = W[q];
-    __syncthreads();
-    for (int h = kBwdBlock / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
-#pragma unroll
-            for (int q = 0; q < 9; ++q) sw[q][threadIdx.x] += sw[q][threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x < 9) Wpart[(int64_t)blockIdx.x * 9 + threadIdx.x] = sw[threadIdx.x][0];
 }
 
 #define REANN_LK_DISPATCH(L, K, CALL)                                              \
@@ -245,46 +325,56 @@ __global__ __launch_bounds__(kBwdBlock) void k_edge_bwd(EdgeArgs a, EdgeConsts e
         else fail(REANN_E_UNSUPPORTED, "no edge kernel compiled for this (L, K)"); \
     } while (0)
 
-void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const EdgeConsts &ec, const void *c,
-                  void *S) {
+void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl) {
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(a.n_ext, 256)), dim3(256), 0, st, a, r_c * r_c, cl.col, cl.nloc,
+                       cl.ngh);
+    LAUNCH_OK("k_compact");
+}
+
+void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
+                  const void *c, void *S) {
     const int B = 128;
-#define FWD(LL, KK)                                                                                        \
-    if (fp64)                                                                                              \
-        hipLaunchKernelGGL((k_edge_fwd<LL, KK, double>), dim3(grid_for(a.n, B)), dim3(B), 0, st, a, ec,    \
-                           (const double *)c, (double *)S);                                                \
-    else                                                                                                   \
-        hipLaunchKernelGGL((k_edge_fwd<LL, KK, float>), dim3(grid_for(a.n, B)), dim3(B), 0, st, a, ec,     \
+#define FWD(LL, KK)                                                                                         \
+    if (fp64)                                                                                               \
+        hipLaunchKernelGGL((k_edge_fwd<LL, KK, double>), dim3(grid_for(a.n, B)), dim3(B), 0, st, a, cl, ec, \
+                           (const double *)c, (double *)S);                                                 \
+    else                                                                                                    \
+        hipLaunchKernelGGL((k_edge_fwd<LL, KK, float>), dim3(grid_for(a.n, B)), dim3(B), 0, st, a, cl, ec,  \
                            (const float *)c, (float *)S);
     REANN_LK_DISPATCH(L, K, FWD);
 #undef FWD
     LAUNCH_OK("k_edge_fwd");
 }
 
-int edge_backward_blocks(int64_t n_ext) { return grid_for(n_ext, kBwdBlock); }
+int edge_backward_blocks(int64_t n_ext) { return grid_for(n_ext, kRowsPerBlock); }
 
-int edge_backward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const EdgeConsts &ec, const void *c,
-                  const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart) {
-    const int nb = edge_backward_blocks(a.n_ext);
-#define BWD(LL, KK)                                                                                          \
-    if (fp64) {                                                                                              \
-        if (want_cbar)                                                                                       \
-            hipLaunchKernelGGL((k_edge_bwd<LL, KK, double, true>), dim3(nb), dim3(kBwdBlock), 0, st, a, ec,  \
-                               (const double *)c, (const double *)Sbar, (double *)F, (double *)cbar, Wpart); \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_edge_bwd<LL, KK, double, false>), dim3(nb), dim3(kBwdBlock), 0, st, a, ec, \
-                               (const double *)c, (const double *)Sbar, (double *)F, (double *)cbar, Wpart); \
-    } else {                                                                                                 \
-        if (want_cbar)                                                                                       \
-            hipLaunchKernelGGL((k_edge_bwd<LL, KK, float, true>), dim3(nb), dim3(kBwdBlock), 0, st, a, ec,   \
-                               (const float *)c, (const float *)Sbar, (float *)F, (float *)cbar, Wpart);     \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_edge_bwd<LL, KK, float, false>), dim3(nb), dim3(kBwdBlock), 0, st, a, ec,  \
-                               (const float *)c, (const float *)Sbar, (float *)F, (float *)cbar, Wpart);     \
+int edge_backward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
+                  const void *c, const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart) {
+    const int nbc = grid_for(a.n, kRowsPerBlock), nbn = grid_for(a.n_ext, kRowsPerBlock);
+#define BWD(LL, KK)                                                                                              \
+    if (fp64) {                                                                                                  \
+        hipLaunchKernelGGL((k_adj_centre<LL, KK, double>), dim3(nbc), dim3(256), 0, st, a, cl, ec,               \
+                           (const double *)c, (const double *)Sbar, (double *)F, Wpart);                         \
+        if (want_cbar)                                                                                           \
+            hipLaunchKernelGGL((k_adj_neighbour<LL, KK, double, true>), dim3(nbn), dim3(256), 0, st, a, cl, ec,  \
+                               (const double *)c, (const double *)Sbar, (double *)F, (double *)cbar);            \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_adj_neighbour<LL, KK, double, false>), dim3(nbn), dim3(256), 0, st, a, cl, ec, \
+                               (const double *)c, (const double *)Sbar, (double *)F, (double *)cbar);            \
+    } else {                                                                                                     \
+        hipLaunchKernelGGL((k_adj_centre<LL, KK, float>), dim3(nbc), dim3(256), 0, st, a, cl, ec,                \
+                           (const float *)c, (const float *)Sbar, (float *)F, Wpart);                            \
+        if (want_cbar)                                                                                           \
+            hipLaunchKernelGGL((k_adj_neighbour<LL, KK, float, true>), dim3(nbn), dim3(256), 0, st, a, cl, ec,   \
+                               (const float *)c, (const float *)Sbar, (float *)F, (float *)cbar);               \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_adj_neighbour<LL, KK, float, false>), dim3(nbn), dim3(256), 0, st, a, cl, ec,  \
+                               (const float *)c, (const float *)Sbar, (float *)F, (float *)cbar);               \
     }
     REANN_LK_DISPATCH(L, K, BWD);
 #undef BWD
-    LAUNCH_OK("k_edge_bwd");
-    return nb;
+    LAUNCH_OK("k_adj");
+    return nbc;
 }
 
 // ------------------------------------------------------------- ghost exchange --

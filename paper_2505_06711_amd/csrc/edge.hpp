@@ -21,16 +21,26 @@ struct EdgeArgs {
     const double *px, *py, *pz;
 };
 
-// S[i][lambda][m] for the n local rows.  c: messages of all ext atoms, [n_ext][K].
-void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const EdgeConsts &ec, const void *c,
-                  void *S);
+// In-cutoff entries of the list for the current positions (same slot ranges as the list):
+// row x's in-cutoff local neighbours at col[row[x] .. row[x] + nloc[x]), its in-cutoff
+// ghost neighbours at col[row[x+1] - ngh[x] .. row[x+1]).
+struct CutList {
+    const int64_t *row;
+    int32_t *col;
+    int32_t *nloc, *ngh;
+};
+void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl);
 
-// Atomics-free adjoint over every ext row (locals: all neighbours; ghosts: local neighbours).
-//   Sbar [n][NL][K] (locals), c [n_ext][K]; F [n_ext][3] is accumulated (+=);
-//   cbar [n_ext][K] is overwritten when want_cbar; Wpart receives one FP64 [9] per block.
-// Returns the number of blocks (rows of Wpart).
-int edge_backward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const EdgeConsts &ec, const void *c,
-                  const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart);
+// S[i][lambda][m] for the n local rows.  c: messages of all ext atoms, [n_ext][K].
+void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
+                  const void *c, void *S);
+
+// Atomics-free adjoint (centre role over local rows, neighbour role over every ext row).
+//   Sbar [n][NL][K] (locals), c [n_ext][K]; F [n_ext][3] is accumulated;
+//   cbar [n_ext][K] is overwritten when want_cbar; Wpart receives one FP64 [9] per block
+// of the centre-role launch.  Returns the number of blocks (rows of Wpart).
+int edge_backward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
+                  const void *c, const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart);
 int edge_backward_blocks(int64_t n_ext);
 
 // c[n + g][:] = c[owner[g]][:]

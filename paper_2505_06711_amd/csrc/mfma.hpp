@@ -1,0 +1,33 @@
+// Matrix-core (MFMA) dense layers for the hidden layers of the atomic NNs and their
+// vector-Jacobian products: C[rows x out] = A[rows x in] * Wt^T with FP32 accumulation.
+// Operands are FP32, bfloat16 or OCP FP8 e4m3 (per-tensor scales); A is FP32 in memory and
+// is rounded to the operand type while it is staged to LDS.
+#pragma once
+
+#include "mlp.hpp"
+
+namespace reann {
+
+enum class OpType { F32 = 0, BF16 = 1, FP8 = 2 };
+
+constexpr int kMfmaKC = 32;   // K chunk staged per iteration; weight rows are padded to it
+
+inline int pad_k(int in) { return (in + kMfmaKC - 1) / kMfmaKC * kMfmaKC; }
+
+// Wt: operand-typed [out][ldw] (ldw = pad_k(in), zero padded).  FP8 only: sA / sW are the
+// device scales of A (amax/448, see amax_scale) and of Wt; the product is rescaled by both.
+void gemm_mfma(hipStream_t st, OpType op, Epi epi, int64_t rows, int in, int out, const float *A, int lda,
+               const void *Wt, int ldw, const float *bias, float *Z, int ldz, float *C, int ldc, const float *sA,
+               const float *sW);
+
+// *d_scale = max(|A|) / 448 over rows x cols (row stride lda), or 1 if A is all zero.
+void amax_scale(hipStream_t st, const float *A, int64_t rows, int cols, int lda, float *d_scale, uint32_t *d_tmp);
+
+// Convert FP32 [rows][cols] (row stride ld_src) into operand type [rows][ld_dst] (zero padded);
+// for FP8 the values are divided by *scale first.
+void convert_operand(hipStream_t st, OpType op, const float *src, int rows, int cols, int ld_src, void *dst,
+                     int ld_dst, const float *scale);
+
+inline size_t op_bytes(OpType op) { return op == OpType::F32 ? 4 : (op == OpType::BF16 ? 2 : 1); }
+
+}  // namespace reann

@@ -5,6 +5,8 @@
 // Atomic NN (Eq. (2)): hidden layers Linear + SiLU, linear output, one NN per element.
 #include "mlp.hpp"
 
+#include <type_traits>
+
 namespace reann {
 
 __device__ inline float d_expm(float x) { return expf(x); }
@@ -18,61 +20,112 @@ template <typename R> __device__ inline R dsilu(R z) {
 
 // ------------------------------------------------------------------ density --
 
-// one thread per (i, l, a): writes rho[l, (a, b)] for b = a..K-1
-template <typename R>
-__global__ void k_density(int64_t n, int L, int K, DensityConsts dc, const R *__restrict__ S, R *__restrict__ rho) {
+// one thread per (atom i, angular order l): the K(K+1)/2 pair features of that l
+template <typename R, int K>
+__global__ void k_density(int64_t n, int L, DensityConsts dc, const R *__restrict__ S, R *__restrict__ rho) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int per = (L + 1) * K;
-    if (t >= n * per) return;
-    const int64_t i = t / per;
-    const int la = (int)(t % per), l = la / K, a = la % K;
+    if (t >= n * (L + 1)) return;
+    const int64_t i = t / (L + 1);
+    const int l = (int)(t % (L + 1));
     const int NL = dc.lstart[L + 1], P = K * (K + 1) / 2, F = (L + 1) * P;
+    const int k0 = dc.lstart[l], k1 = dc.lstart[l + 1];
     const R *Si = S + i * NL * K;
-    R *out = rho + i * F + l * P + a * K - a * (a - 1) / 2;
-    for (int b = a; b < K; ++b) {
-        R s = R(0);
-        for (int k = dc.lstart[l]; k < dc.lstart[l + 1]; ++k) s += R(dc.w[k]) * Si[k * K + a] * Si[k * K + b];
-        out[b - a] = s;
+    R *out = rho + i * F + l * P;
+    // at most 6 Cartesian components share one l when L <= 2 (the dispatcher enforces L <= 2);
+    // unused slots hold zero so every index below is static
+    R v[6][K];
+    const int nk = k1 - k0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const R wq = q < nk ? R(dc.w[k0 + q]) : R(0);
+#pragma unroll
+        for (int m = 0; m < K; ++m) v[q][m] = q < nk ? wq * Si[(k0 + q) * K + m] : R(0);
+    }
+    int f = 0;
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+        for (int b = a; b < K; ++b) {
+            R s = R(0);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s += v[q][a] * (q < nk ? Si[(k0 + q) * K + b] : R(0));
+            out[f++] = s;
+        }
+}
+
+// one thread per (atom i, l): Sbar[lambda][a] = w_lambda sum_b coef(a,b) S[lambda][b] for
+// lambda of order l, with coef the symmetric matrix of rhobar[l] (doubled on the diagonal)
+template <typename R, int K>
+__global__ void k_density_vjp(int64_t n, int L, DensityConsts dc, const R *__restrict__ S, const R *__restrict__ rb,
+                              R *__restrict__ Sbar) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * (L + 1)) return;
+    const int64_t i = t / (L + 1);
+    const int l = (int)(t % (L + 1));
+    const int NL = dc.lstart[L + 1], P = K * (K + 1) / 2, F = (L + 1) * P;
+    const int k0 = dc.lstart[l], k1 = dc.lstart[l + 1];
+    R C[K][K];
+    const R *rbi = rb + i * F + l * P;
+    int f = 0;
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+        for (int b = a; b < K; ++b) {
+            const R v = rbi[f++];
+            C[a][b] = a == b ? R(2) * v : v;
+            C[b][a] = C[a][b];
+        }
+    for (int k = k0; k < k1; ++k) {
+        const R *Sk = S + i * NL * K + k * K;
+        R sv[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m) sv[m] = Sk[m];
+        R *out = Sbar + i * NL * K + k * K;
+        const R w = R(dc.w[k]);
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            R s = R(0);
+#pragma unroll
+            for (int b = 0; b < K; ++b) s += C[a][b] * sv[b];
+            out[a] = w * s;
+        }
     }
 }
 
-// one thread per (i, lambda, a)
-template <typename R>
-__global__ void k_density_vjp(int64_t n, int L, int K, DensityConsts dc, const R *__restrict__ S,
-                              const R *__restrict__ rb, R *__restrict__ Sbar) {
-    const int NL = dc.lstart[L + 1];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * NL * K) return;
-    const int64_t i = t / (NL * K);
-    const int k = (int)((t / K) % NL), a = (int)(t % K);
-    int l = 0;
-    while (dc.lstart[l + 1] <= k) ++l;
-    const int P = K * (K + 1) / 2, F = (L + 1) * P;
-    const R *Si = S + i * NL * K + k * K;
-    const R *rbi = rb + i * F + l * P;
-    R s = R(0);
-    for (int b = 0; b < K; ++b) {
-        const int lo = a < b ? a : b, hi = a < b ? b : a;
-        const R coef = rbi[lo * K - lo * (lo - 1) / 2 + (hi - lo)];
-        s += (a == b ? R(2) : R(1)) * coef * Si[b];
-    }
-    Sbar[t] = R(dc.w[k]) * s;
-}
+#define REANN_K_DISPATCH(K, CALL)                                                      \
+    do {                                                                               \
+        if ((K) == 8) { CALL(8); }                                                     \
+        else if ((K) == 12) { CALL(12); }                                              \
+        else if ((K) == 4) { CALL(4); }                                                \
+        else fail(REANN_E_UNSUPPORTED, "no density kernel compiled for this K");       \
+    } while (0)
 
 void density(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S, void *rho) {
-    const int64_t tot = n * (L + 1) * K;
+    const int64_t tot = n * (L + 1);
     if (tot == 0) return;
-    if (fp64) hipLaunchKernelGGL(k_density<double>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const double *)S, (double *)rho);
-    else hipLaunchKernelGGL(k_density<float>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const float *)S, (float *)rho);
+    if (L > 2) fail(REANN_E_UNSUPPORTED, "density kernel supports L <= 2");
+#define DEN(KK)                                                                                                   \
+    if (fp64) hipLaunchKernelGGL((k_density<double, KK>), dim3(grid_for(tot, 128)), dim3(128), 0, st, n, L, dc,  \
+                                 (const double *)S, (double *)rho);                                              \
+    else hipLaunchKernelGGL((k_density<float, KK>), dim3(grid_for(tot, 128)), dim3(128), 0, st, n, L, dc,        \
+                            (const float *)S, (float *)rho);
+    REANN_K_DISPATCH(K, DEN);
+#undef DEN
     LAUNCH_OK("k_density");
 }
 
 void density_vjp(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S,
                  const void *rhobar, void *Sbar) {
-    const int64_t tot = n * dc.lstart[L + 1] * K;
+    const int64_t tot = n * (L + 1);
     if (tot == 0) return;
-    if (fp64) hipLaunchKernelGGL(k_density_vjp<double>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const double *)S, (const double *)rhobar, (double *)Sbar);
-    else hipLaunchKernelGGL(k_density_vjp<float>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const float *)S, (const float *)rhobar, (float *)Sbar);
+    if (L > 2) fail(REANN_E_UNSUPPORTED, "density kernel supports L <= 2");
+#define DVJ(KK)                                                                                                     \
+    if (fp64) hipLaunchKernelGGL((k_density_vjp<double, KK>), dim3(grid_for(tot, 128)), dim3(128), 0, st, n, L, dc, \
+                                 (const double *)S, (const double *)rhobar, (double *)Sbar);                        \
+    else hipLaunchKernelGGL((k_density_vjp<float, KK>), dim3(grid_for(tot, 128)), dim3(128), 0, st, n, L, dc,       \
+                            (const float *)S, (const float *)rhobar, (float *)Sbar);
+    REANN_K_DISPATCH(K, DVJ);
+#undef DVJ
     LAUNCH_OK("k_density_vjp");
 }
 
@@ -86,14 +139,17 @@ __global__ __launch_bounds__(256) void k_dense(int64_t rows, int in, int out, co
                                                int ldz, R *__restrict__ C, int ldc) {
     __shared__ R As[TK][TM + 1];
     __shared__ R Ws[TK][TN + 1];
+    // output layers (EPI_BIAS) accumulate in FP64: their few outputs per row are sums of
+    // large terms with cancellation, and the cost is negligible
+    using Acc = typename std::conditional<EPI == EPI_BIAS, double, R>::type;
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int64_t r0 = (int64_t)blockIdx.x * TM;
     const int o0 = blockIdx.y * TN;
-    R acc[4][4];
+    Acc acc[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = R(0);
+        for (int q = 0; q < 4; ++q) acc[p][q] = Acc(0);
     for (int k0 = 0; k0 < in; k0 += TK) {
         for (int e = threadIdx.x; e < TM * TK; e += 256) {
             const int rr = e / TK, kk = e % TK;
@@ -121,7 +177,7 @@ __global__ __launch_bounds__(256) void k_dense(int64_t rows, int in, int out, co
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * w[q];
+                for (int q = 0; q < 4; ++q) acc[p][q] += Acc(a[p]) * Acc(w[q]);
         }
         __syncthreads();
     }
@@ -133,13 +189,13 @@ __global__ __launch_bounds__(256) void k_dense(int64_t rows, int in, int out, co
         for (int q = 0; q < 4; ++q) {
             const int o = o0 + tx + 16 * q;
             if (o >= out) continue;
-            R v = acc[p][q];
+            R v = R(acc[p][q]);
             if (EPI == EPI_BIAS_SILU) {
                 v += bias[o];
                 Z[r * ldz + o] = v;
                 v = silu(v);
             } else if (EPI == EPI_BIAS) {
-                v += bias[o];
+                v = R(acc[p][q] + Acc(bias[o]));
             } else if (EPI == EPI_DSILU) {
                 v *= dsilu(Z[r * ldz + o]);
             }

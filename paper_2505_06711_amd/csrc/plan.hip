@@ -9,6 +9,7 @@
 // the edge adjoint adds forces and virial and, for t >= 1, the message adjoints cbar^t of
 // every ext atom, which are summed onto their owners (the reverse exchange) and pulled
 // through the message NN of layer t-1 to give Sbar^{t-1}.  dc^0/dr = 0 ends the sweep.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -63,6 +64,61 @@ DeviceWeights &Model::weights(int device, hipStream_t st) {
     return ref;
 }
 
+const MfmaSet &Model::mfma(int device, hipStream_t st, bool energy, OpType op) {
+    DeviceWeights &w = weights(device, st);
+    std::lock_guard<std::mutex> lk(mu);
+    auto &slot = w.mf[energy ? 1 : 0][(int)op];
+    if (slot) return *slot;
+    auto set = std::make_unique<MfmaSet>();
+    const NNLayout &lay = energy ? en_nn : msg_nn;
+    const std::vector<double> &blob = energy ? en : msg;
+    const int count = energy ? n_species : (T_max - 1) * n_species;
+    // host: padded FP32 copies of every matrix, then one device conversion per matrix
+    std::vector<float> host;
+    std::vector<size_t> foff;          // float offset of each padded matrix in `host`
+    std::vector<int> rows_, cols_, lds_;
+    std::vector<float> scales;
+    for (int q = 0; q < count; ++q)
+        for (int k = 0; k < nh; ++k) {
+            const double *W = blob.data() + (size_t)q * lay.size + lay.w_off[k];
+            const int dout = lay.dout[k], din = lay.din[k];
+            for (int dir = 0; dir < 2; ++dir) {
+                const int r = dir == 0 ? dout : din, cdim = dir == 0 ? din : dout, ld = pad_k(cdim);
+                foff.push_back(host.size());
+                rows_.push_back(r); cols_.push_back(cdim); lds_.push_back(ld);
+                double amax = 0;
+                for (int a = 0; a < r; ++a)
+                    for (int b = 0; b < ld; ++b) {
+                        double v = 0;
+                        if (b < cdim) v = dir == 0 ? W[(size_t)a * din + b] : W[(size_t)b * din + a];
+                        host.push_back((float)v);
+                        amax = std::max(amax, std::fabs(v));
+                    }
+                scales.push_back(op == OpType::FP8 ? (amax > 0 ? (float)(amax / 448.0) : 1.0f) : 1.0f);
+                const int idx = (int)scales.size() - 1;
+                if (dir == 0) { set->sc_fwd.push_back(idx); set->ld_fwd.push_back(ld); }
+                else { set->sc_bwd.push_back(idx); set->ld_bwd.push_back(ld); }
+            }
+        }
+    DevBuf tmp;
+    tmp.ensure(std::max<size_t>(host.size(), 1) * 4);
+    if (!host.empty()) HIP_OK(hipMemcpyAsync(tmp.p, host.data(), host.size() * 4, hipMemcpyHostToDevice, st));
+    set->scales.ensure(std::max<size_t>(scales.size(), 1) * 4);
+    if (!scales.empty()) HIP_OK(hipMemcpyAsync(set->scales.p, scales.data(), scales.size() * 4, hipMemcpyHostToDevice, st));
+    const size_t eb = op_bytes(op);
+    set->buf.ensure(std::max<size_t>(host.size(), 1) * eb);
+    for (size_t i = 0; i < foff.size(); ++i) {
+        const size_t ob = foff[i] * eb;
+        convert_operand(st, op, tmp.as<float>() + foff[i], rows_[i], cols_[i], lds_[i], set->buf.as<char>() + ob,
+                        lds_[i], set->scales.as<float>() + i);
+        if (i % 2 == 0) set->off_fwd.push_back(ob);
+        else set->off_bwd.push_back(ob);
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    slot = std::move(set);
+    return *slot;
+}
+
 EdgeConsts Model::edge_consts() const {
     EdgeConsts e{};
     for (int m = 0; m < K; ++m) { e.centres[m] = centres[m]; e.alphas[m] = alphas[m]; }
@@ -103,9 +159,10 @@ void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const doubl
     if (TT < 1 || TT > m->T_max) fail(REANN_E_INVALID, "T must be in [1, T_max]");
     T = TT;
     prec = opt ? opt->precision : REANN_FP32;
-    if (prec != REANN_FP64 && prec != REANN_FP32)
-        fail(REANN_E_UNSUPPORTED, "precision not available in this build");
+    if (prec != REANN_FP64 && prec != REANN_FP32 && prec != REANN_BF16 && prec != REANN_FP8)
+        fail(REANN_E_INVALID, "unknown precision");
     fp64 = prec == REANN_FP64;
+    op = prec == REANN_BF16 ? OpType::BF16 : (prec == REANN_FP8 ? OpType::FP8 : OpType::F32);
     rs = fp64 ? 8 : 4;
     skin = opt ? opt->skin : 0.0;
     if (!(skin >= 0.0) || !std::isfinite(skin)) fail(REANN_E_INVALID, "skin must be >= 0");
@@ -122,6 +179,12 @@ void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const doubl
     HIP_OK(hipMemcpyAsync(ds, species.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_OK(hipStreamSynchronize(st));
     m->weights(ctx->device, st);
+    if (!fp64) {
+        m->mfma(ctx->device, st, false, op);
+        m->mfma(ctx->device, st, true, op);
+    }
+    fp8s.ensure(16);
+    fp8tmp.ensure(16);
 }
 
 bool Plan::same_system(const Model *mm, const int32_t *spec, int64_t nn, const double cell_[9], const int32_t pbc_[3],
@@ -194,6 +257,9 @@ void Plan::alloc_buffers() {
     Wpart.ensure((size_t)(edge_backward_blocks(ne) + 1) * 9 * 8);
     Wacc.ensure(16 * 8);
     disp.ensure(1025 * 8);
+    col2.ensure((size_t)(nl.n_pairs + 1) * 4);
+    nloc.ensure((size_t)(ne + 1) * 4);
+    ngh.ensure((size_t)(ne + 1) * 4);
 }
 
 void Plan::ensure_list(const double *d_pos, hipStream_t st) {
@@ -227,11 +293,21 @@ void Plan::nn_forward(hipStream_t st, int t, bool energy) {
         const char *p = blob + (size_t)nn_index * lay.size * rs;
         const char *A = rhoptr(t) + (size_t)a * F * rs;
         int lda = F;
+        const MfmaSet *mf = fp64 ? nullptr : &m->mfma(ctx->device, st, energy, op);
         for (int k = 0; k < nh; ++k) {
             char *Zk = Zptr(t, k) + (size_t)a * H * rs;
             char *Hk = Hptr(t, k) + (size_t)a * H * rs;
-            dense(st, fp64, EPI_BIAS_SILU, true, rows, lay.din[k], H, A, lda, p + lay.w_off[k] * rs,
-                  p + lay.b_off[k] * rs, Zk, H, Hk, H);
+            if (fp64) {
+                dense(st, fp64, EPI_BIAS_SILU, true, rows, lay.din[k], H, A, lda, p + lay.w_off[k] * rs,
+                      p + lay.b_off[k] * rs, Zk, H, Hk, H);
+            } else {
+                const size_t qi = (size_t)nn_index * nh + k;
+                if (op == OpType::FP8)
+                    amax_scale(st, (const float *)A, rows, lay.din[k], lda, fp8s.as<float>(), fp8tmp.as<uint32_t>());
+                gemm_mfma(st, op, EPI_BIAS_SILU, rows, lay.din[k], H, (const float *)A, lda,
+                          mf->buf.as<char>() + mf->off_fwd[qi], mf->ld_fwd[qi], (const float *)(p + lay.b_off[k] * rs),
+                          (float *)Zk, H, (float *)Hk, H, fp8s.as<float>(), mf->scales.as<float>() + mf->sc_fwd[qi]);
+            }
             A = Hk;
             lda = H;
         }
@@ -260,18 +336,37 @@ void Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg)
         int ldin = ldg;
         char *bufs[2] = {gA.as<char>(), gB.as<char>()};
         int cur = 0;
+        const MfmaSet *mf = fp64 ? nullptr : &m->mfma(ctx->device, st, energy, op);
         for (int k = nh; k >= 1; --k) {
             char *dst = bufs[cur] + (size_t)a * H * rs;
             const char *Zk = Zptr(t, k - 1) + (size_t)a * H * rs;
-            dense(st, fp64, EPI_DSILU, false, rows, lay.dout[k], lay.din[k], gin, ldin, p + lay.w_off[k] * rs,
-                  nullptr, (void *)Zk, H, dst, H);
+            if (fp64 || k == nh) {   // the output layer's adjoint has few inputs: VALU kernel
+                dense(st, fp64, EPI_DSILU, false, rows, lay.dout[k], lay.din[k], gin, ldin, p + lay.w_off[k] * rs,
+                      nullptr, (void *)Zk, H, dst, H);
+            } else {
+                const size_t qi = (size_t)nn_index * nh + k;
+                if (op == OpType::FP8)
+                    amax_scale(st, (const float *)gin, rows, lay.dout[k], ldin, fp8s.as<float>(), fp8tmp.as<uint32_t>());
+                gemm_mfma(st, op, EPI_DSILU, rows, lay.dout[k], lay.din[k], (const float *)gin, ldin,
+                          mf->buf.as<char>() + mf->off_bwd[qi], mf->ld_bwd[qi], nullptr, (float *)Zk, H, (float *)dst, H,
+                          fp8s.as<float>(), mf->scales.as<float>() + mf->sc_bwd[qi]);
+            }
             gin = dst;
             ldin = H;
             cur ^= 1;
         }
         char *rb = rhobar.as<char>() + (size_t)a * F * rs;
-        dense(st, fp64, EPI_NONE, false, rows, lay.dout[0], F, gin, ldin, p + lay.w_off[0] * rs, nullptr, nullptr, 0,
-              rb, F);
+        if (fp64) {
+            dense(st, fp64, EPI_NONE, false, rows, lay.dout[0], F, gin, ldin, p + lay.w_off[0] * rs, nullptr, nullptr, 0,
+                  rb, F);
+        } else {
+            const size_t qi = (size_t)nn_index * nh;
+            if (op == OpType::FP8)
+                amax_scale(st, (const float *)gin, rows, lay.dout[0], ldin, fp8s.as<float>(), fp8tmp.as<uint32_t>());
+            gemm_mfma(st, op, EPI_NONE, rows, lay.dout[0], F, (const float *)gin, ldin, mf->buf.as<char>() + mf->off_bwd[qi],
+                      mf->ld_bwd[qi], nullptr, nullptr, 0, (float *)rb, F, fp8s.as<float>(),
+                      mf->scales.as<float>() + mf->sc_bwd[qi]);
+        }
     }
     density_vjp(st, fp64, m->L, m->K, n, m->density_consts(), Sptr(t), rhobar.p, Sbar.p);
 }
@@ -286,11 +381,13 @@ void Plan::forward(const double *d_pos, double *d_energy, double *d_atom_energy,
     refresh_positions(st, nl, d_pos, px.as<double>(), py.as<double>(), pz.as<double>());
     init_messages(st, fp64, nl.n_ext, K, nl.spec_ext.ptr(), fp64 ? w.c064.p : w.c032.p, cptr(0));
     EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), px.as<double>(), py.as<double>(), pz.as<double>()};
+    CutList cl = cutlist();
+    compact_cutoff(st, ea, m->r_c, cl);
     const EdgeConsts ec = m->edge_consts();
     const DensityConsts dc = m->density_consts();
     mark(st, 6);
     for (int t = 0; t < T; ++t) {
-        edge_forward(st, fp64, m->L, K, ea, ec, cptr(t), Sptr(t));
+        edge_forward(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sptr(t));
         mark(st, 1, 1);
         density(st, fp64, m->L, K, n, dc, Sptr(t), rhoptr(t));
         if (t < T - 1) {
@@ -312,6 +409,7 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     if (!have_forward) fail(REANN_E_STATE, "backward called before forward");
     const int K = m->K;
     EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), px.as<double>(), py.as<double>(), pz.as<double>()};
+    const CutList cl = cutlist();
     const EdgeConsts ec = m->edge_consts();
     mark(st, -1);
     fill_energy_seed(st, fp64, n, m->energy_scale, d_g, ybar.p);
@@ -321,7 +419,7 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     zero(st, Wacc.p, 9 * 8);
     mark(st, 6);
     for (int t = T - 1; t >= 0; --t) {
-        const int nb = edge_backward(st, fp64, m->L, K, ea, ec, cptr(t), Sbar.p, t > 0, this->F.p, cbar.p,
+        const int nb = edge_backward(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sbar.p, t > 0, this->F.p, cbar.p,
                                      Wpart.as<double>());
         sum_rows(st, Wpart.as<double>(), nb, 9, Wacc.as<double>(), true);
         mark(st, 5, 1);

@@ -7,6 +7,7 @@
 #include <mutex>
 
 #include "edge.hpp"
+#include "mfma.hpp"
 #include "mlp.hpp"
 #include "nlist.hpp"
 
@@ -24,8 +25,19 @@ struct NNLayout {
 };
 NNLayout nn_layout(int F, int H, int nh, int out);
 
+// Matrix-core operands of the hidden layers of every atomic NN: for NN q and hidden layer k,
+// the forward operand W_k [dout][pad(din)] and the backward operand W_k^T [din][pad(dout)],
+// in one operand type, with one scale per matrix (FP8: amax/448; otherwise 1).
+struct MfmaSet {
+    DevBuf buf, scales;
+    std::vector<size_t> off_fwd, off_bwd;   // bytes, index q * nh + k
+    std::vector<int> ld_fwd, ld_bwd;
+    std::vector<int> sc_fwd, sc_bwd;        // index into scales
+};
+
 struct DeviceWeights {
     DevBuf msg64, en64, c064, msg32, en32, c032;
+    std::unique_ptr<MfmaSet> mf[2][3];      // [msg, energy][OpType]
 };
 
 struct Model {
@@ -37,6 +49,8 @@ struct Model {
     std::map<int, std::unique_ptr<DeviceWeights>> dev;
     // device copy of the weights for `device` (created on first use)
     DeviceWeights &weights(int device, hipStream_t st);
+    // matrix-core operands of the message (energy = false) or energy NNs for `op`
+    const MfmaSet &mfma(int device, hipStream_t st, bool energy, OpType op);
     EdgeConsts edge_consts() const;
     DensityConsts density_consts() const;
 };
@@ -45,6 +59,10 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // plans and neighbour lists created on this context; reann_ctx_free defers the release
+    // until the last of them is freed
+    int users = 0;
+    bool released = false;
     std::unique_ptr<struct Plan> cached;   // plan of the last host-API system
     const Model *cached_model = nullptr;
     DevBuf pos, forces, scal;
@@ -69,6 +87,9 @@ struct Plan {
     int64_t rebuilds = 0;
     // layer buffers
     DevBuf px, py, pz, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, Wacc, disp, one;
+    DevBuf col2, nloc, ngh;   // in-cutoff compaction of the list for the current step
+    DevBuf fp8s, fp8tmp;      // per-call activation scale for FP8 products
+    OpType op = OpType::F32;
     bool have_forward = false;
     bool timing = false;
     // events recorded at phase boundaries while timing is on; intervals are attributed to
@@ -101,10 +122,15 @@ struct Plan {
     void nn_forward(hipStream_t st, int t, bool energy);
     void nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg);
     void mark(hipStream_t st, int phase, int nlaunch = 0);
+    CutList cutlist() { return CutList{nl.row.ptr(), col2.as<int32_t>(), nloc.as<int32_t>(), ngh.as<int32_t>()}; }
 };
 
 }  // namespace reann
 
 struct reann_model { reann::Model impl; };
 struct reann_ctx { reann::Ctx impl; };
+namespace reann {
+void ctx_acquire(Ctx *c);
+void ctx_release(Ctx *c);   // frees the context once released and unused
+}
 struct reann_plan { reann::Plan impl; };
