@@ -79,6 +79,94 @@ def cpu_baseline(workload_name, T, max_seconds=30.0):
                 seconds=round(dt, 3))
 
 
+def serve_bench(rn, seconds=6.0, n_systems=256, seed=0):
+    """Serving: Poisson stream of 1 fs velocity-Verlet requests over independent systems
+    (sizes log-uniform 64-20,000 atoms, half water boxes, half FCC crystals), r_c = 5 A,
+    T = 3, BF16 atomic NNs.  Closed loop first (every system always has one request in
+    flight) for the saturation rate, then open-loop Poisson arrivals at 0.5, 0.8 and 0.95 of
+    it; latency is submit -> result ready (library clock)."""
+    import synth
+    m = synth.models.serving_model(T_max=3, seed=seed)
+    model = rn.Model(m)
+    srv = rn.Server(model, T=3, precision="bf16", skin=1.0, use_graph=True)
+    srv.set_masses([synth.systems.MASS_AMU[e] for e in m.elements])
+    mix = synth.systems.serving_mix(n_systems, seed=seed, elements=m.elements)
+    ids, sizes = [], []
+    for k, s in enumerate(mix):
+        v = synth.systems.maxwell_boltzmann(s["species"], m.elements, 300.0, seed=seed + k)
+        ids.append(srv.add_system(s, v))
+        sizes.append(len(s["pos"]))
+    sizes = dict(zip(ids, sizes))
+    rng = np.random.default_rng(seed)
+
+    def drain(inflight, lat, done_atoms):
+        for sid, (t, t_arr) in list(inflight.items()):
+            r = srv.poll(t, sid, forces=False)
+            if r is not None:
+                del inflight[sid]
+                lat.append(r["latency_s"] if t_arr is None else time.perf_counter() - t_arr)
+                done_atoms[0] += sizes[sid]
+
+    # warm-up: residency, first neighbour lists, graph capture
+    inflight = {sid: (srv.submit_vv(sid, 1.0), None) for sid in ids}
+    lat, done = [], [0]
+    t0 = time.perf_counter()
+    while inflight:
+        drain(inflight, lat, done)
+    warm = time.perf_counter() - t0
+    # closed loop
+    lat, done = [], [0]
+    inflight = {sid: (srv.submit_vv(sid, 1.0), None) for sid in ids}
+    t0 = time.perf_counter()
+    nreq = 0
+    while time.perf_counter() - t0 < seconds:
+        before = set(inflight)
+        drain(inflight, lat, done)
+        for sid in before - set(inflight):
+            inflight[sid] = (srv.submit_vv(sid, 1.0), None)
+            nreq += 1
+    el = time.perf_counter() - t0
+    while inflight:
+        drain(inflight, [], [0])
+    sat_atoms = done[0] / el
+    sat_rate = len(lat) / el
+    out = dict(systems=n_systems, atoms_resident=int(sum(sizes.values())), warmup_s=round(warm, 2),
+               saturation=dict(atom_steps_per_s=round(sat_atoms, 1), requests_per_s=round(sat_rate, 1),
+                               p50_ms=round(1e3 * float(np.percentile(lat, 50)), 3),
+                               p99_ms=round(1e3 * float(np.percentile(lat, 99)), 3)))
+    levels = []
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * sat_rate
+        lat, done = [], [0]
+        inflight, waiting = {}, {}
+        t_next = time.perf_counter()
+        t0 = t_next
+        while time.perf_counter() - t0 < seconds:
+            now = time.perf_counter()
+            while t_next <= now:      # arrivals: a random system; queue if it is busy
+                sid = ids[int(rng.integers(len(ids)))]
+                waiting.setdefault(sid, []).append(t_next)
+                t_next += rng.exponential(1.0 / rate)
+            drain(inflight, lat, done)
+            for sid in list(waiting):
+                if sid not in inflight:
+                    t_arr = waiting[sid].pop(0)
+                    if not waiting[sid]:
+                        del waiting[sid]
+                    inflight[sid] = (srv.submit_vv(sid, 1.0), t_arr)
+        el = time.perf_counter() - t0
+        while inflight:
+            drain(inflight, [], [0])
+        levels.append(dict(load=frac, offered_requests_per_s=round(rate, 1), atom_steps_per_s=round(done[0] / el, 1),
+                           p50_ms=round(1e3 * float(np.percentile(lat, 50)), 3) if lat else None,
+                           p99_ms=round(1e3 * float(np.percentile(lat, 99)), 3) if lat else None,
+                           completed=len(lat)))
+    out["open_loop"] = levels
+    out["stats"] = srv.stats()
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +176,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16", "fp8"])
     ap.add_argument("--T", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the subdomain exchange is "
@@ -187,7 +277,11 @@ def main():
                            first_step_s=round(t_build, 3), wall_s=round(wall, 3)),
                phase_ms_per_step={k: round(v, 4) for k, v in ms.items()},
                roofline=roof)
+    if not a.no_serve:
+        print("bench: serving", file=sys.stderr, flush=True)
+        out["serve"] = serve_bench(rn, seconds=a.serve_seconds)
     if not a.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.workload, T)
     print(json.dumps(out), flush=True)
 

@@ -191,7 +191,13 @@ reann_status reann_plan_timing(reann_plan *p, double *ms7, int64_t *launches7, i
 /* ---------------------------------------------------------------- serving --
  * Continuous-batching server: many independent systems stay resident on the device
  * (positions, velocities, neighbour lists, features); requests that arrive while others
- * run are admitted as batch slots and HBM budget free up.
+ * run are admitted as batch slots and HBM budget free up.  Up to 8 requests are in flight at
+ * once, each on its own stream, so steps of different systems overlap on the device; one
+ * request per system is in flight at a time (a velocity-Verlet step needs the previous
+ * forces).  When the budget is exhausted, idle resident systems are evicted (least recently
+ * used first, their state copied back to the host), else the request waits.  A step replays
+ * a captured HIP graph while the neighbour list is unchanged.  Results do not depend on which
+ * other requests are in flight.
  *   hbm_budget_bytes  device memory the resident systems may use (0 = 3/4 of free memory);
  *                     reann_system_add returns REANN_E_CAPACITY for a system that can never fit.
  *   max_batch_atoms   atoms evaluated together in one batched step (0 = 262144).
@@ -235,8 +241,9 @@ reann_status reann_submit(reann_server *s, const reann_request *req, uint64_t *t
 /* Non-blocking: REANN_PENDING while running, REANN_OK when res is filled (the ticket is then
    released), or a negative status. */
 reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res);
-/* Statistics: [0] batches run, [1] requests completed, [2] atoms evaluated, [3] graph replays,
-   [4] admissions deferred for HBM budget, [5] resident bytes. */
+/* Statistics: [0] engine rounds that admitted at least one request, [1] requests completed,
+   [2] atoms evaluated, [3] HIP-graph replays, [4] admissions deferred for the HBM budget,
+   [5] device bytes held by resident systems. */
 reann_status reann_server_stats(reann_server *s, int64_t *stats6);
 void reann_server_destroy(reann_server *s);
 

@@ -5,6 +5,6 @@ in include/reann.h); this package only marshals arguments.  See ``_binding`` for
 host- and device-pointer entry points and ``autograd`` for the torch wrapper.
 """
 from ._binding import (BF16, FP8, FP32, FP64, Context, Model, NeighborList, Plan, ReannError,  # noqa: F401
-                       build_neighbors, energy_forces, load)
+                       Server, build_neighbors, energy_forces, load)
 
 load()   # fail loudly at import when the library has not been built

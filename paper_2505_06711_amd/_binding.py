@@ -344,3 +344,89 @@ def _require_device_f64(t, shape):
         raise ValueError("expected a contiguous float64 device tensor")
     if tuple(t.shape) != tuple(shape):
         raise ValueError("expected shape %s, got %s" % (tuple(shape), tuple(t.shape)))
+
+
+class Server:
+    """Continuous-batching server (``reann_server``): systems stay resident on the device,
+    requests are admitted as slots and HBM budget free up (see include/reann.h)."""
+
+    def __init__(self, model: Model, T: int, precision="bf16", skin: float = 1.0, hbm_budget_bytes: int = 0,
+                 max_batch_atoms: int = 0, use_graph: bool = True, device: int = 0):
+        lib = load()
+        o = _ServerOpts()
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.max_batch_atoms = int(max_batch_atoms)
+        o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        o.T = int(T)
+        o.skin = float(skin)
+        o.use_graph = int(bool(use_graph))
+        o.device = int(device)
+        h = _vp()
+        check(lib.reann_server_create(model.handle, C.byref(o), C.byref(h)))
+        self.handle = h
+        self.model = model
+        self.n_atoms = {}
+        _LIVE["server"].add(self)
+
+    def set_masses(self, masses_amu):
+        m = _f64(masses_amu)
+        check(load().reann_server_set_masses(self.handle, _p(m)))
+
+    def add_system(self, system: dict, vel=None) -> int:
+        pos = _f64(system["pos"])
+        spec = _i32a(system["species"])
+        cell = _f64(system["cell"], (9,))
+        pbc = _i32a(system["pbc"])
+        v = None if vel is None else _f64(vel)
+        sid = C.c_uint64()
+        check(load().reann_system_add(self.handle, _p(spec), pos.shape[0], _p(cell), _p(pbc), _p(pos), _p(v),
+                                      C.byref(sid)))
+        self.n_atoms[sid.value] = pos.shape[0]
+        return sid.value
+
+    def _submit(self, sys_id, kind, dt=0.0, pos=None) -> int:
+        r = _Request()
+        r.sys_id = int(sys_id)
+        r.kind = int(kind)
+        r.dt_fs = float(dt)
+        keep = None
+        if pos is not None:
+            keep = _f64(pos)
+            r.pos = keep.ctypes.data
+        t = C.c_uint64()
+        check(load().reann_submit(self.handle, C.byref(r), C.byref(t)))
+        return t.value
+
+    def submit_eval(self, sys_id: int, pos) -> int:
+        return self._submit(sys_id, REQ_EVAL, pos=pos)
+
+    def submit_vv(self, sys_id: int, dt_fs: float) -> int:
+        return self._submit(sys_id, REQ_VV_STEP, dt=dt_fs)
+
+    def poll(self, ticket: int, sys_id: int, forces: bool = True, positions: bool = False):
+        """None while pending; else a dict with energy, virial, forces, positions, latency_s."""
+        n = self.n_atoms[sys_id]
+        res = _Result()
+        F = np.zeros((n, 3)) if forces else None
+        P = np.zeros((n, 3)) if positions else None
+        res.forces = None if F is None else F.ctypes.data
+        res.positions = None if P is None else P.ctypes.data
+        st = load().reann_poll(self.handle, C.c_uint64(ticket), C.byref(res))
+        if st == PENDING:
+            return None
+        check(st)
+        return dict(energy=res.energy, virial=np.array(res.virial[:]).reshape(3, 3), forces=F, positions=P,
+                    latency_s=(res.t_done_ns - res.t_submit_ns) * 1e-9, t_done_ns=res.t_done_ns)
+
+    def stats(self) -> dict:
+        out = np.zeros(6, np.int64)
+        check(load().reann_server_stats(self.handle, _p(out)))
+        keys = ("admission_rounds", "completed", "atoms", "graph_replays", "deferred", "resident_bytes")
+        return dict(zip(keys, out.tolist()))
+
+    def close(self):
+        if _can_free(self):
+            _lib.reann_server_destroy(self.handle)
+        self.handle = None
+
+    __del__ = close

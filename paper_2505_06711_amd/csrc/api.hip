@@ -17,6 +17,10 @@ static reann_status set_err(reann_status code, const std::string &msg) {
     return code;
 }
 
+namespace reann {
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+}
+
 template <class F> static reann_status guarded(F &&f) {
     try {
         f();

@@ -262,6 +262,17 @@ void Plan::alloc_buffers() {
     ngh.ensure((size_t)(ne + 1) * 4);
 }
 
+size_t Plan::device_bytes() const {
+    size_t b = 0;
+    for (const DevBuf *d : {&px, &py, &pz, &c, &S, &rho, &Z, &Hh, &y, &ybar, &Eat, &Epart, &Sbar, &rhobar, &gA, &gB,
+                            &cbar, &F, &Wpart, &Wacc, &disp, &col2, &nloc, &ngh, &fp8s, &fp8tmp})
+        b += d->bytes;
+    b += nl.perm.bytes() + nl.inv_perm.bytes() + nl.q.bytes() + nl.gh_owner.bytes() + nl.gh_shift.bytes() +
+         nl.copy_ptr.bytes() + nl.copy_idx.bytes() + nl.row.bytes() + nl.col.bytes() + nl.spec_ext.bytes() +
+         nl.xref.bytes() + d_species.bytes();
+    return b;
+}
+
 void Plan::ensure_list(const double *d_pos, hipStream_t st) {
     bool rebuild = !built;
     if (built) {
@@ -371,11 +382,21 @@ void Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg)
     density_vjp(st, fp64, m->L, m->K, n, m->density_consts(), Sptr(t), rhobar.p, Sbar.p);
 }
 
-void Plan::forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st) {
-    mark(st, -1);
+bool Plan::prepare(const double *d_pos, hipStream_t st) {
     const int64_t rb0 = rebuilds;
     ensure_list(d_pos, st);
-    mark(st, 0, rebuilds != rb0 ? 1 : 0);
+    return rebuilds != rb0;
+}
+
+void Plan::forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st) {
+    mark(st, -1);
+    const bool rebuilt = prepare(d_pos, st);
+    mark(st, 0, rebuilt ? 1 : 0);
+    launch_forward(d_pos, d_energy, d_atom_energy, st);
+}
+
+void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st) {
+    if (!built) fail(REANN_E_STATE, "neighbour list not built");
     const int K = m->K;
     DeviceWeights &w = m->weights(ctx->device, st);
     refresh_positions(st, nl, d_pos, px.as<double>(), py.as<double>(), pz.as<double>());

@@ -106,6 +106,12 @@ struct Plan {
     bool same_system(const Model *mm, const int32_t *spec, int64_t nn, const double cell_[9], const int32_t pbc_[3],
                      int TT, const reann_opts *opt) const;
     void forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st);
+    // skin check (one stream synchronisation) and rebuild if needed; true if rebuilt, in which
+    // case device buffers may have moved
+    bool prepare(const double *d_pos, hipStream_t st);
+    // the forward's launches only: no synchronisation and no allocation, so it can be captured
+    void launch_forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st);
+    size_t device_bytes() const;
     void backward(const double *d_g, double *d_forces, double *d_virial, hipStream_t st);
     void get(int what, int t, double *host);
     // per-phase kernel time (ms) accumulated since the last call; returns the step count
@@ -130,6 +136,7 @@ struct Plan {
 struct reann_model { reann::Model impl; };
 struct reann_ctx { reann::Ctx impl; };
 namespace reann {
+void set_last_error(const std::string &msg);   // message returned by reann_last_error on this thread
 void ctx_acquire(Ctx *c);
 void ctx_release(Ctx *c);   // frees the context once released and unused
 }

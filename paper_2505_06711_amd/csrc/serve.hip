@@ -1,13 +1,576 @@
-// Serving engine: placeholder entry points until the continuous-batching engine lands.
+// Continuous-batching server for energy + force requests on many independent systems.
+//
+// Each registered system keeps its positions, velocities, last forces, skinned neighbour
+// list and layer buffers resident on the device once admitted.  An engine thread keeps up
+// to kSlots requests in flight, each on its own stream, so the steps of different systems
+// overlap on the device; a request that arrives while others run is admitted as soon as a
+// slot and HBM budget are free (budget exhausted: idle resident systems are evicted, least
+// recently used first, else the request waits).  A step is one HIP-graph replay of the
+// captured forward + backward when the neighbour list is unchanged; the list is rebuilt and
+// the graph re-captured when an atom has moved more than skin/2.  Every system has its own
+// buffers and the kernels are deterministic, so a result does not depend on what else is in
+// flight.
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <mutex>
+#include <thread>
+
 #include "runtime.hpp"
 
-extern "C" {
-reann_status reann_server_create(const reann_model *, const reann_server_opts *, reann_server **) { return REANN_E_UNSUPPORTED; }
-reann_status reann_server_set_masses(reann_server *, const double *) { return REANN_E_UNSUPPORTED; }
-reann_status reann_system_add(reann_server *, const int32_t *, int64_t, const double *, const int32_t *, const double *,
-                              const double *, uint64_t *) { return REANN_E_UNSUPPORTED; }
-reann_status reann_submit(reann_server *, const reann_request *, uint64_t *) { return REANN_E_UNSUPPORTED; }
-reann_status reann_poll(reann_server *, uint64_t, reann_result *) { return REANN_E_UNSUPPORTED; }
-reann_status reann_server_stats(reann_server *, int64_t *) { return REANN_E_UNSUPPORTED; }
-void reann_server_destroy(reann_server *) {}
+using namespace reann;
+
+namespace {
+
+constexpr int kSlots = 8;
+constexpr double kAccel = 9.648533212e-3;   // (eV/A) / amu in A/fs^2
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
 }
+
+__global__ void k_vv_drift(int64_t n, double dt, const int32_t *__restrict__ spec, const double *__restrict__ minv,
+                           double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ F) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * 3) return;
+    const double a = F[t] * minv[spec[t / 3]] * kAccel;
+    x[t] = x[t] + v[t] * dt + 0.5 * a * dt * dt;
+}
+
+__global__ void k_vv_kick(int64_t n, double dt, const int32_t *__restrict__ spec, const double *__restrict__ minv,
+                          double *__restrict__ v, const double *__restrict__ Fold, const double *__restrict__ Fnew) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * 3) return;
+    v[t] = v[t] + 0.5 * (Fold[t] + Fnew[t]) * minv[spec[t / 3]] * kAccel * dt;
+}
+
+__global__ void k_copy_d(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = a[t];
+}
+
+struct Sys {
+    uint64_t id = 0;
+    int64_t n = 0;
+    std::vector<int32_t> species;
+    double cell[9]{};
+    int32_t pbc[3]{};
+    std::vector<double> pos, vel, forces;   // host copies, authoritative while not resident
+    bool have_forces = false;               // forces of the current positions are known
+    // residency
+    std::unique_ptr<Plan> plan;
+    DevBuf d_pos, d_vel, d_F, d_Fold, d_E, d_W;
+    DArr<int32_t> d_spec;
+    hipGraphExec_t graph = nullptr;
+    int64_t graph_rebuilds = -1;   // plan rebuild count the graph was captured for
+    size_t bytes = 0;
+    int64_t last_used = 0;
+    bool busy = false;
+    ~Sys() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+    }
+};
+
+struct Req {
+    uint64_t ticket = 0, sys = 0;
+    int32_t kind = REANN_REQ_EVAL;
+    double dt = 0;
+    std::vector<double> pos;
+    int64_t t_submit = 0;
+};
+
+struct Done {
+    double energy = 0, virial[9]{};
+    std::vector<double> forces, positions;
+    int64_t t_submit = 0, t_done = 0;
+    reann_status status = REANN_OK;
+    std::string error;
+};
+
+struct Slot {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    bool active = false;
+    Req req;
+    Sys *sys = nullptr;
+    double *h_out = nullptr;          // pinned: energy, virial[9], forces [n][3], positions [n][3]
+    size_t h_cap = 0;
+};
+
+}  // namespace
+
+struct reann_server {
+    Model *m = nullptr;
+    reann_server_opts opt{};
+    Ctx ctx;
+    std::vector<double> minv;           // 1/mass per species (amu^-1), 0 = no dynamics
+    DevBuf d_minv;
+    std::mutex mu;                       // guards systems' registration, queue, results, stats
+    std::condition_variable cv;
+    std::map<uint64_t, std::unique_ptr<Sys>> systems;
+    std::deque<Req> incoming;
+    std::map<uint64_t, Done> results;
+    std::map<uint64_t, bool> known;      // ticket -> outstanding
+    uint64_t next_sys = 1, next_ticket = 1;
+    std::atomic<bool> stop{false};
+    std::thread engine;
+    Slot slots[kSlots];
+    std::list<Req> pending;              // engine-private
+    int64_t budget = 0, resident = 0, in_flight_atoms = 0;
+    std::atomic<int64_t> stats[6]{};
+    std::string fatal;
+
+    void run();
+    bool admit(Req &r);
+    void finish(Slot &s);
+    bool make_resident(Sys &sy, int64_t need);
+    void evict(Sys &sy);
+    int64_t estimate_bytes(const Sys &sy) const;
+    void launch_step(Slot &s, Sys &sy, bool replay_ok);
+};
+
+int64_t reann_server::estimate_bytes(const Sys &sy) const {
+    // extended atoms: periodic images within r_c + skin of the box; pairs at the system density
+    const double rc = m->r_c + opt.skin;
+    double grow = 1.0, vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        const double L = sy.cell[4 * a];
+        vol *= L > 0 ? L : 1.0;
+        if (sy.pbc[a] && L > 0) grow *= 1.0 + 2.0 * rc / L;
+    }
+    const double n = (double)sy.n, ne = n * grow;
+    const double dens = n / vol;
+    const double pairs = std::max(1.0, n * dens * 4.18879 * rc * rc * rc) * 1.3 + ne * 8;
+    const int K = m->K, NL = m->NL, F = m->F, H = m->H, nh = m->nh, T = opt.T;
+    double b = 24 * ne + 4.0 * T * ne * K + 4.0 * T * n * NL * K + 4.0 * T * n * F + 8.0 * T * nh * n * H;
+    b += 4.0 * n * (NL * K + F + 2 * std::max(F, H) + K + 4) + 4.0 * ne * (K + 3) + 8.0 * ne + 12.0 * pairs;
+    b += 160.0 * n + 64.0 * ne;   // list bookkeeping, positions, velocities, forces
+    return (int64_t)(b * 1.2) + (1 << 20);
+}
+
+void reann_server::evict(Sys &sy) {
+    // bring the evolving state home, then release the device memory
+    if (sy.plan) {
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipMemcpy(sy.pos.data(), sy.d_pos.p, sy.n * 24, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(sy.vel.data(), sy.d_vel.p, sy.n * 24, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(sy.forces.data(), sy.d_Fold.p, sy.n * 24, hipMemcpyDeviceToHost));
+    }
+    if (sy.graph) { (void)hipGraphExecDestroy(sy.graph); sy.graph = nullptr; }
+    sy.plan.reset();
+    sy.d_pos.release(); sy.d_vel.release(); sy.d_F.release(); sy.d_Fold.release(); sy.d_E.release(); sy.d_W.release();
+    sy.d_spec.b.release();
+    resident -= sy.bytes;
+    sy.bytes = 0;
+    stats[5] = resident;
+}
+
+bool reann_server::make_resident(Sys &sy, int64_t need) {
+    if (resident + need > budget) {
+        // evict idle systems, least recently used first
+        std::vector<Sys *> idle;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto &kv : systems)
+                if (kv.second->plan && !kv.second->busy) idle.push_back(kv.second.get());
+        }
+        std::sort(idle.begin(), idle.end(), [](Sys *a, Sys *b) { return a->last_used < b->last_used; });
+        for (Sys *v : idle) {
+            if (resident + need <= budget) break;
+            evict(*v);
+        }
+        if (resident + need > budget) return false;
+    }
+    hipStream_t st = ctx.stream;
+    auto p = std::make_unique<Plan>();
+    reann_opts o{};
+    o.precision = opt.precision;
+    o.skin = opt.skin;
+    o.decomp[0] = o.decomp[1] = o.decomp[2] = 1;
+    p->init(&ctx, m, sy.species.data(), sy.n, sy.cell, sy.pbc, opt.T, &o);
+    sy.d_pos.ensure(sy.n * 24); sy.d_vel.ensure(sy.n * 24); sy.d_F.ensure(sy.n * 24); sy.d_Fold.ensure(sy.n * 24);
+    sy.d_E.ensure(64); sy.d_W.ensure(128);
+    int32_t *ds = sy.d_spec.resize(sy.n);
+    HIP_OK(hipMemcpyAsync(ds, sy.species.data(), sy.n * 4, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(sy.d_pos.p, sy.pos.data(), sy.n * 24, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(sy.d_vel.p, sy.vel.data(), sy.n * 24, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(sy.d_Fold.p, sy.forces.data(), sy.n * 24, hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+    sy.plan = std::move(p);
+    sy.graph_rebuilds = -1;
+    sy.bytes = need;   // corrected to the measured size after the first build
+    resident += need;
+    stats[5] = resident;
+    return true;
+}
+
+// Enqueue one step of `sy` on slot `s` (positions for EVAL already staged in d_pos).
+void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok) {
+    hipStream_t st = s.st;
+    Plan &p = *sy.plan;
+    const bool rebuilt = p.prepare(sy.d_pos.as<double>(), st);
+    if (rebuilt) {
+        const int64_t actual = (int64_t)p.device_bytes() + 4 * (int64_t)sy.n * 24;
+        resident += actual - (int64_t)sy.bytes;
+        sy.bytes = actual;
+        stats[5] = resident;
+    }
+    const bool use_graph = opt.use_graph && replay_ok;
+    if (use_graph && (sy.graph == nullptr || sy.graph_rebuilds != p.rebuilds)) {
+        if (sy.graph) { (void)hipGraphExecDestroy(sy.graph); sy.graph = nullptr; }
+        hipGraph_t g = nullptr;
+        HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        p.launch_forward(sy.d_pos.as<double>(), sy.d_E.as<double>(), nullptr, st);
+        p.backward(nullptr, sy.d_F.as<double>(), sy.d_W.as<double>(), st);
+        HIP_OK(hipStreamEndCapture(st, &g));
+        hipError_t e = hipGraphInstantiate(&sy.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_OK(e);
+        sy.graph_rebuilds = p.rebuilds;
+    }
+    if (use_graph) {
+        HIP_OK(hipGraphLaunch(sy.graph, st));
+        stats[3]++;
+    } else {
+        p.launch_forward(sy.d_pos.as<double>(), sy.d_E.as<double>(), nullptr, st);
+        p.backward(nullptr, sy.d_F.as<double>(), sy.d_W.as<double>(), st);
+    }
+}
+
+bool reann_server::admit(Req &r) {
+    Sys *syp;
+    {
+        std::lock_guard<std::mutex> lk(mu);   // registration may insert concurrently
+        syp = systems.at(r.sys).get();
+    }
+    Sys &sy = *syp;
+    if (sy.busy) return false;
+    Slot *s = nullptr;
+    for (auto &x : slots)
+        if (!x.active) { s = &x; break; }
+    if (!s) return false;
+    if (in_flight_atoms > 0 && in_flight_atoms + sy.n > opt.max_batch_atoms) return false;
+    if (!sy.plan) {
+        const int64_t need = estimate_bytes(sy);
+        if (need > budget) {
+            Done d;
+            d.status = REANN_E_CAPACITY;
+            d.error = "system does not fit the server's HBM budget";
+            d.t_submit = r.t_submit;
+            d.t_done = now_ns();
+            std::lock_guard<std::mutex> lk(mu);
+            results[r.ticket] = std::move(d);
+            return true;   // consumed
+        }
+        if (!make_resident(sy, need)) {
+            stats[4]++;
+            return false;
+        }
+    }
+    const size_t need_host = (size_t)(10 + 6 * sy.n) * 8;
+    if (s->h_cap < need_host) {
+        if (s->h_out) (void)hipHostFree(s->h_out);
+        HIP_OK(hipHostMalloc((void **)&s->h_out, need_host, hipHostMallocDefault));
+        s->h_cap = need_host;
+    }
+    hipStream_t st = s->st;
+    const int64_t n3 = sy.n * 3;
+    const int B = 256;
+    bool vv = r.kind == REANN_REQ_VV_STEP;
+    if (vv && !sy.have_forces) {
+        // forces at the current positions first (once per system)
+        launch_step(*s, sy, false);
+        hipLaunchKernelGGL(k_copy_d, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.d_F.as<double>(),
+                           sy.d_Fold.as<double>());
+        LAUNCH_OK("k_copy_d");
+        sy.have_forces = true;
+    }
+    if (vv) {
+        hipLaunchKernelGGL(k_vv_drift, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, r.dt, sy.d_spec.ptr(),
+                           d_minv.as<double>(), sy.d_pos.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>());
+        LAUNCH_OK("k_vv_drift");
+    } else {
+        HIP_OK(hipMemcpyAsync(sy.d_pos.p, r.pos.data(), sy.n * 24, hipMemcpyHostToDevice, st));
+    }
+    launch_step(*s, sy, true);
+    if (vv) {
+        hipLaunchKernelGGL(k_vv_kick, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, r.dt, sy.d_spec.ptr(),
+                           d_minv.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.d_F.as<double>());
+        LAUNCH_OK("k_vv_kick");
+    }
+    hipLaunchKernelGGL(k_copy_d, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.d_F.as<double>(), sy.d_Fold.as<double>());
+    LAUNCH_OK("k_copy_d");
+    sy.have_forces = true;
+    HIP_OK(hipMemcpyAsync(s->h_out, sy.d_E.p, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(s->h_out + 1, sy.d_W.p, 72, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(s->h_out + 10, sy.d_F.p, sy.n * 24, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(s->h_out + 10 + n3, sy.d_pos.p, sy.n * 24, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipEventRecord(s->ev, st));
+    sy.busy = true;
+    sy.last_used = now_ns();
+    s->active = true;
+    s->sys = &sy;
+    s->req = std::move(r);
+    in_flight_atoms += sy.n;
+    return true;
+}
+
+void reann_server::finish(Slot &s) {
+    Sys &sy = *s.sys;
+    const int64_t n3 = sy.n * 3;
+    Done d;
+    d.energy = s.h_out[0];
+    std::memcpy(d.virial, s.h_out + 1, 72);
+    d.forces.assign(s.h_out + 10, s.h_out + 10 + n3);
+    d.positions.assign(s.h_out + 10 + n3, s.h_out + 10 + 2 * n3);
+    d.t_submit = s.req.t_submit;
+    d.t_done = now_ns();
+    sy.busy = false;
+    in_flight_atoms -= sy.n;
+    s.active = false;
+    std::lock_guard<std::mutex> lk(mu);
+    results[s.req.ticket] = std::move(d);
+    stats[1]++;
+    stats[2] += sy.n;
+}
+
+void reann_server::run() {
+    try {
+        HIP_OK(hipSetDevice(ctx.device));
+        while (!stop.load()) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                bool any_active = false;
+                for (auto &x : slots) any_active = any_active || x.active;
+                if (incoming.empty() && pending.empty() && !any_active)
+                    cv.wait_for(lk, std::chrono::milliseconds(2));
+                while (!incoming.empty()) {
+                    pending.push_back(std::move(incoming.front()));
+                    incoming.pop_front();
+                }
+            }
+            bool progressed = false;
+            for (auto &x : slots)
+                if (x.active && hipEventQuery(x.ev) == hipSuccess) {
+                    finish(x);
+                    progressed = true;
+                }
+            bool admitted = false;
+            for (auto it = pending.begin(); it != pending.end();) {
+                if (admit(*it)) {
+                    it = pending.erase(it);
+                    progressed = admitted = true;
+                } else {
+                    ++it;
+                }
+            }
+            if (admitted) stats[0]++;
+            if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+        for (auto &x : slots)
+            if (x.active) { HIP_OK(hipEventSynchronize(x.ev)); finish(x); }
+    } catch (const std::exception &e) {
+        std::lock_guard<std::mutex> lk(mu);
+        fatal = e.what();
+        // fail everything still queued so pollers do not wait forever
+        for (auto &r : pending) {
+            Done d;
+            d.status = REANN_E_DEVICE;
+            d.error = fatal;
+            results[r.ticket] = std::move(d);
+        }
+        pending.clear();
+        for (auto &x : slots)
+            if (x.active) {
+                Done d;
+                d.status = REANN_E_DEVICE;
+                d.error = fatal;
+                results[x.req.ticket] = std::move(d);
+                x.active = false;
+            }
+    }
+}
+
+template <class F> static reann_status serve_guard(F &&f) {
+    try {
+        f();
+        return REANN_OK;
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return REANN_E_NOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return REANN_E_DEVICE;
+    }
+}
+
+extern "C" {
+
+reann_status reann_server_create(const reann_model *m, const reann_server_opts *o, reann_server **out) {
+    return serve_guard([&] {
+        if (!m || !o || !out) fail(REANN_E_INVALID, "NULL argument");
+        if (o->T < 1 || o->T > m->impl.T_max) fail(REANN_E_INVALID, "T must be in [1, T_max]");
+        if (!(o->skin >= 0) || !std::isfinite(o->skin)) fail(REANN_E_INVALID, "skin must be >= 0");
+        if (o->precision < REANN_FP64 || o->precision > REANN_FP8) fail(REANN_E_INVALID, "unknown precision");
+        int nd = 0;
+        HIP_OK(hipGetDeviceCount(&nd));
+        if (o->device < 0 || o->device >= nd) fail(REANN_E_INVALID, "device index out of range");
+        HIP_OK(hipSetDevice(o->device));
+        auto s = std::make_unique<reann_server>();
+        s->m = const_cast<Model *>(&m->impl);
+        s->opt = *o;
+        if (s->opt.max_batch_atoms <= 0) s->opt.max_batch_atoms = 262144;
+        s->ctx.device = o->device;
+        HIP_OK(hipStreamCreateWithFlags(&s->ctx.stream, hipStreamNonBlocking));
+        s->ctx.own_stream = true;
+        size_t fr = 0, tot = 0;
+        HIP_OK(hipMemGetInfo(&fr, &tot));
+        s->budget = o->hbm_budget_bytes > 0 ? o->hbm_budget_bytes : (int64_t)(fr / 4 * 3);
+        for (auto &x : s->slots) {
+            HIP_OK(hipStreamCreateWithFlags(&x.st, hipStreamNonBlocking));
+            HIP_OK(hipEventCreateWithFlags(&x.ev, hipEventDisableTiming));
+        }
+        s->minv.assign(s->m->n_species, 0.0);
+        s->d_minv.ensure(s->m->n_species * 8);
+        HIP_OK(hipMemcpy(s->d_minv.p, s->minv.data(), s->m->n_species * 8, hipMemcpyHostToDevice));
+        s->m->weights(o->device, s->ctx.stream);
+        if (o->precision != REANN_FP64) {
+            const OpType op = o->precision == REANN_BF16 ? OpType::BF16 : (o->precision == REANN_FP8 ? OpType::FP8 : OpType::F32);
+            s->m->mfma(o->device, s->ctx.stream, false, op);
+            s->m->mfma(o->device, s->ctx.stream, true, op);
+        }
+        reann_server *raw = s.release();
+        raw->engine = std::thread([raw] { raw->run(); });
+        *out = raw;
+    });
+}
+
+reann_status reann_server_set_masses(reann_server *s, const double *masses) {
+    return serve_guard([&] {
+        if (!s || !masses) fail(REANN_E_INVALID, "NULL argument");
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (int k = 0; k < s->m->n_species; ++k) {
+            if (!(masses[k] > 0) || !std::isfinite(masses[k])) fail(REANN_E_INVALID, "masses must be > 0");
+            s->minv[k] = 1.0 / masses[k];
+        }
+        HIP_OK(hipSetDevice(s->ctx.device));
+        HIP_OK(hipMemcpy(s->d_minv.p, s->minv.data(), s->m->n_species * 8, hipMemcpyHostToDevice));
+    });
+}
+
+reann_status reann_system_add(reann_server *s, const int32_t *species, int64_t n, const double cell[9],
+                              const int32_t pbc[3], const double *pos, const double *vel, uint64_t *sys_id) {
+    return serve_guard([&] {
+        if (!s || !species || !cell || !pbc || !pos || !sys_id) fail(REANN_E_INVALID, "NULL argument");
+        if (n <= 0) fail(REANN_E_INVALID, "n must be > 0");
+        for (int64_t i = 0; i < n; ++i)
+            if (species[i] < 0 || species[i] >= s->m->n_species) fail(REANN_E_INVALID, "species out of range");
+        for (int64_t i = 0; i < 3 * n; ++i)
+            if (!std::isfinite(pos[i]) || (vel && !std::isfinite(vel[i]))) fail(REANN_E_INVALID, "non-finite input");
+        Geom g{};
+        geom_init(g, cell, pbc, nullptr, s->m->r_c, s->opt.skin);   // validates the cell
+        auto sy = std::make_unique<Sys>();
+        sy->n = n;
+        sy->species.assign(species, species + n);
+        std::memcpy(sy->cell, cell, sizeof sy->cell);
+        std::memcpy(sy->pbc, pbc, sizeof sy->pbc);
+        sy->pos.assign(pos, pos + 3 * n);
+        sy->vel.assign(3 * n, 0.0);
+        if (vel) sy->vel.assign(vel, vel + 3 * n);
+        sy->forces.assign(3 * n, 0.0);
+        if (s->estimate_bytes(*sy) > s->budget) fail(REANN_E_CAPACITY, "system larger than the server's HBM budget");
+        std::lock_guard<std::mutex> lk(s->mu);
+        sy->id = s->next_sys++;
+        *sys_id = sy->id;
+        s->systems[sy->id] = std::move(sy);
+    });
+}
+
+reann_status reann_submit(reann_server *s, const reann_request *req, uint64_t *ticket) {
+    return serve_guard([&] {
+        if (!s || !req || !ticket) fail(REANN_E_INVALID, "NULL argument");
+        Req r;
+        r.t_submit = now_ns();
+        r.sys = req->sys_id;
+        r.kind = req->kind;
+        r.dt = req->dt_fs;
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->fatal.empty()) fail(REANN_E_DEVICE, s->fatal);
+        auto it = s->systems.find(req->sys_id);
+        if (it == s->systems.end()) fail(REANN_E_INVALID, "unknown system");
+        if (r.kind == REANN_REQ_EVAL) {
+            if (!req->pos) fail(REANN_E_INVALID, "EVAL needs positions");
+            const int64_t n3 = it->second->n * 3;
+            for (int64_t i = 0; i < n3; ++i)
+                if (!std::isfinite(req->pos[i])) fail(REANN_E_INVALID, "non-finite positions");
+            r.pos.assign(req->pos, req->pos + n3);
+        } else if (r.kind == REANN_REQ_VV_STEP) {
+            if (!(r.dt > 0) || !std::isfinite(r.dt)) fail(REANN_E_INVALID, "dt must be > 0");
+            for (int k = 0; k < s->m->n_species; ++k)
+                if (s->minv[k] == 0.0) fail(REANN_E_STATE, "set masses before VV_STEP requests");
+        } else {
+            fail(REANN_E_INVALID, "unknown request kind");
+        }
+        r.ticket = s->next_ticket++;
+        *ticket = r.ticket;
+        s->known[r.ticket] = true;
+        s->incoming.push_back(std::move(r));
+        s->cv.notify_one();
+    });
+}
+
+reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res) {
+    if (!s || !res) return REANN_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->known.count(ticket)) return REANN_E_UNKNOWN_TICKET;
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) return REANN_PENDING;
+    Done &d = it->second;
+    res->status = d.status;
+    res->energy = d.energy;
+    std::memcpy(res->virial, d.virial, sizeof d.virial);
+    if (res->forces && !d.forces.empty()) std::memcpy(res->forces, d.forces.data(), d.forces.size() * 8);
+    if (res->positions && !d.positions.empty()) std::memcpy(res->positions, d.positions.data(), d.positions.size() * 8);
+    res->t_submit_ns = d.t_submit;
+    res->t_done_ns = d.t_done;
+    const reann_status st = d.status;
+    if (st != REANN_OK) set_last_error(d.error);
+    s->results.erase(it);
+    s->known.erase(ticket);
+    return st;
+}
+
+reann_status reann_server_stats(reann_server *s, int64_t *st6) {
+    if (!s || !st6) return REANN_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int k = 0; k < 6; ++k) st6[k] = s->stats[k].load();
+    return REANN_OK;
+}
+
+void reann_server_destroy(reann_server *s) {
+    if (!s) return;
+    s->stop.store(true);
+    s->cv.notify_all();
+    if (s->engine.joinable()) s->engine.join();
+    (void)hipSetDevice(s->ctx.device);
+    (void)hipDeviceSynchronize();
+    s->systems.clear();
+    for (auto &x : s->slots) {
+        if (x.h_out) (void)hipHostFree(x.h_out);
+        (void)hipEventDestroy(x.ev);
+        (void)hipStreamDestroy(x.st);
+    }
+    (void)hipStreamDestroy(s->ctx.stream);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""GPU tests of the continuous-batching server (reann_server_* / reann_submit / reann_poll)."""
+import time
+
+import numpy as np
+import pytest
+
+from synth import models, systems
+
+pytestmark = pytest.mark.gpu
+
+MASSES = [1.008, 15.999, 63.546]
+
+
+@pytest.fixture(scope="module")
+def rn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_06711_amd as rn
+    return rn
+
+
+@pytest.fixture(scope="module")
+def model_params():
+    return models.serving_model(T_max=3, seed=3)
+
+
+def mix(seed, sizes):
+    out = []
+    for k, n in enumerate(sizes):
+        s = systems.water_box_n(n, seed=seed + k) if k % 2 == 0 else systems.fcc_n(n, seed=seed + k)
+        out.append(systems.remap_species(s, ["H", "O", "Cu"]))
+    return out
+
+
+def wait(srv, ticket, sid, timeout=60.0, **kw):
+    t0 = time.time()
+    while True:
+        r = srv.poll(ticket, sid, **kw)
+        if r is not None:
+            return r
+        if time.time() - t0 > timeout:
+            raise TimeoutError("request %d did not complete" % ticket)
+        time.sleep(0.0005)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_result_alone_equals_result_in_mix(rn, model_params, use_graph):
+    sys_list = mix(100, [300, 500, 2000, 96, 4000, 864, 1500, 200, 3000, 108])
+    model = rn.Model(model_params)
+    srv = rn.Server(model, T=3, precision="fp32", skin=1.0, use_graph=use_graph)
+    ids = [srv.add_system(s) for s in sys_list]
+    alone = wait(srv, srv.submit_eval(ids[2], sys_list[2]["pos"]), ids[2])
+    tickets = [(srv.submit_eval(i, s["pos"]), i) for i, s in zip(ids, sys_list)]
+    tickets += [(srv.submit_eval(i, s["pos"]), i) for i, s in zip(ids, sys_list)]
+    res = {}
+    for t, i in tickets:
+        res.setdefault(i, []).append(wait(srv, t, i))
+    for r in res[ids[2]]:
+        assert r["energy"] == alone["energy"]
+        np.testing.assert_array_equal(r["forces"], alone["forces"])
+        np.testing.assert_array_equal(r["virial"], alone["virial"])
+    st = srv.stats()
+    assert st["completed"] == len(tickets) + 1
+    if use_graph:
+        assert st["graph_replays"] > 0
+    srv.close()
+
+
+def test_server_matches_plan_path(rn, model_params):
+    sys_list = mix(200, [600, 1372])
+    model = rn.Model(model_params)
+    ctx = rn.Context(0)
+    srv = rn.Server(model, T=3, precision="fp32", skin=1.0, use_graph=True)
+    for s in sys_list:
+        sid = srv.add_system(s)
+        # several replays of the same graph with eager work in between
+        for rep in range(3):
+            r = wait(srv, srv.submit_eval(sid, s["pos"]), sid)
+            E, F, W = rn.energy_forces(ctx, model, s, T=3, precision="fp32", skin=1.0)
+            assert r["energy"] == pytest.approx(E, rel=1e-12, abs=1e-12), rep
+            np.testing.assert_allclose(r["forces"], F, rtol=0, atol=1e-9 * np.abs(F).max())
+
+
+def test_velocity_verlet_steps_and_rebuilds(rn, model_params):
+    s = mix(300, [1500])[0]
+    model = rn.Model(model_params)
+    srv = rn.Server(model, T=3, precision="fp32", skin=0.4, use_graph=True)
+    srv.set_masses(MASSES)
+    vel = systems.maxwell_boltzmann(s["species"], ["H", "O", "Cu"], 300.0, seed=1)
+    sid = srv.add_system(s, vel)
+    energies = []
+    for k in range(40):
+        r = wait(srv, srv.submit_vv(sid, 0.5), sid, positions=True)
+        energies.append(r["energy"])
+    assert np.all(np.isfinite(energies))
+    # positions moved, so the list was rebuilt at least once with a 0.4 A skin
+    assert not np.allclose(r["positions"], s["pos"])
+    srv.close()
+
+
+def test_admission_under_a_tiny_budget(rn, model_params):
+    sys_list = mix(400, [3000, 3000, 3000, 3000])
+    sys_list = [sys_list[0], sys_list[2], dict(sys_list[0], pos=sys_list[0]["pos"] + 0.05),
+                dict(sys_list[2], pos=sys_list[2]["pos"] - 0.05)]
+    model = rn.Model(model_params)
+    probe = rn.Server(model, T=3, precision="fp32", skin=1.0, hbm_budget_bytes=1 << 20)
+    with pytest.raises(rn.ReannError) as e:
+        probe.add_system(sys_list[0])
+    assert e.value.status == -4
+    probe.close()
+    # room for about two of these four systems at a time: requests complete through eviction
+    big = rn.Server(model, T=3, precision="fp32", skin=1.0, hbm_budget_bytes=1 << 40)
+    one = big.add_system(sys_list[0])
+    wait(big, big.submit_eval(one, sys_list[0]["pos"]), one)
+    per_sys = big.stats()["resident_bytes"]
+    big.close()
+    budget = int(per_sys * 2.5)
+    srv = rn.Server(model, T=3, precision="fp32", skin=1.0, hbm_budget_bytes=budget)
+    ids = [srv.add_system(s) for s in sys_list]
+    ref = {}
+    for rep in range(2):
+        ts = [(srv.submit_eval(i, s["pos"]), i) for i, s in zip(ids, sys_list)]
+        for t, i in ts:
+            r = wait(srv, t, i)
+            if rep == 0:
+                ref[i] = r["energy"]
+            else:
+                assert r["energy"] == ref[i]
+    st = srv.stats()
+    print("tiny budget:", budget, st, flush=True)
+    assert st["resident_bytes"] <= budget
+    assert st["completed"] == 8
+    srv.close()
+
+
+def test_bad_requests_do_not_stop_the_server(rn, model_params):
+    s = mix(500, [400])[0]
+    model = rn.Model(model_params)
+    srv = rn.Server(model, T=3, precision="bf16", skin=1.0)
+    sid = srv.add_system(s)
+    with pytest.raises(rn.ReannError):
+        srv.submit_eval(sid + 99, s["pos"])               # unknown system
+    with pytest.raises(rn.ReannError) as e:
+        srv.submit_vv(sid, 1.0)                           # no masses yet
+    assert e.value.status == -7
+    bad = s["pos"].copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(rn.ReannError):
+        srv.submit_eval(sid, bad)
+    r = wait(srv, srv.submit_eval(sid, s["pos"]), sid)
+    assert np.isfinite(r["energy"])
+    from paper_2505_06711_amd._binding import _Result, load
+    import ctypes as C
+    assert load().reann_poll(srv.handle, C.c_uint64(123456), C.byref(_Result())) == -6   # unknown ticket
+    srv.close()
