@@ -167,6 +167,44 @@ def serve_bench(rn, seconds=6.0, n_systems=256, seed=0):
     return out
 
 
+def tsweep(rn, torch, ctx, model, w, a, Ts):
+    """Cost of one energy+force step against the number of MP layers T (Sec. 2.2: the
+    same neighbour list and ghost shell serve every layer, so the cost is linear in T)."""
+    s = w["system"]
+    n = len(s["pos"])
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
+    E = torch.zeros((), dtype=torch.float64, device="cuda")
+    F = torch.zeros_like(pos)
+    rows = []
+    for T in Ts:
+        plan = rn.Plan(ctx, model, s, T=T, precision=a.precision, decomp=w["decomp"], skin=w["skin"])
+        for _ in range(1 + a.warmup):
+            plan.forward(pos, E)
+            plan.backward(F)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(a.steps):
+            plan.forward(pos, E)
+            plan.backward(F)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / a.steps
+        rows.append(dict(T=T, ms_per_step=round(ms, 4), atom_steps_per_s=round(n / (ms * 1e-3), 1)))
+        print("tsweep T=%d %.3f ms" % (T, ms), file=sys.stderr, flush=True)
+        del plan
+    t = np.array([r["T"] for r in rows], float)
+    y = np.array([r["ms_per_step"] for r in rows])
+    A = np.stack([np.ones_like(t), t], 1)
+    coef, *_ = np.linalg.lstsq(A, y, rcond=None)
+    fit = A @ coef
+    r2 = 1 - ((y - fit) ** 2).sum() / max(1e-30, ((y - y.mean()) ** 2).sum())
+    return dict(metric="cost vs number of MP layers T", workload=describe(a.workload, w), precision=a.precision,
+                n_atoms=n, rows=rows, fit_ms=dict(a=round(float(coef[0]), 4), b_per_layer=round(float(coef[1]), 4),
+                                                   r2=round(float(r2), 6),
+                                                   residuals_ms=[round(float(v), 4) for v in (y - fit)]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +216,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--tsweep", default=None,
+                    help="comma list of T values: time each T on the workload instead of the headline run")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the subdomain exchange is "
@@ -197,6 +237,9 @@ def main():
           file=sys.stderr, flush=True)
     ctx = rn.Context(0, torch.cuda.current_stream())
     model = rn.Model(m)
+    if a.tsweep:
+        print(json.dumps(tsweep(rn, torch, ctx, model, w, a, [int(x) for x in a.tsweep.split(",")])), flush=True)
+        return
     plan = rn.Plan(ctx, model, s, T=T, precision=a.precision, decomp=w["decomp"], skin=w["skin"])
     pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
     E = torch.zeros((), dtype=torch.float64, device="cuda")

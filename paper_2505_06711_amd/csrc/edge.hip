@@ -71,21 +71,38 @@ __device__ inline void angular(R ux, R uy, R uz, R s, R *A, R (*dA)[3]) {
 // these entries.
 __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, int32_t *__restrict__ nloc,
                           int32_t *__restrict__ ngh) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= a.n_ext) return;
-    const double xi = a.px[x], yi = a.py[x], zi = a.pz[x];
-    const int64_t lo = a.row[x], hi = a.row[x + 1];
+    // 16 lanes per row take the row's entries 16 at a time; a ballot gives each in-cutoff
+    // entry its rank, so the packed order equals a sequential scan of the row
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t x = t >> 4;
+    const int g = threadIdx.x & 15, gbase = threadIdx.x & 48;
+    const bool active = x < a.n_ext;
+    const int64_t lo = active ? a.row[x] : 0, hi = active ? a.row[x + 1] : 0;
+    const double xi = active ? a.px[x] : 0.0, yi = active ? a.py[x] : 0.0, zi = active ? a.pz[x] : 0.0;
     int64_t front = lo, back = hi;
-    for (int64_t k = lo; k < hi; ++k) {
-        const int32_t j = a.col[k];
-        const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
-        if (dx * dx + dy * dy + dz * dz < rc2) {
-            if (j < a.n) col2[front++] = j;
-            else col2[--back] = j;
+    const uint32_t below = (1u << g) - 1u;
+    for (int64_t base = lo; base < hi; base += 16) {
+        const int64_t k = base + g;
+        bool isl = false, isg = false;
+        int32_t j = 0;
+        if (k < hi) {
+            j = a.col[k];
+            const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
+            const bool in = dx * dx + dy * dy + dz * dz < rc2;
+            isl = in && j < a.n;
+            isg = in && j >= a.n;
         }
+        const uint32_t ml = (uint32_t)(__ballot(isl) >> gbase) & 0xffffu;
+        const uint32_t mg = (uint32_t)(__ballot(isg) >> gbase) & 0xffffu;
+        if (isl) col2[front + __popc(ml & below)] = j;
+        if (isg) col2[back - 1 - __popc(mg & below)] = j;
+        front += __popc(ml);
+        back -= __popc(mg);
     }
-    nloc[x] = (int32_t)(front - lo);
-    ngh[x] = (int32_t)(hi - back);
+    if (active && g == 0) {
+        nloc[x] = (int32_t)(front - lo);
+        ngh[x] = (int32_t)(hi - back);
+    }
 }
 
 // e-th in-cutoff neighbour of row x (locals first, then ghosts)
@@ -94,17 +111,29 @@ __device__ inline int64_t cut_slot(const CutList &cl, int64_t x, int e) {
     return e < nl ? cl.row[x] + e : cl.row[x + 1] - cl.ngh[x] + (e - nl);
 }
 
+// Forward edge pass: G = 4 lanes per row, lane q owning channels m = q, q+4, q+8, ...
+// Each lane walks the whole row (the per-edge geometry is recomputed by the 4 lanes) and
+// keeps NL x K/4 accumulators, so many more waves are resident than with a row per lane.
+constexpr int kFwdLanes = 4;
+
 template <int L, int K, typename R>
 __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeConsts ec, const R *__restrict__ c,
                                                   R *__restrict__ S) {
     constexpr int NL = n_lambda(L);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int G = kFwdLanes, KG = K / G;
+    static_assert(K % G == 0, "K must be a multiple of the lanes per row");
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / G;
+    const int q = (int)(t % G);
     if (i >= a.n) return;
-    R acc[NL][K];
+    R acc[NL][KG];
 #pragma unroll
     for (int l = 0; l < NL; ++l)
 #pragma unroll
-        for (int m = 0; m < K; ++m) acc[l][m] = R(0);
+        for (int u = 0; u < KG; ++u) acc[l][u] = R(0);
+    R cen[KG], alp[KG];
+#pragma unroll
+    for (int u = 0; u < KG; ++u) { cen[u] = R(ec.centres[q + G * u]); alp[u] = R(ec.alphas[q + G * u]); }
     const double xi = a.px[i], yi = a.py[i], zi = a.pz[i];
     const R inv_rc = R(1.0 / ec.r_c);
     const R s = R(ec.ang_scale);
@@ -114,24 +143,24 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
         const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
         const double d2 = dx * dx + dy * dy + dz * dz;
         const R r = d_sqrt(R(d2));
-        const R u = R(0.5) * d_cospi(r * inv_rc) + R(0.5);
-        const R fc = u * u;
+        const R uc = R(0.5) * d_cospi(r * inv_rc) + R(0.5);
+        const R fc = uc * uc;
         R A[NL];
         angular<L, R, false>(R(ec.ang_scale * dx), R(ec.ang_scale * dy), R(ec.ang_scale * dz), s, A, nullptr);
-        const R *cj = c + j * K;
+        const R *cj = c + j * K + q;
 #pragma unroll
-        for (int m = 0; m < K; ++m) {
-            const R xm = r - R(ec.centres[m]);
-            const R w = cj[m] * d_exp(-R(ec.alphas[m]) * xm * xm) * fc;
+        for (int u = 0; u < KG; ++u) {
+            const R xm = r - cen[u];
+            const R w = cj[G * u] * d_exp(-alp[u] * xm * xm) * fc;
 #pragma unroll
-            for (int l = 0; l < NL; ++l) acc[l][m] += w * A[l];
+            for (int l = 0; l < NL; ++l) acc[l][u] += w * A[l];
         }
     }
-    R *out = S + i * NL * K;
+    R *out = S + i * NL * K + q;
 #pragma unroll
     for (int l = 0; l < NL; ++l)
 #pragma unroll
-        for (int m = 0; m < K; ++m) out[l * K + m] = acc[l][m];
+        for (int u = 0; u < KG; ++u) out[l * K + G * u] = acc[l][u];
 }
 
 // Per-edge radial/cutoff factors shared by both adjoint roles.
@@ -326,20 +355,21 @@ __global__ __launch_bounds__(256) void k_adj_neighbour(EdgeArgs a, CutList cl, E
     } while (0)
 
 void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl) {
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(a.n_ext, 256)), dim3(256), 0, st, a, r_c * r_c, cl.col, cl.nloc,
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(a.n_ext * 16, 256)), dim3(256), 0, st, a, r_c * r_c, cl.col, cl.nloc,
                        cl.ngh);
     LAUNCH_OK("k_compact");
 }
 
 void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
                   const void *c, void *S) {
-    const int B = 128;
-#define FWD(LL, KK)                                                                                         \
-    if (fp64)                                                                                               \
-        hipLaunchKernelGGL((k_edge_fwd<LL, KK, double>), dim3(grid_for(a.n, B)), dim3(B), 0, st, a, cl, ec, \
-                           (const double *)c, (double *)S);                                                 \
-    else                                                                                                    \
-        hipLaunchKernelGGL((k_edge_fwd<LL, KK, float>), dim3(grid_for(a.n, B)), dim3(B), 0, st, a, cl, ec,  \
+    const int B = 256;
+    const int64_t nt = a.n * kFwdLanes;
+#define FWD(LL, KK)                                                                                       \
+    if (fp64)                                                                                             \
+        hipLaunchKernelGGL((k_edge_fwd<LL, KK, double>), dim3(grid_for(nt, B)), dim3(B), 0, st, a, cl, ec, \
+                           (const double *)c, (double *)S);                                               \
+    else                                                                                                  \
+        hipLaunchKernelGGL((k_edge_fwd<LL, KK, float>), dim3(grid_for(nt, B)), dim3(B), 0, st, a, cl, ec,  \
                            (const float *)c, (float *)S);
     REANN_LK_DISPATCH(L, K, FWD);
 #undef FWD

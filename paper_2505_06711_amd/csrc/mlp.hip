@@ -33,13 +33,13 @@ __global__ void k_density(int64_t n, int L, DensityConsts dc, const R *__restric
     R *out = rho + i * F + l * P;
     // at most 6 Cartesian components share one l when L <= 2 (the dispatcher enforces L <= 2);
     // unused slots hold zero so every index below is static
-    R v[6][K];
+    R v[6][K], w[6];
     const int nk = k1 - k0;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-        const R wq = q < nk ? R(dc.w[k0 + q]) : R(0);
+        w[q] = q < nk ? R(dc.w[k0 + q]) : R(0);
 #pragma unroll
-        for (int m = 0; m < K; ++m) v[q][m] = q < nk ? wq * Si[(k0 + q) * K + m] : R(0);
+        for (int m = 0; m < K; ++m) v[q][m] = q < nk ? Si[(k0 + q) * K + m] : R(0);
     }
     int f = 0;
 #pragma unroll
@@ -48,7 +48,7 @@ __global__ void k_density(int64_t n, int L, DensityConsts dc, const R *__restric
         for (int b = a; b < K; ++b) {
             R s = R(0);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) s += v[q][a] * (q < nk ? Si[(k0 + q) * K + b] : R(0));
+            for (int q = 0; q < 6; ++q) s += w[q] * v[q][a] * v[q][b];
             out[f++] = s;
         }
 }
@@ -272,25 +272,83 @@ int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const vo
 }
 
 __global__ void k_sum_rows(const double *__restrict__ part, int nb, int width, double *__restrict__ out, int acc) {
-    // one block; thread q < width sums column q over the rows in a fixed tree order
+    // block q sums column q over the rows in a fixed order (strided per thread, then a tree)
     __shared__ double sm[256];
-    for (int q = 0; q < width; ++q) {
-        double s = 0.0;
-        for (int r = threadIdx.x; r < nb; r += blockDim.x) s += part[(int64_t)r * width + q];
-        sm[threadIdx.x] = s;
-        __syncthreads();
-        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[q] = acc ? out[q] + sm[0] : sm[0];
+    const int q = blockIdx.x;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) s += part[(int64_t)r * width + q];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
         __syncthreads();
     }
+    if (threadIdx.x == 0) out[q] = acc ? out[q] + sm[0] : sm[0];
 }
 
 void sum_rows(hipStream_t st, const double *partials, int nb, int width, double *out, bool accumulate) {
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, partials, nb, width, out, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(k_sum_rows, dim3(width), dim3(256), 0, st, partials, nb, width, out, accumulate ? 1 : 0);
     LAUNCH_OK("k_sum_rows");
+}
+
+// ------------------------------------------------------------ output layers --
+// The last layer of an atomic NN has few outputs (K messages or one energy), too narrow for a
+// 64-wide tile.  64 rows per block: the activations are staged in LDS, W [out][in] too, and
+// every output accumulates in FP64 (these are sums of large terms with cancellation).
+constexpr int kOutRows = 64, kOutMaxIn = 128, kOutMaxOut = 16;
+
+__global__ __launch_bounds__(256) void k_out_fwd(int64_t rows, int in, int out, const float *__restrict__ A, int lda,
+                                                 const float *__restrict__ W, const float *__restrict__ b,
+                                                 float *__restrict__ C, int ldc) {
+    __shared__ float sA[kOutRows][kOutMaxIn + 1];
+    __shared__ float sW[kOutMaxOut][kOutMaxIn];
+    const int64_t r0 = (int64_t)blockIdx.x * kOutRows;
+    for (int e = threadIdx.x; e < kOutRows * in; e += 256) {
+        const int rr = e / in, k = e % in;
+        sA[rr][k] = r0 + rr < rows ? A[(r0 + rr) * lda + k] : 0.0f;
+    }
+    for (int e = threadIdx.x; e < out * in; e += 256) sW[e / in][e % in] = W[e];
+    __syncthreads();
+    const int rr = threadIdx.x >> 2, q0 = threadIdx.x & 3;
+    const int64_t r = r0 + rr;
+    if (r >= rows) return;
+    for (int o = q0; o < out; o += 4) {
+        double s = 0.0;
+        for (int k = 0; k < in; ++k) s += (double)sA[rr][k] * (double)sW[o][k];
+        C[r * ldc + o] = (float)(s + (double)b[o]);
+    }
+}
+
+// zbar[r][q] = (sum_o ybar[r][o] W[o][q]) * SiLU'(Z[r][q])
+__global__ void k_out_vjp(int64_t rows, int out, int in, const float *__restrict__ G, int ldg,
+                          const float *__restrict__ W, const float *__restrict__ Z, int ldz, float *__restrict__ C,
+                          int ldc) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * in) return;
+    const int64_t r = t / in;
+    const int q = (int)(t % in);
+    float s = 0.0f;
+    for (int o = 0; o < out; ++o) s += G[r * ldg + o] * W[(int64_t)o * in + q];
+    C[r * ldc + q] = s * dsilu(Z[r * ldz + q]);
+}
+
+void out_layer_fwd(hipStream_t st, int64_t rows, int in, int out, const float *A, int lda, const float *W,
+                   const float *b, float *C, int ldc) {
+    if (rows <= 0) return;
+    if (in > kOutMaxIn || out > kOutMaxOut) {   // wide layers: the tiled kernel (also FP64-accumulated)
+        dense(st, false, EPI_BIAS, true, rows, in, out, A, lda, W, b, nullptr, 0, C, ldc);
+        return;
+    }
+    hipLaunchKernelGGL(k_out_fwd, dim3(grid_for(rows, kOutRows)), dim3(256), 0, st, rows, in, out, A, lda, W, b, C, ldc);
+    LAUNCH_OK("k_out_fwd");
+}
+
+void out_layer_vjp(hipStream_t st, int64_t rows, int out, int in, const float *G, int ldg, const float *W,
+                   const float *Z, int ldz, float *C, int ldc) {
+    if (rows <= 0) return;
+    const int64_t tot = rows * in;
+    hipLaunchKernelGGL(k_out_vjp, dim3(grid_for(tot, 256)), dim3(256), 0, st, rows, out, in, G, ldg, W, Z, ldz, C, ldc);
+    LAUNCH_OK("k_out_vjp");
 }
 
 template <typename R>

@@ -27,6 +27,13 @@ enum Epi { EPI_BIAS_SILU = 0, EPI_BIAS = 1, EPI_DSILU = 2, EPI_NONE = 3 };
 void dense(hipStream_t st, bool fp64, Epi epi, bool trans_w, int64_t rows, int in, int out, const void *A, int lda,
            const void *W, const void *b, void *Z, int ldz, void *C, int ldc);
 
+// Output layer of an atomic NN (FP32 data, FP64 accumulation): C = A W^T + b, W [out][in].
+void out_layer_fwd(hipStream_t st, int64_t rows, int in, int out, const float *A, int lda, const float *W,
+                   const float *b, float *C, int ldc);
+// Its adjoint into the last hidden layer: C[r][q] = (sum_o G[r][o] W[o][q]) * SiLU'(Z[r][q]).
+void out_layer_vjp(hipStream_t st, int64_t rows, int out, int in, const float *G, int ldg, const float *W,
+                   const float *Z, int ldz, float *C, int ldc);
+
 // Eat[perm[i]] = scale * y[i] (FP64), and per-block partial sums of Eat in local order.
 int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const void *y, const int32_t *perm,
                     double *Eat_user, double *partials);

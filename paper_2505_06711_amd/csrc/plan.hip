@@ -324,8 +324,12 @@ void Plan::nn_forward(hipStream_t st, int t, bool energy) {
         }
         char *out = energy ? y.as<char>() + (size_t)a * rs : cptr(t + 1) + (size_t)a * K * rs;
         const int dout = energy ? 1 : K;
-        dense(st, fp64, EPI_BIAS, true, rows, H, dout, A, lda, p + lay.w_off[nh] * rs, p + lay.b_off[nh] * rs,
-              nullptr, 0, out, dout);
+        if (fp64)
+            dense(st, fp64, EPI_BIAS, true, rows, H, dout, A, lda, p + lay.w_off[nh] * rs, p + lay.b_off[nh] * rs,
+                  nullptr, 0, out, dout);
+        else
+            out_layer_fwd(st, rows, H, dout, (const float *)A, lda, (const float *)(p + lay.w_off[nh] * rs),
+                          (const float *)(p + lay.b_off[nh] * rs), (float *)out, dout);
     }
 }
 
@@ -351,9 +355,12 @@ void Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg)
         for (int k = nh; k >= 1; --k) {
             char *dst = bufs[cur] + (size_t)a * H * rs;
             const char *Zk = Zptr(t, k - 1) + (size_t)a * H * rs;
-            if (fp64 || k == nh) {   // the output layer's adjoint has few inputs: VALU kernel
+            if (fp64) {
                 dense(st, fp64, EPI_DSILU, false, rows, lay.dout[k], lay.din[k], gin, ldin, p + lay.w_off[k] * rs,
                       nullptr, (void *)Zk, H, dst, H);
+            } else if (k == nh) {   // the output layer's adjoint has few inputs
+                out_layer_vjp(st, rows, lay.dout[k], lay.din[k], (const float *)gin, ldin,
+                              (const float *)(p + lay.w_off[k] * rs), (const float *)Zk, H, (float *)dst, H);
             } else {
                 const size_t qi = (size_t)nn_index * nh + k;
                 if (op == OpType::FP8)

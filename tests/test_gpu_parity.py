@@ -341,3 +341,42 @@ def test_precision_ladder_reports(rn, ctx, oracle_lib, prec):
     lim_e, lim_f = (2e-2, 5e-2) if prec == "bf16" else (3e-1, 5e-1)
     assert rel_energy(E, ref) <= lim_e
     assert rel_force_rmse(F, ref) <= lim_f
+
+
+@pytest.mark.parametrize("T", [2, 3])
+def test_water1207296_decomposed_equals_whole_fp64(rn, ctx, T):
+    """The 1,207,296-atom water box split 2x2x2 with per-layer ghost gathers equals the
+    whole-system evaluation in FP64 (Sec. 2.2: no redundant computation, same result), and
+    both match the oracle's stored values (tests/golden/make_golden.py)."""
+    import torch
+    from tests.golden.make_golden import positions_digest
+    w = synth.workload("water1207296")
+    s, m = w["system"], w["model"]
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
+    model = rn.Model(m)
+    out = {}
+    for dec in ((1, 1, 1), (2, 2, 2)):
+        plan = rn.Plan(ctx, model, s, T=T, precision="fp64", decomp=dec, skin=w["skin"])
+        e = torch.zeros((), dtype=torch.float64, device="cuda")
+        ae = torch.zeros(len(s["pos"]), dtype=torch.float64, device="cuda")
+        F = torch.zeros_like(pos)
+        W = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+        plan.forward(pos, e, ae)
+        plan.backward(F, virial=W)
+        torch.cuda.synchronize()
+        out[dec] = (float(e), ae.cpu().numpy(), F.cpu().numpy(), W.cpu().numpy())
+        del plan
+    a, b = out[(1, 1, 1)], out[(2, 2, 2)]
+    den = np.abs(a[1]).sum()
+    print("T=%d whole E=%.10f split E=%.10f rel %.2e" % (T, a[0], b[0], abs(a[0] - b[0]) / den), flush=True)
+    assert abs(a[0] - b[0]) <= 1e-12 * den
+    assert np.abs(a[2] - b[2]).max() <= 1e-10 * np.abs(a[2]).max()
+    assert np.abs(a[3] - b[3]).max() <= 1e-10 * np.abs(a[3]).max()
+    g = _golden("water1207296", T)
+    assert positions_digest(s["pos"]) == g["positions_sha256"]
+    idx = np.array(g["sample_index"])
+    assert abs(b[0] - g["energy"]) <= 1e-12 * g["sum_abs_atom_energy"]
+    np.testing.assert_allclose(b[1][idx], g["sample_atom_energy"], rtol=0,
+                               atol=1e-11 * np.abs(g["sample_atom_energy"]).max())
+    np.testing.assert_allclose(b[2][idx], np.array(g["sample_forces"]).reshape(-1, 3), rtol=0,
+                               atol=1e-10 * np.abs(b[2]).max())
