@@ -225,4 +225,312 @@ void convert_operand(hipStream_t st, OpType op, const float *src, int rows, int 
     LAUNCH_OK("k_convert");
 }
 
+// ------------------------------------------------------- fused atomic NNs --
+//
+// One workgroup takes kFuseBM rows of one element's NN through every layer; the activations
+// stay in LDS between layers and only the pre-activations Z_k (needed by the adjoint) and
+// the outputs reach HBM.  Each of the 4 waves owns every row of the tile and the column
+// blocks j = wave + 4 jj of the layer output; its weight fragments come straight from
+// global memory (every tile reads the same weights, so they stay in cache) one K chunk
+// ahead of the matrix instructions.
+//
+// Operand order inside a K chunk: lane l (row or column l % 16, group g = l / 16) holds a
+// contiguous run of k; for FP32 the run is 4 long and sub-step s of the chunk uses element s,
+// so the instruction's k index g stands for k0 + 4 g + s on both operands (the contraction
+// is a sum over k, so any common order of k gives the same product).
+
+namespace {
+
+constexpr int kFuseWaves = 4;
+constexpr int kOutParts = 8;   // threads per row in the output layer (kFuseBM * kOutParts = 256)
+static_assert(kFuseBM * kOutParts == 256, "output layer mapping");
+
+template <OpType OP> struct Fuse;
+template <> struct Fuse<OpType::F32> {
+    using T = float;
+    static constexpr int KC = 16;    // k per chunk
+    static constexpr int PAD = 4;    // LDS row padding (elements): row stride = 4 banks mod 64
+};
+template <> struct Fuse<OpType::BF16> {
+    using T = uint16_t;
+    static constexpr int KC = 32;
+    static constexpr int PAD = 8;
+};
+
+typedef float fl4 __attribute__((ext_vector_type(4)));
+
+// acc[rb][cb] = sum_k X[16 rb + i][k] Wt[16 (wave + 4 cb) + j][k] over k < kin (a multiple of
+// the chunk).  Columns at or past `out` read row 0 of Wt; the caller never stores them.
+template <OpType OP, int NCB>
+__device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const typename Fuse<OP>::T *__restrict__ Wt,
+                                   int ldw, int kin, int out, int wave, int lane, f4 (&acc)[kFuseBM / 16][NCB]) {
+    constexpr int RB = kFuseBM / 16, KC = Fuse<OP>::KC;
+    const int li = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+    const typename Fuse<OP>::T *wrow[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        const int col = 16 * (wave + kFuseWaves * cb) + li;
+        wrow[cb] = Wt + (size_t)(col < out ? col : 0) * ldw;
+    }
+    if constexpr (OP == OpType::F32) {
+        fl4 b[NCB], bn[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const fl4 *>(wrow[cb] + 4 * lg);
+        for (int k0 = 0; k0 < kin; k0 += KC) {
+            const int kn = k0 + KC < kin ? k0 + KC : k0;   // the last chunk reloads itself
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) bn[cb] = *reinterpret_cast<const fl4 *>(wrow[cb] + kn + 4 * lg);
+            fl4 a[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) a[rb] = *reinterpret_cast<const fl4 *>(X + (16 * rb + li) * ldx + k0 + 4 * lg);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s], b[cb][s], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) b[cb] = bn[cb];
+        }
+    } else {
+        u16x8 b[NCB], bn[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const u16x8 *>(wrow[cb] + 8 * lg);
+        for (int k0 = 0; k0 < kin; k0 += KC) {
+            const int kn = k0 + KC < kin ? k0 + KC : k0;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) bn[cb] = *reinterpret_cast<const u16x8 *>(wrow[cb] + kn + 8 * lg);
+            u16x8 a[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) a[rb] = *reinterpret_cast<const u16x8 *>(X + (16 * rb + li) * ldx + k0 + 8 * lg);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, a[rb]), __builtin_bit_cast(bf16x8, b[cb]), acc[rb][cb], 0, 0, 0);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) b[cb] = bn[cb];
+        }
+    }
+}
+
+}  // namespace
+
+// Forward of one element's NN over rows [0, rows): C = out_layer(SiLU(... SiLU(A W_0^T + b_0) ...)).
+// NCB = H / 64 column blocks per wave.
+template <OpType OP, int NCB>
+__global__ __launch_bounds__(256) void k_mlp_fwd(FusedNN p) {
+    using T = typename Fuse<OP>::T;
+    constexpr int BM = kFuseBM, RB = BM / 16;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.x * BM;
+    const int F = p.F, H = p.H, Fp = pad_k(F);
+    const int ldx = (Fp > H ? Fp : H) + Fuse<OP>::PAD, ldh = H + Fuse<OP>::PAD, ldf = H + 4;
+    T *buf[2] = {reinterpret_cast<T *>(smem), reinterpret_cast<T *>(smem) + BM * ldx};
+    float *hf = reinterpret_cast<float *>(buf[1] + BM * ldh);   // FP32 copy of the last hidden layer
+    // layer-0 input, rounded to the operand type and zero padded to Fp columns: thread tid
+    // takes column tid of every row, so each wave reads one contiguous segment per row
+    {
+        float v[BM];
+#pragma unroll
+        for (int r = 0; r < BM; ++r) v[r] = (tid < F && m0 + r < p.rows) ? p.A[(m0 + r) * p.lda + tid] : 0.0f;
+        if (tid < Fp) {
+#pragma unroll
+            for (int r = 0; r < BM; ++r) buf[0][r * ldx + tid] = to_op<OP>(v[r], 1.0f);
+        }
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int k = 0; k < p.nh; ++k) {
+        const int ldin = cur == 0 ? ldx : ldh, ldout = cur == 0 ? ldh : ldx;
+        float bias[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) bias[cb] = p.b[k][16 * (wave + kFuseWaves * cb) + li];
+        f4 acc[RB][NCB];
+        fused_layer<OP, NCB>(buf[cur], ldin, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], k == 0 ? Fp : H, H, wave,
+                             lane, acc);
+        const bool last = k + 1 == p.nh;
+        T *dst = buf[cur ^ 1];
+        float *Zk = p.Z[k];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const int col = 16 * (wave + kFuseWaves * cb) + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = 16 * rb + 4 * lg + r;
+                    const int64_t row = m0 + rr;
+                    const float z = acc[rb][cb][r] + bias[cb];
+                    if (row < p.rows) Zk[row * p.ldz + col] = z;
+                    const float h = silu_f(z);
+                    dst[rr * ldout + col] = to_op<OP>(h, 1.0f);
+                    if (OP != OpType::F32 && last) hf[rr * ldf + col] = h;
+                }
+            }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // output layer (FP32 data, FP64 accumulation): W_out is staged in the buffer the last
+    // hidden layer read; kOutParts threads share a row and combine their partial sums
+    const float *hl = (OP == OpType::F32) ? reinterpret_cast<const float *>(buf[cur]) : hf;
+    const int ldl = (OP == OpType::F32) ? (cur == 0 ? ldx : ldh) : ldf;
+    float *wo = reinterpret_cast<float *>(buf[cur ^ 1]);
+    for (int e = tid; e < p.dout * H; e += 256) wo[e] = p.Wout[e];
+    __syncthreads();
+    constexpr int QM = kFuseMaxH / kOutParts;
+    const int row = tid / kOutParts, part = tid % kOutParts, qn = H / kOutParts;
+    float hv[QM];
+#pragma unroll
+    for (int j = 0; j < QM; ++j) hv[j] = j < qn ? hl[row * ldl + part * qn + j] : 0.0f;
+    const int64_t grow = m0 + row;
+    for (int o = 0; o < p.dout; ++o) {
+        const float *w = wo + o * H + part * qn;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < QM; ++j)
+            if (j < qn) s += (double)hv[j] * (double)w[j];
+#pragma unroll
+        for (int d = 1; d < kOutParts; d <<= 1) s += __shfl_xor(s, d, kOutParts);
+        if (part == 0 && grow < p.rows) p.C[grow * p.ldc + o] = (float)(s + (double)p.bout[o]);
+    }
+}
+
+// Adjoint of one element's NN: C = dE/dA from G = dE/d(output), using the stored Z_k.
+// NCB = H / 64 and NCBF = column blocks per wave of the F-wide first layer.
+template <OpType OP, int NCB, int NCBF>
+__global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
+    using T = typename Fuse<OP>::T;
+    constexpr int BM = kFuseBM, RB = BM / 16;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.x * BM;
+    const int F = p.F, H = p.H, dout = p.dout;
+    const int ldh = H + Fuse<OP>::PAD;
+    T *buf[2] = {reinterpret_cast<T *>(smem), reinterpret_cast<T *>(smem) + BM * ldh};
+    float *wo = reinterpret_cast<float *>(buf[1] + BM * ldh);   // W_out [dout][H]
+    float *gs = wo + dout * H;                                    // G tile [BM][dout]
+    // output layer: zbar[r][q] = (sum_o G[r][o] Wout[o][q]) * SiLU'(Z_{nh-1}[r][q]); thread tid
+    // takes column q = tid % H of rows r0, r0 + 256 / H, ...
+    {
+        for (int e = tid; e < dout * H; e += 256) wo[e] = p.Wout[e];
+        for (int e = tid; e < BM * dout; e += 256) {
+            const int r = e / dout, o = e % dout;
+            gs[e] = m0 + r < p.rows ? p.G[(m0 + r) * p.ldg + o] : 0.0f;
+        }
+        constexpr int NR = BM * kFuseMaxH / 256;
+        const int q = tid % H, r0 = tid / H, rstep = 256 / H, nr = BM / rstep;
+        const float *Zl = p.Z[p.nh - 1];
+        float z[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int64_t row = m0 + r0 + rstep * i;
+            z[i] = (i < nr && row < p.rows) ? Zl[row * p.ldz + q] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (i >= nr) continue;
+            const int r = r0 + rstep * i;
+            float s = 0.0f;
+            for (int o = 0; o < dout; ++o) s += gs[r * dout + o] * wo[o * H + q];
+            const float v = m0 + r < p.rows ? s * dsilu_f(z[i]) : 0.0f;
+            buf[0][r * ldh + q] = to_op<OP>(v, 1.0f);
+        }
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int k = p.nh - 1; k >= 1; --k) {
+        const float *Zk = p.Z[k - 1];
+        float zp[RB][NCB][4];   // issued before the matrix loop so their latency is hidden
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + 16 * rb + 4 * lg + r;
+                    const int col = 16 * (wave + kFuseWaves * cb) + li;
+                    zp[rb][cb][r] = row < p.rows ? Zk[row * p.ldz + col] : 0.0f;
+                }
+        f4 acc[RB][NCB];
+        fused_layer<OP, NCB>(buf[cur], ldh, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], H, H, wave, lane, acc);
+        T *dst = buf[cur ^ 1];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const int col = 16 * (wave + kFuseWaves * cb) + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = 16 * rb + 4 * lg + r;
+                    const float v = m0 + rr < p.rows ? acc[rb][cb][r] * dsilu_f(zp[rb][cb][r]) : 0.0f;
+                    dst[rr * ldh + col] = to_op<OP>(v, 1.0f);
+                }
+            }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // first layer: C = zbar_0 W_0 (F columns)
+    f4 acc[RB][NCBF];
+    fused_layer<OP, NCBF>(buf[cur], ldh, reinterpret_cast<const T *>(p.W[0]), p.ldw[0], H, F, wave, lane, acc);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCBF; ++cb) {
+            const int col = 16 * (wave + kFuseWaves * cb) + li;
+            if (col >= F) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + 16 * rb + 4 * lg + r;
+                if (row < p.rows) p.C[row * p.ldc + col] = acc[rb][cb][r];
+            }
+        }
+}
+
+bool fused_nn_ok(OpType op, int F, int H, int nh, int dout) {
+    return op != OpType::FP8 && (H == 64 || H == 128) && F >= 1 && F <= kFuseMaxF && nh >= 1 && nh <= kFuseMaxNh &&
+           dout >= 1 && dout <= kFuseMaxOut;
+}
+
+static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout) {
+    const size_t eb = op_bytes(op), pad = op == OpType::F32 ? 4 : 8;
+    const size_t Fp = pad_k(F), ldh = H + pad;
+    if (!fwd) return 2 * kFuseBM * ldh * eb + (size_t)(dout * H + kFuseBM * dout) * 4;
+    const size_t ldx = std::max<size_t>(Fp, H) + pad;
+    size_t b = kFuseBM * (ldx + ldh) * eb;
+    if (op != OpType::F32) b += (size_t)kFuseBM * (H + 4) * 4;
+    return b;
+}
+
+void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
+    if (p.rows <= 0) return;
+    if (!fused_nn_ok(op, p.F, p.H, p.nh, p.dout)) fail(REANN_E_DEVICE, "mlp_fused: unsupported layer shape");
+    const size_t smem = fused_smem(op, fwd, p.F, p.H, p.dout);
+    const dim3 grid((unsigned)((p.rows + kFuseBM - 1) / kFuseBM));
+    const bool h128 = p.H == 128, f256 = p.F > 128;
+#define FWD_(OPV, NC) hipLaunchKernelGGL((k_mlp_fwd<OPV, NC>), grid, dim3(256), smem, st, p)
+#define BWD_(OPV, NC, NF) hipLaunchKernelGGL((k_mlp_bwd<OPV, NC, NF>), grid, dim3(256), smem, st, p)
+#define ALL_(OPV)                                                                \
+    if (fwd) {                                                                   \
+        if (h128) FWD_(OPV, 2); else FWD_(OPV, 1);                               \
+    } else {                                                                     \
+        if (h128) { if (f256) BWD_(OPV, 2, 4); else BWD_(OPV, 2, 2); }           \
+        else { if (f256) BWD_(OPV, 1, 4); else BWD_(OPV, 1, 2); }                \
+    }
+    if (op == OpType::F32) { ALL_(OpType::F32) }
+    else { ALL_(OpType::BF16) }
+#undef ALL_
+#undef BWD_
+#undef FWD_
+    LAUNCH_OK(fwd ? "k_mlp_fwd" : "k_mlp_bwd");
+}
+
 }  // namespace reann

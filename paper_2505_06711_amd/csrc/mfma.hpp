@@ -12,7 +12,7 @@ enum class OpType { F32 = 0, BF16 = 1, FP8 = 2 };
 
 constexpr int kMfmaKC = 32;   // K chunk staged per iteration; weight rows are padded to it
 
-inline int pad_k(int in) { return (in + kMfmaKC - 1) / kMfmaKC * kMfmaKC; }
+__host__ __device__ inline int pad_k(int in) { return (in + kMfmaKC - 1) / kMfmaKC * kMfmaKC; }
 
 // Wt: operand-typed [out][ldw] (ldw = pad_k(in), zero padded).  FP8 only: sA / sW are the
 // device scales of A (amax/448, see amax_scale) and of Wt; the product is rescaled by both.
@@ -27,6 +27,37 @@ void amax_scale(hipStream_t st, const float *A, int64_t rows, int cols, int lda,
 // for FP8 the values are divided by *scale first.
 void convert_operand(hipStream_t st, OpType op, const float *src, int rows, int cols, int ld_src, void *dst,
                      int ld_dst, const float *scale);
+
+// Fused atomic NN (every layer of one element's NN in one launch, FP32 or BF16 operands).
+constexpr int kFuseBM = 32;      // rows per workgroup
+constexpr int kFuseMaxH = 128;   // hidden width (64 or 128)
+constexpr int kFuseMaxF = 256;   // input width
+constexpr int kFuseMaxNh = 4;    // hidden layers
+constexpr int kFuseMaxOut = 16;  // output width
+
+struct FusedNN {
+    int64_t rows;                 // rows of this element's segment
+    int F, H, nh, dout;           // input width, hidden width, hidden layers, output width
+    const float *A;               // forward: input [rows][lda]
+    int lda;
+    // forward: W[k] = layer k as [out][ldw] (gemm_mfma's forward operand)
+    // adjoint: W[k] = layer k transposed, [in][ldw]
+    const void *W[kFuseMaxNh];
+    int ldw[kFuseMaxNh];
+    const float *b[kFuseMaxNh];   // forward: hidden-layer biases
+    float *Z[kFuseMaxNh];         // pre-activations [rows][ldz]: written by forward, read by adjoint
+    int ldz;
+    const float *Wout, *bout;     // output layer [dout][H], [dout] (FP32)
+    const float *G;               // adjoint: output adjoint [rows][ldg]
+    int ldg;
+    float *C;                     // forward: outputs [rows][ldc]; adjoint: dE/dA [rows][ldc]
+    int ldc;
+};
+
+bool fused_nn_ok(OpType op, int F, int H, int nh, int dout);
+// Forward (fwd = true: hidden layers, Z stores, output layer with FP64 accumulation) or
+// adjoint (fwd = false: output layer, hidden layers, dE/dA) of one element's NN.
+void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p);
 
 inline size_t op_bytes(OpType op) { return op == OpType::F32 ? 4 : (op == OpType::BF16 ? 2 : 1); }
 

@@ -305,6 +305,26 @@ void Plan::nn_forward(hipStream_t st, int t, bool energy) {
         const char *A = rhoptr(t) + (size_t)a * F * rs;
         int lda = F;
         const MfmaSet *mf = fp64 ? nullptr : &m->mfma(ctx->device, st, energy, op);
+        char *out = energy ? y.as<char>() + (size_t)a * rs : cptr(t + 1) + (size_t)a * K * rs;
+        const int dout = energy ? 1 : K;
+        if (!fp64 && fused_nn_ok(op, F, H, nh, dout)) {
+            FusedNN f{};
+            f.rows = rows; f.F = F; f.H = H; f.nh = nh; f.dout = dout;
+            f.A = (const float *)A; f.lda = lda;
+            for (int k = 0; k < nh; ++k) {
+                const size_t qi = (size_t)nn_index * nh + k;
+                f.W[k] = mf->buf.as<char>() + mf->off_fwd[qi];
+                f.ldw[k] = mf->ld_fwd[qi];
+                f.b[k] = (const float *)(p + lay.b_off[k] * rs);
+                f.Z[k] = (float *)(Zptr(t, k) + (size_t)a * H * rs);
+            }
+            f.ldz = H;
+            f.Wout = (const float *)(p + lay.w_off[nh] * rs);
+            f.bout = (const float *)(p + lay.b_off[nh] * rs);
+            f.C = (float *)out; f.ldc = dout;
+            mlp_fused(st, op, true, f);
+            continue;
+        }
         for (int k = 0; k < nh; ++k) {
             char *Zk = Zptr(t, k) + (size_t)a * H * rs;
             char *Hk = Hptr(t, k) + (size_t)a * H * rs;
@@ -322,8 +342,6 @@ void Plan::nn_forward(hipStream_t st, int t, bool energy) {
             A = Hk;
             lda = H;
         }
-        char *out = energy ? y.as<char>() + (size_t)a * rs : cptr(t + 1) + (size_t)a * K * rs;
-        const int dout = energy ? 1 : K;
         if (fp64)
             dense(st, fp64, EPI_BIAS, true, rows, H, dout, A, lda, p + lay.w_off[nh] * rs, p + lay.b_off[nh] * rs,
                   nullptr, 0, out, dout);
@@ -352,6 +370,22 @@ void Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg)
         char *bufs[2] = {gA.as<char>(), gB.as<char>()};
         int cur = 0;
         const MfmaSet *mf = fp64 ? nullptr : &m->mfma(ctx->device, st, energy, op);
+        if (!fp64 && fused_nn_ok(op, F, H, nh, lay.dout[nh])) {
+            FusedNN f{};
+            f.rows = rows; f.F = F; f.H = H; f.nh = nh; f.dout = lay.dout[nh];
+            for (int k = 0; k < nh; ++k) {
+                const size_t qi = (size_t)nn_index * nh + k;
+                f.W[k] = mf->buf.as<char>() + mf->off_bwd[qi];
+                f.ldw[k] = mf->ld_bwd[qi];
+                f.Z[k] = (float *)(Zptr(t, k) + (size_t)a * H * rs);
+            }
+            f.ldz = H;
+            f.Wout = (const float *)(p + lay.w_off[nh] * rs);
+            f.G = (const float *)gin; f.ldg = ldin;
+            f.C = (float *)(rhobar.as<char>() + (size_t)a * F * rs); f.ldc = F;
+            mlp_fused(st, op, false, f);
+            continue;
+        }
         for (int k = nh; k >= 1; --k) {
             char *dst = bufs[cur] + (size_t)a * H * rs;
             const char *Zk = Zptr(t, k - 1) + (size_t)a * H * rs;
