@@ -8,11 +8,12 @@
 //   g_ij = d/dd [ f_c sum_lambda A_lambda(d) sum_m Sbar_i[lambda][m] c_j[m] R_m(r) ],
 // contributing +g_ij to F_i, -g_ij to F_j, -d (x) g_ij to the virial and
 //   f_c R_m sum_lambda Sbar_i[lambda][m] A_lambda(d)  to  cbar_j[m] = dE/dc_j[m].
-// No atomics: every ext row k gathers what lands on k -- as centre (its own edges, one
-// kernel) and as neighbour (the edges j->k of its local neighbours j, whose Sbar it
-// reads, a second kernel).  Each edge is evaluated at both ends; sums over a row's
-// edges are taken across the 32 lanes of a half-wave in a fixed order, so results are
-// deterministic.
+// No atomics: the centre-role kernel evaluates each edge i->j once (Sbar_i staged in LDS)
+// and keeps +g_ij for F_i and the virial; what lands on j (-g_ij and the cbar_j terms) is
+// written as a record at the edge's list slot.  The neighbour-role kernel then gives every
+// ext row k the sum of the records of its edges j->k, found through the list's reverse
+// slots.  Sums over a row's edges are taken across the lanes of a half-wave in a fixed
+// order, so results are deterministic.
 #include "edge.hpp"
 
 namespace reann {
@@ -69,8 +70,8 @@ __device__ inline void angular(R ux, R uy, R uz, R s, R *A, R (*dA)[3]) {
 // in-cutoff local neighbours are packed at the front of its slot range and its in-cutoff
 // ghost neighbours at the back (reverse order).  Every later pass of the step reads only
 // these entries.
-__global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, int32_t *__restrict__ nloc,
-                          int32_t *__restrict__ ngh) {
+__global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, int32_t *__restrict__ fslot,
+                          int32_t *__restrict__ nloc, int32_t *__restrict__ ngh) {
     // 16 lanes per row take the row's entries 16 at a time; a ballot gives each in-cutoff
     // entry its rank, so the packed order equals a sequential scan of the row
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -94,8 +95,16 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
         }
         const uint32_t ml = (uint32_t)(__ballot(isl) >> gbase) & 0xffffu;
         const uint32_t mg = (uint32_t)(__ballot(isg) >> gbase) & 0xffffu;
-        if (isl) col2[front + __popc(ml & below)] = j;
-        if (isg) col2[back - 1 - __popc(mg & below)] = j;
+        if (isl) {
+            const int64_t d = front + __popc(ml & below);
+            col2[d] = j;
+            fslot[d] = (int32_t)k;
+        }
+        if (isg) {
+            const int64_t d = back - 1 - __popc(mg & below);
+            col2[d] = j;
+            fslot[d] = (int32_t)k;
+        }
         front += __popc(ml);
         back -= __popc(mg);
     }
@@ -188,6 +197,23 @@ __device__ inline void edge_geo(const EdgeConsts &ec, double dx, double dy, doub
     }
 }
 
+// 16-byte vector stores / loads of 4 consecutive values (edge records are 16-byte aligned)
+__device__ inline void st4(float *p, float a, float b, float c, float d) {
+    *reinterpret_cast<float4 *>(p) = make_float4(a, b, c, d);
+}
+__device__ inline void st4(double *p, double a, double b, double c, double d) {
+    reinterpret_cast<double2 *>(p)[0] = make_double2(a, b);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(c, d);
+}
+__device__ inline void add4(const float *p, float (&v)[4]) {
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    v[0] += t.x; v[1] += t.y; v[2] += t.z; v[3] += t.w;
+}
+__device__ inline void add4(const double *p, double (&v)[4]) {
+    const double2 t0 = reinterpret_cast<const double2 *>(p)[0], t1 = reinterpret_cast<const double2 *>(p)[1];
+    v[0] += t0.x; v[1] += t0.y; v[2] += t1.x; v[3] += t1.y;
+}
+
 template <typename R> __device__ inline R hw_sum(R v) {   // sum over the 32 lanes of a half-wave
 #pragma unroll
     for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
@@ -198,13 +224,17 @@ constexpr int kRowsPerBlock = 8;   // 256 threads = 8 half-waves, one row each
 
 // Centre role: for local row k and each in-cutoff neighbour j (edge k -> j),
 //   g = d/dd [ f_c sum_lambda A_lambda(d) sum_m Sbar_k[lambda][m] c_j[m] R_m(r) ]
-// adds +g to F_k and -d (x) g to the virial.  Sbar_k is staged in LDS and read by all
-// 32 lanes of its half-wave; lanes take the row's edges in turn.
-template <int L, int K, typename R>
+// adds +g to F_k and -d (x) g to the virial; the edge's record gets g and (CBAR) the terms
+//   f_c R_m sum_lambda Sbar_k[lambda][m] A_lambda(d)  of  cbar_j[m].
+// Sbar_k is staged in LDS and read by all 32 lanes of its half-wave; lanes take the row's
+// edges in turn.  Record of list slot f: rec[f * RS + 0..2] = g, rec[f * RS + 4 + m] = terms
+// (RS = 4 + K with CBAR, 4 without).
+template <int L, int K, typename R, bool CBAR>
 __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, EdgeConsts ec, const R *__restrict__ c,
                                                     const R *__restrict__ Sbar, R *__restrict__ F,
-                                                    double *__restrict__ Wpart) {
+                                                    double *__restrict__ Wpart, R *__restrict__ rec) {
     constexpr int NL = n_lambda(L);
+    constexpr int RS = CBAR ? 4 + K : 4;
     __shared__ R sS[kRowsPerBlock][NL * K];
     __shared__ double sW[kRowsPerBlock][9];
     const int hw = threadIdx.x >> 5, lane = threadIdx.x & 31;
@@ -228,28 +258,48 @@ __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, Edge
             // keep Sbar_k in LDS: without this the compiler hoists all NL*K reads out of
             // the loop into registers, which caps occupancy
             asm volatile("" ::: "memory");
-            const int64_t j = cl.col[cut_slot(cl, x, e)];
+            const int64_t slot = cut_slot(cl, x, e);
+            const int64_t j = cl.col[slot];
+            const int64_t f = cl.fslot[slot];
             const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
             EdgeGeo<K, R> g;
             edge_geo<K, R>(ec, dx, dy, dz, g);
             R A[NL], dA[NL][3];
             angular<L, R, true>(R(ec.ang_scale * dx), R(ec.ang_scale * dy), R(ec.ang_scale * dz), s, A, dA);
             const R *cj = c + j * K;
-            R u[K], v[K];
+            R u[K], v[K], cacc[K];
 #pragma unroll
-            for (int m = 0; m < K; ++m) { const R cm = cj[m]; u[m] = cm * g.Rm[m]; v[m] = cm * g.dRm[m]; }
+            for (int m = 0; m < K; ++m) {
+                const R cm = cj[m];
+                u[m] = cm * g.Rm[m];
+                v[m] = cm * g.dRm[m];
+                cacc[m] = R(0);
+            }
             R gx = R(0), gy = R(0), gz = R(0), sAP = R(0), sAQ = R(0);
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
                 R P = R(0), Q = R(0);
 #pragma unroll
-                for (int m = 0; m < K; ++m) { const R w = sb[l * K + m]; P += w * u[m]; Q += w * v[m]; }
+                for (int m = 0; m < K; ++m) {
+                    const R w = sb[l * K + m];
+                    P += w * u[m];
+                    Q += w * v[m];
+                    if constexpr (CBAR) cacc[m] += w * A[l];
+                }
                 gx += P * dA[l][0]; gy += P * dA[l][1]; gz += P * dA[l][2];
                 sAP += A[l] * P; sAQ += A[l] * Q;
             }
             const R rad = g.dfc * sAP + g.fc * sAQ;
             gx = g.fc * gx + rad * g.ex; gy = g.fc * gy + rad * g.ey; gz = g.fc * gz + rad * g.ez;
             f0 += gx; f1 += gy; f2 += gz;
+            R *out = rec + f * RS;
+            st4(out, gx, gy, gz, R(0));
+            if constexpr (CBAR) {
+#pragma unroll
+                for (int m = 0; m < K; m += 4)
+                    st4(out + 4 + m, g.fc * g.Rm[m] * cacc[m], g.fc * g.Rm[m + 1] * cacc[m + 1],
+                        g.fc * g.Rm[m + 2] * cacc[m + 2], g.fc * g.Rm[m + 3] * cacc[m + 3]);
+            }
             const double gd[3] = {double(gx), double(gy), double(gz)}, dd[3] = {dx, dy, dz};
 #pragma unroll
             for (int p = 0; p < 3; ++p)
@@ -273,74 +323,39 @@ __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, Edge
     }
 }
 
-// Neighbour role: for ext row k (local or ghost) and each in-cutoff *local* neighbour j,
-// the edge j -> k (centre j, displacement -d) gives
-//   g' = d/dd' [ f_c sum_lambda A_lambda(-d) sum_m Sbar_j[lambda][m] c_k[m] R_m(r) ]
-// which adds -g' to F_k, and f_c R_m sum_lambda Sbar_j[lambda][m] A_lambda(-d) to cbar_k[m].
-template <int L, int K, typename R, bool CBAR>
-__global__ __launch_bounds__(256) void k_adj_neighbour(EdgeArgs a, CutList cl, EdgeConsts ec,
-                                                       const R *__restrict__ c, const R *__restrict__ Sbar,
-                                                       R *__restrict__ F, R *__restrict__ cbar) {
-    constexpr int NL = n_lambda(L);
+// Neighbour role: ext row k (local or ghost) sums the records of the edges j -> k over its
+// in-cutoff local neighbours j (slot rev[fslot] of each entry): F_k -= sum g and, with
+// CBAR, cbar_k[m] = sum of the terms.  With CBAR 4 lanes share an edge record (one group
+// of 4 values each, 8 edges per pass of the half-wave); without it a lane takes an edge.
+template <int K, typename R, bool CBAR>
+__global__ __launch_bounds__(256) void k_adj_gather(EdgeArgs a, CutList cl, const R *__restrict__ rec,
+                                                    R *__restrict__ F, R *__restrict__ cbar) {
+    constexpr int RS = CBAR ? 4 + K : 4;
+    constexpr int NP = RS / 4;              // groups of 4 values per record
+    constexpr int LPE = CBAR ? 4 : 1;       // lanes per edge
+    constexpr int EPP = 32 / LPE;           // edges per pass
+    static_assert(K % 4 == 0 && (NP <= LPE || !CBAR), "record layout");
     const int hw = threadIdx.x >> 5, lane = threadIdx.x & 31;
     const int64_t x = (int64_t)blockIdx.x * kRowsPerBlock + hw;
     if (x >= a.n_ext) return;   // whole half-wave leaves together
-    R ck[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) ck[m] = c[x * K + m];
-    R f0 = R(0), f1 = R(0), f2 = R(0);
-    R cb[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) cb[m] = R(0);
-    const double xi = a.px[x], yi = a.py[x], zi = a.pz[x];
-    const R s = R(ec.ang_scale);
+    const int part = lane % LPE, eg = lane / LPE;
+    R acc[4] = {R(0), R(0), R(0), R(0)};
     const int cnt = cl.nloc[x];
     const int64_t lo = cl.row[x];
-    for (int e = lane; e < cnt; e += 32) {
-        const int64_t j = cl.col[lo + e];
-        const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
-        EdgeGeo<K, R> g;
-        edge_geo<K, R>(ec, dx, dy, dz, g);
-        R A[NL], dA[NL][3];
-        angular<L, R, true>(R(-ec.ang_scale * dx), R(-ec.ang_scale * dy), R(-ec.ang_scale * dz), s, A, dA);
-        const R *sbj = Sbar + j * NL * K;
-        R u[K], v[K], cacc[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m) { u[m] = ck[m] * g.Rm[m]; v[m] = ck[m] * g.dRm[m]; cacc[m] = R(0); }
-        R gx = R(0), gy = R(0), gz = R(0), sAP = R(0), sAQ = R(0);
-#pragma unroll
-        for (int l = 0; l < NL; ++l) {
-            R P = R(0), Q = R(0);
-#pragma unroll
-            for (int m = 0; m < K; ++m) {
-                const R w = sbj[l * K + m];
-                P += w * u[m];
-                Q += w * v[m];
-                if constexpr (CBAR) cacc[m] += w * A[l];
-            }
-            gx += P * dA[l][0]; gy += P * dA[l][1]; gz += P * dA[l][2];
-            sAP += A[l] * P; sAQ += A[l] * Q;
-        }
-        const R rad = g.dfc * sAP + g.fc * sAQ;
-        // unit vector of the edge j -> k is -e
-        f0 += g.fc * gx - rad * g.ex;
-        f1 += g.fc * gy - rad * g.ey;
-        f2 += g.fc * gz - rad * g.ez;
-        if constexpr (CBAR) {
-#pragma unroll
-            for (int m = 0; m < K; ++m) cb[m] += g.fc * g.Rm[m] * cacc[m];
-        }
+    for (int e = eg; e < cnt; e += EPP) {
+        const int64_t r = cl.rev[cl.fslot[lo + e]];
+        if (part < NP) add4(rec + r * RS + 4 * part, acc);
     }
-    f0 = hw_sum(f0); f1 = hw_sum(f1); f2 = hw_sum(f2);
-    if constexpr (CBAR) {
 #pragma unroll
-        for (int m = 0; m < K; ++m) cb[m] = hw_sum(cb[m]);
-    }
-    if (lane == 0) {
-        F[3 * x] -= f0; F[3 * x + 1] -= f1; F[3 * x + 2] -= f2;
-        if constexpr (CBAR) {
+    for (int o = LPE; o < 32; o <<= 1)
 #pragma unroll
-            for (int m = 0; m < K; ++m) cbar[x * K + m] = cb[m];
+        for (int q = 0; q < 4; ++q) acc[q] += __shfl_xor(acc[q], o, 32);
+    if (eg == 0) {
+        if (part == 0) {
+            F[3 * x] -= acc[0]; F[3 * x + 1] -= acc[1]; F[3 * x + 2] -= acc[2];
+        } else if (CBAR && part < NP) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cbar[x * K + 4 * (part - 1) + q] = acc[q];
         }
     }
 }
@@ -355,8 +370,8 @@ __global__ __launch_bounds__(256) void k_adj_neighbour(EdgeArgs a, CutList cl, E
     } while (0)
 
 void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl) {
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(a.n_ext * 16, 256)), dim3(256), 0, st, a, r_c * r_c, cl.col, cl.nloc,
-                       cl.ngh);
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(a.n_ext * 16, 256)), dim3(256), 0, st, a, r_c * r_c, cl.col, cl.fslot,
+                       cl.nloc, cl.ngh);
     LAUNCH_OK("k_compact");
 }
 
@@ -379,31 +394,26 @@ void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, co
 int edge_backward_blocks(int64_t n_ext) { return grid_for(n_ext, kRowsPerBlock); }
 
 int edge_backward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
-                  const void *c, const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart) {
+                  const void *c, const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart, void *rec) {
     const int nbc = grid_for(a.n, kRowsPerBlock), nbn = grid_for(a.n_ext, kRowsPerBlock);
-#define BWD(LL, KK)                                                                                              \
-    if (fp64) {                                                                                                  \
-        hipLaunchKernelGGL((k_adj_centre<LL, KK, double>), dim3(nbc), dim3(256), 0, st, a, cl, ec,               \
-                           (const double *)c, (const double *)Sbar, (double *)F, Wpart);                         \
-        if (want_cbar)                                                                                           \
-            hipLaunchKernelGGL((k_adj_neighbour<LL, KK, double, true>), dim3(nbn), dim3(256), 0, st, a, cl, ec,  \
-                               (const double *)c, (const double *)Sbar, (double *)F, (double *)cbar);            \
-        else                                                                                                     \
-            hipLaunchKernelGGL((k_adj_neighbour<LL, KK, double, false>), dim3(nbn), dim3(256), 0, st, a, cl, ec, \
-                               (const double *)c, (const double *)Sbar, (double *)F, (double *)cbar);            \
-    } else {                                                                                                     \
-        hipLaunchKernelGGL((k_adj_centre<LL, KK, float>), dim3(nbc), dim3(256), 0, st, a, cl, ec,                \
-                           (const float *)c, (const float *)Sbar, (float *)F, Wpart);                            \
-        if (want_cbar)                                                                                           \
-            hipLaunchKernelGGL((k_adj_neighbour<LL, KK, float, true>), dim3(nbn), dim3(256), 0, st, a, cl, ec,   \
-                               (const float *)c, (const float *)Sbar, (float *)F, (float *)cbar);               \
-        else                                                                                                     \
-            hipLaunchKernelGGL((k_adj_neighbour<LL, KK, float, false>), dim3(nbn), dim3(256), 0, st, a, cl, ec,  \
-                               (const float *)c, (const float *)Sbar, (float *)F, (float *)cbar);               \
+#define BWD_T(LL, KK, R, CB)                                                                                       \
+    hipLaunchKernelGGL((k_adj_centre<LL, KK, R, CB>), dim3(nbc), dim3(256), 0, st, a, cl, ec, (const R *)c,      \
+                       (const R *)Sbar, (R *)F, Wpart, (R *)rec);                                               \
+    LAUNCH_OK("k_adj_centre");                                                                                  \
+    hipLaunchKernelGGL((k_adj_gather<KK, R, CB>), dim3(nbn), dim3(256), 0, st, a, cl, (const R *)rec, (R *)F,    \
+                       (R *)cbar);                                                                              \
+    LAUNCH_OK("k_adj_gather");
+#define BWD(LL, KK)                                             \
+    if (fp64) {                                                 \
+        if (want_cbar) { BWD_T(LL, KK, double, true) }          \
+        else { BWD_T(LL, KK, double, false) }                   \
+    } else {                                                    \
+        if (want_cbar) { BWD_T(LL, KK, float, true) }           \
+        else { BWD_T(LL, KK, float, false) }                    \
     }
     REANN_LK_DISPATCH(L, K, BWD);
 #undef BWD
-    LAUNCH_OK("k_adj");
+#undef BWD_T
     return nbc;
 }
 

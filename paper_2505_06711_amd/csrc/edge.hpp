@@ -24,10 +24,13 @@ struct EdgeArgs {
 // In-cutoff entries of the list for the current positions (same slot ranges as the list):
 // row x's in-cutoff local neighbours at col[row[x] .. row[x] + nloc[x]), its in-cutoff
 // ghost neighbours at col[row[x+1] - ngh[x] .. row[x+1]).
+// fslot[s]: the list slot of the entry compacted into s; rev: the list's reverse slots.
 struct CutList {
     const int64_t *row;
     int32_t *col;
     int32_t *nloc, *ngh;
+    int32_t *fslot;
+    const int32_t *rev;
 };
 void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl);
 
@@ -35,12 +38,17 @@ void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl);
 void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
                   const void *c, void *S);
 
-// Atomics-free adjoint (centre role over local rows, neighbour role over every ext row).
+// Atomics-free adjoint: the centre role over local rows evaluates every edge once and
+// writes, at the edge's list slot, what it gives the neighbour end; the neighbour role
+// over every ext row sums those records through the reverse slots.
 //   Sbar [n][NL][K] (locals), c [n_ext][K]; F [n_ext][3] is accumulated;
 //   cbar [n_ext][K] is overwritten when want_cbar; Wpart receives one FP64 [9] per block
-// of the centre-role launch.  Returns the number of blocks (rows of Wpart).
+// of the centre-role launch; rec holds edge_record_elems(K) working-type values per list
+// slot.  Returns the number of blocks (rows of Wpart).
 int edge_backward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
-                  const void *c, const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart);
+                  const void *c, const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart, void *rec);
+// Values per edge record: the edge gradient (3, padded to 4) and K adjoint-message terms.
+inline int edge_record_elems(int K) { return 4 + K; }
 int edge_backward_blocks(int64_t n_ext);
 
 // c[n + g][:] = c[owner[g]][:]

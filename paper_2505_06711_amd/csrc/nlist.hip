@@ -221,6 +221,68 @@ __global__ void k_sort_segments32(int64_t nseg, const int32_t *__restrict__ star
     }
 }
 
+// Sort every row of the list ascending.  One wave per row: each entry's rank is the number
+// of smaller entries of the row (columns of a row are distinct), taken against an LDS copy;
+// a row longer than kSortLds is sorted by one lane instead.
+constexpr int kSortLds = 2048;
+
+__global__ __launch_bounds__(256) void k_sort_rows(int64_t nrow, const int64_t *__restrict__ row,
+                                                   int32_t *__restrict__ col) {
+    __shared__ int32_t sv[4][kSortLds];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t x = (int64_t)blockIdx.x * 4 + w;
+    const bool valid = x < nrow;
+    const int64_t lo = valid ? row[x] : 0;
+    const int m = valid ? (int)(row[x + 1] - lo) : 0;
+    const bool in_lds = m <= kSortLds;
+    if (in_lds)
+        for (int e = lane; e < m; e += 64) sv[w][e] = col[lo + e];
+    __syncthreads();
+    if (in_lds) {
+        for (int e = lane; e < m; e += 64) {
+            const int32_t v = sv[w][e];
+            int rank = 0;
+            for (int q = 0; q < m; ++q) rank += sv[w][q] < v;
+            col[lo + rank] = v;
+        }
+    } else if (lane == 0) {
+        for (int64_t i = lo + 1; i < lo + m; ++i) {
+            const int32_t v = col[i];
+            int64_t j = i - 1;
+            while (j >= lo && col[j] > v) { col[j + 1] = col[j]; --j; }
+            col[j + 1] = v;
+        }
+    }
+}
+
+// rev[f] for the entry f = (x -> j) of a sorted list: the slot of (j -> x) in row j when j is
+// local (binary search), -1 when j is a ghost.  Sets *bad when a reverse entry is missing.
+__global__ void k_reverse(int64_t n, int64_t n_ext, const int64_t *__restrict__ row, const int32_t *__restrict__ col,
+                          int32_t *__restrict__ rev, int32_t *__restrict__ bad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t x = t >> 4;
+    const int g = (int)(t & 15);
+    if (x >= n_ext) return;
+    const int64_t hi = row[x + 1];
+    for (int64_t f = row[x] + g; f < hi; f += 16) {
+        const int32_t j = col[f];
+        if (j >= n) { rev[f] = -1; continue; }
+        int64_t a = row[j], b = row[j + 1];
+        const int64_t end = b;
+        while (a < b) {
+            const int64_t mid = (a + b) >> 1;
+            if (col[mid] < x) a = mid + 1;
+            else b = mid;
+        }
+        if (a < end && col[a] == (int32_t)x) {
+            rev[f] = (int32_t)a;
+        } else {
+            rev[f] = -1;
+            atomicOr(bad, 1);
+        }
+    }
+}
+
 __global__ void k_build_ext(Bins b, int64_t n, int64_t n_ext, const int32_t *__restrict__ order,
                             const double *__restrict__ w, const int32_t *__restrict__ dom, const int32_t *__restrict__ species,
                             const double *__restrict__ g_pos, const int32_t *__restrict__ g_dom,
@@ -528,6 +590,20 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, n, n_ext, pext,
                        d_dom_ext, d_bin_ext, kstart, nullptr, row, col);
     LAUNCH_OK("k_rows<fill>");
+    // rows ascending, then the reverse slot of every entry with a local neighbour
+    hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n_ext, 4)), dim3(256), 0, st, n_ext, row, col);
+    LAUNCH_OK("k_sort_rows");
+    {
+        int32_t *rev = nl.rev.resize(n_pairs + 1);
+        int32_t *flag = static_cast<int32_t *>(s.flag.ensure(64));
+        HIP_OK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_reverse, dim3(grid_for(n_ext * 16, B)), dim3(B), 0, st, n, n_ext, row, col, rev, flag);
+        LAUNCH_OK("k_reverse");
+        int32_t hflag = 0;
+        HIP_OK(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (hflag) fail(REANN_E_DEVICE, "neighbour build: list is not symmetric");
+    }
 
     // owner -> ghost copies
     int32_t *copy_ptr = nl.copy_ptr.resize(n + 1);

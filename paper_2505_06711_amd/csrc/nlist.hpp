@@ -23,6 +23,7 @@ struct Geom {
 // ordered by (subdomain, spatial bin, generation order).  Rows of locals list every
 // ext atom of the same subdomain within r_c + skin; rows of ghosts list only the
 // locals of their subdomain within r_c + skin (used by the atomics-free backward).
+// Every row is sorted ascending, so its locals come before its ghosts.
 struct NList {
     Geom g{};
     int64_t n = 0, n_gh = 0, n_ext = 0, n_pairs = 0, n_local_pairs = 0;
@@ -38,13 +39,14 @@ struct NList {
     DArr<int32_t> copy_idx;      // [n_gh] ghost indices in increasing order per owner
     DArr<int64_t> row;           // [n_ext+1]
     DArr<int32_t> col;           // [n_pairs] ext indices
+    DArr<int32_t> rev;           // [n_pairs] slot of the reverse entry (j -> x) if j is local, else -1
     DArr<int8_t> spec_ext;       // [n_ext]
     DArr<double> xref;           // [n*3] caller positions at build time, local order
 };
 
 // Scratch reused between builds.
 struct NListScratch {
-    DevBuf a, b, c, d, e, f, g, h, i, j, k, l, m;
+    DevBuf a, b, c, d, e, f, g, h, i, j, k, l, m, flag;
 };
 
 void geom_init(Geom &g, const double cell[9], const int32_t pbc[3], const int32_t P[3], double r_c, double skin);

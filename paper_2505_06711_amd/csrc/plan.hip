@@ -234,6 +234,11 @@ int64_t Plan::collect_timing(double *ms7, int64_t *launches7) {
     return steps;
 }
 
+// whether both atomic NNs run as fused kernels (FP32 or BF16 operands, supported widths)
+bool Plan::fused() const {
+    return !fp64 && fused_nn_ok(op, m->F, m->H, m->nh, m->K) && fused_nn_ok(op, m->F, m->H, m->nh, 1);
+}
+
 void Plan::alloc_buffers() {
     const int K = m->K, NL = m->NL, F = m->F, H = m->H, nh = m->nh;
     const int64_t ne = nl.n_ext;
@@ -242,22 +247,26 @@ void Plan::alloc_buffers() {
     S.ensure((size_t)T * n * NL * K * rs);
     rho.ensure((size_t)T * n * F * rs);
     Z.ensure((size_t)T * nh * n * H * rs);
-    Hh.ensure((size_t)T * nh * n * H * rs);
+    if (!fused()) Hh.ensure((size_t)2 * n * H * rs);
     y.ensure((size_t)n * K * rs);
     ybar.ensure((size_t)n * rs);
     Eat.ensure((size_t)n * 8);
     Epart.ensure((size_t)(grid_for(n, 256) + 1) * 8);
     Sbar.ensure((size_t)n * NL * K * rs);
     rhobar.ensure((size_t)n * F * rs);
-    const int wmax = F > H ? F : H;
-    gA.ensure((size_t)n * wmax * rs);
-    gB.ensure((size_t)n * wmax * rs);
+    if (!fused()) {
+        const int wmax = F > H ? F : H;
+        gA.ensure((size_t)n * wmax * rs);
+        gB.ensure((size_t)n * wmax * rs);
+    }
     cbar.ensure((size_t)ne * K * rs);
     this->F.ensure((size_t)ne * 3 * rs);
     Wpart.ensure((size_t)(edge_backward_blocks(ne) + 1) * 9 * 8);
     Wacc.ensure(16 * 8);
     disp.ensure(1025 * 8);
     col2.ensure((size_t)(nl.n_pairs + 1) * 4);
+    fslot.ensure((size_t)(nl.n_pairs + 1) * 4);
+    erec.ensure((size_t)(nl.n_pairs + 1) * edge_record_elems(K) * rs);
     nloc.ensure((size_t)(ne + 1) * 4);
     ngh.ensure((size_t)(ne + 1) * 4);
 }
@@ -265,10 +274,10 @@ void Plan::alloc_buffers() {
 size_t Plan::device_bytes() const {
     size_t b = 0;
     for (const DevBuf *d : {&px, &py, &pz, &c, &S, &rho, &Z, &Hh, &y, &ybar, &Eat, &Epart, &Sbar, &rhobar, &gA, &gB,
-                            &cbar, &F, &Wpart, &Wacc, &disp, &col2, &nloc, &ngh, &fp8s, &fp8tmp})
+                            &cbar, &F, &Wpart, &Wacc, &disp, &col2, &fslot, &nloc, &ngh, &erec, &fp8s, &fp8tmp})
         b += d->bytes;
     b += nl.perm.bytes() + nl.inv_perm.bytes() + nl.q.bytes() + nl.gh_owner.bytes() + nl.gh_shift.bytes() +
-         nl.copy_ptr.bytes() + nl.copy_idx.bytes() + nl.row.bytes() + nl.col.bytes() + nl.spec_ext.bytes() +
+         nl.copy_ptr.bytes() + nl.copy_idx.bytes() + nl.row.bytes() + nl.col.bytes() + nl.rev.bytes() + nl.spec_ext.bytes() +
          nl.xref.bytes() + d_species.bytes();
     return b;
 }
@@ -307,7 +316,7 @@ void Plan::nn_forward(hipStream_t st, int t, bool energy) {
         const MfmaSet *mf = fp64 ? nullptr : &m->mfma(ctx->device, st, energy, op);
         char *out = energy ? y.as<char>() + (size_t)a * rs : cptr(t + 1) + (size_t)a * K * rs;
         const int dout = energy ? 1 : K;
-        if (!fp64 && fused_nn_ok(op, F, H, nh, dout)) {
+        if (fused()) {
             FusedNN f{};
             f.rows = rows; f.F = F; f.H = H; f.nh = nh; f.dout = dout;
             f.A = (const float *)A; f.lda = lda;
@@ -370,7 +379,7 @@ void Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg)
         char *bufs[2] = {gA.as<char>(), gB.as<char>()};
         int cur = 0;
         const MfmaSet *mf = fp64 ? nullptr : &m->mfma(ctx->device, st, energy, op);
-        if (!fp64 && fused_nn_ok(op, F, H, nh, lay.dout[nh])) {
+        if (fused()) {
             FusedNN f{};
             f.rows = rows; f.F = F; f.H = H; f.nh = nh; f.dout = lay.dout[nh];
             for (int k = 0; k < nh; ++k) {
@@ -482,7 +491,7 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     mark(st, 6);
     for (int t = T - 1; t >= 0; --t) {
         const int nb = edge_backward(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sbar.p, t > 0, this->F.p, cbar.p,
-                                     Wpart.as<double>());
+                                     Wpart.as<double>(), erec.p);
         sum_rows(st, Wpart.as<double>(), nb, 9, Wacc.as<double>(), true);
         mark(st, 5, 1);
         if (t > 0) {

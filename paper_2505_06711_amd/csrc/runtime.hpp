@@ -87,7 +87,8 @@ struct Plan {
     int64_t rebuilds = 0;
     // layer buffers
     DevBuf px, py, pz, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, Wacc, disp, one;
-    DevBuf col2, nloc, ngh;   // in-cutoff compaction of the list for the current step
+    DevBuf col2, fslot, nloc, ngh;   // in-cutoff compaction of the list for the current step
+    DevBuf erec;                     // per-slot edge records of the adjoint
     DevBuf fp8s, fp8tmp;      // per-call activation scale for FP8 products
     OpType op = OpType::F32;
     bool have_forward = false;
@@ -124,11 +125,16 @@ struct Plan {
     char *Sptr(int t) const { return S.as<char>() + (size_t)t * n * m->NL * m->K * rs; }
     char *rhoptr(int t) const { return rho.as<char>() + (size_t)t * n * m->F * rs; }
     char *Zptr(int t, int k) const { return Z.as<char>() + ((size_t)t * m->nh + k) * n * m->H * rs; }
-    char *Hptr(int t, int k) const { return Hh.as<char>() + ((size_t)t * m->nh + k) * n * m->H * rs; }
+    // hidden activations of the per-layer (unfused) path: two buffers used in turn
+    char *Hptr(int, int k) const { return Hh.as<char>() + (size_t)(k & 1) * n * m->H * rs; }
+    bool fused() const;
     void nn_forward(hipStream_t st, int t, bool energy);
     void nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg);
     void mark(hipStream_t st, int phase, int nlaunch = 0);
-    CutList cutlist() { return CutList{nl.row.ptr(), col2.as<int32_t>(), nloc.as<int32_t>(), ngh.as<int32_t>()}; }
+    CutList cutlist() {
+        return CutList{nl.row.ptr(), col2.as<int32_t>(), nloc.as<int32_t>(), ngh.as<int32_t>(), fslot.as<int32_t>(),
+                       nl.rev.ptr()};
+    }
 };
 
 }  // namespace reann
