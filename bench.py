@@ -35,24 +35,97 @@ def describe(name, w):
                "x".join(map(str, w["decomp"]))))
 
 
-def work_model(w, n_local_pairs, n_in_cutoff, prec):
-    """Algorithmic bytes and flops per launch of each kernel phase (per MP layer)."""
+def work_model(w, n_pairs_local, n_in_cutoff, prec):
+    """Algorithmic work of one launch of each single-kernel phase (one MP layer, all atoms).
+
+    Per atom and layer, with n_l list entries (r_c + skin) and n_c in-cutoff edges per atom,
+    Lam = (L+1)(L+2)(L+3)/6 angular components and rs bytes per working value:
+      edge forward  bytes 4 n_l + 24 + rs K + rs Lam K;   VALU n_c (2 Lam K + 7 K + 40)
+      edge adjoint, centre role  bytes 4 n_l + 24 + 2 rs K + rs Lam K + 3 rs;
+                    VALU n_c (4 Lam K + 12 K + 80), + 2 Lam K per edge when it also forms
+                    the adjoint-message terms (every layer but the first)
+      edge adjoint, neighbour role  bytes per in-cutoff local edge: two slot indices and one
+                    record (rs (4 + K), or 4 rs without message terms); + rs (3 + K) out
+      atomic NN     2 (F H + (h - 1) H^2 + H K_out) flop (forward; the adjoint the same)
+    (an exp counts as 4 VALU slots; bytes count each atom's own data once and exclude cache
+    re-reads of gathered neighbours)."""
     m, n = w["model"], len(w["system"]["pos"])
     K, L = m.K, m.L
-    NL = (L + 1) * (L + 2) * (L + 3) // 6
+    lam = (L + 1) * (L + 2) * (L + 3) // 6
     F, H, nh = m.F, m.hidden, m.n_hidden
     rs = 8 if prec == "fp64" else 4
+    n_l, n_c = n_pairs_local / n, n_in_cutoff / n
     out = {}
-    # edge forward: list indices, own position, own message, written S; S += w*A per in-cutoff edge
-    out["edge_fwd"] = dict(bytes=4 * n_local_pairs + n * (24 + rs * K + rs * NL * K),
-                           flops=2 * NL * K * n_in_cutoff)
-    # edge backward: + Sbar read, cbar and force written; P, Q and cbar contractions per edge
-    out["edge_bwd"] = dict(bytes=4 * n_local_pairs + n * (24 + rs * K + 2 * rs * NL * K + rs * K + rs * 3),
-                           flops=6 * NL * K * n_in_cutoff)
-    macs_msg = F * H + (nh - 1) * H * H + H * K
-    macs_en = F * H + (nh - 1) * H * H + H
-    out["nn"] = dict(flops_per_atom_msg=2 * macs_msg, flops_per_atom_en=2 * macs_en)
+    out["edge_fwd"] = dict(bytes=n * (4 * n_l + 24 + rs * K + rs * lam * K), flops=n * n_c * (2 * lam * K + 7 * K + 40))
+    out["adj_centre"] = dict(bytes=n * (4 * n_l + 24 + 2 * rs * K + rs * lam * K + 3 * rs),
+                             flops=n * n_c * (4 * lam * K + 12 * K + 80),
+                             flops_cbar=n * n_c * (6 * lam * K + 12 * K + 80))
+    out["adj_gather"] = dict(bytes=n_in_cutoff * (8 + rs * (4 + K)) + n * rs * (3 + K),
+                             bytes_nocbar=n_in_cutoff * (8 + 4 * rs) + n * rs * 3)
+    out["nn"] = dict(flops_msg=2 * n * (F * H + (nh - 1) * H * H + H * K),
+                     flops_en=2 * n * (F * H + (nh - 1) * H * H + H))
     return out
+
+
+def load_traffic(kernel, workload, precision):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary, or
+    None when there is none or the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.md" % (kernel, workload, precision))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    src = os.path.join(ROOT, "paper_2505_06711_amd", "csrc", fields.get("source", ""))
+    if not os.path.isfile(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+        return None
+    return float(fields["traffic_bytes_per_dispatch"])
+
+
+KERNEL_OF_PHASE = {"edge_fwd": "k_edge_fwd", "adj_centre": "k_adj_centre", "adj_gather": "k_adj_gather",
+                   "nn_fwd": "k_mlp_fwd", "nn_bwd": "k_mlp_bwd", "density": "k_density",
+                   "density_adj": "k_density_vjp"}
+
+
+def roofline(wk, tim, T, prec, workload):
+    """Roofline entry of the single-kernel phase with the largest share of the step: its
+    algorithmic work per launch over its average launch time (library HIP events)."""
+    phases = [p for p in ("edge_fwd", "adj_centre", "adj_gather", "nn_fwd", "nn_bwd")
+              if tim["launches"].get(p, 0) > 0]
+    dom = max(phases, key=lambda p: tim["ms"][p])
+    nla = tim["launches"][dom]
+    steps = max(1, tim["steps"])
+    per_launch_ms = tim["ms"][dom] / nla
+    vec = "fp64_vector" if prec == "fp64" else "fp32_vector"
+    if dom == "edge_fwd":
+        flops, byts, kind = wk["edge_fwd"]["flops"], wk["edge_fwd"]["bytes"], vec
+    elif dom == "adj_centre":   # T - 1 launches form message terms, one does not
+        flops = ((T - 1) * wk["adj_centre"]["flops_cbar"] + wk["adj_centre"]["flops"]) / T
+        byts, kind = wk["adj_centre"]["bytes"], vec
+    elif dom == "adj_gather":
+        flops = 0.0
+        byts = ((T - 1) * wk["adj_gather"]["bytes"] + wk["adj_gather"]["bytes_nocbar"]) / T
+        kind = None
+    else:                       # atomic NNs: T - 1 message NNs and one energy NN per step
+        flops = ((T - 1) * wk["nn"]["flops_msg"] + wk["nn"]["flops_en"]) / (nla / steps)
+        byts, kind = None, {"fp64": "fp64_mfma", "fp32": "fp32_mfma", "bf16": "bf16_mfma", "fp8": "fp8_mfma"}[prec]
+    if kind is None or (byts is not None and kind.endswith("vector")
+                        and flops / (PEAK_TFLOPS[kind] * 1e12) < byts / (HBM_PEAK_GBS * 1e9)):
+        achieved = byts / (per_launch_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4))
+    else:
+        achieved = flops / (per_launch_ms * 1e-3) / 1e12
+        roof = dict(bound="alu" if kind.endswith("vector") else "mfma", achieved=round(achieved, 3),
+                    peak=PEAK_TFLOPS[kind], unit="TFLOP/s", frac=round(achieved / PEAK_TFLOPS[kind], 4))
+    roof["traffic"] = load_traffic(KERNEL_OF_PHASE[dom], workload, prec)
+    roof.update(kernel=KERNEL_OF_PHASE[dom], per_launch_ms=round(per_launch_ms, 4), launches=nla,
+                algorithmic_flops_per_launch=round(flops), algorithmic_bytes_per_launch=
+                None if byts is None else round(byts))
+    return roof
 
 
 def cpu_baseline(workload_name, T, max_seconds=30.0):
@@ -218,6 +291,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--tsweep", default=None,
                     help="comma list of T values: time each T on the workload instead of the headline run")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (the known-size "
+                         "kernel that scales rocprofv3's FETCH_SIZE / WRITE_SIZE readings)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the subdomain exchange is "
@@ -225,6 +301,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if a.copy_calibration:
+        nbytes = a.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_calibration_bytes=nbytes, repeats=3)), flush=True)
+        return
     import synth
     import paper_2505_06711_amd as rn
 
@@ -282,34 +367,8 @@ def main():
 
     steps_t = max(1, tim["steps"])
     ms = {k: v / steps_t for k, v in tim["ms"].items()}
-    dominant = max(("edge_fwd", "edge_bwd", "nn_fwd", "nn_bwd"), key=lambda k: ms[k])
     la = tim["launches"]
-    if dominant in ("edge_fwd", "edge_bwd"):
-        per_launch_ms = tim["ms"][dominant] / max(1, la[dominant])
-        flops = wk[dominant]["flops"]
-        byts = wk[dominant]["bytes"]
-        t_alu = flops / (PEAK_TFLOPS["fp32_vector" if a.precision != "fp64" else "fp64_vector"] * 1e12)
-        t_hbm = byts / (HBM_PEAK_GBS * 1e9)
-        if t_alu >= t_hbm:
-            peak = PEAK_TFLOPS["fp32_vector" if a.precision != "fp64" else "fp64_vector"]
-            achieved = flops / (per_launch_ms * 1e-3) / 1e12
-            roof = dict(bound="alu", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                        frac=round(achieved / peak, 4), traffic=None)
-        else:
-            achieved = byts / (per_launch_ms * 1e-3) / 1e9
-            roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
-        roof.update(kernel=dominant, per_launch_ms=round(per_launch_ms, 4), launches=la[dominant],
-                    algorithmic_flops=flops, algorithmic_bytes=byts)
-    else:
-        # atomic NN phase: dense layers (forward: T NNs; backward: T VJPs)
-        nnf = wk["nn"]
-        flops_step = n * ((T - 1) * nnf["flops_per_atom_msg"] + nnf["flops_per_atom_en"])
-        achieved = flops_step / (ms[dominant] * 1e-3) / 1e12
-        key = {"fp64": "fp64_mfma", "fp32": "fp32_mfma", "bf16": "bf16_mfma", "fp8": "fp8_mfma"}[a.precision]
-        roof = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK_TFLOPS[key], unit="TFLOP/s",
-                    frac=round(achieved / PEAK_TFLOPS[key], 4), traffic=None, kernel=dominant,
-                    phase_ms_per_step=round(ms[dominant], 4))
+    roof = roofline(wk, tim, T, a.precision, a.workload)
 
     out = dict(metric=METRIC, value=round(value, 1), unit="atom-steps/s", n_gpus=1, steps=a.steps,
                warmup=a.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",

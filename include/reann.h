@@ -177,16 +177,19 @@ reann_status reann_plan_get(reann_plan *p, int32_t what, int32_t t, double *host
 
 /* Kernel time per phase, measured with HIP events recorded on the evaluation stream at
  * phase boundaries while timing is enabled (reann_plan_set_timing), accumulated over every
- * forward+backward since the previous reann_plan_timing call:
- *   [0] neighbour build, [1] edge forward, [2] density + atomic NN forward, [3] ghost exchange,
- *   [4] atomic NN backward + density adjoint, [5] edge backward, [6] other (refresh, seeds,
- *   reductions, output).
- * ms7: host [7] milliseconds; launches7 (host [7] or NULL): kernel launches counted for the
- * phases that time a single kernel type ([0] builds, [1] edge-forward and [5] edge-backward
- * launches); steps (or NULL): backward passes covered.  Synchronises on the last event and
- * resets the accumulators. */
+ * forward+backward since the previous reann_plan_timing call.  REANN_N_PHASES phases:
+ *   [0] neighbour-list reuse check and rebuilds, [1] edge forward (orbital sums),
+ *   [2] density contraction, [3] atomic NN forward, [4] ghost exchange,
+ *   [5] atomic NN adjoint, [6] density adjoint, [7] edge adjoint, centre role,
+ *   [8] edge adjoint, neighbour role, [9] other (refresh, compaction, seeds, reductions,
+ *   output).
+ * ms: host [REANN_N_PHASES] milliseconds; launches (host [REANN_N_PHASES] or NULL): kernel
+ * launches of the phases that time one kernel type ([1], [2], [6], [7], [8], and [3], [5]
+ * when the atomic NNs run fused; 0 elsewhere; [0] counts rebuilds); steps (or NULL):
+ * backward passes covered.  Synchronises on the last event and resets the accumulators. */
+#define REANN_N_PHASES 10
 reann_status reann_plan_set_timing(reann_plan *p, int32_t enable);
-reann_status reann_plan_timing(reann_plan *p, double *ms7, int64_t *launches7, int64_t *steps);
+reann_status reann_plan_timing(reann_plan *p, double *ms, int64_t *launches, int64_t *steps);
 
 /* ---------------------------------------------------------------- serving --
  * Continuous-batching server: many independent systems stay resident on the device

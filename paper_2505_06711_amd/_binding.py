@@ -319,12 +319,13 @@ class Plan:
     def set_timing(self, on: bool = True):
         check(load().reann_plan_set_timing(self.handle, int(bool(on))))
 
-    PHASES = ("nlist", "edge_fwd", "nn_fwd", "ghost", "nn_bwd", "edge_bwd", "other")
+    PHASES = ("nlist", "edge_fwd", "density", "nn_fwd", "ghost", "nn_bwd", "density_adj", "adj_centre",
+              "adj_gather", "other")
 
     def timing(self) -> dict:
         """Per-phase kernel milliseconds accumulated since the last call (see reann.h)."""
-        ms = np.zeros(7)
-        la = np.zeros(7, np.int64)
+        ms = np.zeros(len(self.PHASES))
+        la = np.zeros(len(self.PHASES), np.int64)
         steps = _i64()
         check(load().reann_plan_timing(self.handle, _p(ms), _p(la), C.byref(steps)))
         return dict(ms=dict(zip(self.PHASES, ms.tolist())), launches=dict(zip(self.PHASES, la.tolist())),

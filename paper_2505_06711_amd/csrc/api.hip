@@ -365,11 +365,11 @@ reann_status reann_plan_set_timing(reann_plan *p, int32_t enable) {
     });
 }
 
-reann_status reann_plan_timing(reann_plan *p, double *ms7, int64_t *launches7, int64_t *steps) {
+reann_status reann_plan_timing(reann_plan *p, double *ms, int64_t *launches, int64_t *steps) {
     return guarded([&] {
-        REQUIRE(p && ms7, "NULL argument");
+        REQUIRE(p && ms, "NULL argument");
         HIP_OK(hipSetDevice(p->impl.ctx->device));
-        const int64_t s = p->impl.collect_timing(ms7, launches7);
+        const int64_t s = p->impl.collect_timing(ms, launches);
         if (steps) *steps = s;
     });
 }

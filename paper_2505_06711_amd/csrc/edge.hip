@@ -393,28 +393,49 @@ void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, co
 
 int edge_backward_blocks(int64_t n_ext) { return grid_for(n_ext, kRowsPerBlock); }
 
-int edge_backward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
-                  const void *c, const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart, void *rec) {
-    const int nbc = grid_for(a.n, kRowsPerBlock), nbn = grid_for(a.n_ext, kRowsPerBlock);
-#define BWD_T(LL, KK, R, CB)                                                                                       \
+int edge_adjoint_centre(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl,
+                        const EdgeConsts &ec, const void *c, const void *Sbar, bool want_cbar, void *F, double *Wpart,
+                        void *rec) {
+    const int nbc = grid_for(a.n, kRowsPerBlock);
+#define CEN_T(LL, KK, R, CB)                                                                                       \
     hipLaunchKernelGGL((k_adj_centre<LL, KK, R, CB>), dim3(nbc), dim3(256), 0, st, a, cl, ec, (const R *)c,      \
-                       (const R *)Sbar, (R *)F, Wpart, (R *)rec);                                               \
-    LAUNCH_OK("k_adj_centre");                                                                                  \
-    hipLaunchKernelGGL((k_adj_gather<KK, R, CB>), dim3(nbn), dim3(256), 0, st, a, cl, (const R *)rec, (R *)F,    \
-                       (R *)cbar);                                                                              \
-    LAUNCH_OK("k_adj_gather");
-#define BWD(LL, KK)                                             \
+                       (const R *)Sbar, (R *)F, Wpart, (R *)rec);
+#define CEN(LL, KK)                                             \
     if (fp64) {                                                 \
-        if (want_cbar) { BWD_T(LL, KK, double, true) }          \
-        else { BWD_T(LL, KK, double, false) }                   \
+        if (want_cbar) { CEN_T(LL, KK, double, true) }          \
+        else { CEN_T(LL, KK, double, false) }                   \
     } else {                                                    \
-        if (want_cbar) { BWD_T(LL, KK, float, true) }           \
-        else { BWD_T(LL, KK, float, false) }                    \
+        if (want_cbar) { CEN_T(LL, KK, float, true) }           \
+        else { CEN_T(LL, KK, float, false) }                    \
     }
-    REANN_LK_DISPATCH(L, K, BWD);
-#undef BWD
-#undef BWD_T
+    REANN_LK_DISPATCH(L, K, CEN);
+#undef CEN
+#undef CEN_T
+    LAUNCH_OK("k_adj_centre");
     return nbc;
+}
+
+void edge_adjoint_gather(hipStream_t st, bool fp64, int K, const EdgeArgs &a, const CutList &cl, bool want_cbar,
+                         const void *rec, void *F, void *cbar) {
+    const int nbn = grid_for(a.n_ext, kRowsPerBlock);
+#define GAT_T(KK, R, CB)                                                                                         \
+    hipLaunchKernelGGL((k_adj_gather<KK, R, CB>), dim3(nbn), dim3(256), 0, st, a, cl, (const R *)rec, (R *)F,     \
+                       (R *)cbar);
+#define GAT(KK)                                                 \
+    if (fp64) {                                                 \
+        if (want_cbar) { GAT_T(KK, double, true) }              \
+        else { GAT_T(KK, double, false) }                       \
+    } else {                                                    \
+        if (want_cbar) { GAT_T(KK, float, true) }               \
+        else { GAT_T(KK, float, false) }                        \
+    }
+    if (K == 4) { GAT(4) }
+    else if (K == 8) { GAT(8) }
+    else if (K == 12) { GAT(12) }
+    else fail(REANN_E_UNSUPPORTED, "no edge kernel compiled for this K");
+#undef GAT
+#undef GAT_T
+    LAUNCH_OK("k_adj_gather");
 }
 
 // ------------------------------------------------------------- ghost exchange --

@@ -38,15 +38,20 @@ void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl);
 void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
                   const void *c, void *S);
 
-// Atomics-free adjoint: the centre role over local rows evaluates every edge once and
-// writes, at the edge's list slot, what it gives the neighbour end; the neighbour role
-// over every ext row sums those records through the reverse slots.
+// Atomics-free adjoint of one layer in two launches.  Centre role (local rows): evaluates
+// every in-cutoff edge once, adds its gradient to F of the centre and the virial, and
+// writes at the edge's list slot the record of what it gives the neighbour end.
+// Neighbour role (every ext row): sums the records of the row's incoming edges through
+// the list's reverse slots.
 //   Sbar [n][NL][K] (locals), c [n_ext][K]; F [n_ext][3] is accumulated;
 //   cbar [n_ext][K] is overwritten when want_cbar; Wpart receives one FP64 [9] per block
-// of the centre-role launch; rec holds edge_record_elems(K) working-type values per list
-// slot.  Returns the number of blocks (rows of Wpart).
-int edge_backward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
-                  const void *c, const void *Sbar, bool want_cbar, void *F, void *cbar, double *Wpart, void *rec);
+// of the centre-role launch (the return value is that block count); rec holds
+// edge_record_elems(K) working-type values per list slot.
+int edge_adjoint_centre(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl,
+                        const EdgeConsts &ec, const void *c, const void *Sbar, bool want_cbar, void *F, double *Wpart,
+                        void *rec);
+void edge_adjoint_gather(hipStream_t st, bool fp64, int K, const EdgeArgs &a, const CutList &cl, bool want_cbar,
+                         const void *rec, void *F, void *cbar);
 // Values per edge record: the edge gradient (3, padded to 4) and K adjoint-message terms.
 inline int edge_record_elems(int K) { return 4 + K; }
 int edge_backward_blocks(int64_t n_ext);

@@ -211,26 +211,26 @@ void Plan::mark(hipStream_t st, int phase, int nlaunch) {
     }
     HIP_OK(hipEventRecord(ev[nev], st));
     ev_phase[nev] = phase;
-    if (phase >= 0 && phase < 7) launches[phase] += nlaunch;
+    if (phase >= 0 && phase < REANN_N_PHASES) launches[phase] += nlaunch;
     ++nev;
 }
 
-int64_t Plan::collect_timing(double *ms7, int64_t *launches7) {
-    for (int q = 0; q < 7; ++q) ms7[q] = 0.0;
+int64_t Plan::collect_timing(double *ms, int64_t *nlaunch) {
+    for (int q = 0; q < REANN_N_PHASES; ++q) ms[q] = 0.0;
     if (nev > 0) HIP_OK(hipEventSynchronize(ev[nev - 1]));
     for (size_t i = 1; i < nev; ++i) {
         const int ph = ev_phase[i];
-        if (ph < 0 || ph >= 7) continue;
-        float ms = 0;
-        HIP_OK(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
-        ms7[ph] += ms;
+        if (ph < 0 || ph >= REANN_N_PHASES) continue;
+        float t = 0;
+        HIP_OK(hipEventElapsedTime(&t, ev[i - 1], ev[i]));
+        ms[ph] += t;
     }
-    if (launches7)
-        for (int q = 0; q < 7; ++q) launches7[q] = launches[q];
+    if (nlaunch)
+        for (int q = 0; q < REANN_N_PHASES; ++q) nlaunch[q] = launches[q];
     const int64_t steps = timed_steps;
     nev = 0;
     timed_steps = 0;
-    for (int q = 0; q < 7; ++q) launches[q] = 0;
+    for (int q = 0; q < REANN_N_PHASES; ++q) launches[q] = 0;
     return steps;
 }
 
@@ -300,12 +300,13 @@ void Plan::ensure_list(const double *d_pos, hipStream_t st) {
     }
 }
 
-void Plan::nn_forward(hipStream_t st, int t, bool energy) {
+int Plan::nn_forward(hipStream_t st, int t, bool energy) {
     DeviceWeights &w = m->weights(ctx->device, st);
     const NNLayout &lay = energy ? m->en_nn : m->msg_nn;
     const char *blob = energy ? (fp64 ? w.en64.as<char>() : w.en32.as<char>())
                               : (fp64 ? w.msg64.as<char>() : w.msg32.as<char>());
     const int F = m->F, H = m->H, nh = m->nh, K = m->K;
+    int nfused = 0;
     for (int s = 0; s < m->n_species; ++s) {
         const int64_t a = nl.seg[s], rows = nl.seg[s + 1] - nl.seg[s];
         if (rows <= 0) continue;
@@ -332,6 +333,7 @@ void Plan::nn_forward(hipStream_t st, int t, bool energy) {
             f.bout = (const float *)(p + lay.b_off[nh] * rs);
             f.C = (float *)out; f.ldc = dout;
             mlp_fused(st, op, true, f);
+            ++nfused;
             continue;
         }
         for (int k = 0; k < nh; ++k) {
@@ -358,16 +360,18 @@ void Plan::nn_forward(hipStream_t st, int t, bool energy) {
             out_layer_fwd(st, rows, H, dout, (const float *)A, lda, (const float *)(p + lay.w_off[nh] * rs),
                           (const float *)(p + lay.b_off[nh] * rs), (float *)out, dout);
     }
+    return nfused;
 }
 
 // VJP of the NN applied at layer t (energy NN if `energy`), from output adjoint gout
-// [n][ldg] to Sbar (through rho^t and S^t).
-void Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) {
+// [n][ldg] to rhobar.
+int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) {
     DeviceWeights &w = m->weights(ctx->device, st);
     const NNLayout &lay = energy ? m->en_nn : m->msg_nn;
     const char *blob = energy ? (fp64 ? w.en64.as<char>() : w.en32.as<char>())
                               : (fp64 ? w.msg64.as<char>() : w.msg32.as<char>());
     const int F = m->F, H = m->H, nh = m->nh;
+    int nfused = 0;
     for (int s = 0; s < m->n_species; ++s) {
         const int64_t a = nl.seg[s], rows = nl.seg[s + 1] - nl.seg[s];
         if (rows <= 0) continue;
@@ -393,6 +397,7 @@ void Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg)
             f.G = (const float *)gin; f.ldg = ldin;
             f.C = (float *)(rhobar.as<char>() + (size_t)a * F * rs); f.ldc = F;
             mlp_fused(st, op, false, f);
+            ++nfused;
             continue;
         }
         for (int k = nh; k >= 1; --k) {
@@ -429,7 +434,7 @@ void Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg)
                       mf->scales.as<float>() + mf->sc_bwd[qi]);
         }
     }
-    density_vjp(st, fp64, m->L, m->K, n, m->density_consts(), Sptr(t), rhobar.p, Sbar.p);
+    return nfused;
 }
 
 bool Plan::prepare(const double *d_pos, hipStream_t st) {
@@ -441,7 +446,7 @@ bool Plan::prepare(const double *d_pos, hipStream_t st) {
 void Plan::forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st) {
     mark(st, -1);
     const bool rebuilt = prepare(d_pos, st);
-    mark(st, 0, rebuilt ? 1 : 0);
+    mark(st, PH_NLIST, rebuilt ? 1 : 0);
     launch_forward(d_pos, d_energy, d_atom_energy, st);
 }
 
@@ -456,23 +461,22 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
     compact_cutoff(st, ea, m->r_c, cl);
     const EdgeConsts ec = m->edge_consts();
     const DensityConsts dc = m->density_consts();
-    mark(st, 6);
+    mark(st, PH_OTHER);
     for (int t = 0; t < T; ++t) {
         edge_forward(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sptr(t));
-        mark(st, 1, 1);
+        mark(st, PH_EDGE_FWD, 1);
         density(st, fp64, m->L, K, n, dc, Sptr(t), rhoptr(t));
+        mark(st, PH_DENSITY, 1);
         if (t < T - 1) {
-            nn_forward(st, t, false);
-            mark(st, 2);
+            mark(st, PH_NN_FWD, nn_forward(st, t, false));
             ghost_gather(st, fp64, n, nl.n_gh, K, nl.gh_owner.ptr(), cptr(t + 1));
-            mark(st, 3);
+            mark(st, PH_GHOST);
         }
     }
-    nn_forward(st, T - 1, true);
-    mark(st, 2);
+    mark(st, PH_NN_FWD, nn_forward(st, T - 1, true));
     const int nb = energy_finalize(st, fp64, n, m->energy_scale, y.p, nl.perm.ptr(), d_atom_energy, Epart.as<double>());
     sum_rows(st, Epart.as<double>(), nb, 1, d_energy, false);
-    mark(st, 6);
+    mark(st, PH_OTHER);
     have_forward = true;
 }
 
@@ -482,30 +486,36 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), px.as<double>(), py.as<double>(), pz.as<double>()};
     const CutList cl = cutlist();
     const EdgeConsts ec = m->edge_consts();
+    const DensityConsts dc = m->density_consts();
     mark(st, -1);
     fill_energy_seed(st, fp64, n, m->energy_scale, d_g, ybar.p);
-    nn_vjp(st, T - 1, true, ybar.as<char>(), 1);
-    mark(st, 4);
     zero(st, this->F.p, (size_t)nl.n_ext * 3 * rs);
     zero(st, Wacc.p, 9 * 8);
-    mark(st, 6);
+    mark(st, PH_OTHER);
+    mark(st, PH_NN_BWD, nn_vjp(st, T - 1, true, ybar.as<char>(), 1));
+    density_vjp(st, fp64, m->L, K, n, dc, Sptr(T - 1), rhobar.p, Sbar.p);
+    mark(st, PH_DENSITY_ADJ, 1);
     for (int t = T - 1; t >= 0; --t) {
-        const int nb = edge_backward(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sbar.p, t > 0, this->F.p, cbar.p,
-                                     Wpart.as<double>(), erec.p);
+        const int nb = edge_adjoint_centre(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sbar.p, t > 0, this->F.p,
+                                           Wpart.as<double>(), erec.p);
+        mark(st, PH_ADJ_CENTRE, 1);
+        edge_adjoint_gather(st, fp64, K, ea, cl, t > 0, erec.p, this->F.p, cbar.p);
+        mark(st, PH_ADJ_GATHER, 1);
         sum_rows(st, Wpart.as<double>(), nb, 9, Wacc.as<double>(), true);
-        mark(st, 5, 1);
+        mark(st, PH_OTHER);
         if (t > 0) {
             ghost_reduce(st, fp64, n, K, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), cbar.p);
-            mark(st, 3);
-            nn_vjp(st, t - 1, false, cbar.as<char>(), K);
-            mark(st, 4);
+            mark(st, PH_GHOST);
+            mark(st, PH_NN_BWD, nn_vjp(st, t - 1, false, cbar.as<char>(), K));
+            density_vjp(st, fp64, m->L, K, n, dc, Sptr(t - 1), rhobar.p, Sbar.p);
+            mark(st, PH_DENSITY_ADJ, 1);
         }
     }
     ghost_reduce(st, fp64, n, 3, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), this->F.p);
-    mark(st, 3);
+    mark(st, PH_GHOST);
     // the seed carried g; forces are -dE/dx already scaled
     forces_out(st, fp64, n, this->F.p, nl.perm.ptr(), nullptr, d_forces, Wacc.as<double>(), d_virial);
-    mark(st, 6);
+    mark(st, PH_OTHER);
     if (timing) ++timed_steps;
 }
 

@@ -68,6 +68,13 @@ struct Ctx {
     DevBuf pos, forces, scal;
 };
 
+// timing phases (reann_plan_timing)
+enum Phase {
+    PH_NLIST = 0, PH_EDGE_FWD, PH_DENSITY, PH_NN_FWD, PH_GHOST, PH_NN_BWD, PH_DENSITY_ADJ, PH_ADJ_CENTRE,
+    PH_ADJ_GATHER, PH_OTHER
+};
+static_assert(PH_OTHER + 1 == REANN_N_PHASES, "phase count");
+
 struct Plan {
     Ctx *ctx = nullptr;
     Model *m = nullptr;
@@ -99,7 +106,7 @@ struct Plan {
     std::vector<int> ev_phase;
     size_t nev = 0;
     int64_t timed_steps = 0;
-    int64_t launches[7]{};
+    int64_t launches[REANN_N_PHASES]{};
 
     ~Plan();
     void init(Ctx *c, Model *mm, const int32_t *spec, int64_t nn, const double cell_[9], const int32_t pbc_[3], int TT,
@@ -116,7 +123,7 @@ struct Plan {
     void backward(const double *d_g, double *d_forces, double *d_virial, hipStream_t st);
     void get(int what, int t, double *host);
     // per-phase kernel time (ms) accumulated since the last call; returns the step count
-    int64_t collect_timing(double *ms7, int64_t *launches7);
+    int64_t collect_timing(double *ms, int64_t *nlaunch);
 
   private:
     void ensure_list(const double *d_pos, hipStream_t st);
@@ -128,8 +135,9 @@ struct Plan {
     // hidden activations of the per-layer (unfused) path: two buffers used in turn
     char *Hptr(int, int k) const { return Hh.as<char>() + (size_t)(k & 1) * n * m->H * rs; }
     bool fused() const;
-    void nn_forward(hipStream_t st, int t, bool energy);
-    void nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg);
+    // both return the launches of the fused NN kernel (0 on the per-layer path)
+    int nn_forward(hipStream_t st, int t, bool energy);
+    int nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg);
     void mark(hipStream_t st, int phase, int nlaunch = 0);
     CutList cutlist() {
         return CutList{nl.row.ptr(), col2.as<int32_t>(), nloc.as<int32_t>(), ngh.as<int32_t>(), fslot.as<int32_t>(),
