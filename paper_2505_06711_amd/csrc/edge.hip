@@ -18,6 +18,15 @@
 
 namespace reann {
 
+// Workgroup b is dispatched to XCD b % 8.  Give each XCD one contiguous range of row tiles
+// (atoms are ordered by spatial bin, so neighbouring rows share their neighbours' data and
+// that data then stays in one XCD's L2).  A bijection on [0, nb).
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
+    constexpr int64_t kXcd = 8;
+    const int64_t x = b % kXcd, q = b / kXcd, per = nb / kXcd, rem = nb % kXcd;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
 template <int L> struct LamTab {
     static constexpr int N = n_lambda(L);
     int lx[N], ly[N], lz[N];
@@ -74,7 +83,7 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
                           int32_t *__restrict__ nloc, int32_t *__restrict__ ngh) {
     // 16 lanes per row take the row's entries 16 at a time; a ballot gives each in-cutoff
     // entry its rank, so the packed order equals a sequential scan of the row
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t x = t >> 4;
     const int g = threadIdx.x & 15, gbase = threadIdx.x & 48;
     const bool active = x < a.n_ext;
@@ -131,7 +140,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
     constexpr int NL = n_lambda(L);
     constexpr int G = kFwdLanes, KG = K / G;
     static_assert(K % G == 0, "K must be a multiple of the lanes per row");
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t i = t / G;
     const int q = (int)(t % G);
     if (i >= a.n) return;
@@ -146,21 +155,45 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
     const double xi = a.px[i], yi = a.py[i], zi = a.pz[i];
     const R inv_rc = R(1.0 / ec.r_c);
     const R s = R(ec.ang_scale);
-    const int cnt = cl.nloc[i] + cl.ngh[i];
+    const int nl = cl.nloc[i], cnt = nl + cl.ngh[i];
+    const int64_t lo = cl.row[i], gb = cl.row[i + 1] - cl.ngh[i];
+    // software pipeline without branches: while edge e is evaluated, the position and message
+    // of edge e + 1 and the list entry of edge e + 2 are in flight (indices clamped to the
+    // row's last edge)
+    const int last = cnt - 1;
+    auto slot = [&](int e) -> int64_t { return e < nl ? lo + e : gb + (e - nl); };
+    double xn = 0.0, yn = 0.0, zn = 0.0;
+    R cn[KG];
+    int32_t jn = 0;
+    if (cnt > 0) {
+        const int32_t j0 = cl.col[slot(0)];
+        jn = cl.col[slot(min(1, last))];
+        xn = a.px[j0]; yn = a.py[j0]; zn = a.pz[j0];
+#pragma unroll
+        for (int u = 0; u < KG; ++u) cn[u] = c[(int64_t)j0 * K + q + G * u];
+    }
     for (int e = 0; e < cnt; ++e) {
-        const int64_t j = cl.col[cut_slot(cl, i, e)];
-        const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
+        const double dx = xn - xi, dy = yn - yi, dz = zn - zi;
+        R cj[KG];
+#pragma unroll
+        for (int u = 0; u < KG; ++u) cj[u] = cn[u];
+        {
+            const int64_t jj = jn;
+            xn = a.px[jj]; yn = a.py[jj]; zn = a.pz[jj];
+#pragma unroll
+            for (int u = 0; u < KG; ++u) cn[u] = c[jj * K + q + G * u];
+            jn = cl.col[slot(min(e + 2, last))];
+        }
         const double d2 = dx * dx + dy * dy + dz * dz;
         const R r = d_sqrt(R(d2));
         const R uc = R(0.5) * d_cospi(r * inv_rc) + R(0.5);
         const R fc = uc * uc;
         R A[NL];
         angular<L, R, false>(R(ec.ang_scale * dx), R(ec.ang_scale * dy), R(ec.ang_scale * dz), s, A, nullptr);
-        const R *cj = c + j * K + q;
 #pragma unroll
         for (int u = 0; u < KG; ++u) {
             const R xm = r - cen[u];
-            const R w = cj[G * u] * d_exp(-alp[u] * xm * xm) * fc;
+            const R w = cj[u] * d_exp(-alp[u] * xm * xm) * fc;
 #pragma unroll
             for (int l = 0; l < NL; ++l) acc[l][u] += w * A[l];
         }
@@ -226,25 +259,38 @@ constexpr int kRowsPerBlock = 8;   // 256 threads = 8 half-waves, one row each
 //   g = d/dd [ f_c sum_lambda A_lambda(d) sum_m Sbar_k[lambda][m] c_j[m] R_m(r) ]
 // adds +g to F_k and -d (x) g to the virial; the edge's record gets g and (CBAR) the terms
 //   f_c R_m sum_lambda Sbar_k[lambda][m] A_lambda(d)  of  cbar_j[m].
-// Sbar_k is staged in LDS and read by all 32 lanes of its half-wave; lanes take the row's
-// edges in turn.  Record of list slot f: rec[f * RS + 0..2] = g, rec[f * RS + 4 + m] = terms
-// (RS = 4 + K with CBAR, 4 without).
+// kCentreLanes lanes share a row and take its edges in turn; Sbar_k is staged in LDS and
+// read by all of them.  Each lane runs a two-stage pipeline: the list entry of its edge after
+// next and the position and message of its next edge are loaded while the current edge is
+// evaluated.  The record of edge k -> j is stored at the edge's list slot f:
+// rec[f * RS + 0..2] = g, rec[f * RS + 4 + m] = terms (RS = 4 + K with CBAR, 4 without).
+constexpr int kCentreLanes = 16;
+constexpr int kCentreRows = 256 / kCentreLanes;
+
+template <typename R> __device__ inline R row_sum(R v) {   // over the kCentreLanes lanes of a row
+#pragma unroll
+    for (int o = kCentreLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kCentreLanes);
+    return v;
+}
+
 template <int L, int K, typename R, bool CBAR>
 __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, EdgeConsts ec, const R *__restrict__ c,
                                                     const R *__restrict__ Sbar, R *__restrict__ F,
                                                     double *__restrict__ Wpart, R *__restrict__ rec) {
-    constexpr int NL = n_lambda(L);
+    constexpr int NL = n_lambda(L), LPR = kCentreLanes;
     constexpr int RS = CBAR ? 4 + K : 4;
-    __shared__ R sS[kRowsPerBlock][NL * K];
-    __shared__ double sW[kRowsPerBlock][9];
-    const int hw = threadIdx.x >> 5, lane = threadIdx.x & 31;
-    const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock;
-    for (int t = threadIdx.x; t < kRowsPerBlock * NL * K; t += 256) {
+    constexpr LamTab<L> LT{};
+    __shared__ R sS[kCentreRows][NL * K];
+    __shared__ double sW[kCentreRows][9];
+    const int grp = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t row0 = tile * kCentreRows;
+    for (int t = threadIdx.x; t < kCentreRows * NL * K; t += 256) {
         const int64_t rr = row0 + t / (NL * K);
         sS[t / (NL * K)][t % (NL * K)] = rr < a.n ? Sbar[row0 * NL * K + t] : R(0);
     }
     __syncthreads();
-    const int64_t x = row0 + hw;
+    const int64_t x = row0 + grp;
     R f0 = R(0), f1 = R(0), f2 = R(0);
     double W[9];
 #pragma unroll
@@ -252,42 +298,77 @@ __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, Edge
     if (x < a.n) {
         const double xi = a.px[x], yi = a.py[x], zi = a.pz[x];
         const R s = R(ec.ang_scale);
-        const R *sb = sS[hw];
-        const int cnt = cl.nloc[x] + cl.ngh[x];
-        for (int e = lane; e < cnt; e += 32) {
-            // keep Sbar_k in LDS: without this the compiler hoists all NL*K reads out of
-            // the loop into registers, which caps occupancy
+        const R *sb = sS[grp];
+        const int nl = cl.nloc[x], cnt = nl + cl.ngh[x];
+        const int64_t lo = cl.row[x], gb = cl.row[x + 1] - cl.ngh[x];
+        auto slot = [&](int e) -> int64_t { return e < nl ? lo + e : gb + (e - nl); };
+        // two-stage pipeline without branches: the next edge's position and message and the
+        // list entry after it are loaded (indices clamped to the row's last edge) while the
+        // current edge is evaluated
+        int e = lane;
+        const int last = cnt - 1;
+        double xc = 0.0, yc = 0.0, zc = 0.0;
+        R cc[K];
+        int32_t fcur = 0, jn = 0, fn = 0;
+        if (e < cnt) {
+            const int64_t s0 = slot(e), s1 = slot(min(e + LPR, last));
+            const int32_t j0 = cl.col[s0];
+            fcur = cl.fslot[s0];
+            jn = cl.col[s1];
+            fn = cl.fslot[s1];
+            xc = a.px[j0]; yc = a.py[j0]; zc = a.pz[j0];
+#pragma unroll
+            for (int m = 0; m < K; ++m) cc[m] = c[(int64_t)j0 * K + m];
+        }
+        for (; e < cnt; e += LPR) {
+            // keep Sbar_k in LDS: without this the compiler hoists the NL*K reads out of the
+            // loop into registers, which caps occupancy
             asm volatile("" ::: "memory");
-            const int64_t slot = cut_slot(cl, x, e);
-            const int64_t j = cl.col[slot];
-            const int64_t f = cl.fslot[slot];
-            const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
+            const double dx = xc - xi, dy = yc - yi, dz = zc - zi;
+            const int64_t f = fcur;
             EdgeGeo<K, R> g;
             edge_geo<K, R>(ec, dx, dy, dz, g);
-            R A[NL], dA[NL][3];
-            angular<L, R, true>(R(ec.ang_scale * dx), R(ec.ang_scale * dy), R(ec.ang_scale * dz), s, A, dA);
-            const R *cj = c + j * K;
             R u[K], v[K], cacc[K];
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const R cm = cj[m];
-                u[m] = cm * g.Rm[m];
-                v[m] = cm * g.dRm[m];
+                u[m] = cc[m] * g.Rm[m];
+                v[m] = cc[m] * g.dRm[m];
                 cacc[m] = R(0);
             }
+            {
+                const int64_t jj = jn, s2 = slot(min(e + 2 * LPR, last));
+                xc = a.px[jj]; yc = a.py[jj]; zc = a.pz[jj];
+#pragma unroll
+                for (int m = 0; m < K; ++m) cc[m] = c[jj * K + m];
+                fcur = fn;
+                jn = cl.col[s2];
+                fn = cl.fslot[s2];
+            }
+            // powers of the scaled displacement; A_lambda and its gradient are formed per lambda
+            const R ux = R(ec.ang_scale * dx), uy = R(ec.ang_scale * dy), uz = R(ec.ang_scale * dz);
+            R px[L + 1], py[L + 1], pz[L + 1];
+            px[0] = py[0] = pz[0] = R(1);
+#pragma unroll
+            for (int k = 1; k <= L; ++k) { px[k] = px[k - 1] * ux; py[k] = py[k - 1] * uy; pz[k] = pz[k - 1] * uz; }
             R gx = R(0), gy = R(0), gz = R(0), sAP = R(0), sAQ = R(0);
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
+                // one row of Sbar_k at a time (the compiler would otherwise load them all ahead)
+                asm volatile("" ::: "memory");
+                const int lx = LT.lx[l], ly = LT.ly[l], lz = LT.lz[l];
+                const R Al = px[lx] * py[ly] * pz[lz];
                 R P = R(0), Q = R(0);
 #pragma unroll
                 for (int m = 0; m < K; ++m) {
                     const R w = sb[l * K + m];
                     P += w * u[m];
                     Q += w * v[m];
-                    if constexpr (CBAR) cacc[m] += w * A[l];
+                    if constexpr (CBAR) cacc[m] += w * Al;
                 }
-                gx += P * dA[l][0]; gy += P * dA[l][1]; gz += P * dA[l][2];
-                sAP += A[l] * P; sAQ += A[l] * Q;
+                if (lx) gx += P * (s * R(lx) * px[lx > 0 ? lx - 1 : 0] * py[ly] * pz[lz]);
+                if (ly) gy += P * (s * R(ly) * px[lx] * py[ly > 0 ? ly - 1 : 0] * pz[lz]);
+                if (lz) gz += P * (s * R(lz) * px[lx] * py[ly] * pz[lz > 0 ? lz - 1 : 0]);
+                sAP += Al * P; sAQ += Al * Q;
             }
             const R rad = g.dfc * sAP + g.fc * sAQ;
             gx = g.fc * gx + rad * g.ex; gy = g.fc * gy + rad * g.ey; gz = g.fc * gz + rad * g.ez;
@@ -307,24 +388,24 @@ __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, Edge
                 for (int q = 0; q < 3; ++q) W[3 * p + q] -= dd[p] * gd[q];
         }
     }
-    f0 = hw_sum(f0); f1 = hw_sum(f1); f2 = hw_sum(f2);
+    f0 = row_sum(f0); f1 = row_sum(f1); f2 = row_sum(f2);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) W[q] = hw_sum(W[q]);
+    for (int q = 0; q < 9; ++q) W[q] = row_sum(W[q]);
     if (lane == 0) {
         if (x < a.n) { F[3 * x] += f0; F[3 * x + 1] += f1; F[3 * x + 2] += f2; }
 #pragma unroll
-        for (int q = 0; q < 9; ++q) sW[hw][q] = W[q];
+        for (int q = 0; q < 9; ++q) sW[grp][q] = W[q];
     }
     __syncthreads();
     if (threadIdx.x < 9) {
         double t = 0.0;
-        for (int h = 0; h < kRowsPerBlock; ++h) t += sW[h][threadIdx.x];
-        Wpart[(int64_t)blockIdx.x * 9 + threadIdx.x] = t;
+        for (int h = 0; h < kCentreRows; ++h) t += sW[h][threadIdx.x];
+        Wpart[tile * 9 + threadIdx.x] = t;
     }
 }
 
 // Neighbour role: ext row k (local or ghost) sums the records of the edges j -> k over its
-// in-cutoff local neighbours j (slot rev[fslot] of each entry): F_k -= sum g and, with
+// in-cutoff local neighbours j (at the reverse slot of each entry k -> j): F_k -= sum g and, with
 // CBAR, cbar_k[m] = sum of the terms.  With CBAR 4 lanes share an edge record (one group
 // of 4 values each, 8 edges per pass of the half-wave); without it a lane takes an edge.
 template <int K, typename R, bool CBAR>
@@ -336,7 +417,7 @@ __global__ __launch_bounds__(256) void k_adj_gather(EdgeArgs a, CutList cl, cons
     constexpr int EPP = 32 / LPE;           // edges per pass
     static_assert(K % 4 == 0 && (NP <= LPE || !CBAR), "record layout");
     const int hw = threadIdx.x >> 5, lane = threadIdx.x & 31;
-    const int64_t x = (int64_t)blockIdx.x * kRowsPerBlock + hw;
+    const int64_t x = xcd_tile(blockIdx.x, gridDim.x) * kRowsPerBlock + hw;
     if (x >= a.n_ext) return;   // whole half-wave leaves together
     const int part = lane % LPE, eg = lane / LPE;
     R acc[4] = {R(0), R(0), R(0), R(0)};
@@ -391,12 +472,12 @@ void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, co
     LAUNCH_OK("k_edge_fwd");
 }
 
-int edge_backward_blocks(int64_t n_ext) { return grid_for(n_ext, kRowsPerBlock); }
+int edge_backward_blocks(int64_t n_ext) { return grid_for(n_ext, kCentreRows); }
 
 int edge_adjoint_centre(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl,
                         const EdgeConsts &ec, const void *c, const void *Sbar, bool want_cbar, void *F, double *Wpart,
                         void *rec) {
-    const int nbc = grid_for(a.n, kRowsPerBlock);
+    const int nbc = grid_for(a.n, kCentreRows);
 #define CEN_T(LL, KK, R, CB)                                                                                       \
     hipLaunchKernelGGL((k_adj_centre<LL, KK, R, CB>), dim3(nbc), dim3(256), 0, st, a, cl, ec, (const R *)c,      \
                        (const R *)Sbar, (R *)F, Wpart, (R *)rec);

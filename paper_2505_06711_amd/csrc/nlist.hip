@@ -255,9 +255,10 @@ __global__ __launch_bounds__(256) void k_sort_rows(int64_t nrow, const int64_t *
     }
 }
 
-// rev[f] for the entry f = (x -> j) of a sorted list: the slot of (j -> x) in row j when j is
-// local (binary search), -1 when j is a ghost.  Sets *bad when a reverse entry is missing.
-__global__ void k_reverse(int64_t n, int64_t n_ext, const int64_t *__restrict__ row, const int32_t *__restrict__ col,
+// rev[f] for the entry f = (x -> j) of a sorted list: the slot of (j -> x) in row j (binary
+// search).  Every entry has one: rows of locals list every ext atom in range, rows of ghosts
+// every local in range, and a row of a ghost only holds locals.  Sets *bad when one is missing.
+__global__ void k_reverse(int64_t n_ext, const int64_t *__restrict__ row, const int32_t *__restrict__ col,
                           int32_t *__restrict__ rev, int32_t *__restrict__ bad) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t x = t >> 4;
@@ -266,7 +267,6 @@ __global__ void k_reverse(int64_t n, int64_t n_ext, const int64_t *__restrict__ 
     const int64_t hi = row[x + 1];
     for (int64_t f = row[x] + g; f < hi; f += 16) {
         const int32_t j = col[f];
-        if (j >= n) { rev[f] = -1; continue; }
         int64_t a = row[j], b = row[j + 1];
         const int64_t end = b;
         while (a < b) {
@@ -590,14 +590,14 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, n, n_ext, pext,
                        d_dom_ext, d_bin_ext, kstart, nullptr, row, col);
     LAUNCH_OK("k_rows<fill>");
-    // rows ascending, then the reverse slot of every entry with a local neighbour
+    // rows ascending, then the reverse slot of every entry
     hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n_ext, 4)), dim3(256), 0, st, n_ext, row, col);
     LAUNCH_OK("k_sort_rows");
     {
         int32_t *rev = nl.rev.resize(n_pairs + 1);
         int32_t *flag = static_cast<int32_t *>(s.flag.ensure(64));
         HIP_OK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
-        hipLaunchKernelGGL(k_reverse, dim3(grid_for(n_ext * 16, B)), dim3(B), 0, st, n, n_ext, row, col, rev, flag);
+        hipLaunchKernelGGL(k_reverse, dim3(grid_for(n_ext * 16, B)), dim3(B), 0, st, n_ext, row, col, rev, flag);
         LAUNCH_OK("k_reverse");
         int32_t hflag = 0;
         HIP_OK(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));

@@ -39,7 +39,7 @@ struct NList {
     DArr<int32_t> copy_idx;      // [n_gh] ghost indices in increasing order per owner
     DArr<int64_t> row;           // [n_ext+1]
     DArr<int32_t> col;           // [n_pairs] ext indices
-    DArr<int32_t> rev;           // [n_pairs] slot of the reverse entry (j -> x) if j is local, else -1
+    DArr<int32_t> rev;           // [n_pairs] slot of the reverse entry (j -> x) of entry (x -> j)
     DArr<int8_t> spec_ext;       // [n_ext]
     DArr<double> xref;           // [n*3] caller positions at build time, local order
 };
