@@ -10,6 +10,8 @@
 // and likewise for B = Wt^T; the 16x16 result holds C[4(l/16) + r][l%16] in register r.
 #include "mfma.hpp"
 
+#include <type_traits>
+
 namespace reann {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -276,17 +278,21 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
         const int col = 16 * (wave + kFuseWaves * cb) + li;
         wrow[cb] = Wt + (size_t)(col < out ? col : 0) * ldw;
     }
-    if constexpr (OP == OpType::F32) {
-        fl4 b[NCB], bn[NCB];
+    // weight fragments in two register sets used in turn: the set for chunk k0 + KC is
+    // requested before the matrix instructions of chunk k0 are issued (the scheduling
+    // barriers keep the compiler from moving the requests next to their use)
+    using T = typename Fuse<OP>::T;
+    using V = typename std::conditional<OP == OpType::F32, fl4, u16x8>::type;
+    constexpr int RUN = OP == OpType::F32 ? 4 : 8;   // k per lane per chunk
+    auto load_b = [&](V (&b)[NCB], int k0) {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const fl4 *>(wrow[cb] + 4 * lg);
-        for (int k0 = 0; k0 < kin; k0 += KC) {
-            const int kn = k0 + KC < kin ? k0 + KC : k0;   // the last chunk reloads itself
+        for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const V *>(wrow[cb] + k0 + RUN * lg);
+    };
+    auto mma = [&](const V (&b)[NCB], int k0) {
+        V a[RB];
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) bn[cb] = *reinterpret_cast<const fl4 *>(wrow[cb] + kn + 4 * lg);
-            fl4 a[RB];
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) a[rb] = *reinterpret_cast<const fl4 *>(X + (16 * rb + li) * ldx + k0 + 4 * lg);
+        for (int rb = 0; rb < RB; ++rb) a[rb] = *reinterpret_cast<const V *>(X + (16 * rb + li) * ldx + k0 + RUN * lg);
+        if constexpr (OP == OpType::F32) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -294,37 +300,40 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
 #pragma unroll
                     for (int cb = 0; cb < NCB; ++cb)
                         acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s], b[cb][s], acc[rb][cb], 0, 0, 0);
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) b[cb] = bn[cb];
-        }
-    } else {
-        u16x8 b[NCB], bn[NCB];
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const u16x8 *>(wrow[cb] + 8 * lg);
-        for (int k0 = 0; k0 < kin; k0 += KC) {
-            const int kn = k0 + KC < kin ? k0 + KC : k0;
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) bn[cb] = *reinterpret_cast<const u16x8 *>(wrow[cb] + kn + 8 * lg);
-            u16x8 a[RB];
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) a[rb] = *reinterpret_cast<const u16x8 *>(X + (16 * rb + li) * ldx + k0 + 8 * lg);
+        } else {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb)
                     acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                         __builtin_bit_cast(bf16x8, a[rb]), __builtin_bit_cast(bf16x8, b[cb]), acc[rb][cb], 0, 0, 0);
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) b[cb] = bn[cb];
         }
+    };
+    // pairs of chunks per trip, so that a trip is one basic block and the requests cannot be
+    // sunk into a later block next to their use
+    V b0[NCB], b1[NCB];
+    const int nck = kin / KC, klast = kin - KC;
+    load_b(b0, 0);
+    int k0 = 0;
+    for (int pr = 0; pr + 2 <= nck; pr += 2) {
+        load_b(b1, k0 + KC);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b0, k0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b(b0, min(k0 + 2 * KC, klast));
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b1, k0 + KC);
+        __builtin_amdgcn_sched_barrier(0);
+        k0 += 2 * KC;
     }
+    if (nck & 1) mma(b0, k0);   // b0 holds the last chunk
 }
 
 }  // namespace
 
-// Forward of one element's NN over rows [0, rows): C = out_layer(SiLU(... SiLU(A W_0^T + b_0) ...)).
-// NCB = H / 64 column blocks per wave.
-template <OpType OP, int NCB>
+// Forward of one element's NN over rows [0, rows): C = out_layer(SiLU(... SiLU(rho W_0^T + b_0) ...))
+// with rho the density of S.  NCB = H / 64 column blocks per wave; (L, K) fix the density.
+template <OpType OP, int NCB, int L, int K>
 __global__ __launch_bounds__(256) void k_mlp_fwd(FusedNN p) {
     using T = typename Fuse<OP>::T;
     constexpr int BM = kFuseBM, RB = BM / 16;
@@ -333,18 +342,55 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(FusedNN p) {
     const int64_t m0 = (int64_t)blockIdx.x * BM;
     const int F = p.F, H = p.H, Fp = pad_k(F);
     const int ldx = (Fp > H ? Fp : H) + Fuse<OP>::PAD, ldh = H + Fuse<OP>::PAD, ldf = H + 4;
-    T *buf[2] = {reinterpret_cast<T *>(smem), reinterpret_cast<T *>(smem) + BM * ldx};
-    float *hf = reinterpret_cast<float *>(buf[1] + BM * ldh);   // FP32 copy of the last hidden layer
-    // layer-0 input, rounded to the operand type and zero padded to Fp columns: thread tid
-    // takes column tid of every row, so each wave reads one contiguous segment per row
+    // LDS regions, addressed from `smem` by offset arithmetic only (a pointer picked from an
+    // array would lose its address space and turn every LDS access into a flat one)
+    const int off1 = BM * ldx * (int)sizeof(T), offf = off1 + BM * ldh * (int)sizeof(T);
+    auto buf = [&](int which) { return reinterpret_cast<T *>(smem + (which ? off1 : 0)); };
+    float *hf = reinterpret_cast<float *>(smem + offf);   // FP32 copy of the last hidden layer
+    // layer-0 input: the density of this tile's orbital sums, rounded to the operand type
+    // and zero padded to Fp columns.  The S tile is staged in the region the first hidden
+    // layer writes later; one thread per (row, l) keeps that l's components in registers.
     {
-        float v[BM];
+        constexpr int NLK = n_lambda(L) * K, P = K * (K + 1) / 2, NT = BM * NLK;
+        float *Sl = reinterpret_cast<float *>(smem + off1);
+        const int64_t avail = (p.rows - m0) * NLK;
+        constexpr int SV = (NT + 255) / 256;
+        float v[SV];
 #pragma unroll
-        for (int r = 0; r < BM; ++r) v[r] = (tid < F && m0 + r < p.rows) ? p.A[(m0 + r) * p.lda + tid] : 0.0f;
-        if (tid < Fp) {
-#pragma unroll
-            for (int r = 0; r < BM; ++r) buf[0][r * ldx + tid] = to_op<OP>(v[r], 1.0f);
+        for (int i = 0; i < SV; ++i) {
+            const int e = tid + 256 * i;
+            v[i] = (e < NT && e < avail) ? p.S[m0 * NLK + e] : 0.0f;
         }
+#pragma unroll
+        for (int i = 0; i < SV; ++i) {
+            const int e = tid + 256 * i;
+            if (e < NT) Sl[e] = v[i];
+        }
+        __syncthreads();
+        for (int it = tid; it < BM * (L + 1); it += 256) {
+            const int r = it / (L + 1), l = it % (L + 1);
+            const int q0 = l * (l + 1) * (l + 2) / 6, nq = (l + 1) * (l + 2) / 2;   // components of order l
+            float sv[6][K], w[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                w[q] = q < nq ? (float)p.dc.w[q0 + q] : 0.0f;
+#pragma unroll
+                for (int m = 0; m < K; ++m) sv[q][m] = q < nq ? Sl[r * NLK + (q0 + q) * K + m] : 0.0f;
+            }
+            T *xr = buf(0) + r * ldx + l * P;
+            int f = 0;
+#pragma unroll
+            for (int a = 0; a < K; ++a)
+#pragma unroll
+                for (int b = a; b < K; ++b) {
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) acc += w[q] * sv[q][a] * sv[q][b];
+                    xr[f++] = to_op<OP>(acc, 1.0f);
+                }
+        }
+        for (int it = tid; it < BM * (Fp - F); it += 256)
+            buf(0)[(it / (Fp - F)) * ldx + F + it % (Fp - F)] = to_op<OP>(0.0f, 1.0f);
     }
     __syncthreads();
     int cur = 0;
@@ -354,10 +400,10 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(FusedNN p) {
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) bias[cb] = p.b[k][16 * (wave + kFuseWaves * cb) + li];
         f4 acc[RB][NCB];
-        fused_layer<OP, NCB>(buf[cur], ldin, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], k == 0 ? Fp : H, H, wave,
+        fused_layer<OP, NCB>(buf(cur), ldin, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], k == 0 ? Fp : H, H, wave,
                              lane, acc);
         const bool last = k + 1 == p.nh;
-        T *dst = buf[cur ^ 1];
+        T *dst = buf(cur ^ 1);
         float *Zk = p.Z[k];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -380,9 +426,9 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(FusedNN p) {
     }
     // output layer (FP32 data, FP64 accumulation): W_out is staged in the buffer the last
     // hidden layer read; kOutParts threads share a row and combine their partial sums
-    const float *hl = (OP == OpType::F32) ? reinterpret_cast<const float *>(buf[cur]) : hf;
+    const float *hl = (OP == OpType::F32) ? reinterpret_cast<const float *>(buf(cur)) : hf;
     const int ldl = (OP == OpType::F32) ? (cur == 0 ? ldx : ldh) : ldf;
-    float *wo = reinterpret_cast<float *>(buf[cur ^ 1]);
+    float *wo = reinterpret_cast<float *>(buf(cur ^ 1));
     for (int e = tid; e < p.dout * H; e += 256) wo[e] = p.Wout[e];
     __syncthreads();
     constexpr int QM = kFuseMaxH / kOutParts;
@@ -403,10 +449,11 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(FusedNN p) {
     }
 }
 
-// Adjoint of one element's NN: C = dE/dA from G = dE/d(output), using the stored Z_k.
-// NCB = H / 64 and NCBF = column blocks per wave of the F-wide first layer.
-template <OpType OP, int NCB, int NCBF>
+// Adjoint of one element's NN: C = dE/dS from G = dE/d(output), using the stored Z_k.
+// NCB = H / 64 column blocks per wave; (L, K) fix the density and the F-wide first layer.
+template <OpType OP, int NCB, int L, int K>
 __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
+    constexpr int NCBF = (L + 1) * K * (K + 1) / 2 > 128 ? 4 : 2;   // column blocks per wave, first layer
     using T = typename Fuse<OP>::T;
     constexpr int BM = kFuseBM, RB = BM / 16;
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -414,9 +461,28 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
     const int64_t m0 = (int64_t)blockIdx.x * BM;
     const int F = p.F, H = p.H, dout = p.dout;
     const int ldh = H + Fuse<OP>::PAD;
-    T *buf[2] = {reinterpret_cast<T *>(smem), reinterpret_cast<T *>(smem) + BM * ldh};
-    float *wo = reinterpret_cast<float *>(buf[1] + BM * ldh);   // W_out [dout][H]
-    float *gs = wo + dout * H;                                    // G tile [BM][dout]
+    // LDS regions from `smem` by offset arithmetic only (see the forward kernel).  Region A
+    // holds the two adjoint tiles, later dE/drho; region B holds W_out and the G tile, later
+    // the S tile.
+    const int off1 = BM * ldh * (int)sizeof(T), ldr = F + 4;
+    const int offB = max(2 * off1, BM * ldr * 4);
+    auto buf = [&](int which) { return reinterpret_cast<T *>(smem + (which ? off1 : 0)); };
+    float *wo = reinterpret_cast<float *>(smem + offB);   // W_out [dout][H]
+    float *gs = wo + dout * H;                             // G tile [BM][dout]
+    float *Rb = reinterpret_cast<float *>(smem);          // dE/drho [BM][ldr]
+    float *Sl = reinterpret_cast<float *>(smem + offB);   // S tile [BM][NLK]
+    // the S tile is requested now and parked in registers until region B is free
+    constexpr int NLK = n_lambda(L) * K, nlk_tile = BM * NLK;
+    constexpr int SV = (nlk_tile + 255) / 256;
+    float sv[SV];
+    {
+        const int64_t avail = (p.rows - m0) * NLK;
+#pragma unroll
+        for (int i = 0; i < SV; ++i) {
+            const int e = tid + 256 * i;
+            sv[i] = (e < nlk_tile && e < avail) ? p.S[m0 * NLK + e] : 0.0f;
+        }
+    }
     // output layer: zbar[r][q] = (sum_o G[r][o] Wout[o][q]) * SiLU'(Z_{nh-1}[r][q]); thread tid
     // takes column q = tid % H of rows r0, r0 + 256 / H, ...
     {
@@ -442,10 +508,16 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
             float s = 0.0f;
             for (int o = 0; o < dout; ++o) s += gs[r * dout + o] * wo[o * H + q];
             const float v = m0 + r < p.rows ? s * dsilu_f(z[i]) : 0.0f;
-            buf[0][r * ldh + q] = to_op<OP>(v, 1.0f);
+            buf(0)[r * ldh + q] = to_op<OP>(v, 1.0f);
         }
     }
     __syncthreads();
+    // W_out and G are no longer needed: park the S tile in region B
+#pragma unroll
+    for (int i = 0; i < SV; ++i) {
+        const int e = tid + 256 * i;
+        if (e < nlk_tile) Sl[e] = sv[i];
+    }
     int cur = 0;
     for (int k = p.nh - 1; k >= 1; --k) {
         const float *Zk = p.Z[k - 1];
@@ -461,8 +533,8 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
                     zp[rb][cb][r] = row < p.rows ? Zk[row * p.ldz + col] : 0.0f;
                 }
         f4 acc[RB][NCB];
-        fused_layer<OP, NCB>(buf[cur], ldh, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], H, H, wave, lane, acc);
-        T *dst = buf[cur ^ 1];
+        fused_layer<OP, NCB>(buf(cur), ldh, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], H, H, wave, lane, acc);
+        T *dst = buf(cur ^ 1);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -478,9 +550,11 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
         __syncthreads();
         cur ^= 1;
     }
-    // first layer: C = zbar_0 W_0 (F columns)
+    // first layer: dE/drho = zbar_0 W_0 (F columns), into region A once every wave is done
+    // reading the adjoint tile
     f4 acc[RB][NCBF];
-    fused_layer<OP, NCBF>(buf[cur], ldh, reinterpret_cast<const T *>(p.W[0]), p.ldw[0], H, F, wave, lane, acc);
+    fused_layer<OP, NCBF>(buf(cur), ldh, reinterpret_cast<const T *>(p.W[0]), p.ldw[0], H, F, wave, lane, acc);
+    __syncthreads();
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -488,48 +562,79 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
             const int col = 16 * (wave + kFuseWaves * cb) + li;
             if (col >= F) continue;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = m0 + 16 * rb + 4 * lg + r;
-                if (row < p.rows) p.C[row * p.ldc + col] = acc[rb][cb][r];
-            }
+            for (int r = 0; r < 4; ++r) Rb[(16 * rb + 4 * lg + r) * ldr + col] = acc[rb][cb][r];
         }
+    __syncthreads();
+    // density adjoint: dE/dS[lambda][a] = w_lambda sum_b M_l[a][b] S[lambda][b] for lambda of
+    // order l, with M_l the symmetric matrix of dE/drho[l] (doubled on the diagonal); one
+    // thread per (row, lambda)
+    constexpr int P = K * (K + 1) / 2, NL = n_lambda(L);
+    for (int it = tid; it < BM * NL; it += 256) {
+        const int r = it / NL, lam = it % NL;
+        const int l = lam == 0 ? 0 : (lam < 4 ? 1 : (lam < 10 ? 2 : 3));
+        const float *rb = Rb + r * ldr + l * P;
+        float sl[K];
+#pragma unroll
+        for (int b = 0; b < K; ++b) sl[b] = Sl[r * NLK + lam * K + b];
+        const float wl = (float)p.dc.w[lam];
+        const int64_t row = m0 + r;
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            float acc2 = 0.0f;
+#pragma unroll
+            for (int b = 0; b < K; ++b) {
+                const int lo = a < b ? a : b, hi = a < b ? b : a;
+                const float m = rb[lo * K - lo * (lo - 1) / 2 + (hi - lo)];
+                acc2 += (a == b ? 2.0f * m : m) * sl[b];
+            }
+            if (row < p.rows) p.C[row * NLK + lam * K + a] = wl * acc2;
+        }
+    }
 }
 
-bool fused_nn_ok(OpType op, int F, int H, int nh, int dout) {
+bool fused_nn_ok(OpType op, int F, int H, int nh, int dout, int NLK) {
     return op != OpType::FP8 && (H == 64 || H == 128) && F >= 1 && F <= kFuseMaxF && nh >= 1 && nh <= kFuseMaxNh &&
-           dout >= 1 && dout <= kFuseMaxOut;
+           dout >= 1 && dout <= kFuseMaxOut && NLK >= 1 && NLK <= kFuseMaxNLK;
 }
 
-static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout) {
+static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout, int NLK) {
     const size_t eb = op_bytes(op), pad = op == OpType::F32 ? 4 : 8;
-    const size_t Fp = pad_k(F), ldh = H + pad;
-    if (!fwd) return 2 * kFuseBM * ldh * eb + (size_t)(dout * H + kFuseBM * dout) * 4;
-    const size_t ldx = std::max<size_t>(Fp, H) + pad;
-    size_t b = kFuseBM * (ldx + ldh) * eb;
+    const size_t Fp = pad_k(F), ldh = H + pad, s_tile = (size_t)kFuseBM * NLK * 4;
+    if (!fwd) {
+        const size_t a = std::max<size_t>(2 * kFuseBM * ldh * eb, (size_t)kFuseBM * (F + 4) * 4);
+        return a + std::max<size_t>((size_t)(dout * H + kFuseBM * dout) * 4, s_tile);
+    }
+    const size_t ldx = std::max<size_t>(Fp, H) + pad, off1 = kFuseBM * ldx * eb;
+    size_t b = off1 + kFuseBM * ldh * eb;
     if (op != OpType::F32) b += (size_t)kFuseBM * (H + 4) * 4;
-    return b;
+    return std::max(b, off1 + s_tile);   // the S tile is staged from off1
 }
 
 void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
     if (p.rows <= 0) return;
-    if (!fused_nn_ok(op, p.F, p.H, p.nh, p.dout)) fail(REANN_E_DEVICE, "mlp_fused: unsupported layer shape");
-    const size_t smem = fused_smem(op, fwd, p.F, p.H, p.dout);
+    const int NLK = p.dc.lstart[p.L + 1] * p.K;
+    if (!fused_nn_ok(op, p.F, p.H, p.nh, p.dout, NLK) || p.F != (p.L + 1) * p.K * (p.K + 1) / 2)
+        fail(REANN_E_DEVICE, "mlp_fused: unsupported layer shape");
+    const size_t smem = fused_smem(op, fwd, p.F, p.H, p.dout, NLK);
     const dim3 grid((unsigned)((p.rows + kFuseBM - 1) / kFuseBM));
-    const bool h128 = p.H == 128, f256 = p.F > 128;
-#define FWD_(OPV, NC) hipLaunchKernelGGL((k_mlp_fwd<OPV, NC>), grid, dim3(256), smem, st, p)
-#define BWD_(OPV, NC, NF) hipLaunchKernelGGL((k_mlp_bwd<OPV, NC, NF>), grid, dim3(256), smem, st, p)
-#define ALL_(OPV)                                                                \
-    if (fwd) {                                                                   \
-        if (h128) FWD_(OPV, 2); else FWD_(OPV, 1);                               \
-    } else {                                                                     \
-        if (h128) { if (f256) BWD_(OPV, 2, 4); else BWD_(OPV, 2, 2); }           \
-        else { if (f256) BWD_(OPV, 1, 4); else BWD_(OPV, 1, 2); }                \
-    }
+    const bool h128 = p.H == 128;
+#define LK_(OPV, NC, LL, KK)                                                                          \
+    if (fwd) hipLaunchKernelGGL((k_mlp_fwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);        \
+    else hipLaunchKernelGGL((k_mlp_bwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);
+#define NC_(OPV, LL, KK)                       \
+    if (h128) { LK_(OPV, 2, LL, KK) }          \
+    else { LK_(OPV, 1, LL, KK) }
+#define ALL_(OPV)                                                                       \
+    if (p.L == 2 && p.K == 8) { NC_(OPV, 2, 8) }                                        \
+    else if (p.L == 2 && p.K == 12) { NC_(OPV, 2, 12) }                                 \
+    else if (p.L == 1 && p.K == 4) { NC_(OPV, 1, 4) }                                   \
+    else if (p.L == 2 && p.K == 4) { NC_(OPV, 2, 4) }                                   \
+    else fail(REANN_E_UNSUPPORTED, "mlp_fused: no kernel compiled for this (L, K)");
     if (op == OpType::F32) { ALL_(OpType::F32) }
     else { ALL_(OpType::BF16) }
 #undef ALL_
-#undef BWD_
-#undef FWD_
+#undef NC_
+#undef LK_
     LAUNCH_OK(fwd ? "k_mlp_fwd" : "k_mlp_bwd");
 }
 

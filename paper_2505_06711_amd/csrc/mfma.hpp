@@ -34,12 +34,14 @@ constexpr int kFuseMaxH = 128;   // hidden width (64 or 128)
 constexpr int kFuseMaxF = 256;   // input width
 constexpr int kFuseMaxNh = 4;    // hidden layers
 constexpr int kFuseMaxOut = 16;  // output width
+constexpr int kFuseMaxNLK = 160; // orbital sums per row (NL * K)
 
 struct FusedNN {
     int64_t rows;                 // rows of this element's segment
     int F, H, nh, dout;           // input width, hidden width, hidden layers, output width
-    const float *A;               // forward: input [rows][lda]
-    int lda;
+    int L, K;                     // angular order and radial channels of the density input
+    DensityConsts dc;             // its multinomial weights and component ranges
+    const float *S;               // orbital sums [rows][NL*K] (the NN input is their density)
     // forward: W[k] = layer k as [out][ldw] (gemm_mfma's forward operand)
     // adjoint: W[k] = layer k transposed, [in][ldw]
     const void *W[kFuseMaxNh];
@@ -50,13 +52,14 @@ struct FusedNN {
     const float *Wout, *bout;     // output layer [dout][H], [dout] (FP32)
     const float *G;               // adjoint: output adjoint [rows][ldg]
     int ldg;
-    float *C;                     // forward: outputs [rows][ldc]; adjoint: dE/dA [rows][ldc]
+    float *C;                     // forward: outputs [rows][ldc]; adjoint: dE/dS [rows][NL*K]
     int ldc;
 };
 
-bool fused_nn_ok(OpType op, int F, int H, int nh, int dout);
-// Forward (fwd = true: hidden layers, Z stores, output layer with FP64 accumulation) or
-// adjoint (fwd = false: output layer, hidden layers, dE/dA) of one element's NN.
+bool fused_nn_ok(OpType op, int F, int H, int nh, int dout, int NLK);
+// Forward (fwd = true: density of S, hidden layers, Z stores, output layer with FP64
+// accumulation) or adjoint (fwd = false: output layer, hidden layers, first layer, density
+// adjoint to dE/dS) of one element's NN.
 void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p);
 
 inline size_t op_bytes(OpType op) { return op == OpType::F32 ? 4 : (op == OpType::BF16 ? 2 : 1); }

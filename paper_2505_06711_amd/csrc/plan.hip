@@ -236,7 +236,8 @@ int64_t Plan::collect_timing(double *ms, int64_t *nlaunch) {
 
 // whether both atomic NNs run as fused kernels (FP32 or BF16 operands, supported widths)
 bool Plan::fused() const {
-    return !fp64 && fused_nn_ok(op, m->F, m->H, m->nh, m->K) && fused_nn_ok(op, m->F, m->H, m->nh, 1);
+    return !fp64 && fused_nn_ok(op, m->F, m->H, m->nh, m->K, m->NL * m->K) &&
+           fused_nn_ok(op, m->F, m->H, m->nh, 1, m->NL * m->K);
 }
 
 void Plan::alloc_buffers() {
@@ -245,7 +246,7 @@ void Plan::alloc_buffers() {
     px.ensure(ne * 8); py.ensure(ne * 8); pz.ensure(ne * 8);
     c.ensure((size_t)T * ne * K * rs);
     S.ensure((size_t)T * n * NL * K * rs);
-    rho.ensure((size_t)T * n * F * rs);
+    if (!fused()) rho.ensure((size_t)T * n * F * rs);
     Z.ensure((size_t)T * nh * n * H * rs);
     if (!fused()) Hh.ensure((size_t)2 * n * H * rs);
     y.ensure((size_t)n * K * rs);
@@ -253,7 +254,7 @@ void Plan::alloc_buffers() {
     Eat.ensure((size_t)n * 8);
     Epart.ensure((size_t)(grid_for(n, 256) + 1) * 8);
     Sbar.ensure((size_t)n * NL * K * rs);
-    rhobar.ensure((size_t)n * F * rs);
+    if (!fused()) rhobar.ensure((size_t)n * F * rs);
     if (!fused()) {
         const int wmax = F > H ? F : H;
         gA.ensure((size_t)n * wmax * rs);
@@ -320,7 +321,8 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
         if (fused()) {
             FusedNN f{};
             f.rows = rows; f.F = F; f.H = H; f.nh = nh; f.dout = dout;
-            f.A = (const float *)A; f.lda = lda;
+            f.L = m->L; f.K = K; f.dc = m->density_consts();
+            f.S = (const float *)(Sptr(t) + (size_t)a * m->NL * K * rs);
             for (int k = 0; k < nh; ++k) {
                 const size_t qi = (size_t)nn_index * nh + k;
                 f.W[k] = mf->buf.as<char>() + mf->off_fwd[qi];
@@ -364,7 +366,7 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
 }
 
 // VJP of the NN applied at layer t (energy NN if `energy`), from output adjoint gout
-// [n][ldg] to rhobar.
+// [n][ldg] to Sbar when the NN is fused (the density adjoint included), else to rhobar.
 int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) {
     DeviceWeights &w = m->weights(ctx->device, st);
     const NNLayout &lay = energy ? m->en_nn : m->msg_nn;
@@ -386,6 +388,8 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
         if (fused()) {
             FusedNN f{};
             f.rows = rows; f.F = F; f.H = H; f.nh = nh; f.dout = lay.dout[nh];
+            f.L = m->L; f.K = m->K; f.dc = m->density_consts();
+            f.S = (const float *)(Sptr(t) + (size_t)a * m->NL * m->K * rs);
             for (int k = 0; k < nh; ++k) {
                 const size_t qi = (size_t)nn_index * nh + k;
                 f.W[k] = mf->buf.as<char>() + mf->off_bwd[qi];
@@ -395,7 +399,7 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
             f.ldz = H;
             f.Wout = (const float *)(p + lay.w_off[nh] * rs);
             f.G = (const float *)gin; f.ldg = ldin;
-            f.C = (float *)(rhobar.as<char>() + (size_t)a * F * rs); f.ldc = F;
+            f.C = (float *)(Sbar.as<char>() + (size_t)a * m->NL * m->K * rs); f.ldc = m->NL * m->K;
             mlp_fused(st, op, false, f);
             ++nfused;
             continue;
@@ -465,8 +469,10 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
     for (int t = 0; t < T; ++t) {
         edge_forward(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sptr(t));
         mark(st, PH_EDGE_FWD, 1);
-        density(st, fp64, m->L, K, n, dc, Sptr(t), rhoptr(t));
-        mark(st, PH_DENSITY, 1);
+        if (!fused()) {   // the fused NN kernels contract S themselves
+            density(st, fp64, m->L, K, n, dc, Sptr(t), rhoptr(t));
+            mark(st, PH_DENSITY, 1);
+        }
         if (t < T - 1) {
             mark(st, PH_NN_FWD, nn_forward(st, t, false));
             ghost_gather(st, fp64, n, nl.n_gh, K, nl.gh_owner.ptr(), cptr(t + 1));
@@ -493,8 +499,10 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     zero(st, Wacc.p, 9 * 8);
     mark(st, PH_OTHER);
     mark(st, PH_NN_BWD, nn_vjp(st, T - 1, true, ybar.as<char>(), 1));
-    density_vjp(st, fp64, m->L, K, n, dc, Sptr(T - 1), rhobar.p, Sbar.p);
-    mark(st, PH_DENSITY_ADJ, 1);
+    if (!fused()) {
+        density_vjp(st, fp64, m->L, K, n, dc, Sptr(T - 1), rhobar.p, Sbar.p);
+        mark(st, PH_DENSITY_ADJ, 1);
+    }
     for (int t = T - 1; t >= 0; --t) {
         const int nb = edge_adjoint_centre(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sbar.p, t > 0, this->F.p,
                                            Wpart.as<double>(), erec.p);
@@ -507,8 +515,10 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
             ghost_reduce(st, fp64, n, K, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), cbar.p);
             mark(st, PH_GHOST);
             mark(st, PH_NN_BWD, nn_vjp(st, t - 1, false, cbar.as<char>(), K));
-            density_vjp(st, fp64, m->L, K, n, dc, Sptr(t - 1), rhobar.p, Sbar.p);
-            mark(st, PH_DENSITY_ADJ, 1);
+            if (!fused()) {
+                density_vjp(st, fp64, m->L, K, n, dc, Sptr(t - 1), rhobar.p, Sbar.p);
+                mark(st, PH_DENSITY_ADJ, 1);
+            }
         }
     }
     ghost_reduce(st, fp64, n, 3, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), this->F.p);
