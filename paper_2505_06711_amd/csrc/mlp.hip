@@ -273,10 +273,16 @@ int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const vo
 
 __global__ void k_sum_rows(const double *__restrict__ part, int nb, int width, double *__restrict__ out, int acc) {
     // block q sums column q over the rows in a fixed order (strided per thread, then a tree)
+    // eight independent running sums per thread keep eight loads in flight
     __shared__ double sm[256];
     const int q = blockIdx.x;
-    double s = 0.0;
-    for (int r = threadIdx.x; r < nb; r += blockDim.x) s += part[(int64_t)r * width + q];
+    double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int r = threadIdx.x;
+    for (; r + 7 * 256 < nb; r += 8 * 256)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s8[u] += part[(int64_t)(r + u * 256) * width + q];
+    for (; r < nb; r += 256) s8[0] += part[(int64_t)r * width + q];
+    const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     sm[threadIdx.x] = s;
     __syncthreads();
     for (int h = blockDim.x / 2; h > 0; h >>= 1) {
