@@ -129,10 +129,24 @@ __device__ inline int64_t cut_slot(const CutList &cl, int64_t x, int e) {
     return e < nl ? cl.row[x] + e : cl.row[x + 1] - cl.ngh[x] + (e - nl);
 }
 
-// Forward edge pass: G = 4 lanes per row, lane q owning channels m = q, q+4, q+8, ...
-// Each lane walks the whole row (the per-edge geometry is recomputed by the 4 lanes) and
-// keeps NL x K/4 accumulators, so many more waves are resident than with a row per lane.
+// Forward edge pass: the 4 lanes of a quad own one row, lane q the channels m = q, q+4, ...
+// The row's edges are taken in groups of 4: lane q evaluates the geometry of edge 4g + q
+// (r, f_c and the angular terms, from one position gather), and the quad exchanges these
+// with DPP quad broadcasts, so that every lane accumulates all 4 edges into its channels.
+// The list entries, positions and messages of group g + 1 are loaded while group g is
+// evaluated (indices clamped to the row's last edge; a lane past the end contributes 0).
 constexpr int kFwdLanes = 4;
+
+// value of lane SRC of this lane's quad (all 4 lanes must be active)
+template <int SRC> __device__ inline int quad_bcast(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, SRC * 0x55, 0xF, 0xF, false);
+}
+template <int SRC> __device__ inline float quad_bcast(float v) { return __int_as_float(quad_bcast<SRC>(__float_as_int(v))); }
+template <int SRC> __device__ inline double quad_bcast(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = quad_bcast<SRC>((int)(uint32_t)(b & 0xffffffffll)), hi = quad_bcast<SRC>((int)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
 
 template <int L, int K, typename R>
 __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeConsts ec, const R *__restrict__ c,
@@ -143,7 +157,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t i = t / G;
     const int q = (int)(t % G);
-    if (i >= a.n) return;
+    if (i >= a.n) return;   // the whole quad leaves together
     R acc[NL][KG];
 #pragma unroll
     for (int l = 0; l < NL; ++l)
@@ -155,48 +169,70 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
     const double xi = a.px[i], yi = a.py[i], zi = a.pz[i];
     const R inv_rc = R(1.0 / ec.r_c);
     const R s = R(ec.ang_scale);
-    const int nl = cl.nloc[i], cnt = nl + cl.ngh[i];
+    const int nl = cl.nloc[i], cnt = nl + cl.ngh[i], last = cnt - 1;
     const int64_t lo = cl.row[i], gb = cl.row[i + 1] - cl.ngh[i];
-    // software pipeline without branches: while edge e is evaluated, the position and message
-    // of edge e + 1 and the list entry of edge e + 2 are in flight (indices clamped to the
-    // row's last edge)
-    const int last = cnt - 1;
     auto slot = [&](int e) -> int64_t { return e < nl ? lo + e : gb + (e - nl); };
-    double xn = 0.0, yn = 0.0, zn = 0.0;
-    R cn[KG];
-    int32_t jn = 0;
-    if (cnt > 0) {
-        const int32_t j0 = cl.col[slot(0)];
-        jn = cl.col[slot(min(1, last))];
-        xn = a.px[j0]; yn = a.py[j0]; zn = a.pz[j0];
+    const int ngroups = (cnt + G - 1) / G;
+    // group 0 in registers, and the own list entry of group 1
+    double xo = 0.0, yo = 0.0, zo = 0.0;
+    R cg[G][KG];
+    int32_t jnext = 0;
+    if (ngroups > 0) {
+        const int32_t j0 = cl.col[slot(min(q, last))];
+        jnext = cl.col[slot(min(G + q, last))];
+        xo = a.px[j0]; yo = a.py[j0]; zo = a.pz[j0];
+        const int32_t js[G] = {quad_bcast<0>(j0), quad_bcast<1>(j0), quad_bcast<2>(j0), quad_bcast<3>(j0)};
 #pragma unroll
-        for (int u = 0; u < KG; ++u) cn[u] = c[(int64_t)j0 * K + q + G * u];
+        for (int sl = 0; sl < G; ++sl)
+#pragma unroll
+            for (int u = 0; u < KG; ++u) cg[sl][u] = c[(int64_t)js[sl] * K + q + G * u];
     }
-    for (int e = 0; e < cnt; ++e) {
-        const double dx = xn - xi, dy = yn - yi, dz = zn - zi;
-        R cj[KG];
+    for (int g = 0; g < ngroups; ++g) {
+        const double dx = xo - xi, dy = yo - yi, dz = zo - zi;
+        const bool live = g * G + q <= last;
+        R cur[G][KG];
 #pragma unroll
-        for (int u = 0; u < KG; ++u) cj[u] = cn[u];
-        {
-            const int64_t jj = jn;
-            xn = a.px[jj]; yn = a.py[jj]; zn = a.pz[jj];
+        for (int sl = 0; sl < G; ++sl)
 #pragma unroll
-            for (int u = 0; u < KG; ++u) cn[u] = c[jj * K + q + G * u];
-            jn = cl.col[slot(min(e + 2, last))];
+            for (int u = 0; u < KG; ++u) cur[sl][u] = cg[sl][u];
+        {   // group g + 1: own position, the quad's messages, and the own entry of group g + 2
+            const int32_t j1 = jnext;
+            xo = a.px[j1]; yo = a.py[j1]; zo = a.pz[j1];
+            const int32_t js[G] = {quad_bcast<0>(j1), quad_bcast<1>(j1), quad_bcast<2>(j1), quad_bcast<3>(j1)};
+#pragma unroll
+            for (int sl = 0; sl < G; ++sl)
+#pragma unroll
+                for (int u = 0; u < KG; ++u) cg[sl][u] = c[(int64_t)js[sl] * K + q + G * u];
+            jnext = cl.col[slot(min((g + 2) * G + q, last))];
         }
+        // own edge: geometry
         const double d2 = dx * dx + dy * dy + dz * dz;
         const R r = d_sqrt(R(d2));
         const R uc = R(0.5) * d_cospi(r * inv_rc) + R(0.5);
-        const R fc = uc * uc;
+        const R fc = live ? uc * uc : R(0);
         R A[NL];
         angular<L, R, false>(R(ec.ang_scale * dx), R(ec.ang_scale * dy), R(ec.ang_scale * dz), s, A, nullptr);
+        // the quad's 4 edges into this lane's channels
+        auto edge = [&](const R rs, const R fs, const R (&As)[NL], const R (&cs)[KG]) {
 #pragma unroll
-        for (int u = 0; u < KG; ++u) {
-            const R xm = r - cen[u];
-            const R w = cj[u] * d_exp(-alp[u] * xm * xm) * fc;
+            for (int u = 0; u < KG; ++u) {
+                const R xm = rs - cen[u];
+                const R w = cs[u] * d_exp(-alp[u] * xm * xm) * fs;
 #pragma unroll
-            for (int l = 0; l < NL; ++l) acc[l][u] += w * A[l];
+                for (int l = 0; l < NL; ++l) acc[l][u] += w * As[l];
+            }
+        };
+#define REANN_FWD_SRC(SRC)                                                          \
+        {                                                                           \
+            R As[NL];                                                               \
+            _Pragma("unroll") for (int l = 0; l < NL; ++l) As[l] = quad_bcast<SRC>(A[l]); \
+            edge(quad_bcast<SRC>(r), quad_bcast<SRC>(fc), As, cur[SRC]);            \
         }
+        REANN_FWD_SRC(0)
+        REANN_FWD_SRC(1)
+        REANN_FWD_SRC(2)
+        REANN_FWD_SRC(3)
+#undef REANN_FWD_SRC
     }
     R *out = S + i * NL * K + q;
 #pragma unroll
