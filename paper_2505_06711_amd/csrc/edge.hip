@@ -386,26 +386,31 @@ __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, Edge
             px[0] = py[0] = pz[0] = R(1);
 #pragma unroll
             for (int k = 1; k <= L; ++k) { px[k] = px[k - 1] * ux; py[k] = py[k - 1] * uy; pz[k] = pz[k - 1] * uz; }
-            R gx = R(0), gy = R(0), gz = R(0), sAP = R(0), sAQ = R(0);
+            // P_lambda = sum_m Sbar[lambda][m] u_m for the angular gradient, and
+            // cacc_m = sum_lambda Sbar[lambda][m] A_lambda; the two radial contractions then
+            // follow as sum_lambda A_lambda P_lambda = cacc . u and
+            // sum_lambda A_lambda sum_m Sbar[lambda][m] v_m = cacc . v
+            R gx = R(0), gy = R(0), gz = R(0);
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
                 // one row of Sbar_k at a time (the compiler would otherwise load them all ahead)
                 asm volatile("" ::: "memory");
                 const int lx = LT.lx[l], ly = LT.ly[l], lz = LT.lz[l];
                 const R Al = px[lx] * py[ly] * pz[lz];
-                R P = R(0), Q = R(0);
+                R P = R(0);
 #pragma unroll
                 for (int m = 0; m < K; ++m) {
                     const R w = sb[l * K + m];
                     P += w * u[m];
-                    Q += w * v[m];
-                    if constexpr (CBAR) cacc[m] += w * Al;
+                    cacc[m] += w * Al;
                 }
                 if (lx) gx += P * (s * R(lx) * px[lx > 0 ? lx - 1 : 0] * py[ly] * pz[lz]);
                 if (ly) gy += P * (s * R(ly) * px[lx] * py[ly > 0 ? ly - 1 : 0] * pz[lz]);
                 if (lz) gz += P * (s * R(lz) * px[lx] * py[ly] * pz[lz > 0 ? lz - 1 : 0]);
-                sAP += Al * P; sAQ += Al * Q;
             }
+            R sAP = R(0), sAQ = R(0);
+#pragma unroll
+            for (int m = 0; m < K; ++m) { sAP += cacc[m] * u[m]; sAQ += cacc[m] * v[m]; }
             const R rad = g.dfc * sAP + g.fc * sAQ;
             gx = g.fc * gx + rad * g.ex; gy = g.fc * gy + rad * g.ey; gz = g.fc * gz + rad * g.ez;
             f0 += gx; f1 += gy; f2 += gz;
