@@ -323,6 +323,31 @@ def test_cu100800_full_size_against_oracle_golden(rn, ctx, prec):
     assert np.abs(W.cpu().numpy() - Wref).max() <= tol_w * np.abs(Wref).max()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_precision_ladder_cu100800(rn, ctx, prec):
+    """Precision ladder on the full 100,800-atom Cu workload (T = 3): atomic-NN products in
+    FP32, BF16 or FP8 e4m3 (per-tensor scales), FP32 accumulation, against the oracle's
+    stored FP64 energy and 256 sampled forces.  Prints the energy error in meV/atom and the
+    force RMSE over the sample in meV/A; the bounds are sanity limits per rung."""
+    from tests.golden.make_golden import positions_digest
+    g = _golden("cu100800", 3)
+    w = synth.workload("cu100800")
+    s, m = w["system"], w["model"]
+    assert positions_digest(s["pos"]) == g["positions_sha256"]
+    n = len(s["pos"])
+    E, F, _ = rn.energy_forces(ctx, rn.Model(m), s, T=3, precision=prec, skin=w["skin"])
+    idx = np.array(g["sample_index"])
+    Fref = np.array(g["sample_forces"]).reshape(-1, 3)
+    de = abs(E - g["energy"]) / n * 1e3
+    frmse = np.sqrt(((F[idx] - Fref) ** 2).mean()) * 1e3
+    rel = abs(E - g["energy"]) / max(abs(g["energy"]), g["sum_abs_atom_energy"])
+    print("ladder %s: |dE| = %.3e meV/atom (E/N = %.4f eV), force RMSE = %.3e meV/A (force RMS %.3f eV/A), "
+          "rel E %.2e" % (prec, de, g["energy"] / n, frmse, g["force_rms"], rel), flush=True)
+    lim = {"fp32": 1e-6, "bf16": 2e-2, "fp8": 3e-1}[prec]
+    assert rel <= lim
+    assert frmse / 1e3 <= {"fp32": 1e-5, "bf16": 5e-2, "fp8": 5e-1}[prec] * g["force_rms"]
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_precision_ladder_reports(rn, ctx, oracle_lib, prec):
     """Atomic-NN products in BF16 / FP8 (FP32 accumulation) on a 4,000-atom piece of the Cu
