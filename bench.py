@@ -370,6 +370,16 @@ def main():
     la = tim["launches"]
     roof = roofline(wk, tim, T, a.precision, a.workload)
 
+    # the host-pointer entry point on the same system: positions in and forces / virial out
+    # over PCIe each call (reported beside the device-resident rate, never as `value`)
+    nh = max(1, min(5, a.steps))
+    rn.energy_forces(ctx, model, s, T=T, precision=a.precision, decomp=w["decomp"], skin=w["skin"])
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    for _ in range(nh):
+        rn.energy_forces(ctx, model, s, T=T, precision=a.precision, decomp=w["decomp"], skin=w["skin"])
+    host_ms = (time.perf_counter() - th) / nh * 1e3
+
     out = dict(metric=METRIC, value=round(value, 1), unit="atom-steps/s", n_gpus=1, steps=a.steps,
                warmup=a.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype={"fp64": "f64", "fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[a.precision],
@@ -378,6 +388,8 @@ def main():
                            ghosts=nl["n_ghosts"], list_pairs=n_local_pairs, in_cutoff_edges=n_in_cutoff,
                            first_step_s=round(t_build, 3), wall_s=round(wall, 3)),
                phase_ms_per_step={k: round(v, 4) for k, v in ms.items()},
+               host_pointer_path=dict(ms_per_call=round(host_ms, 3), atom_steps_per_s=round(n / (host_ms * 1e-3), 1),
+                                      note="reann_energy_forces with host buffers: PCIe copies included"),
                roofline=roof)
     if not a.no_serve:
         print("bench: serving", file=sys.stderr, flush=True)
