@@ -293,7 +293,8 @@ constexpr int kRowsPerBlock = 8;   // 256 threads = 8 half-waves, one row each
 
 // Centre role: for local row k and each in-cutoff neighbour j (edge k -> j),
 //   g = d/dd [ f_c sum_lambda A_lambda(d) sum_m Sbar_k[lambda][m] c_j[m] R_m(r) ]
-// adds +g to F_k and -d (x) g to the virial; the edge's record gets g and (CBAR) the terms
+// adds +g to F_k and the symmetric part of -d (x) g to the virial; the edge's record gets g
+// and (CBAR) the terms
 //   f_c R_m sum_lambda Sbar_k[lambda][m] A_lambda(d)  of  cbar_j[m].
 // kCentreLanes lanes share a row and take its edges in turn; Sbar_k is staged in LDS and
 // read by all of them.  Each lane runs a two-stage pipeline: the list entry of its edge after
@@ -310,7 +311,7 @@ template <typename R> __device__ inline R row_sum(R v) {   // over the kCentreLa
 }
 
 template <int L, int K, typename R, bool CBAR>
-__global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, EdgeConsts ec, const R *__restrict__ c,
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(EdgeArgs a, CutList cl, EdgeConsts ec, const R *__restrict__ c,
                                                     const R *__restrict__ Sbar, R *__restrict__ F,
                                                     double *__restrict__ Wpart, R *__restrict__ rec) {
     constexpr int NL = n_lambda(L), LPR = kCentreLanes;
@@ -328,9 +329,11 @@ __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, Edge
     __syncthreads();
     const int64_t x = row0 + grp;
     R f0 = R(0), f1 = R(0), f2 = R(0);
-    double W[9];
+    // virial: the total over all edges of a rotation-invariant energy is symmetric, so the
+    // symmetric part of each -d (x) g is accumulated (xx, yy, zz, xy, xz, yz) in FP64
+    double W[6];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) W[q] = 0.0;
+    for (int q = 0; q < 6; ++q) W[q] = 0.0;
     if (x < a.n) {
         const double xi = a.px[x], yi = a.py[x], zi = a.pz[x];
         const R s = R(ec.ang_scale);
@@ -364,11 +367,10 @@ __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, Edge
             const int64_t f = fcur;
             EdgeGeo<K, R> g;
             edge_geo<K, R>(ec, dx, dy, dz, g);
-            R u[K], v[K], cacc[K];
+            R u[K], cacc[K];
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 u[m] = cc[m] * g.Rm[m];
-                v[m] = cc[m] * g.dRm[m];
                 cacc[m] = R(0);
             }
             {
@@ -408,9 +410,13 @@ __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, Edge
                 if (ly) gy += P * (s * R(ly) * px[lx] * py[ly > 0 ? ly - 1 : 0] * pz[lz]);
                 if (lz) gz += P * (s * R(lz) * px[lx] * py[ly] * pz[lz > 0 ? lz - 1 : 0]);
             }
+            // c_m dR_m/dr = -2 alpha_m (r - r_m) u_m, formed here rather than kept through the loop
             R sAP = R(0), sAQ = R(0);
 #pragma unroll
-            for (int m = 0; m < K; ++m) { sAP += cacc[m] * u[m]; sAQ += cacc[m] * v[m]; }
+            for (int m = 0; m < K; ++m) {
+                sAP += cacc[m] * u[m];
+                sAQ += cacc[m] * (R(-2) * R(ec.alphas[m]) * (g.r - R(ec.centres[m])) * u[m]);
+            }
             const R rad = g.dfc * sAP + g.fc * sAQ;
             gx = g.fc * gx + rad * g.ex; gy = g.fc * gy + rad * g.ey; gz = g.fc * gz + rad * g.ez;
             f0 += gx; f1 += gy; f2 += gz;
@@ -422,20 +428,24 @@ __global__ __launch_bounds__(256) void k_adj_centre(EdgeArgs a, CutList cl, Edge
                     st4(out + 4 + m, g.fc * g.Rm[m] * cacc[m], g.fc * g.Rm[m + 1] * cacc[m + 1],
                         g.fc * g.Rm[m + 2] * cacc[m + 2], g.fc * g.Rm[m + 3] * cacc[m + 3]);
             }
-            const double gd[3] = {double(gx), double(gy), double(gz)}, dd[3] = {dx, dy, dz};
-#pragma unroll
-            for (int p = 0; p < 3; ++p)
-#pragma unroll
-                for (int q = 0; q < 3; ++q) W[3 * p + q] -= dd[p] * gd[q];
+            const double gxd = double(gx), gyd = double(gy), gzd = double(gz);
+            W[0] -= dx * gxd;
+            W[1] -= dy * gyd;
+            W[2] -= dz * gzd;
+            W[3] -= 0.5 * (dx * gyd + dy * gxd);
+            W[4] -= 0.5 * (dx * gzd + dz * gxd);
+            W[5] -= 0.5 * (dy * gzd + dz * gyd);
         }
     }
     f0 = row_sum(f0); f1 = row_sum(f1); f2 = row_sum(f2);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) W[q] = row_sum(W[q]);
+    for (int q = 0; q < 6; ++q) W[q] = row_sum(W[q]);
     if (lane == 0) {
         if (x < a.n) { F[3 * x] += f0; F[3 * x + 1] += f1; F[3 * x + 2] += f2; }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) sW[grp][q] = W[q];
+        sW[grp][0] = W[0]; sW[grp][4] = W[1]; sW[grp][8] = W[2];
+        sW[grp][1] = sW[grp][3] = W[3];
+        sW[grp][2] = sW[grp][6] = W[4];
+        sW[grp][5] = sW[grp][7] = W[5];
     }
     __syncthreads();
     if (threadIdx.x < 9) {
