@@ -334,76 +334,67 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
 // Forward of one element's NN over rows [0, rows): C = out_layer(SiLU(... SiLU(rho W_0^T + b_0) ...))
 // with rho the density of S.  NCB = H / 64 column blocks per wave; (L, K) fix the density.
 template <OpType OP, int NCB, int L, int K>
-__global__ __launch_bounds__(256) void k_mlp_fwd(FusedNN p) {
+__global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
     using T = typename Fuse<OP>::T;
     constexpr int BM = kFuseBM, RB = BM / 16;
+    constexpr int NLK = n_lambda(L) * K, P = K * (K + 1) / 2;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
     const int64_t m0 = (int64_t)blockIdx.x * BM;
     const int F = p.F, H = p.H, Fp = pad_k(F);
-    const int ldx = (Fp > H ? Fp : H) + Fuse<OP>::PAD, ldh = H + Fuse<OP>::PAD, ldf = H + 4;
-    // LDS regions, addressed from `smem` by offset arithmetic only (a pointer picked from an
-    // array would lose its address space and turn every LDS access into a flat one)
-    const int off1 = BM * ldx * (int)sizeof(T), offf = off1 + BM * ldh * (int)sizeof(T);
-    auto buf = [&](int which) { return reinterpret_cast<T *>(smem + (which ? off1 : 0)); };
-    float *hf = reinterpret_cast<float *>(smem + offf);   // FP32 copy of the last hidden layer
-    // layer-0 input: the density of this tile's orbital sums, rounded to the operand type
-    // and zero padded to Fp columns.  The S tile is staged in the region the first hidden
-    // layer writes later; one thread per (row, l) keeps that l's components in registers.
-    {
-        constexpr int NLK = n_lambda(L) * K, P = K * (K + 1) / 2, NT = BM * NLK;
-        float *Sl = reinterpret_cast<float *>(smem + off1);
-        const int64_t avail = (p.rows - m0) * NLK;
-        constexpr int SV = (NT + 255) / 256;
-        float v[SV];
+    const int ldx = (Fp > H ? Fp : H) + Fuse<OP>::PAD, ldf = H + 4;
+    // LDS, addressed from `smem` by offset arithmetic only (a pointer picked from an array
+    // would lose its address space and turn every LDS access into a flat one): X [BM][ldx]
+    // holds the layer-0 input and then, in place, every hidden layer's output; non-FP32
+    // operands add an FP32 copy of the last hidden layer; W_out [dout][H].  One region for
+    // the activations keeps four workgroups per CU.
+    const int offf = BM * ldx * (int)sizeof(T);
+    const int offw = offf + (OP == OpType::F32 ? 0 : BM * ldf * 4);
+    T *X = reinterpret_cast<T *>(smem);
+    float *hf = reinterpret_cast<float *>(smem + offf);
+    float *wo = reinterpret_cast<float *>(smem + offw);
+    for (int e = tid; e < p.dout * H; e += 256) wo[e] = p.Wout[e];
+    // layer-0 input: the density of this tile's orbital sums, rounded to the operand type and
+    // zero padded to Fp columns; one thread per (row, l) reads that l's components of S
+    for (int it = tid; it < BM * (L + 1); it += 256) {
+        const int r = it / (L + 1), l = it % (L + 1);
+        const int q0 = l * (l + 1) * (l + 2) / 6, nq = (l + 1) * (l + 2) / 2;   // components of order l
+        const bool ok = m0 + r < p.rows;
+        const float4 *Sg = reinterpret_cast<const float4 *>(p.S + (m0 + r) * NLK + q0 * K);
+        float sv[6][K], w[6];
 #pragma unroll
-        for (int i = 0; i < SV; ++i) {
-            const int e = tid + 256 * i;
-            v[i] = (e < NT && e < avail) ? p.S[m0 * NLK + e] : 0.0f;
-        }
+        for (int q = 0; q < 6; ++q) {
+            w[q] = q < nq ? (float)p.dc.w[q0 + q] : 0.0f;
 #pragma unroll
-        for (int i = 0; i < SV; ++i) {
-            const int e = tid + 256 * i;
-            if (e < NT) Sl[e] = v[i];
-        }
-        __syncthreads();
-        for (int it = tid; it < BM * (L + 1); it += 256) {
-            const int r = it / (L + 1), l = it % (L + 1);
-            const int q0 = l * (l + 1) * (l + 2) / 6, nq = (l + 1) * (l + 2) / 2;   // components of order l
-            float sv[6][K], w[6];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                w[q] = q < nq ? (float)p.dc.w[q0 + q] : 0.0f;
-#pragma unroll
-                for (int m = 0; m < K; ++m) sv[q][m] = q < nq ? Sl[r * NLK + (q0 + q) * K + m] : 0.0f;
+            for (int m4 = 0; m4 < K / 4; ++m4) {
+                const float4 v4 = (q < nq && ok) ? Sg[q * (K / 4) + m4] : make_float4(0.f, 0.f, 0.f, 0.f);
+                sv[q][4 * m4] = v4.x; sv[q][4 * m4 + 1] = v4.y; sv[q][4 * m4 + 2] = v4.z; sv[q][4 * m4 + 3] = v4.w;
             }
-            T *xr = buf(0) + r * ldx + l * P;
-            int f = 0;
-#pragma unroll
-            for (int a = 0; a < K; ++a)
-#pragma unroll
-                for (int b = a; b < K; ++b) {
-                    float acc = 0.0f;
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) acc += w[q] * sv[q][a] * sv[q][b];
-                    xr[f++] = to_op<OP>(acc, 1.0f);
-                }
         }
-        for (int it = tid; it < BM * (Fp - F); it += 256)
-            buf(0)[(it / (Fp - F)) * ldx + F + it % (Fp - F)] = to_op<OP>(0.0f, 1.0f);
+        T *xr = X + r * ldx + l * P;
+        int f = 0;
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+            for (int b = a; b < K; ++b) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) acc += w[q] * sv[q][a] * sv[q][b];
+                xr[f++] = to_op<OP>(acc, 1.0f);
+            }
     }
+    for (int it = tid; it < BM * (Fp - F); it += 256)
+        X[(it / (Fp - F)) * ldx + F + it % (Fp - F)] = to_op<OP>(0.0f, 1.0f);
     __syncthreads();
-    int cur = 0;
     for (int k = 0; k < p.nh; ++k) {
-        const int ldin = cur == 0 ? ldx : ldh, ldout = cur == 0 ? ldh : ldx;
         float bias[NCB];
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) bias[cb] = p.b[k][16 * (wave + kFuseWaves * cb) + li];
         f4 acc[RB][NCB];
-        fused_layer<OP, NCB>(buf(cur), ldin, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], k == 0 ? Fp : H, H, wave,
-                             lane, acc);
+        fused_layer<OP, NCB>(X, ldx, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], k == 0 ? Fp : H, H, wave, lane,
+                             acc);
+        __syncthreads();   // every wave has read this layer's input
         const bool last = k + 1 == p.nh;
-        T *dst = buf(cur ^ 1);
         float *Zk = p.Z[k];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -417,20 +408,16 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(FusedNN p) {
                     const float z = acc[rb][cb][r] + bias[cb];
                     if (row < p.rows) Zk[row * p.ldz + col] = z;
                     const float h = silu_f(z);
-                    dst[rr * ldout + col] = to_op<OP>(h, 1.0f);
+                    X[rr * ldx + col] = to_op<OP>(h, 1.0f);
                     if (OP != OpType::F32 && last) hf[rr * ldf + col] = h;
                 }
             }
         __syncthreads();
-        cur ^= 1;
     }
-    // output layer (FP32 data, FP64 accumulation): W_out is staged in the buffer the last
-    // hidden layer read; kOutParts threads share a row and combine their partial sums
-    const float *hl = (OP == OpType::F32) ? reinterpret_cast<const float *>(buf(cur)) : hf;
-    const int ldl = (OP == OpType::F32) ? (cur == 0 ? ldx : ldh) : ldf;
-    float *wo = reinterpret_cast<float *>(buf(cur ^ 1));
-    for (int e = tid; e < p.dout * H; e += 256) wo[e] = p.Wout[e];
-    __syncthreads();
+    // output layer (FP32 data, FP64 accumulation): kOutParts threads share a row and combine
+    // their partial sums
+    const float *hl = (OP == OpType::F32) ? reinterpret_cast<const float *>(X) : hf;
+    const int ldl = (OP == OpType::F32) ? ldx : ldf;
     constexpr int QM = kFuseMaxH / kOutParts;
     const int row = tid / kOutParts, part = tid % kOutParts, qn = H / kOutParts;
     float hv[QM];
@@ -450,39 +437,25 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(FusedNN p) {
 }
 
 // Adjoint of one element's NN: C = dE/dS from G = dE/d(output), using the stored Z_k.
-// NCB = H / 64 column blocks per wave; (L, K) fix the density and the F-wide first layer.
 template <OpType OP, int NCB, int L, int K>
-__global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
+__global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
     constexpr int NCBF = (L + 1) * K * (K + 1) / 2 > 128 ? 4 : 2;   // column blocks per wave, first layer
     using T = typename Fuse<OP>::T;
     constexpr int BM = kFuseBM, RB = BM / 16;
+    constexpr int NLK = n_lambda(L) * K, P = K * (K + 1) / 2, NL = n_lambda(L);
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
     const int64_t m0 = (int64_t)blockIdx.x * BM;
     const int F = p.F, H = p.H, dout = p.dout;
-    const int ldh = H + Fuse<OP>::PAD;
-    // LDS regions from `smem` by offset arithmetic only (see the forward kernel).  Region A
-    // holds the two adjoint tiles, later dE/drho; region B holds W_out and the G tile, later
-    // the S tile.
-    const int off1 = BM * ldh * (int)sizeof(T), ldr = F + 4;
-    const int offB = max(2 * off1, BM * ldr * 4);
-    auto buf = [&](int which) { return reinterpret_cast<T *>(smem + (which ? off1 : 0)); };
+    const int ldh = H + Fuse<OP>::PAD, ldr = F + 4;
+    // LDS from `smem` by offset arithmetic only (see the forward kernel).  Region A holds the
+    // adjoint tile, updated in place layer by layer, and finally dE/drho; region B holds W_out
+    // and the G tile.
+    const int offB = max(BM * ldh * (int)sizeof(T), BM * ldr * 4);
+    T *Ga = reinterpret_cast<T *>(smem);
+    float *Rb = reinterpret_cast<float *>(smem);          // dE/drho [BM][ldr]
     float *wo = reinterpret_cast<float *>(smem + offB);   // W_out [dout][H]
     float *gs = wo + dout * H;                             // G tile [BM][dout]
-    float *Rb = reinterpret_cast<float *>(smem);          // dE/drho [BM][ldr]
-    float *Sl = reinterpret_cast<float *>(smem + offB);   // S tile [BM][NLK]
-    // the S tile is requested now and parked in registers until region B is free
-    constexpr int NLK = n_lambda(L) * K, nlk_tile = BM * NLK;
-    constexpr int SV = (nlk_tile + 255) / 256;
-    float sv[SV];
-    {
-        const int64_t avail = (p.rows - m0) * NLK;
-#pragma unroll
-        for (int i = 0; i < SV; ++i) {
-            const int e = tid + 256 * i;
-            sv[i] = (e < nlk_tile && e < avail) ? p.S[m0 * NLK + e] : 0.0f;
-        }
-    }
     // output layer: zbar[r][q] = (sum_o G[r][o] Wout[o][q]) * SiLU'(Z_{nh-1}[r][q]); thread tid
     // takes column q = tid % H of rows r0, r0 + 256 / H, ...
     {
@@ -508,17 +481,10 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
             float s = 0.0f;
             for (int o = 0; o < dout; ++o) s += gs[r * dout + o] * wo[o * H + q];
             const float v = m0 + r < p.rows ? s * dsilu_f(z[i]) : 0.0f;
-            buf(0)[r * ldh + q] = to_op<OP>(v, 1.0f);
+            Ga[r * ldh + q] = to_op<OP>(v, 1.0f);
         }
     }
     __syncthreads();
-    // W_out and G are no longer needed: park the S tile in region B
-#pragma unroll
-    for (int i = 0; i < SV; ++i) {
-        const int e = tid + 256 * i;
-        if (e < nlk_tile) Sl[e] = sv[i];
-    }
-    int cur = 0;
     for (int k = p.nh - 1; k >= 1; --k) {
         const float *Zk = p.Z[k - 1];
         float zp[RB][NCB][4];   // issued before the matrix loop so their latency is hidden
@@ -533,8 +499,8 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
                     zp[rb][cb][r] = row < p.rows ? Zk[row * p.ldz + col] : 0.0f;
                 }
         f4 acc[RB][NCB];
-        fused_layer<OP, NCB>(buf(cur), ldh, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], H, H, wave, lane, acc);
-        T *dst = buf(cur ^ 1);
+        fused_layer<OP, NCB>(Ga, ldh, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], H, H, wave, lane, acc);
+        __syncthreads();   // every wave has read the tile
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -544,16 +510,15 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
                 for (int r = 0; r < 4; ++r) {
                     const int rr = 16 * rb + 4 * lg + r;
                     const float v = m0 + rr < p.rows ? acc[rb][cb][r] * dsilu_f(zp[rb][cb][r]) : 0.0f;
-                    dst[rr * ldh + col] = to_op<OP>(v, 1.0f);
+                    Ga[rr * ldh + col] = to_op<OP>(v, 1.0f);
                 }
             }
         __syncthreads();
-        cur ^= 1;
     }
     // first layer: dE/drho = zbar_0 W_0 (F columns), into region A once every wave is done
     // reading the adjoint tile
     f4 acc[RB][NCBF];
-    fused_layer<OP, NCBF>(buf(cur), ldh, reinterpret_cast<const T *>(p.W[0]), p.ldw[0], H, F, wave, lane, acc);
+    fused_layer<OP, NCBF>(Ga, ldh, reinterpret_cast<const T *>(p.W[0]), p.ldw[0], H, F, wave, lane, acc);
     __syncthreads();
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -567,17 +532,21 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
     __syncthreads();
     // density adjoint: dE/dS[lambda][a] = w_lambda sum_b M_l[a][b] S[lambda][b] for lambda of
     // order l, with M_l the symmetric matrix of dE/drho[l] (doubled on the diagonal); one
-    // thread per (row, lambda)
-    constexpr int P = K * (K + 1) / 2, NL = n_lambda(L);
+    // thread per (row, lambda), S read from global
     for (int it = tid; it < BM * NL; it += 256) {
         const int r = it / NL, lam = it % NL;
+        const int64_t row = m0 + r;
+        if (row >= p.rows) continue;
         const int l = lam == 0 ? 0 : (lam < 4 ? 1 : (lam < 10 ? 2 : 3));
         const float *rb = Rb + r * ldr + l * P;
+        const float4 *Sg = reinterpret_cast<const float4 *>(p.S + row * NLK + lam * K);
         float sl[K];
 #pragma unroll
-        for (int b = 0; b < K; ++b) sl[b] = Sl[r * NLK + lam * K + b];
+        for (int m4 = 0; m4 < K / 4; ++m4) {
+            const float4 v4 = Sg[m4];
+            sl[4 * m4] = v4.x; sl[4 * m4 + 1] = v4.y; sl[4 * m4 + 2] = v4.z; sl[4 * m4 + 3] = v4.w;
+        }
         const float wl = (float)p.dc.w[lam];
-        const int64_t row = m0 + r;
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             float acc2 = 0.0f;
@@ -587,7 +556,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(FusedNN p) {
                 const float m = rb[lo * K - lo * (lo - 1) / 2 + (hi - lo)];
                 acc2 += (a == b ? 2.0f * m : m) * sl[b];
             }
-            if (row < p.rows) p.C[row * NLK + lam * K + a] = wl * acc2;
+            p.C[row * NLK + lam * K + a] = wl * acc2;
         }
     }
 }
@@ -598,16 +567,17 @@ bool fused_nn_ok(OpType op, int F, int H, int nh, int dout, int NLK) {
 }
 
 static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout, int NLK) {
+    (void)NLK;
     const size_t eb = op_bytes(op), pad = op == OpType::F32 ? 4 : 8;
-    const size_t Fp = pad_k(F), ldh = H + pad, s_tile = (size_t)kFuseBM * NLK * 4;
+    const size_t Fp = pad_k(F), ldh = H + pad;
     if (!fwd) {
-        const size_t a = std::max<size_t>(2 * kFuseBM * ldh * eb, (size_t)kFuseBM * (F + 4) * 4);
-        return a + std::max<size_t>((size_t)(dout * H + kFuseBM * dout) * 4, s_tile);
+        const size_t a = std::max<size_t>(kFuseBM * ldh * eb, (size_t)kFuseBM * (F + 4) * 4);
+        return a + (size_t)(dout * H + kFuseBM * dout) * 4;
     }
-    const size_t ldx = std::max<size_t>(Fp, H) + pad, off1 = kFuseBM * ldx * eb;
-    size_t b = off1 + kFuseBM * ldh * eb;
+    const size_t ldx = std::max<size_t>(Fp, H) + pad;
+    size_t b = kFuseBM * ldx * eb;
     if (op != OpType::F32) b += (size_t)kFuseBM * (H + 4) * 4;
-    return std::max(b, off1 + s_tile);   // the S tile is staged from off1
+    return b + (size_t)dout * H * 4;
 }
 
 void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
