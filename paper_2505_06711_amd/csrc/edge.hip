@@ -41,8 +41,14 @@ template <int L> struct LamTab {
     }
 };
 
-__device__ inline float d_exp(float x) { return expf(x); }
-__device__ inline double d_exp(double x) { return exp(x); }
+// Radial Gaussian exp(-alpha x^2).  FP32: 2^(-alpha log2(e) x^2) with the hardware base-2
+// exponential (a single instruction; the exponent carries the same FP32 rounding as the
+// product it replaces).  FP64: exp.  `a` is the matching constant of EdgeConsts.
+__device__ inline float gauss(float a2, float x) { return __builtin_amdgcn_exp2f(-a2 * x * x); }
+__device__ inline double gauss(double a, double x) { return exp(-a * x * x); }
+template <typename R> __device__ inline R gauss_const(const EdgeConsts &ec, int m) {
+    return sizeof(R) == 4 ? R(ec.alphas2[m]) : R(ec.alphas[m]);
+}
 __device__ inline float d_cospi(float x) { return cospif(x); }
 __device__ inline double d_cospi(double x) { return cospi(x); }
 __device__ inline float d_sinpi(float x) { return sinpif(x); }
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
         for (int u = 0; u < KG; ++u) acc[l][u] = R(0);
     R cen[KG], alp[KG];
 #pragma unroll
-    for (int u = 0; u < KG; ++u) { cen[u] = R(ec.centres[q + G * u]); alp[u] = R(ec.alphas[q + G * u]); }
+    for (int u = 0; u < KG; ++u) { cen[u] = R(ec.centres[q + G * u]); alp[u] = gauss_const<R>(ec, q + G * u); }
     const double xi = a.px[i], yi = a.py[i], zi = a.pz[i];
     const R inv_rc = R(1.0 / ec.r_c);
     const R s = R(ec.ang_scale);
@@ -217,7 +223,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
 #pragma unroll
             for (int u = 0; u < KG; ++u) {
                 const R xm = rs - cen[u];
-                const R w = cs[u] * d_exp(-alp[u] * xm * xm) * fs;
+                const R w = cs[u] * gauss(alp[u], xm) * fs;
 #pragma unroll
                 for (int l = 0; l < NL; ++l) acc[l][u] += w * As[l];
             }
@@ -261,7 +267,7 @@ __device__ inline void edge_geo(const EdgeConsts &ec, double dx, double dy, doub
     for (int m = 0; m < K; ++m) {
         const R xm = g.r - R(ec.centres[m]);
         const R al = R(ec.alphas[m]);
-        g.Rm[m] = d_exp(-al * xm * xm);
+        g.Rm[m] = gauss(gauss_const<R>(ec, m), xm);
         g.dRm[m] = R(-2) * al * xm * g.Rm[m];
     }
 }

@@ -9,6 +9,7 @@ namespace reann {
 struct EdgeConsts {
     double centres[16];
     double alphas[16];
+    double alphas2[16];   // alphas * log2(e): the FP32 kernels evaluate exp(-a x^2) as 2^(-a2 x^2)
     double r_c;
     double rc2;       // r_c^2 in FP64: in-cutoff test of a list entry
     double ang_scale;

@@ -121,7 +121,11 @@ const MfmaSet &Model::mfma(int device, hipStream_t st, bool energy, OpType op) {
 
 EdgeConsts Model::edge_consts() const {
     EdgeConsts e{};
-    for (int m = 0; m < K; ++m) { e.centres[m] = centres[m]; e.alphas[m] = alphas[m]; }
+    for (int m = 0; m < K; ++m) {
+        e.centres[m] = centres[m];
+        e.alphas[m] = alphas[m];
+        e.alphas2[m] = alphas[m] * 1.4426950408889634;   // log2(e)
+    }
     e.r_c = r_c;
     e.rc2 = r_c * r_c;
     e.ang_scale = ang_scale;
