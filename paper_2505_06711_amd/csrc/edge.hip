@@ -97,17 +97,25 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
     const double xi = active ? a.px[x] : 0.0, yi = active ? a.py[x] : 0.0, zi = active ? a.pz[x] : 0.0;
     int64_t front = lo, back = hi;
     const uint32_t below = (1u << g) - 1u;
+    // two-stage pipeline (indices clamped to the row's last entry): the positions of the next
+    // pass and the entries of the pass after it are loaded while this pass is tested
+    const int64_t last = hi - 1;
+    int32_t jc = 0, jn = 0;
+    double xc = 0.0, yc = 0.0, zc = 0.0;
+    if (lo < hi) {
+        jc = a.col[min(lo + g, last)];
+        jn = a.col[min(lo + 16 + g, last)];
+        xc = a.px[jc]; yc = a.py[jc]; zc = a.pz[jc];
+    }
     for (int64_t base = lo; base < hi; base += 16) {
         const int64_t k = base + g;
-        bool isl = false, isg = false;
-        int32_t j = 0;
-        if (k < hi) {
-            j = a.col[k];
-            const double dx = a.px[j] - xi, dy = a.py[j] - yi, dz = a.pz[j] - zi;
-            const bool in = dx * dx + dy * dy + dz * dz < rc2;
-            isl = in && j < a.n;
-            isg = in && j >= a.n;
-        }
+        const int32_t j = jc;
+        const double dx = xc - xi, dy = yc - yi, dz = zc - zi;
+        jc = jn;
+        xc = a.px[jn]; yc = a.py[jn]; zc = a.pz[jn];
+        jn = a.col[min(base + 32 + g, last)];
+        const bool in = k < hi && dx * dx + dy * dy + dz * dz < rc2;
+        const bool isl = in && j < a.n, isg = in && j >= a.n;
         const uint32_t ml = (uint32_t)(__ballot(isl) >> gbase) & 0xffffu;
         const uint32_t mg = (uint32_t)(__ballot(isg) >> gbase) & 0xffffu;
         if (isl) {
