@@ -40,9 +40,15 @@ template <OpType OP> __device__ inline typename OpT<OP>::T to_op(float v, float 
     else return f2fp8(v * inv_scale);
 }
 
-__device__ inline float silu_f(float z) { return z / (1.0f + expf(-z)); }
+// SiLU and its derivative in FP32 from the hardware base-2 exponential and reciprocal:
+// sigma(z) = 1 / (1 + 2^(-z log2(e))), silu = z sigma, silu' = sigma (1 + z (1 - sigma)).
+// For z below -126 / log2(e) the exponential overflows to +inf and sigma is 0, the limit.
+__device__ inline float sigm_f(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
+__device__ inline float silu_f(float z) { return z * sigm_f(z); }
 __device__ inline float dsilu_f(float z) {
-    const float s = 1.0f / (1.0f + expf(-z));
+    const float s = sigm_f(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -288,10 +294,11 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const V *>(wrow[cb] + k0 + RUN * lg);
     };
-    auto mma = [&](const V (&b)[NCB], int k0) {
-        V a[RB];
+    auto load_a = [&](V (&a)[RB], int k0) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) a[rb] = *reinterpret_cast<const V *>(X + (16 * rb + li) * ldx + k0 + RUN * lg);
+    };
+    auto mma = [&](const V (&a)[RB], const V (&b)[NCB]) {
         if constexpr (OP == OpType::F32) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
@@ -310,23 +317,28 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
         }
     };
     // pairs of chunks per trip, so that a trip is one basic block and the requests cannot be
-    // sunk into a later block next to their use
-    V b0[NCB], b1[NCB];
+    // sunk into a later block next to their use; both operands of chunk k0 + KC (weights from
+    // global memory, the activation tile from LDS) are requested before chunk k0 is multiplied
+    V a0[RB], a1[RB], b0[NCB], b1[NCB];
     const int nck = kin / KC, klast = kin - KC;
     load_b(b0, 0);
+    load_a(a0, 0);
     int k0 = 0;
     for (int pr = 0; pr + 2 <= nck; pr += 2) {
         load_b(b1, k0 + KC);
+        load_a(a1, k0 + KC);
         __builtin_amdgcn_sched_barrier(0);
-        mma(b0, k0);
+        mma(a0, b0);
         __builtin_amdgcn_sched_barrier(0);
-        load_b(b0, min(k0 + 2 * KC, klast));
+        const int k2 = min(k0 + 2 * KC, klast);
+        load_b(b0, k2);
+        load_a(a0, k2);
         __builtin_amdgcn_sched_barrier(0);
-        mma(b1, k0 + KC);
+        mma(a1, b1);
         __builtin_amdgcn_sched_barrier(0);
         k0 += 2 * KC;
     }
-    if (nck & 1) mma(b0, k0);   // b0 holds the last chunk
+    if (nck & 1) mma(a0, b0);   // a0, b0 hold the last chunk
 }
 
 }  // namespace
