@@ -152,6 +152,39 @@ def cpu_baseline(workload_name, T, max_seconds=30.0):
                 seconds=round(dt, 3))
 
 
+def md_amortised(rn, w, precision, steps=100, dt_fs=1.0, temperature=300.0):
+    """The workload run as molecular dynamics: `steps` velocity-Verlet steps of dt_fs on the
+    device (one request each, through the server), the list rebuilt by the skin rule when
+    needed.  Reports the rate including rebuilds and the number of builds."""
+    import synth
+    m, s = w["model"], w["system"]
+    srv = rn.Server(rn.Model(m), T=w["T"], precision=precision, skin=w["skin"], use_graph=True)
+    srv.set_masses([synth.systems.MASS_AMU[e] for e in m.elements])
+    vel = synth.systems.maxwell_boltzmann(s["species"], m.elements, temperature, seed=7)
+    sid = srv.add_system(s, vel)
+
+    def run_one():
+        t = srv.submit_vv(sid, dt_fs)
+        while True:
+            r = srv.poll(t, sid, forces=False)
+            if r is not None:
+                return r
+            time.sleep(0.0001)
+
+    run_one()                           # first build, graph capture
+    b0 = srv.stats()["list_builds"]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = run_one()
+    el = time.perf_counter() - t0
+    builds = srv.stats()["list_builds"] - b0
+    srv.close()
+    n = len(s["pos"])
+    return dict(steps=steps, dt_fs=dt_fs, temperature_K=temperature, ms_per_step=round(el / steps * 1e3, 4),
+                atom_steps_per_s=round(n * steps / el, 1), list_rebuilds=int(builds),
+                final_energy=r["energy"], note="host submit/poll per step included")
+
+
 def serve_bench(rn, seconds=6.0, n_systems=256, seed=0):
     """Serving: Poisson stream of 1 fs velocity-Verlet requests over independent systems
     (sizes log-uniform 64-20,000 atoms, half water boxes, half FCC crystals), r_c = 5 A,
@@ -281,8 +314,8 @@ def tsweep(rn, torch, ctx, model, w, a, Ts):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cu100800")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16", "fp8"])
     ap.add_argument("--T", type=int, default=None)
@@ -346,14 +379,15 @@ def main():
     plan.timing()                     # reset accumulators
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(a.steps):
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    evs[0].record()
+    for k in range(a.steps):
         step()
-    ev1.record()
+        evs[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms = evs[0].elapsed_time(evs[-1])
+    per_step = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(a.steps)])
     tim = plan.timing()
     plan.set_timing(False)
     ms_per_step = gpu_ms / a.steps
@@ -369,6 +403,16 @@ def main():
     ms = {k: v / steps_t for k, v in tim["ms"].items()}
     la = tim["launches"]
     roof = roofline(wk, tim, T, a.precision, a.workload)
+
+    # neighbour-list build on its own (the C-ABI build of the same list), median of three
+    tb = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rn.build_neighbors(ctx, s, m.r_c, w["skin"], w["decomp"])
+        torch.cuda.synchronize()
+        tb.append((time.perf_counter() - t1) * 1e3)
+    nlist_ms = float(np.median(tb))
 
     # the host-pointer entry point on the same system: positions in and forces / virial out
     # over PCIe each call (reported beside the device-resident rate, never as `value`)
@@ -387,11 +431,16 @@ def main():
                config=dict(workload=describe(a.workload, w), precision=a.precision, n_atoms=n,
                            ghosts=nl["n_ghosts"], list_pairs=n_local_pairs, in_cutoff_edges=n_in_cutoff,
                            first_step_s=round(t_build, 3), wall_s=round(wall, 3)),
+               step_ms=dict(median=round(float(np.median(per_step)), 4),
+                            iqr=round(float(np.percentile(per_step, 75) - np.percentile(per_step, 25)), 4)),
+               nlist_build_ms=round(nlist_ms, 3),
                phase_ms_per_step={k: round(v, 4) for k, v in ms.items()},
                host_pointer_path=dict(ms_per_call=round(host_ms, 3), atom_steps_per_s=round(n / (host_ms * 1e-3), 1),
                                       note="reann_energy_forces with host buffers: PCIe copies included"),
                roofline=roof)
     if not a.no_serve:
+        print("bench: MD-amortised run", file=sys.stderr, flush=True)
+        out["md_amortised"] = md_amortised(rn, w, a.precision)
         print("bench: serving", file=sys.stderr, flush=True)
         out["serve"] = serve_bench(rn, seconds=a.serve_seconds)
     if not a.no_cpu_baseline:

@@ -244,10 +244,12 @@ reann_status reann_submit(reann_server *s, const reann_request *req, uint64_t *t
 /* Non-blocking: REANN_PENDING while running, REANN_OK when res is filled (the ticket is then
    released), or a negative status. */
 reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res);
-/* Statistics: [0] engine rounds that admitted at least one request, [1] requests completed,
-   [2] atoms evaluated, [3] HIP-graph replays, [4] admissions deferred for the HBM budget,
-   [5] device bytes held by resident systems. */
-reann_status reann_server_stats(reann_server *s, int64_t *stats6);
+/* Statistics, host [REANN_N_SERVER_STATS]: [0] engine rounds that admitted at least one
+   request, [1] requests completed, [2] atoms evaluated, [3] HIP-graph replays, [4] admissions
+   deferred for the HBM budget, [5] device bytes held by resident systems, [6] neighbour-list
+   builds (first builds and skin-rule rebuilds). */
+#define REANN_N_SERVER_STATS 7
+reann_status reann_server_stats(reann_server *s, int64_t *stats);
 void reann_server_destroy(reann_server *s);
 
 #ifdef __cplusplus

@@ -420,9 +420,10 @@ class Server:
                     latency_s=(res.t_done_ns - res.t_submit_ns) * 1e-9, t_done_ns=res.t_done_ns)
 
     def stats(self) -> dict:
-        out = np.zeros(6, np.int64)
+        keys = ("admission_rounds", "completed", "atoms", "graph_replays", "deferred", "resident_bytes",
+                "list_builds")
+        out = np.zeros(len(keys), np.int64)
         check(load().reann_server_stats(self.handle, _p(out)))
-        keys = ("admission_rounds", "completed", "atoms", "graph_replays", "deferred", "resident_bytes")
         return dict(zip(keys, out.tolist()))
 
     def close(self):

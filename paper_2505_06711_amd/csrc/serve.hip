@@ -123,7 +123,7 @@ struct reann_server {
     Slot slots[kSlots];
     std::list<Req> pending;              // engine-private
     int64_t budget = 0, resident = 0, in_flight_atoms = 0;
-    std::atomic<int64_t> stats[6]{};
+    std::atomic<int64_t> stats[REANN_N_SERVER_STATS]{};
     std::string fatal;
 
     void run();
@@ -216,6 +216,7 @@ void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok) {
     Plan &p = *sy.plan;
     const bool rebuilt = p.prepare(sy.d_pos.as<double>(), st);
     if (rebuilt) {
+        stats[6]++;
         const int64_t actual = (int64_t)p.device_bytes() + 4 * (int64_t)sy.n * 24;
         resident += actual - (int64_t)sy.bytes;
         sy.bytes = actual;
@@ -549,10 +550,10 @@ reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res) {
     return st;
 }
 
-reann_status reann_server_stats(reann_server *s, int64_t *st6) {
-    if (!s || !st6) return REANN_E_INVALID;
+reann_status reann_server_stats(reann_server *s, int64_t *st) {
+    if (!s || !st) return REANN_E_INVALID;
     std::lock_guard<std::mutex> lk(s->mu);
-    for (int k = 0; k < 6; ++k) st6[k] = s->stats[k].load();
+    for (int k = 0; k < REANN_N_SERVER_STATS; ++k) st[k] = s->stats[k].load();
     return REANN_OK;
 }
 
