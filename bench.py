@@ -148,8 +148,29 @@ def cpu_baseline(workload_name, T, max_seconds=30.0):
     t0 = time.perf_counter()
     oracle.evaluate(w["model"], s, T=T, skin=w["skin"], threads=threads)
     dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="atom-steps/s", cores=threads, kind="oracle", sample=sample,
-                seconds=round(dt, 3))
+    out = dict(value=n / dt, unit="atom-steps/s", cores=threads, kind="oracle", sample=sample,
+               seconds=round(dt, 3), nproc=os.cpu_count(), cpu_model=_cpu_model())
+    # one core, on a sub-box of the same crystal and model (a few seconds of work)
+    if workload_name == "cu100800":
+        s1 = synth.systems.fcc_crystal((12, 12, 12))
+        t0 = time.perf_counter()
+        oracle.evaluate(w["model"], s1, T=T, skin=w["skin"], threads=1)
+        dt1 = time.perf_counter() - t0
+        out["single_core"] = dict(value=len(s1["pos"]) / dt1, unit="atom-steps/s", cores=1,
+                                  sample="12x12x12-cell sub-box (6,912 atoms) of the same crystal and model",
+                                  seconds=round(dt1, 3))
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def md_amortised(rn, w, precision, steps=100, dt_fs=1.0, temperature=300.0):

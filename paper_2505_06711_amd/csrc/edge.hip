@@ -10,9 +10,9 @@
 //   f_c R_m sum_lambda Sbar_i[lambda][m] A_lambda(d)  to  cbar_j[m] = dE/dc_j[m].
 // No atomics: the centre-role kernel evaluates each edge i->j once (Sbar_i staged in LDS)
 // and keeps +g_ij for F_i and the virial; what lands on j (-g_ij and the cbar_j terms) is
-// written as a record at the edge's list slot.  The neighbour-role kernel then gives every
-// ext row k the sum of the records of its edges j->k, found through the list's reverse
-// slots.  Sums over a row's edges are taken across the lanes of a half-wave in a fixed
+// written as a record at the edge's compacted slot.  The neighbour-role kernel then gives
+// every ext row k the sum of the records of its edges j->k, found through a per-step map of
+// each entry to the compacted slot of its reverse.  Sums over a row's edges are taken across the lanes of a half-wave in a fixed
 // order, so results are deterministic.
 #include "edge.hpp"
 
@@ -84,9 +84,10 @@ __device__ inline void angular(R ux, R uy, R uz, R s, R *A, R (*dA)[3]) {
 // In-cutoff compaction of the (r_c + skin) list for the current positions: each row's
 // in-cutoff local neighbours are packed at the front of its slot range and its in-cutoff
 // ghost neighbours at the back (reverse order).  Every later pass of the step reads only
-// these entries.
+// these entries.  fslot maps a compacted slot to its list slot and cpos the other way (cpos
+// is written for in-cutoff entries only).
 __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, int32_t *__restrict__ fslot,
-                          int32_t *__restrict__ nloc, int32_t *__restrict__ ngh) {
+                          int32_t *__restrict__ cpos, int32_t *__restrict__ nloc, int32_t *__restrict__ ngh) {
     // 16 lanes per row take the row's entries 16 at a time; a ballot gives each in-cutoff
     // entry its rank, so the packed order equals a sequential scan of the row
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -122,11 +123,13 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
             const int64_t d = front + __popc(ml & below);
             col2[d] = j;
             fslot[d] = (int32_t)k;
+            cpos[k] = (int32_t)d;
         }
         if (isg) {
             const int64_t d = back - 1 - __popc(mg & below);
             col2[d] = j;
             fslot[d] = (int32_t)k;
+            cpos[k] = (int32_t)d;
         }
         front += __popc(ml);
         back -= __popc(mg);
@@ -134,6 +137,35 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
     if (active && g == 0) {
         nloc[x] = (int32_t)(front - lo);
         ngh[x] = (int32_t)(hi - back);
+    }
+}
+
+// For the in-cutoff local neighbours of every ext row x (compacted slots s in
+// [row[x], row[x] + nloc[x])): rslot[s] = compacted slot of the reverse entry, the edge from
+// that neighbour back to x.  The reverse of an in-cutoff entry is in cutoff (its
+// displacement is the exact negation), so its cpos is set.  16 lanes per row, U entries
+// per lane at a time so that U chains of dependent loads are in flight.
+__global__ void k_rslot(int64_t n_ext, const int64_t *__restrict__ row, const int32_t *__restrict__ nloc,
+                        const int32_t *__restrict__ fslot, const int32_t *__restrict__ rev,
+                        const int32_t *__restrict__ cpos, int32_t *__restrict__ rslot) {
+    constexpr int U = 4, G = 16;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t x = t / G;
+    const int g = (int)(t % G);
+    if (x >= n_ext) return;
+    const int64_t lo = row[x];
+    const int cnt = nloc[x], last = cnt - 1;
+    for (int e0 = g; e0 < cnt; e0 += U * G) {
+        int32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = fslot[lo + min(e0 + u * G, last)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = rev[v[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = cpos[v[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u * G < cnt) rslot[lo + e0 + u * G] = v[u];
     }
 }
 
@@ -313,8 +345,9 @@ constexpr int kRowsPerBlock = 8;   // 256 threads = 8 half-waves, one row each
 // kCentreLanes lanes share a row and take its edges in turn; Sbar_k is staged in LDS and
 // read by all of them.  Each lane runs a two-stage pipeline: the list entry of its edge after
 // next and the position and message of its next edge are loaded while the current edge is
-// evaluated.  The record of edge k -> j is stored at the edge's list slot f:
-// rec[f * RS + 0..2] = g, rec[f * RS + 4 + m] = terms (RS = 4 + K with CBAR, 4 without).
+// evaluated.  The record of edge k -> j is stored at the edge's compacted slot f (so a row's
+// records are contiguous): rec[f * RS + 0..2] = g, rec[f * RS + 4 + m] = terms (RS = 4 + K
+// with CBAR, 4 without).
 constexpr int kCentreLanes = 16;
 constexpr int kCentreRows = 256 / kCentreLanes;
 
@@ -344,10 +377,11 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(Edge
     const int64_t x = row0 + grp;
     R f0 = R(0), f1 = R(0), f2 = R(0);
     // virial: the total over all edges of a rotation-invariant energy is symmetric, so the
-    // symmetric part of each -d (x) g is accumulated (xx, yy, zz, xy, xz, yz) in FP64
-    double W[6];
+    // symmetric part of each -d (x) g is accumulated (xx, yy, zz, xy, xz, yz); a lane's few
+    // edges in the working type, the row and block sums in FP64
+    R W[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) W[q] = 0.0;
+    for (int q = 0; q < 6; ++q) W[q] = R(0);
     if (x < a.n) {
         const double xi = a.px[x], yi = a.py[x], zi = a.pz[x];
         const R s = R(ec.ang_scale);
@@ -362,13 +396,11 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(Edge
         const int last = cnt - 1;
         double xc = 0.0, yc = 0.0, zc = 0.0;
         R cc[K];
-        int32_t fcur = 0, jn = 0, fn = 0;
+        int32_t jn = 0;
         if (e < cnt) {
             const int64_t s0 = slot(e), s1 = slot(min(e + LPR, last));
             const int32_t j0 = cl.col[s0];
-            fcur = cl.fslot[s0];
             jn = cl.col[s1];
-            fn = cl.fslot[s1];
             xc = a.px[j0]; yc = a.py[j0]; zc = a.pz[j0];
 #pragma unroll
             for (int m = 0; m < K; ++m) cc[m] = c[(int64_t)j0 * K + m];
@@ -378,7 +410,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(Edge
             // loop into registers, which caps occupancy
             asm volatile("" ::: "memory");
             const double dx = xc - xi, dy = yc - yi, dz = zc - zi;
-            const int64_t f = fcur;
+            const int64_t f = slot(e);
             EdgeGeo<K, R> g;
             edge_geo<K, R>(ec, dx, dy, dz, g);
             R u[K], cacc[K];
@@ -392,9 +424,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(Edge
                 xc = a.px[jj]; yc = a.py[jj]; zc = a.pz[jj];
 #pragma unroll
                 for (int m = 0; m < K; ++m) cc[m] = c[jj * K + m];
-                fcur = fn;
                 jn = cl.col[s2];
-                fn = cl.fslot[s2];
             }
             // powers of the scaled displacement; A_lambda and its gradient are formed per lambda
             const R ux = R(ec.ang_scale * dx), uy = R(ec.ang_scale * dy), uz = R(ec.ang_scale * dz);
@@ -442,24 +472,25 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(Edge
                     st4(out + 4 + m, g.fc * g.Rm[m] * cacc[m], g.fc * g.Rm[m + 1] * cacc[m + 1],
                         g.fc * g.Rm[m + 2] * cacc[m + 2], g.fc * g.Rm[m + 3] * cacc[m + 3]);
             }
-            const double gxd = double(gx), gyd = double(gy), gzd = double(gz);
-            W[0] -= dx * gxd;
-            W[1] -= dy * gyd;
-            W[2] -= dz * gzd;
-            W[3] -= 0.5 * (dx * gyd + dy * gxd);
-            W[4] -= 0.5 * (dx * gzd + dz * gxd);
-            W[5] -= 0.5 * (dy * gzd + dz * gyd);
+            const R ddx = R(dx), ddy = R(dy), ddz = R(dz);
+            W[0] -= ddx * gx;
+            W[1] -= ddy * gy;
+            W[2] -= ddz * gz;
+            W[3] -= R(0.5) * (ddx * gy + ddy * gx);
+            W[4] -= R(0.5) * (ddx * gz + ddz * gx);
+            W[5] -= R(0.5) * (ddy * gz + ddz * gy);
         }
     }
     f0 = row_sum(f0); f1 = row_sum(f1); f2 = row_sum(f2);
+    double Wd[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) W[q] = row_sum(W[q]);
+    for (int q = 0; q < 6; ++q) Wd[q] = row_sum(double(W[q]));
     if (lane == 0) {
         if (x < a.n) { F[3 * x] += f0; F[3 * x + 1] += f1; F[3 * x + 2] += f2; }
-        sW[grp][0] = W[0]; sW[grp][4] = W[1]; sW[grp][8] = W[2];
-        sW[grp][1] = sW[grp][3] = W[3];
-        sW[grp][2] = sW[grp][6] = W[4];
-        sW[grp][5] = sW[grp][7] = W[5];
+        sW[grp][0] = Wd[0]; sW[grp][4] = Wd[1]; sW[grp][8] = Wd[2];
+        sW[grp][1] = sW[grp][3] = Wd[3];
+        sW[grp][2] = sW[grp][6] = Wd[4];
+        sW[grp][5] = sW[grp][7] = Wd[5];
     }
     __syncthreads();
     if (threadIdx.x < 9) {
@@ -486,11 +517,26 @@ __global__ __launch_bounds__(256) void k_adj_gather(EdgeArgs a, CutList cl, cons
     if (x >= a.n_ext) return;   // whole half-wave leaves together
     const int part = lane % LPE, eg = lane / LPE;
     R acc[4] = {R(0), R(0), R(0), R(0)};
-    const int cnt = cl.nloc[x];
+    const int cnt = cl.nloc[x], last = cnt - 1;
     const int64_t lo = cl.row[x];
-    for (int e = eg; e < cnt; e += EPP) {
-        const int64_t r = cl.rev[cl.fslot[lo + e]];
-        if (part < NP) add4(rec + r * RS + 4 * part, acc);
+    // U passes at a time, so that each lane has U independent (reverse slot -> record) loads
+    // in flight; indices past the row's end are clamped to its last edge and their records
+    // are not added
+    constexpr int U = 4;
+    const int pc = part < NP ? 4 * part : 0;
+    for (int e0 = eg; e0 < cnt; e0 += U * EPP) {
+        int32_t rv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) rv[u] = cl.rslot[lo + min(e0 + u * EPP, last)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            R v[4] = {R(0), R(0), R(0), R(0)};
+            add4(rec + (int64_t)rv[u] * RS + pc, v);
+            if (e0 + u * EPP < cnt && part < NP) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] += v[q];
+            }
+        }
     }
 #pragma unroll
     for (int o = LPE; o < 32; o <<= 1)
@@ -517,8 +563,14 @@ __global__ __launch_bounds__(256) void k_adj_gather(EdgeArgs a, CutList cl, cons
 
 void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl) {
     hipLaunchKernelGGL(k_compact, dim3(grid_for(a.n_ext * 16, 256)), dim3(256), 0, st, a, r_c * r_c, cl.col, cl.fslot,
-                       cl.nloc, cl.ngh);
+                       cl.cpos, cl.nloc, cl.ngh);
     LAUNCH_OK("k_compact");
+}
+
+void reverse_slots(hipStream_t st, const EdgeArgs &a, const CutList &cl) {
+    hipLaunchKernelGGL(k_rslot, dim3(grid_for(a.n_ext * 16, 256)), dim3(256), 0, st, a.n_ext, cl.row, cl.nloc,
+                       cl.fslot, cl.rev, cl.cpos, cl.rslot);
+    LAUNCH_OK("k_rslot");
 }
 
 void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,

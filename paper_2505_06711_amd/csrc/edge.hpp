@@ -25,15 +25,19 @@ struct EdgeArgs {
 // In-cutoff entries of the list for the current positions (same slot ranges as the list):
 // row x's in-cutoff local neighbours at col[row[x] .. row[x] + nloc[x]), its in-cutoff
 // ghost neighbours at col[row[x+1] - ngh[x] .. row[x+1]).
-// fslot[s]: the list slot of the entry compacted into s; rev: the list's reverse slots.
+// fslot[s]: the list slot of the entry compacted into s; cpos[f]: the compacted slot of the
+// in-cutoff list entry f; rev: the list's reverse slots; rslot[s] (for the in-cutoff local
+// neighbours of each row): the compacted slot of the reverse of entry s.
 struct CutList {
     const int64_t *row;
     int32_t *col;
     int32_t *nloc, *ngh;
-    int32_t *fslot;
+    int32_t *fslot, *cpos, *rslot;
     const int32_t *rev;
 };
 void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl);
+// rslot from fslot, rev and cpos (after compact_cutoff; needed by edge_adjoint_gather)
+void reverse_slots(hipStream_t st, const EdgeArgs &a, const CutList &cl);
 
 // S[i][lambda][m] for the n local rows.  c: messages of all ext atoms, [n_ext][K].
 void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
@@ -41,13 +45,13 @@ void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, co
 
 // Atomics-free adjoint of one layer in two launches.  Centre role (local rows): evaluates
 // every in-cutoff edge once, adds its gradient to F of the centre and the virial, and
-// writes at the edge's list slot the record of what it gives the neighbour end.
+// writes at the edge's compacted slot the record of what it gives the neighbour end.
 // Neighbour role (every ext row): sums the records of the row's incoming edges through
-// the list's reverse slots.
+// rslot.
 //   Sbar [n][NL][K] (locals), c [n_ext][K]; F [n_ext][3] is accumulated;
 //   cbar [n_ext][K] is overwritten when want_cbar; Wpart receives one FP64 [9] per block
 // of the centre-role launch (the return value is that block count); rec holds
-// edge_record_elems(K) working-type values per list slot.
+// edge_record_elems(K) working-type values per (compacted) list slot.
 int edge_adjoint_centre(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl,
                         const EdgeConsts &ec, const void *c, const void *Sbar, bool want_cbar, void *F, double *Wpart,
                         void *rec);

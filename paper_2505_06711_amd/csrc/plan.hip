@@ -271,6 +271,8 @@ void Plan::alloc_buffers() {
     disp.ensure(1025 * 8);
     col2.ensure((size_t)(nl.n_pairs + 1) * 4);
     fslot.ensure((size_t)(nl.n_pairs + 1) * 4);
+    cpos.ensure((size_t)(nl.n_pairs + 1) * 4);
+    rslot.ensure((size_t)(nl.n_pairs + 1) * 4);
     erec.ensure((size_t)(nl.n_pairs + 1) * edge_record_elems(K) * rs);
     nloc.ensure((size_t)(ne + 1) * 4);
     ngh.ensure((size_t)(ne + 1) * 4);
@@ -279,7 +281,8 @@ void Plan::alloc_buffers() {
 size_t Plan::device_bytes() const {
     size_t b = 0;
     for (const DevBuf *d : {&px, &py, &pz, &c, &S, &rho, &Z, &Hh, &y, &ybar, &Eat, &Epart, &Sbar, &rhobar, &gA, &gB,
-                            &cbar, &F, &Wpart, &Wacc, &disp, &col2, &fslot, &nloc, &ngh, &erec, &fp8s, &fp8tmp})
+                            &cbar, &F, &Wpart, &Wacc, &disp, &col2, &fslot, &cpos, &rslot, &nloc, &ngh, &erec, &fp8s,
+                            &fp8tmp})
         b += d->bytes;
     b += nl.perm.bytes() + nl.inv_perm.bytes() + nl.q.bytes() + nl.gh_owner.bytes() + nl.gh_shift.bytes() +
          nl.copy_ptr.bytes() + nl.copy_idx.bytes() + nl.row.bytes() + nl.col.bytes() + nl.rev.bytes() + nl.spec_ext.bytes() +
@@ -501,6 +504,7 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     fill_energy_seed(st, fp64, n, m->energy_scale, d_g, ybar.p);
     zero(st, this->F.p, (size_t)nl.n_ext * 3 * rs);
     zero(st, Wacc.p, 9 * 8);
+    reverse_slots(st, ea, cl);
     mark(st, PH_OTHER);
     mark(st, PH_NN_BWD, nn_vjp(st, T - 1, true, ybar.as<char>(), 1));
     if (!fused()) {

@@ -94,7 +94,7 @@ struct Plan {
     int64_t rebuilds = 0;
     // layer buffers
     DevBuf px, py, pz, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, Wacc, disp, one;
-    DevBuf col2, fslot, nloc, ngh;   // in-cutoff compaction of the list for the current step
+    DevBuf col2, fslot, cpos, rslot, nloc, ngh;   // in-cutoff compaction of the list for the current step
     DevBuf erec;                     // per-slot edge records of the adjoint
     DevBuf fp8s, fp8tmp;      // per-call activation scale for FP8 products
     OpType op = OpType::F32;
@@ -140,8 +140,8 @@ struct Plan {
     int nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg);
     void mark(hipStream_t st, int phase, int nlaunch = 0);
     CutList cutlist() {
-        return CutList{nl.row.ptr(), col2.as<int32_t>(), nloc.as<int32_t>(), ngh.as<int32_t>(), fslot.as<int32_t>(),
-                       nl.rev.ptr()};
+        return CutList{nl.row.ptr(),        col2.as<int32_t>(),  nloc.as<int32_t>(), ngh.as<int32_t>(),
+                       fslot.as<int32_t>(), cpos.as<int32_t>(), rslot.as<int32_t>(), nl.rev.ptr()};
     }
 };
 
