@@ -267,6 +267,69 @@ template <> struct Fuse<OpType::BF16> {
 
 typedef float fl4 __attribute__((ext_vector_type(4)));
 
+// Lane permutations within rows of 16 lanes (DPP; registers only, no LDS round trip).
+template <int CTRL> __device__ inline double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- lane 7 - i within each group of 8
+
+template <int CTRL> __device__ inline float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over each group of 8 consecutive lanes (every lane gets the same value: the quad sums
+// are formed in the same order everywhere and the last step adds two of them, which
+// commutes exactly).
+template <typename A> __device__ inline A sum8(A v) {
+    if constexpr (sizeof(A) == 8) {
+        v += dpp_f64<kDppXor1>(v);
+        v += dpp_f64<kDppXor2>(v);
+        return v + dpp_f64<kDppHalfMirror>(v);
+    } else {
+        v += dpp_f32<kDppXor1>(v);
+        v += dpp_f32<kDppXor2>(v);
+        return v + dpp_f32<kDppHalfMirror>(v);
+    }
+}
+
+// Output layer of the forward (FP32 data, accumulation in A): kOutParts threads share a row,
+// each takes H / kOutParts hidden units for all DOUT outputs, and the partial sums are
+// combined across the row's threads; thread `part` writes outputs part, part + kOutParts, ...
+// The energy NN (one output) accumulates in FP64, the message NNs in FP32 like their hidden
+// layers.
+template <int DOUT, typename A>
+__device__ inline void out_layer(const float *hl, int ldl, const float *wo, const FusedNN &p, int64_t m0, int tid) {
+    constexpr int QM = kFuseMaxH / kOutParts;
+    const int H = p.H;
+    const int row = tid / kOutParts, part = tid % kOutParts, qn = H / kOutParts;
+    A hv[QM];
+#pragma unroll
+    for (int j = 0; j < QM; ++j) hv[j] = j < qn ? (A)hl[row * ldl + part * qn + j] : A(0);
+    A s[DOUT];
+#pragma unroll
+    for (int o = 0; o < DOUT; ++o) {
+        const float *w = wo + o * H + part * qn;
+        A a = A(0);
+#pragma unroll
+        for (int j = 0; j < QM; ++j)
+            if (j < qn) a += hv[j] * (A)w[j];
+        s[o] = a;
+    }
+#pragma unroll
+    for (int o = 0; o < DOUT; ++o) s[o] = sum8(s[o]);
+    const int64_t grow = m0 + row;
+    if (grow < p.rows) {
+#pragma unroll
+        for (int o = 0; o < DOUT; ++o)
+            if (o % kOutParts == part) p.C[grow * p.ldc + o] = (float)(s[o] + (A)p.bout[o]);
+    }
+}
+
 // acc[rb][cb] = sum_k X[16 rb + i][k] Wt[16 (wave + 4 cb) + j][k] over k < kin (a multiple of
 // the chunk).  Columns at or past `out` read row 0 of Wt; the caller never stores them.
 template <OpType OP, int NCB>
@@ -426,25 +489,40 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
             }
         __syncthreads();
     }
-    // output layer (FP32 data, FP64 accumulation): kOutParts threads share a row and combine
-    // their partial sums
+    // output layer: dout is K (message NNs) or 1 (energy NN)
     const float *hl = (OP == OpType::F32) ? reinterpret_cast<const float *>(X) : hf;
     const int ldl = (OP == OpType::F32) ? ldx : ldf;
-    constexpr int QM = kFuseMaxH / kOutParts;
-    const int row = tid / kOutParts, part = tid % kOutParts, qn = H / kOutParts;
-    float hv[QM];
+    if (p.dout == K) out_layer<K, float>(hl, ldl, wo, p, m0, tid);
+    else out_layer<1, double>(hl, ldl, wo, p, m0, tid);
+}
+
+// Output layer of the adjoint: Ga[r][q] = (sum_o G[r][o] Wout[o][q]) * SiLU'(z) for column
+// q = tid % H of rows r0, r0 + 256 / H, ... (z holds those rows' pre-activations); the
+// thread keeps its column of Wout in registers and reads each G row as vectors.
+template <OpType OP, int DOUT, int NR>
+__device__ inline void out_adjoint(const FusedNN &p, const float *wo, const float *gs, const float (&z)[NR],
+                                   typename Fuse<OP>::T *Ga, int ldh, int64_t m0, int tid) {
+    const int H = p.H, q = tid % H, r0 = tid / H, rstep = 256 / H, nr = kFuseBM / rstep;
+    float wq[DOUT];
 #pragma unroll
-    for (int j = 0; j < QM; ++j) hv[j] = j < qn ? hl[row * ldl + part * qn + j] : 0.0f;
-    const int64_t grow = m0 + row;
-    for (int o = 0; o < p.dout; ++o) {
-        const float *w = wo + o * H + part * qn;
-        double s = 0.0;
+    for (int o = 0; o < DOUT; ++o) wq[o] = wo[o * H + q];
 #pragma unroll
-        for (int j = 0; j < QM; ++j)
-            if (j < qn) s += (double)hv[j] * (double)w[j];
+    for (int i = 0; i < NR; ++i) {
+        if (i >= nr) continue;
+        const int r = r0 + rstep * i;
+        float s = 0.0f;
+        if constexpr (DOUT % 4 == 0) {
 #pragma unroll
-        for (int d = 1; d < kOutParts; d <<= 1) s += __shfl_xor(s, d, kOutParts);
-        if (part == 0 && grow < p.rows) p.C[grow * p.ldc + o] = (float)(s + (double)p.bout[o]);
+            for (int o = 0; o < DOUT; o += 4) {
+                const float4 g4 = *reinterpret_cast<const float4 *>(gs + r * DOUT + o);
+                s += g4.x * wq[o] + g4.y * wq[o + 1] + g4.z * wq[o + 2] + g4.w * wq[o + 3];
+            }
+        } else {
+#pragma unroll
+            for (int o = 0; o < DOUT; ++o) s += gs[r * DOUT + o] * wq[o];
+        }
+        const float v = m0 + r < p.rows ? s * dsilu_f(z[i]) : 0.0f;
+        Ga[r * ldh + q] = to_op<OP>(v, 1.0f);
     }
 }
 
@@ -486,15 +564,8 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
             z[i] = (i < nr && row < p.rows) ? Zl[row * p.ldz + q] : 0.0f;
         }
         __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            if (i >= nr) continue;
-            const int r = r0 + rstep * i;
-            float s = 0.0f;
-            for (int o = 0; o < dout; ++o) s += gs[r * dout + o] * wo[o * H + q];
-            const float v = m0 + r < p.rows ? s * dsilu_f(z[i]) : 0.0f;
-            Ga[r * ldh + q] = to_op<OP>(v, 1.0f);
-        }
+        if (dout == K) out_adjoint<OP, K, NR>(p, wo, gs, z, Ga, ldh, m0, tid);
+        else out_adjoint<OP, 1, NR>(p, wo, gs, z, Ga, ldh, m0, tid);
     }
     __syncthreads();
     for (int k = p.nh - 1; k >= 1; --k) {
@@ -595,7 +666,8 @@ static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout, int NLK) {
 void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
     if (p.rows <= 0) return;
     const int NLK = p.dc.lstart[p.L + 1] * p.K;
-    if (!fused_nn_ok(op, p.F, p.H, p.nh, p.dout, NLK) || p.F != (p.L + 1) * p.K * (p.K + 1) / 2)
+    if (!fused_nn_ok(op, p.F, p.H, p.nh, p.dout, NLK) || p.F != (p.L + 1) * p.K * (p.K + 1) / 2 ||
+        (p.dout != p.K && p.dout != 1))
         fail(REANN_E_DEVICE, "mlp_fused: unsupported layer shape");
     const size_t smem = fused_smem(op, fwd, p.F, p.H, p.dout, NLK);
     const dim3 grid((unsigned)((p.rows + kFuseBM - 1) / kFuseBM));
