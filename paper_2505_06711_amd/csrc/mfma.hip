@@ -406,6 +406,43 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
 
 }  // namespace
 
+// Density features of order l of tile row r for the pairs (a, b >= a) with a in [A0, A1):
+// X[r][l P + idx(a, b)] = sum over the components q of order l of w_q S[q][a] S[q][b].
+template <OpType OP, int L, int K, int l, int A0, int A1>
+__device__ inline void density_part(const FusedNN &p, typename Fuse<OP>::T *X, int ldx, int64_t m0, int r) {
+    constexpr int NLK = n_lambda(L) * K, P = K * (K + 1) / 2;
+    constexpr int q0 = l * (l + 1) * (l + 2) / 6, nq = (l + 1) * (l + 2) / 2;
+    const bool ok = m0 + r < p.rows;
+    const float4 *Sg = reinterpret_cast<const float4 *>(p.S + (m0 + r) * NLK + q0 * K);
+    float sv[nq][K], w[nq];
+#pragma unroll
+    for (int q = 0; q < nq; ++q) {
+        w[q] = (float)p.dc.w[q0 + q];
+#pragma unroll
+        for (int m4 = 0; m4 < K / 4; ++m4) {
+            const float4 v4 = ok ? Sg[q * (K / 4) + m4] : make_float4(0.f, 0.f, 0.f, 0.f);
+            sv[q][4 * m4] = v4.x; sv[q][4 * m4 + 1] = v4.y; sv[q][4 * m4 + 2] = v4.z; sv[q][4 * m4 + 3] = v4.w;
+        }
+    }
+    typename Fuse<OP>::T *xr = X + r * ldx + l * P;
+#pragma unroll
+    for (int a = A0; a < A1; ++a)
+#pragma unroll
+        for (int b = a; b < K; ++b) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int q = 0; q < nq; ++q) acc += w[q] * sv[q][a] * sv[q][b];
+            xr[a * K - a * (a - 1) / 2 + (b - a)] = to_op<OP>(acc, 1.0f);
+        }
+}
+
+// Split of the pairs a <= b of K channels into a < A and a >= A with about half on each side.
+constexpr int pair_split(int K) {
+    int A = 0, n = 0;
+    while (2 * n < K * (K + 1) / 2) n += K - A++;
+    return A;
+}
+
 // Forward of one element's NN over rows [0, rows): C = out_layer(SiLU(... SiLU(rho W_0^T + b_0) ...))
 // with rho the density of S.  NCB = H / 64 column blocks per wave; (L, K) fix the density.
 template <OpType OP, int NCB, int L, int K>
@@ -430,33 +467,21 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
     float *wo = reinterpret_cast<float *>(smem + offw);
     for (int e = tid; e < p.dout * H; e += 256) wo[e] = p.Wout[e];
     // layer-0 input: the density of this tile's orbital sums, rounded to the operand type and
-    // zero padded to Fp columns; one thread per (row, l) reads that l's components of S
-    for (int it = tid; it < BM * (L + 1); it += 256) {
-        const int r = it / (L + 1), l = it % (L + 1);
-        const int q0 = l * (l + 1) * (l + 2) / 6, nq = (l + 1) * (l + 2) / 2;   // components of order l
-        const bool ok = m0 + r < p.rows;
-        const float4 *Sg = reinterpret_cast<const float4 *>(p.S + (m0 + r) * NLK + q0 * K);
-        float sv[6][K], w[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            w[q] = q < nq ? (float)p.dc.w[q0 + q] : 0.0f;
-#pragma unroll
-            for (int m4 = 0; m4 < K / 4; ++m4) {
-                const float4 v4 = (q < nq && ok) ? Sg[q * (K / 4) + m4] : make_float4(0.f, 0.f, 0.f, 0.f);
-                sv[q][4 * m4] = v4.x; sv[q][4 * m4 + 1] = v4.y; sv[q][4 * m4 + 2] = v4.z; sv[q][4 * m4 + 3] = v4.w;
-            }
+    // zero padded to Fp columns.  One task per wave (lanes 0..31 take the tile's rows): the
+    // orders l < L whole, and order L (the most components) split in two halves of its pairs,
+    // so that no wave runs divergent code and the longest task is about half of order L.
+    static_assert(L == 1 || L == 2, "density tasks are laid out for L = 1, 2");
+    if (lane < BM) {
+        constexpr int AS = pair_split(K);
+        if (wave == 0) density_part<OP, L, K, 0, 0, (L == 1 ? K : K)>(p, X, ldx, m0, lane);
+        if constexpr (L == 2) {
+            if (wave == 1) density_part<OP, L, K, 1, 0, K>(p, X, ldx, m0, lane);
+            if (wave == 2) density_part<OP, L, K, 2, 0, AS>(p, X, ldx, m0, lane);
+            if (wave == 3) density_part<OP, L, K, 2, AS, K>(p, X, ldx, m0, lane);
+        } else {
+            if (wave == 1) density_part<OP, L, K, 1, 0, AS>(p, X, ldx, m0, lane);
+            if (wave == 2) density_part<OP, L, K, 1, AS, K>(p, X, ldx, m0, lane);
         }
-        T *xr = X + r * ldx + l * P;
-        int f = 0;
-#pragma unroll
-        for (int a = 0; a < K; ++a)
-#pragma unroll
-            for (int b = a; b < K; ++b) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int q = 0; q < 6; ++q) acc += w[q] * sv[q][a] * sv[q][b];
-                xr[f++] = to_op<OP>(acc, 1.0f);
-            }
     }
     for (int it = tid; it < BM * (Fp - F); it += 256)
         X[(it / (Fp - F)) * ldx + F + it % (Fp - F)] = to_op<OP>(0.0f, 1.0f);
@@ -630,17 +655,25 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
             sl[4 * m4] = v4.x; sl[4 * m4 + 1] = v4.y; sl[4 * m4 + 2] = v4.z; sl[4 * m4 + 3] = v4.w;
         }
         const float wl = (float)p.dc.w[lam];
+        // each of the K (K + 1) / 2 distinct matrix entries is read once and used for both
+        // (a, b) and (b, a); every acc[a] still receives its terms in the order b = 0 .. K - 1
+        float acc2[K];
 #pragma unroll
-        for (int a = 0; a < K; ++a) {
-            float acc2 = 0.0f;
+        for (int a = 0; a < K; ++a) acc2[a] = 0.0f;
 #pragma unroll
-            for (int b = 0; b < K; ++b) {
-                const int lo = a < b ? a : b, hi = a < b ? b : a;
-                const float m = rb[lo * K - lo * (lo - 1) / 2 + (hi - lo)];
-                acc2 += (a == b ? 2.0f * m : m) * sl[b];
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+            for (int b = a; b < K; ++b) {
+                const float m = rb[a * K - a * (a - 1) / 2 + (b - a)];
+                if (a == b) {
+                    acc2[a] += 2.0f * m * sl[a];
+                } else {
+                    acc2[a] += m * sl[b];
+                    acc2[b] += m * sl[a];
+                }
             }
-            p.C[row * NLK + lam * K + a] = wl * acc2;
-        }
+#pragma unroll
+        for (int a = 0; a < K; ++a) p.C[row * NLK + lam * K + a] = wl * acc2[a];
     }
 }
 
