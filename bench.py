@@ -44,7 +44,7 @@ def work_model(w, n_pairs_local, n_in_cutoff, prec):
       edge adjoint, centre role  bytes 4 n_l + 24 + 2 rs K + rs Lam K + 3 rs;
                     VALU n_c (4 Lam K + 12 K + 80), + 2 Lam K per edge when it also forms
                     the adjoint-message terms (every layer but the first)
-      edge adjoint, neighbour role  bytes per in-cutoff local edge: two slot indices and one
+      edge adjoint, neighbour role  bytes per in-cutoff local edge: one slot index and one
                     record (rs (4 + K), or 4 rs without message terms); + rs (3 + K) out
       atomic NN     2 (F H + (h - 1) H^2 + H K_out) flop (forward; the adjoint the same)
     (an exp counts as 4 VALU slots; bytes count each atom's own data once and exclude cache
@@ -60,8 +60,8 @@ def work_model(w, n_pairs_local, n_in_cutoff, prec):
     out["adj_centre"] = dict(bytes=n * (4 * n_l + 24 + 2 * rs * K + rs * lam * K + 3 * rs),
                              flops=n * n_c * (4 * lam * K + 12 * K + 80),
                              flops_cbar=n * n_c * (6 * lam * K + 12 * K + 80))
-    out["adj_gather"] = dict(bytes=n_in_cutoff * (8 + rs * (4 + K)) + n * rs * (3 + K),
-                             bytes_nocbar=n_in_cutoff * (8 + 4 * rs) + n * rs * 3)
+    out["adj_gather"] = dict(bytes=n_in_cutoff * (4 + rs * (4 + K)) + n * rs * (3 + K),
+                             bytes_nocbar=n_in_cutoff * (4 + 4 * rs) + n * rs * 3)
     out["nn"] = dict(flops_msg=2 * n * (F * H + (nh - 1) * H * H + H * K),
                      flops_en=2 * n * (F * H + (nh - 1) * H * H + H))
     return out
