@@ -205,7 +205,11 @@ reann_status reann_plan_timing(reann_plan *p, double *ms, int64_t *launches, int
  *                     reann_system_add returns REANN_E_CAPACITY for a system that can never fit.
  *   max_batch_atoms   atoms evaluated together in one batched step (0 = 262144).
  *   precision, T, skin as in reann_opts.  use_graph != 0 replays a captured HIP graph for the
- *   batched step when the batch shape repeats. */
+ *   batched step when the batch shape repeats.
+ *   thermostat_K, thermostat_tau_fs: both > 0 ends every REANN_REQ_VV_STEP with a Berendsen
+ *   velocity rescaling (Berendsen et al., J. Chem. Phys. 81, 3684 (1984)) toward
+ *   thermostat_K with time constant thermostat_tau_fs: v *= sqrt(1 + (dt / tau)(T0 / T - 1)),
+ *   T = 2 K / (3 n k_B) from the kinetic energy K after the step; 0 (either) = constant energy. */
 typedef struct {
     int64_t hbm_budget_bytes;
     int64_t max_batch_atoms;
@@ -214,6 +218,8 @@ typedef struct {
     double skin;
     int32_t use_graph;
     int32_t device;
+    double thermostat_K;
+    double thermostat_tau_fs;
 } reann_server_opts;
 
 #define REANN_REQ_EVAL 0      /* evaluate E, F, W at the given positions (pos required)        */
@@ -233,6 +239,8 @@ typedef struct {
     double *positions;        /* caller-owned host [n][3], or NULL: positions after the step */
     int64_t t_submit_ns, t_done_ns;   /* CLOCK_MONOTONIC                                    */
     reann_status status;      /* status of the request itself                              */
+    double kinetic;           /* REANN_REQ_VV_STEP: kinetic energy (eV) of the velocities after
+                                 the step (after any rescaling); 0 for REANN_REQ_EVAL        */
 } reann_result;
 
 reann_status reann_server_create(const reann_model *m, const reann_server_opts *opt, reann_server **out);

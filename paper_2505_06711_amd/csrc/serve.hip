@@ -28,6 +28,7 @@ using namespace reann;
 namespace {
 
 constexpr int kSlots = 8;
+constexpr int kOutHead = 14;   // energy, virial (9), kinetic energy, displacement^2, max |v_c|, max |a_c|
 constexpr double kAccel = 9.648533212e-3;   // (eV/A) / amu in A/fs^2
 
 int64_t now_ns() {
@@ -50,6 +51,97 @@ __global__ void k_vv_kick(int64_t n, double dt, const int32_t *__restrict__ spec
     v[t] = v[t] + 0.5 * (Fold[t] + Fnew[t]) * minv[spec[t / 3]] * kAccel * dt;
 }
 
+constexpr double kBoltzmann = 8.617333262e-5;   // eV / K
+constexpr int kKeBlock = 256;
+
+// Kinetic energy K = (1/2) sum m v^2 of one system in a fixed order: per-block partial sums of
+// m v^2 over consecutive components (a tree in LDS), then one block sums the partials in
+// block order.  The blocks also take the largest velocity and acceleration components
+// (|v_c| and |F_c / m| in A/fs and A/fs^2).  The final block forms the Berendsen factor
+// lambda = sqrt(1 + (dt / tau)(T0 / T - 1)), T = 2 K / (3 n k_B), when T0 > 0 and tau > 0
+// (else 1), and writes aux[0] = lambda and, to the result head, lambda^2 K (eV: the kinetic
+// energy after the rescaling that k_vv_post applies), the squared largest displacement
+// since the list was built (aux[1], from max_displacement2), lambda max|v_c| and max|a_c|.
+constexpr int kAuxDisp = 1;      // max_displacement2 output and its partials (<= 1025 values)
+constexpr int kAuxKe = 1100;     // kinetic partials, 3 per block
+
+__global__ __launch_bounds__(kKeBlock) void k_ke_part(int64_t n3, const int32_t *__restrict__ spec,
+                                                       const double *__restrict__ minv, const double *__restrict__ v,
+                                                       const double *__restrict__ F, double *__restrict__ part) {
+    __shared__ double sh[3][kKeBlock];
+    const int64_t t = (int64_t)blockIdx.x * kKeBlock + threadIdx.x;
+    double s = 0.0, vm = 0.0, am = 0.0;
+    if (t < n3) {
+        const double mi = minv[spec[t / 3]];
+        if (mi > 0.0) {
+            s = v[t] * v[t] / mi;
+            vm = fabs(v[t]);
+            am = fabs(F[t] * mi * kAccel);
+        }
+    }
+    sh[0][threadIdx.x] = s; sh[1][threadIdx.x] = vm; sh[2][threadIdx.x] = am;
+    __syncthreads();
+    for (int h = kKeBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + h]);
+            sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = sh[0][0]; part[3 * blockIdx.x + 1] = sh[1][0]; part[3 * blockIdx.x + 2] = sh[2][0];
+    }
+}
+
+__global__ __launch_bounds__(kKeBlock) void k_ke_final(int64_t n, int nb, double dt, double T0, double tau,
+                                                        double *__restrict__ aux, double *__restrict__ head) {
+    __shared__ double sh[3][kKeBlock];
+    const double *part = aux + kAuxKe;
+    double s = 0.0, vm = 0.0, am = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kKeBlock) {
+        s += part[3 * b];
+        vm = fmax(vm, part[3 * b + 1]);
+        am = fmax(am, part[3 * b + 2]);
+    }
+    sh[0][threadIdx.x] = s; sh[1][threadIdx.x] = vm; sh[2][threadIdx.x] = am;
+    __syncthreads();
+    for (int h = kKeBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + h]);
+            sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double K = 0.5 * sh[0][0] / kAccel;   // amu A^2 / fs^2 -> eV
+        double lam2 = 1.0;
+        if (T0 > 0.0 && tau > 0.0 && K > 0.0) {
+            const double Tcur = 2.0 * K / (3.0 * (double)n * kBoltzmann);
+            lam2 = fmax(0.0, 1.0 + dt / tau * (T0 / Tcur - 1.0));
+        }
+        const double lam = sqrt(lam2);
+        aux[0] = lam;
+        head[0] = lam2 * K;
+        head[1] = aux[kAuxDisp];
+        head[2] = lam * sh[1][0];
+        head[3] = sh[2][0];
+    }
+}
+
+// After a step: the new forces become the old ones, the positions go to the output block,
+// and (velocity-Verlet steps) the velocities take the factor aux[0].
+__global__ void k_vv_post(int64_t n3, const double *__restrict__ F, double *__restrict__ Fold,
+                          const double *__restrict__ x, double *__restrict__ xout, double *__restrict__ v,
+                          const double *__restrict__ aux) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n3) return;
+    Fold[t] = F[t];
+    xout[t] = x[t];
+    if (v) v[t] *= aux[0];
+}
+
 __global__ void k_copy_d(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) b[t] = a[t];
@@ -65,7 +157,20 @@ struct Sys {
     bool have_forces = false;               // forces of the current positions are known
     // residency
     std::unique_ptr<Plan> plan;
-    DevBuf d_pos, d_vel, d_F, d_Fold, d_E, d_W;
+    // d_out = [E, W (9), K, d^2, vmax, amax, F (3n), positions (3n)]: the step writes E, W and
+    // F in place, the motion figures and positions are written after it, and one
+    // device-to-host copy returns the lot
+    DevBuf d_pos, d_vel, d_Fold, d_out, d_aux;   // d_aux: [lambda, displacement scratch, kinetic partials]
+    // motion after the last velocity-Verlet step (largest displacement since the list was
+    // built, largest velocity and acceleration components): bound the next step's
+    // displacement, so that the skin check (a device round trip) is needed only near the edge
+    bool motion_known = false;
+    double disp = 0, vmax = 0, amax = 0;
+    double *E() { return d_out.as<double>(); }
+    double *W() { return d_out.as<double>() + 1; }
+    double *KE() { return d_out.as<double>() + 10; }
+    double *F() { return d_out.as<double>() + kOutHead; }
+    double *P() { return d_out.as<double>() + kOutHead + 3 * n; }
     DArr<int32_t> d_spec;
     hipGraphExec_t graph = nullptr;
     int64_t graph_rebuilds = -1;   // plan rebuild count the graph was captured for
@@ -86,7 +191,7 @@ struct Req {
 };
 
 struct Done {
-    double energy = 0, virial[9]{};
+    double energy = 0, virial[9]{}, kinetic = 0;
     std::vector<double> forces, positions;
     int64_t t_submit = 0, t_done = 0;
     reann_status status = REANN_OK;
@@ -132,7 +237,7 @@ struct reann_server {
     bool make_resident(Sys &sy, int64_t need);
     void evict(Sys &sy);
     int64_t estimate_bytes(const Sys &sy) const;
-    void launch_step(Slot &s, Sys &sy, bool replay_ok);
+    void launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid = false);
 };
 
 int64_t reann_server::estimate_bytes(const Sys &sy) const {
@@ -164,7 +269,7 @@ void reann_server::evict(Sys &sy) {
     }
     if (sy.graph) { (void)hipGraphExecDestroy(sy.graph); sy.graph = nullptr; }
     sy.plan.reset();
-    sy.d_pos.release(); sy.d_vel.release(); sy.d_F.release(); sy.d_Fold.release(); sy.d_E.release(); sy.d_W.release();
+    sy.d_pos.release(); sy.d_vel.release(); sy.d_Fold.release(); sy.d_out.release(); sy.d_aux.release();
     sy.d_spec.b.release();
     resident -= sy.bytes;
     sy.bytes = 0;
@@ -194,8 +299,10 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
     o.skin = opt.skin;
     o.decomp[0] = o.decomp[1] = o.decomp[2] = 1;
     p->init(&ctx, m, sy.species.data(), sy.n, sy.cell, sy.pbc, opt.T, &o);
-    sy.d_pos.ensure(sy.n * 24); sy.d_vel.ensure(sy.n * 24); sy.d_F.ensure(sy.n * 24); sy.d_Fold.ensure(sy.n * 24);
-    sy.d_E.ensure(64); sy.d_W.ensure(128);
+    sy.d_pos.ensure(sy.n * 24); sy.d_vel.ensure(sy.n * 24); sy.d_Fold.ensure(sy.n * 24);
+    sy.d_out.ensure((kOutHead + 6 * sy.n) * 8);
+    sy.d_aux.ensure((size_t)(kAuxKe + 3 * grid_for(sy.n * 3, kKeBlock)) * 8);
+    sy.motion_known = false;
     int32_t *ds = sy.d_spec.resize(sy.n);
     HIP_OK(hipMemcpyAsync(ds, sy.species.data(), sy.n * 4, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(sy.d_pos.p, sy.pos.data(), sy.n * 24, hipMemcpyHostToDevice, st));
@@ -211,10 +318,11 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
 }
 
 // Enqueue one step of `sy` on slot `s` (positions for EVAL already staged in d_pos).
-void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok) {
+void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid) {
     hipStream_t st = s.st;
     Plan &p = *sy.plan;
-    const bool rebuilt = p.prepare(sy.d_pos.as<double>(), st);
+    // the skin check waits for the device; skipped when the caller has shown the list valid
+    const bool rebuilt = list_valid ? false : p.prepare(sy.d_pos.as<double>(), st);
     if (rebuilt) {
         stats[6]++;
         const int64_t actual = (int64_t)p.device_bytes() + 4 * (int64_t)sy.n * 24;
@@ -227,8 +335,8 @@ void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok) {
         if (sy.graph) { (void)hipGraphExecDestroy(sy.graph); sy.graph = nullptr; }
         hipGraph_t g = nullptr;
         HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        p.launch_forward(sy.d_pos.as<double>(), sy.d_E.as<double>(), nullptr, st);
-        p.backward(nullptr, sy.d_F.as<double>(), sy.d_W.as<double>(), st);
+        p.launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
+        p.backward(nullptr, sy.F(), sy.W(), st);
         HIP_OK(hipStreamEndCapture(st, &g));
         hipError_t e = hipGraphInstantiate(&sy.graph, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -239,8 +347,8 @@ void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok) {
         HIP_OK(hipGraphLaunch(sy.graph, st));
         stats[3]++;
     } else {
-        p.launch_forward(sy.d_pos.as<double>(), sy.d_E.as<double>(), nullptr, st);
-        p.backward(nullptr, sy.d_F.as<double>(), sy.d_W.as<double>(), st);
+        p.launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
+        p.backward(nullptr, sy.F(), sy.W(), st);
     }
 }
 
@@ -274,7 +382,7 @@ bool reann_server::admit(Req &r) {
             return false;
         }
     }
-    const size_t need_host = (size_t)(10 + 6 * sy.n) * 8;
+    const size_t need_host = (size_t)(kOutHead + 6 * sy.n) * 8;
     if (s->h_cap < need_host) {
         if (s->h_out) (void)hipHostFree(s->h_out);
         HIP_OK(hipHostMalloc((void **)&s->h_out, need_host, hipHostMallocDefault));
@@ -287,10 +395,17 @@ bool reann_server::admit(Req &r) {
     if (vv && !sy.have_forces) {
         // forces at the current positions first (once per system)
         launch_step(*s, sy, false);
-        hipLaunchKernelGGL(k_copy_d, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.d_F.as<double>(),
-                           sy.d_Fold.as<double>());
+        hipLaunchKernelGGL(k_copy_d, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.F(), sy.d_Fold.as<double>());
         LAUNCH_OK("k_copy_d");
         sy.have_forces = true;
+    }
+    // velocity-Verlet step with the motion of the previous step known: the drift moves atom
+    // component c by v_c dt + a_c dt^2 / 2, so no atom gets further than
+    // disp + sqrt(3) (dt max|v_c| + dt^2 max|a_c| / 2) from where the list was built
+    bool list_valid = false;
+    if (vv && sy.motion_known) {
+        const double bound = sy.disp + 1.7320508075688772 * (r.dt * sy.vmax + 0.5 * r.dt * r.dt * sy.amax);
+        list_valid = bound < 0.5 * opt.skin * (1.0 - 1e-9);
     }
     if (vv) {
         hipLaunchKernelGGL(k_vv_drift, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, r.dt, sy.d_spec.ptr(),
@@ -299,19 +414,26 @@ bool reann_server::admit(Req &r) {
     } else {
         HIP_OK(hipMemcpyAsync(sy.d_pos.p, r.pos.data(), sy.n * 24, hipMemcpyHostToDevice, st));
     }
-    launch_step(*s, sy, true);
+    launch_step(*s, sy, true, list_valid);
     if (vv) {
         hipLaunchKernelGGL(k_vv_kick, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, r.dt, sy.d_spec.ptr(),
-                           d_minv.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.d_F.as<double>());
+                           d_minv.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.F());
         LAUNCH_OK("k_vv_kick");
+        const int nb = grid_for(n3, kKeBlock);
+        double *aux = sy.d_aux.as<double>();
+        max_displacement2(st, sy.plan->nl, sy.d_pos.as<double>(), aux + kAuxDisp);
+        hipLaunchKernelGGL(k_ke_part, dim3(nb), dim3(kKeBlock), 0, st, n3, sy.d_spec.ptr(), d_minv.as<double>(),
+                           sy.d_vel.as<double>(), sy.F(), aux + kAuxKe);
+        LAUNCH_OK("k_ke_part");
+        hipLaunchKernelGGL(k_ke_final, dim3(1), dim3(kKeBlock), 0, st, sy.n, nb, r.dt, opt.thermostat_K,
+                           opt.thermostat_tau_fs, aux, sy.KE());
+        LAUNCH_OK("k_ke_final");
     }
-    hipLaunchKernelGGL(k_copy_d, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.d_F.as<double>(), sy.d_Fold.as<double>());
-    LAUNCH_OK("k_copy_d");
+    hipLaunchKernelGGL(k_vv_post, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.F(), sy.d_Fold.as<double>(),
+                       sy.d_pos.as<double>(), sy.P(), vv ? sy.d_vel.as<double>() : nullptr, sy.d_aux.as<double>());
+    LAUNCH_OK("k_vv_post");
     sy.have_forces = true;
-    HIP_OK(hipMemcpyAsync(s->h_out, sy.d_E.p, 8, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(s->h_out + 1, sy.d_W.p, 72, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(s->h_out + 10, sy.d_F.p, sy.n * 24, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(s->h_out + 10 + n3, sy.d_pos.p, sy.n * 24, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(s->h_out, sy.d_out.p, (kOutHead + 2 * n3) * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipEventRecord(s->ev, st));
     sy.busy = true;
     sy.last_used = now_ns();
@@ -328,8 +450,16 @@ void reann_server::finish(Slot &s) {
     Done d;
     d.energy = s.h_out[0];
     std::memcpy(d.virial, s.h_out + 1, 72);
-    d.forces.assign(s.h_out + 10, s.h_out + 10 + n3);
-    d.positions.assign(s.h_out + 10 + n3, s.h_out + 10 + 2 * n3);
+    const bool vv = s.req.kind == REANN_REQ_VV_STEP;
+    d.kinetic = vv ? s.h_out[10] : 0.0;
+    sy.motion_known = vv;
+    if (vv) {
+        sy.disp = std::sqrt(s.h_out[11]);
+        sy.vmax = s.h_out[12];
+        sy.amax = s.h_out[13];
+    }
+    d.forces.assign(s.h_out + kOutHead, s.h_out + kOutHead + n3);
+    d.positions.assign(s.h_out + kOutHead + n3, s.h_out + kOutHead + 2 * n3);
     d.t_submit = s.req.t_submit;
     d.t_done = now_ns();
     sy.busy = false;
@@ -364,6 +494,10 @@ void reann_server::run() {
                 }
             bool admitted = false;
             for (auto it = pending.begin(); it != pending.end();) {
+                // nothing more can start while every slot is taken
+                bool free_slot = false;
+                for (auto &x : slots) free_slot = free_slot || !x.active;
+                if (!free_slot) break;
                 if (admit(*it)) {
                     it = pending.erase(it);
                     progressed = admitted = true;
@@ -422,6 +556,9 @@ reann_status reann_server_create(const reann_model *m, const reann_server_opts *
         if (o->T < 1 || o->T > m->impl.T_max) fail(REANN_E_INVALID, "T must be in [1, T_max]");
         if (!(o->skin >= 0) || !std::isfinite(o->skin)) fail(REANN_E_INVALID, "skin must be >= 0");
         if (o->precision < REANN_FP64 || o->precision > REANN_FP8) fail(REANN_E_INVALID, "unknown precision");
+        if (!(o->thermostat_K >= 0) || !(o->thermostat_tau_fs >= 0) || !std::isfinite(o->thermostat_K) ||
+            !std::isfinite(o->thermostat_tau_fs))
+            fail(REANN_E_INVALID, "thermostat temperature and time constant must be finite and >= 0");
         int nd = 0;
         HIP_OK(hipGetDeviceCount(&nd));
         if (o->device < 0 || o->device >= nd) fail(REANN_E_INVALID, "device index out of range");
@@ -543,6 +680,7 @@ reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res) {
     if (res->positions && !d.positions.empty()) std::memcpy(res->positions, d.positions.data(), d.positions.size() * 8);
     res->t_submit_ns = d.t_submit;
     res->t_done_ns = d.t_done;
+    res->kinetic = d.kinetic;
     const reann_status st = d.status;
     if (st != REANN_OK) set_last_error(d.error);
     s->results.erase(it);

@@ -154,3 +154,55 @@ def test_bad_requests_do_not_stop_the_server(rn, model_params):
     import ctypes as C
     assert load().reann_poll(srv.handle, C.c_uint64(123456), C.byref(_Result())) == -6   # unknown ticket
     srv.close()
+
+
+def _vv_run(rn, model_params, s, dt, steps, prec, T0=0.0, tau=0.0, temp=300.0):
+    srv = rn.Server(rn.Model(model_params), T=3, precision=prec, skin=1.0, use_graph=True, thermostat_K=T0,
+                    thermostat_tau_fs=tau)
+    srv.set_masses(MASSES)
+    v = systems.maxwell_boltzmann(s["species"], ["H", "O", "Cu"], temp, seed=5)
+    sid = srv.add_system(s, v)
+    Ep, K = [], []
+    for _ in range(steps):
+        r = wait(srv, srv.submit_vv(sid, dt), sid, forces=False)
+        Ep.append(r["energy"])
+        K.append(r["kinetic"])
+    srv.close()
+    return np.array(Ep), np.array(K)
+
+
+def test_vv_conserves_energy_to_second_order(rn, model_params):
+    # constant-energy velocity Verlet (FP64 forces) over the same 20 fs at two time steps: the
+    # total energy stays within a small fraction of the potential energy it exchanges, and its
+    # deviation shrinks ~4x when the step halves (the method is second order)
+    s = systems.remap_species(systems.fcc_n(400, seed=1), ["H", "O", "Cu"])
+    dev = {}
+    for dt in (0.5, 0.25):
+        Ep, K = _vv_run(rn, model_params, s, dt, int(round(20 / dt)), "fp64")
+        Et = Ep + K
+        dev[dt] = np.abs(Et - Et[0]).max()
+        assert dev[dt] < 1e-3 * (Ep.max() - Ep.min())
+        assert K.min() > 0
+    assert 3.0 < dev[0.5] / dev[0.25] < 5.0, dev
+
+
+def test_berendsen_thermostat_pulls_toward_target(rn, model_params):
+    # from a 3000 K start the random-weight potential keeps heating the crystal at constant
+    # energy; the thermostat (300 K, tau = 10 fs) brings it down instead
+    s = systems.remap_species(systems.fcc_n(400, seed=1), ["H", "O", "Cu"])
+    kB, n = 8.617333262e-5, len(s["pos"])
+    _, K_nve = _vv_run(rn, model_params, s, 0.5, 200, "fp32", temp=3000.0)
+    _, K_th = _vv_run(rn, model_params, s, 0.5, 200, "fp32", T0=300.0, tau=10.0, temp=3000.0)
+    T_nve, T_th = 2 * K_nve / (3 * n * kB), 2 * K_th / (3 * n * kB)
+    assert T_nve[-1] > T_nve[0]
+    assert T_th[-1] < 0.5 * T_th[0]
+    assert T_th[-1] < 0.25 * T_nve[-1]
+
+
+def test_eval_request_reports_no_kinetic_energy(rn, model_params):
+    s = mix(7, [200])[0]
+    srv = rn.Server(rn.Model(model_params), T=2, precision="fp32", skin=1.0)
+    sid = srv.add_system(s)
+    r = wait(srv, srv.submit_eval(sid, s["pos"]), sid)
+    assert r["kinetic"] == 0.0
+    srv.close()
