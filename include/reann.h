@@ -92,6 +92,14 @@ typedef struct {
 } reann_model_desc;
 
 reann_status reann_model_create(const reann_model_desc *desc, reann_model **out);
+/* The same model from files.  spec_json_path: a JSON object with the members
+ *   "format": "reann-model", "version": 1, n_species, L, K, T_max, n_hidden, hidden, r_c,
+ *   ang_scale, energy_scale (numbers) and "weights": path of the weight file (relative paths
+ *   are taken from the spec's directory); other members (e.g. element names) are ignored.
+ * The weight file is raw little-endian FP64: centres[K], alphas[K], c0[n_species][K], msg,
+ * en, laid out as in reann_model_desc; its size must match the dimensions exactly.
+ * REANN_E_INVALID for an unreadable or malformed spec or weight file. */
+reann_status reann_model_load(const char *spec_json_path, reann_model **out);
 void reann_model_free(reann_model *m);
 
 /* ---------------------------------------------------------------- context --
@@ -174,6 +182,11 @@ void reann_plan_free(reann_plan *p);
  * components ordered by l, then lx descending, then ly descending); 1: messages c^t [n][K];
  * 2: atomic energies [n] (t ignored).  Synchronises the stream. */
 reann_status reann_plan_get(reann_plan *p, int32_t what, int32_t t, double *host_out);
+/* The two device-pointer steps under their short names: reann_forward_dev is
+ * reann_plan_forward without per-atom energies, reann_backward_dev is reann_plan_backward. */
+reann_status reann_forward_dev(reann_plan *p, const double *d_pos, double *d_energy, void *hip_stream);
+reann_status reann_backward_dev(reann_plan *p, const double *d_grad_energy, double *d_forces, double *d_virial,
+                                void *hip_stream);
 
 /* Kernel time per phase, measured with HIP events recorded on the evaluation stream at
  * phase boundaries while timing is enabled (reann_plan_set_timing), accumulated over every

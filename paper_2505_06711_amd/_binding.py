@@ -6,6 +6,7 @@ kernels.  Importing fails loudly when the library has not been built.
 from __future__ import annotations
 
 import atexit
+import json
 import ctypes as C
 import os
 import weakref
@@ -60,6 +61,9 @@ _SIGS = {
     "reann_last_error": (C.c_char_p, []),
     "reann_model_create": (_i32, [C.POINTER(_ModelDesc), C.POINTER(_vp)]),
     "reann_model_free": (None, [_vp]),
+    "reann_model_load": (_i32, [C.c_char_p, C.POINTER(_vp)]),
+    "reann_forward_dev": (_i32, [_vp, _vp, _vp, _vp]),
+    "reann_backward_dev": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "reann_ctx_create": (_i32, [_i32, _vp, C.POINTER(_vp)]),
     "reann_ctx_free": (None, [_vp]),
     "reann_build_neighbors": (_i32, [_vp, _vp, _i64, _vp, _vp, _d, _d, _vp, C.POINTER(_vp)]),
@@ -165,6 +169,39 @@ class Model:
         self.T_max = params.T_max
         self.K, self.L = params.K, params.L
         _LIVE["model"].add(self)
+
+    @classmethod
+    def load(cls, spec_json_path: str) -> "Model":
+        """A model from a spec written by ``save`` (``reann_model_load``); ``params`` is None."""
+        self = cls.__new__(cls)
+        h = _vp()
+        check(load().reann_model_load(os.fsencode(spec_json_path), C.byref(h)))
+        self.handle = h
+        self.params = None
+        self._keep = []
+        spec = json.load(open(spec_json_path))
+        self.r_c, self.T_max, self.K, self.L = float(spec["r_c"]), int(spec["T_max"]), int(spec["K"]), int(spec["L"])
+        _LIVE["model"].add(self)
+        return self
+
+    def save(self, spec_json_path: str, weights_name: str = None):
+        """Write the parameters as a JSON spec plus a raw FP64 weight file (the formats read
+        by ``reann_model_load``); the weight file goes next to the spec."""
+        p = self.params
+        if p is None:
+            raise ValueError("model was loaded from files; nothing to save")
+        base = os.path.splitext(os.path.basename(spec_json_path))[0]
+        weights_name = weights_name or base + ".weights.f64"
+        d = os.path.dirname(os.path.abspath(spec_json_path))
+        blob = np.concatenate([np.asarray(a, np.float64).ravel() for a in
+                               (p.centres, p.alphas, p.c0, p.msg_blob, p.energy_blob)])
+        blob.astype("<f8").tofile(os.path.join(d, weights_name))
+        spec = dict(format="reann-model", version=1, n_species=int(p.n_species), L=int(p.L), K=int(p.K),
+                    T_max=int(p.T_max), n_hidden=int(p.n_hidden), hidden=int(p.hidden), r_c=float(p.r_c),
+                    ang_scale=float(p.ang_scale), energy_scale=float(p.energy_scale),
+                    elements=list(getattr(p, "elements", [])), weights=weights_name)
+        with open(spec_json_path, "w") as f:
+            json.dump(spec, f, indent=1)
 
     def close(self):
         if _can_free(self):

@@ -1,10 +1,17 @@
 // C ABI entry points.  Every call converts library exceptions into a status code and a
 // thread-local message; no exception crosses the boundary.
 #include <algorithm>
+#include <cctype>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
 #include <new>
+#include <sstream>
+#include <string>
+#include <vector>
 
 #include "runtime.hpp"
 
@@ -110,6 +117,140 @@ reann_status reann_model_create(const reann_model_desc *d, reann_model **out) {
         for (double v : M.msg) if (!std::isfinite(v)) { delete m; fail(REANN_E_INVALID, "non-finite weight"); }
         for (double v : M.en) if (!std::isfinite(v)) { delete m; fail(REANN_E_INVALID, "non-finite weight"); }
         *out = m;
+    });
+}
+
+// ---- model files: a JSON object of scalars next to a raw FP64 weight file ----
+namespace {
+
+// Top-level members of a JSON object whose values are numbers or strings (nested values are
+// skipped).  Enough for the model spec; anything malformed is reported.
+std::map<std::string, std::string> json_scalars(const std::string &t) {
+    std::map<std::string, std::string> out;
+    size_t i = 0;
+    auto ws = [&] { while (i < t.size() && std::isspace((unsigned char)t[i])) ++i; };
+    auto str = [&]() -> std::string {
+        if (i >= t.size() || t[i] != '"') fail(REANN_E_INVALID, "model spec: string expected");
+        std::string v;
+        for (++i; i < t.size() && t[i] != '"'; ++i) {
+            if (t[i] == '\\' && i + 1 < t.size()) ++i;
+            v.push_back(t[i]);
+        }
+        if (i >= t.size()) fail(REANN_E_INVALID, "model spec: unterminated string");
+        ++i;
+        return v;
+    };
+    auto skip_nested = [&] {
+        int depth = 0;
+        bool in_str = false;
+        for (; i < t.size(); ++i) {
+            const char c = t[i];
+            if (in_str) { if (c == '\\') ++i; else if (c == '"') in_str = false; continue; }
+            if (c == '"') in_str = true;
+            else if (c == '[' || c == '{') ++depth;
+            else if (c == ']' || c == '}') { if (--depth == 0) { ++i; return; } }
+        }
+        fail(REANN_E_INVALID, "model spec: unbalanced brackets");
+    };
+    ws();
+    if (i >= t.size() || t[i] != '{') fail(REANN_E_INVALID, "model spec: JSON object expected");
+    ++i;
+    for (;;) {
+        ws();
+        if (i < t.size() && t[i] == '}') break;
+        const std::string key = str();
+        ws();
+        if (i >= t.size() || t[i] != ':') fail(REANN_E_INVALID, "model spec: ':' expected");
+        ++i;
+        ws();
+        if (i < t.size() && t[i] == '"') {
+            out[key] = str();
+        } else if (i < t.size() && (t[i] == '[' || t[i] == '{')) {
+            skip_nested();
+        } else {
+            const size_t b = i;
+            while (i < t.size() && t[i] != ',' && t[i] != '}' && !std::isspace((unsigned char)t[i])) ++i;
+            out[key] = t.substr(b, i - b);
+        }
+        ws();
+        if (i < t.size() && t[i] == ',') { ++i; continue; }
+        if (i < t.size() && t[i] == '}') break;
+        fail(REANN_E_INVALID, "model spec: ',' or '}' expected");
+    }
+    return out;
+}
+
+size_t nn_doubles(int in, int hidden, int nh, int out) {
+    size_t n = 0;
+    int prev = in;
+    for (int k = 0; k < nh; ++k) { n += (size_t)hidden * prev + hidden; prev = hidden; }
+    return n + (size_t)out * prev + out;
+}
+
+}  // namespace
+
+reann_status reann_model_load(const char *spec_json_path, reann_model **out) {
+    return guarded([&] {
+        REQUIRE(spec_json_path && out, "NULL argument");
+        std::ifstream f(spec_json_path);
+        if (!f) fail(REANN_E_INVALID, std::string("cannot open model spec ") + spec_json_path);
+        std::stringstream ss;
+        ss << f.rdbuf();
+        const auto kv = json_scalars(ss.str());
+        auto get = [&](const char *k) -> const std::string & {
+            auto it = kv.find(k);
+            if (it == kv.end()) fail(REANN_E_INVALID, std::string("model spec: missing \"") + k + "\"");
+            return it->second;
+        };
+        auto num = [&](const char *k) {
+            const std::string &v = get(k);
+            char *end = nullptr;
+            const double x = std::strtod(v.c_str(), &end);
+            if (end == v.c_str() || *end != '\0') fail(REANN_E_INVALID, std::string("model spec: \"") + k + "\" is not a number");
+            return x;
+        };
+        auto integer = [&](const char *k) {
+            const double x = num(k);
+            if (x != std::floor(x) || std::fabs(x) > 1e9) fail(REANN_E_INVALID, std::string("model spec: \"") + k + "\" is not an integer");
+            return (int32_t)x;
+        };
+        if (get("format") != "reann-model") fail(REANN_E_INVALID, "model spec: \"format\" must be \"reann-model\"");
+        if (integer("version") != 1) fail(REANN_E_UNSUPPORTED, "model spec: unsupported version");
+        reann_model_desc d{};
+        d.n_species = integer("n_species"); d.L = integer("L"); d.K = integer("K"); d.T_max = integer("T_max");
+        d.n_hidden = integer("n_hidden"); d.hidden = integer("hidden");
+        d.r_c = num("r_c"); d.ang_scale = num("ang_scale"); d.energy_scale = num("energy_scale");
+        REQUIRE(d.n_species >= 1 && d.n_species <= 64 && d.K >= 1 && d.K <= 64 && d.L >= 0 && d.L <= 4 &&
+                    d.T_max >= 1 && d.T_max <= 16 && d.n_hidden >= 1 && d.n_hidden <= 4 && d.hidden >= 1 &&
+                    d.hidden <= 256,
+                "model spec: dimension out of range");
+        // weight file: relative paths are taken from the spec's directory
+        std::string wpath = get("weights");
+        const std::string sp(spec_json_path);
+        const size_t slash = sp.find_last_of('/');
+        if (!wpath.empty() && wpath[0] != '/' && slash != std::string::npos) wpath = sp.substr(0, slash + 1) + wpath;
+        const int F = n_feat(d.L, d.K);
+        const size_t nmsg = (size_t)(d.T_max - 1) * d.n_species * nn_doubles(F, d.hidden, d.n_hidden, d.K);
+        const size_t nen = (size_t)d.n_species * nn_doubles(F, d.hidden, d.n_hidden, 1);
+        const size_t total = 2 * (size_t)d.K + (size_t)d.n_species * d.K + nmsg + nen;
+        std::ifstream w(wpath, std::ios::binary | std::ios::ate);
+        if (!w) fail(REANN_E_INVALID, "cannot open model weights " + wpath);
+        const std::streamoff bytes = w.tellg();
+        if (bytes != (std::streamoff)(total * 8))
+            fail(REANN_E_INVALID, "model weights: " + std::to_string((long long)bytes) + " bytes, expected " +
+                                      std::to_string((unsigned long long)(total * 8)));
+        std::vector<double> buf(total);
+        w.seekg(0);
+        if (!w.read(reinterpret_cast<char *>(buf.data()), (std::streamsize)(total * 8)))
+            fail(REANN_E_INVALID, "model weights: read failed");
+        const double *q = buf.data();
+        d.centres = q; q += d.K;
+        d.alphas = q; q += d.K;
+        d.c0 = q; q += (size_t)d.n_species * d.K;
+        d.msg = nmsg ? q : nullptr; q += nmsg;
+        d.en = q;
+        const reann_status st = reann_model_create(&d, out);
+        if (st != REANN_OK) throw Error(st, reann_last_error());
     });
 }
 
@@ -348,6 +489,15 @@ reann_status reann_plan_backward(reann_plan *p, const double *d_grad_energy, dou
         HIP_OK(hipSetDevice(p->impl.ctx->device));
         p->impl.backward(d_grad_energy, d_forces, d_virial, (hipStream_t)hip_stream);
     });
+}
+
+reann_status reann_forward_dev(reann_plan *p, const double *d_pos, double *d_energy, void *hip_stream) {
+    return reann_plan_forward(p, d_pos, d_energy, nullptr, hip_stream);
+}
+
+reann_status reann_backward_dev(reann_plan *p, const double *d_grad_energy, double *d_forces, double *d_virial,
+                                void *hip_stream) {
+    return reann_plan_backward(p, d_grad_energy, d_forces, d_virial, hip_stream);
 }
 
 reann_status reann_plan_get(reann_plan *p, int32_t what, int32_t t, double *host_out) {
