@@ -175,7 +175,9 @@ __device__ inline int64_t cut_slot(const CutList &cl, int64_t x, int e) {
     return e < nl ? cl.row[x] + e : cl.row[x + 1] - cl.ngh[x] + (e - nl);
 }
 
-// Forward edge pass: the 4 lanes of a quad own one row, lane q the channels m = q, q+4, ...
+// Forward edge pass: the 4 lanes of a quad own one row, lane q the channels
+// m = q K/4 .. (q+1) K/4 - 1 (a contiguous block, so a neighbour's message block is one
+// vector load and the lane's part of S is written with vector stores).
 // The row's edges are taken in groups of 4: lane q evaluates the geometry of edge 4g + q
 // (r, f_c and the angular terms, from one position gather), and the quad exchanges these
 // with DPP quad broadcasts, so that every lane accumulates all 4 edges into its channels.
@@ -211,7 +213,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
         for (int u = 0; u < KG; ++u) acc[l][u] = R(0);
     R cen[KG], alp[KG];
 #pragma unroll
-    for (int u = 0; u < KG; ++u) { cen[u] = R(ec.centres[q + G * u]); alp[u] = gauss_const<R>(ec, q + G * u); }
+    for (int u = 0; u < KG; ++u) { cen[u] = R(ec.centres[KG * q + u]); alp[u] = gauss_const<R>(ec, KG * q + u); }
     const double xi = a.px[i], yi = a.py[i], zi = a.pz[i];
     const R inv_rc = R(1.0 / ec.r_c);
     const R s = R(ec.ang_scale);
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
 #pragma unroll
         for (int sl = 0; sl < G; ++sl)
 #pragma unroll
-            for (int u = 0; u < KG; ++u) cg[sl][u] = c[(int64_t)js[sl] * K + q + G * u];
+            for (int u = 0; u < KG; ++u) cg[sl][u] = c[(int64_t)js[sl] * K + KG * q + u];
     }
     for (int g = 0; g < ngroups; ++g) {
         const double dx = xo - xi, dy = yo - yi, dz = zo - zi;
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
 #pragma unroll
             for (int sl = 0; sl < G; ++sl)
 #pragma unroll
-                for (int u = 0; u < KG; ++u) cg[sl][u] = c[(int64_t)js[sl] * K + q + G * u];
+                for (int u = 0; u < KG; ++u) cg[sl][u] = c[(int64_t)js[sl] * K + KG * q + u];
             jnext = cl.col[slot(min((g + 2) * G + q, last))];
         }
         // own edge: geometry
@@ -280,11 +282,11 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
         REANN_FWD_SRC(3)
 #undef REANN_FWD_SRC
     }
-    R *out = S + i * NL * K + q;
+    R *out = S + i * NL * K + KG * q;
 #pragma unroll
     for (int l = 0; l < NL; ++l)
 #pragma unroll
-        for (int u = 0; u < KG; ++u) out[l * K + G * u] = acc[l][u];
+        for (int u = 0; u < KG; ++u) out[l * K + u] = acc[l][u];
 }
 
 // Per-edge radial/cutoff factors shared by both adjoint roles.
