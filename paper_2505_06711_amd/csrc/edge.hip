@@ -95,7 +95,8 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
     const int g = threadIdx.x & 15, gbase = threadIdx.x & 48;
     const bool active = x < a.n_ext;
     const int64_t lo = active ? a.row[x] : 0, hi = active ? a.row[x + 1] : 0;
-    const double xi = active ? a.px[x] : 0.0, yi = active ? a.py[x] : 0.0, zi = active ? a.pz[x] : 0.0;
+    const double4 pi = active ? a.p4[x] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
     int64_t front = lo, back = hi;
     const uint32_t below = (1u << g) - 1u;
     // two-stage pipeline (indices clamped to the row's last entry): the positions of the next
@@ -106,14 +107,14 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
     if (lo < hi) {
         jc = a.col[min(lo + g, last)];
         jn = a.col[min(lo + 16 + g, last)];
-        xc = a.px[jc]; yc = a.py[jc]; zc = a.pz[jc];
+        { const double4 q = a.p4[jc]; xc = q.x; yc = q.y; zc = q.z; }
     }
     for (int64_t base = lo; base < hi; base += 16) {
         const int64_t k = base + g;
         const int32_t j = jc;
         const double dx = xc - xi, dy = yc - yi, dz = zc - zi;
         jc = jn;
-        xc = a.px[jn]; yc = a.py[jn]; zc = a.pz[jn];
+        { const double4 q = a.p4[jn]; xc = q.x; yc = q.y; zc = q.z; }
         jn = a.col[min(base + 32 + g, last)];
         const bool in = k < hi && dx * dx + dy * dy + dz * dz < rc2;
         const bool isl = in && j < a.n, isg = in && j >= a.n;
@@ -214,7 +215,8 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
     R cen[KG], alp[KG];
 #pragma unroll
     for (int u = 0; u < KG; ++u) { cen[u] = R(ec.centres[KG * q + u]); alp[u] = gauss_const<R>(ec, KG * q + u); }
-    const double xi = a.px[i], yi = a.py[i], zi = a.pz[i];
+    const double4 pi = a.p4[i];
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
     const R inv_rc = R(1.0 / ec.r_c);
     const R s = R(ec.ang_scale);
     const int nl = cl.nloc[i], cnt = nl + cl.ngh[i], last = cnt - 1;
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
     if (ngroups > 0) {
         const int32_t j0 = cl.col[slot(min(q, last))];
         jnext = cl.col[slot(min(G + q, last))];
-        xo = a.px[j0]; yo = a.py[j0]; zo = a.pz[j0];
+        { const double4 q = a.p4[j0]; xo = q.x; yo = q.y; zo = q.z; }
         const int32_t js[G] = {quad_bcast<0>(j0), quad_bcast<1>(j0), quad_bcast<2>(j0), quad_bcast<3>(j0)};
 #pragma unroll
         for (int sl = 0; sl < G; ++sl)
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
             for (int u = 0; u < KG; ++u) cur[sl][u] = cg[sl][u];
         {   // group g + 1: own position, the quad's messages, and the own entry of group g + 2
             const int32_t j1 = jnext;
-            xo = a.px[j1]; yo = a.py[j1]; zo = a.pz[j1];
+            { const double4 q = a.p4[j1]; xo = q.x; yo = q.y; zo = q.z; }
             const int32_t js[G] = {quad_bcast<0>(j1), quad_bcast<1>(j1), quad_bcast<2>(j1), quad_bcast<3>(j1)};
 #pragma unroll
             for (int sl = 0; sl < G; ++sl)
@@ -385,7 +387,8 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(Edge
 #pragma unroll
     for (int q = 0; q < 6; ++q) W[q] = R(0);
     if (x < a.n) {
-        const double xi = a.px[x], yi = a.py[x], zi = a.pz[x];
+        const double4 pi = a.p4[x];
+        const double xi = pi.x, yi = pi.y, zi = pi.z;
         const R s = R(ec.ang_scale);
         const R *sb = sS[grp];
         const int nl = cl.nloc[x], cnt = nl + cl.ngh[x];
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(Edge
             const int64_t s0 = slot(e), s1 = slot(min(e + LPR, last));
             const int32_t j0 = cl.col[s0];
             jn = cl.col[s1];
-            xc = a.px[j0]; yc = a.py[j0]; zc = a.pz[j0];
+            { const double4 q = a.p4[j0]; xc = q.x; yc = q.y; zc = q.z; }
 #pragma unroll
             for (int m = 0; m < K; ++m) cc[m] = c[(int64_t)j0 * K + m];
         }
@@ -423,7 +426,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(Edge
             }
             {
                 const int64_t jj = jn, s2 = slot(min(e + 2 * LPR, last));
-                xc = a.px[jj]; yc = a.py[jj]; zc = a.pz[jj];
+                { const double4 q = a.p4[jj]; xc = q.x; yc = q.y; zc = q.z; }
 #pragma unroll
                 for (int m = 0; m < K; ++m) cc[m] = c[jj * K + m];
                 jn = cl.col[s2];

@@ -19,7 +19,7 @@ struct EdgeArgs {
     int64_t n, n_ext;
     const int64_t *row;
     const int32_t *col;
-    const double *px, *py, *pz;
+    const double4 *p4;   // ext positions (x, y, z, 0)
 };
 
 // In-cutoff entries of the list for the current positions (same slot ranges as the list):

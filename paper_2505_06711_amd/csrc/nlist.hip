@@ -639,8 +639,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
 
 __global__ void k_refresh(Geom g, int64_t n, int64_t n_ext, const double *__restrict__ pos, const int32_t *__restrict__ perm,
                           const int32_t *__restrict__ q, const int32_t *__restrict__ gh_owner,
-                          const int32_t *__restrict__ gh_shift, double *__restrict__ px, double *__restrict__ py,
-                          double *__restrict__ pz) {
+                          const int32_t *__restrict__ gh_shift, double4 *__restrict__ p4) {
     int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n_ext) return;
     int64_t i = x < n ? x : gh_owner[x - n];
@@ -659,14 +658,12 @@ __global__ void k_refresh(Geom g, int64_t n, int64_t n_ext, const double *__rest
         for (int a = 0; a < 3; ++a)
             if (g.per[a]) w[a] = w[a] + (double)gh_shift[3 * gi + a] * g.L[a];
     }
-    px[x] = w[0];
-    py[x] = w[1];
-    pz[x] = w[2];
+    p4[x] = make_double4(w[0], w[1], w[2], 0.0);
 }
 
-void refresh_positions(hipStream_t st, const NList &nl, const double *d_pos, double *px, double *py, double *pz) {
+void refresh_positions(hipStream_t st, const NList &nl, const double *d_pos, double4 *p4) {
     hipLaunchKernelGGL(k_refresh, dim3(grid_for(nl.n_ext, 256)), dim3(256), 0, st, nl.g, nl.n, nl.n_ext, d_pos,
-                       nl.perm.ptr(), nl.q.ptr(), nl.gh_owner.ptr(), nl.gh_shift.ptr(), px, py, pz);
+                       nl.perm.ptr(), nl.q.ptr(), nl.gh_owner.ptr(), nl.gh_shift.ptr(), p4);
     LAUNCH_OK("k_refresh");
 }
 

@@ -60,7 +60,9 @@ int64_t scan_exclusive_i64(hipStream_t st, int64_t *d, int64_t n, DevBuf &tmp);
 
 // Positions of the extended system from caller positions: w_i = x_{perm i} - q_i L for
 // locals, owner position + shift L for ghosts.  SoA output px/py/pz [n_ext].
-void refresh_positions(hipStream_t st, const NList &nl, const double *d_pos, double *px, double *py, double *pz);
+// Wrapped positions of all ext atoms (locals then ghost copies) as (x, y, z, 0), one 32-byte
+// record per atom so that a neighbour's position is a single cache line.
+void refresh_positions(hipStream_t st, const NList &nl, const double *d_pos, double4 *p4);
 
 // max_i |x_i - xref_i|^2 over locals -> d_out[0]; d_out holds 1 + 1024 doubles (partials after it).
 void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_out);

@@ -247,7 +247,7 @@ bool Plan::fused() const {
 void Plan::alloc_buffers() {
     const int K = m->K, NL = m->NL, F = m->F, H = m->H, nh = m->nh;
     const int64_t ne = nl.n_ext;
-    px.ensure(ne * 8); py.ensure(ne * 8); pz.ensure(ne * 8);
+    p4.ensure(ne * 32);
     c.ensure((size_t)T * ne * K * rs);
     S.ensure((size_t)T * n * NL * K * rs);
     if (!fused()) rho.ensure((size_t)T * n * F * rs);
@@ -280,7 +280,7 @@ void Plan::alloc_buffers() {
 
 size_t Plan::device_bytes() const {
     size_t b = 0;
-    for (const DevBuf *d : {&px, &py, &pz, &c, &S, &rho, &Z, &Hh, &y, &ybar, &Eat, &Epart, &Sbar, &rhobar, &gA, &gB,
+    for (const DevBuf *d : {&p4, &c, &S, &rho, &Z, &Hh, &y, &ybar, &Eat, &Epart, &Sbar, &rhobar, &gA, &gB,
                             &cbar, &F, &Wpart, &Wacc, &disp, &col2, &fslot, &cpos, &rslot, &nloc, &ngh, &erec, &fp8s,
                             &fp8tmp})
         b += d->bytes;
@@ -465,9 +465,9 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
     if (!built) fail(REANN_E_STATE, "neighbour list not built");
     const int K = m->K;
     DeviceWeights &w = m->weights(ctx->device, st);
-    refresh_positions(st, nl, d_pos, px.as<double>(), py.as<double>(), pz.as<double>());
+    refresh_positions(st, nl, d_pos, p4.as<double4>());
     init_messages(st, fp64, nl.n_ext, K, nl.spec_ext.ptr(), fp64 ? w.c064.p : w.c032.p, cptr(0));
-    EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), px.as<double>(), py.as<double>(), pz.as<double>()};
+    EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), p4.as<double4>()};
     CutList cl = cutlist();
     compact_cutoff(st, ea, m->r_c, cl);
     const EdgeConsts ec = m->edge_consts();
@@ -496,7 +496,7 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
 void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipStream_t st) {
     if (!have_forward) fail(REANN_E_STATE, "backward called before forward");
     const int K = m->K;
-    EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), px.as<double>(), py.as<double>(), pz.as<double>()};
+    EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), p4.as<double4>()};
     const CutList cl = cutlist();
     const EdgeConsts ec = m->edge_consts();
     const DensityConsts dc = m->density_consts();

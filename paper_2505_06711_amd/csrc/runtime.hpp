@@ -93,7 +93,7 @@ struct Plan {
     bool built = false;
     int64_t rebuilds = 0;
     // layer buffers
-    DevBuf px, py, pz, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, Wacc, disp, one;
+    DevBuf p4, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, Wacc, disp, one;
     DevBuf col2, fslot, cpos, rslot, nloc, ngh;   // in-cutoff compaction of the list for the current step
     DevBuf erec;                     // per-slot edge records of the adjoint
     DevBuf fp8s, fp8tmp;      // per-call activation scale for FP8 products
