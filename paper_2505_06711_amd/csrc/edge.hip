@@ -141,35 +141,6 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
     }
 }
 
-// For the in-cutoff local neighbours of every ext row x (compacted slots s in
-// [row[x], row[x] + nloc[x])): rslot[s] = compacted slot of the reverse entry, the edge from
-// that neighbour back to x.  The reverse of an in-cutoff entry is in cutoff (its
-// displacement is the exact negation), so its cpos is set.  16 lanes per row, U entries
-// per lane at a time so that U chains of dependent loads are in flight.
-__global__ void k_rslot(int64_t n_ext, const int64_t *__restrict__ row, const int32_t *__restrict__ nloc,
-                        const int32_t *__restrict__ fslot, const int32_t *__restrict__ rev,
-                        const int32_t *__restrict__ cpos, int32_t *__restrict__ rslot) {
-    constexpr int U = 4, G = 16;
-    const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int64_t x = t / G;
-    const int g = (int)(t % G);
-    if (x >= n_ext) return;
-    const int64_t lo = row[x];
-    const int cnt = nloc[x], last = cnt - 1;
-    for (int e0 = g; e0 < cnt; e0 += U * G) {
-        int32_t v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = fslot[lo + min(e0 + u * G, last)];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = rev[v[u]];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = cpos[v[u]];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (e0 + u * G < cnt) rslot[lo + e0 + u * G] = v[u];
-    }
-}
-
 // e-th in-cutoff neighbour of row x (locals first, then ghosts)
 __device__ inline int64_t cut_slot(const CutList &cl, int64_t x, int e) {
     const int nl = cl.nloc[x];
@@ -506,10 +477,13 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void k_adj_centre(Edge
 }
 
 // Neighbour role: ext row k (local or ghost) sums the records of the edges j -> k over its
-// in-cutoff local neighbours j (at the reverse slot of each entry k -> j): F_k -= sum g and, with
-// CBAR, cbar_k[m] = sum of the terms.  With CBAR 4 lanes share an edge record (one group
+// in-cutoff local neighbours j (at the compacted slot of the reverse of each entry k -> j):
+// F_k -= sum g and, with CBAR, cbar_k[m] = sum of the terms.  The reverse of an in-cutoff
+// entry is in cutoff (its displacement is the exact negation), so its compacted slot is set.
+// MAKE (the step's first gather) finds that slot through fslot, rev and cpos and stores it in
+// rslot; the later gathers read rslot.  With CBAR 4 lanes share an edge record (one group
 // of 4 values each, 8 edges per pass of the half-wave); without it a lane takes an edge.
-template <int K, typename R, bool CBAR>
+template <int K, typename R, bool CBAR, bool MAKE>
 __global__ __launch_bounds__(256) void k_adj_gather(EdgeArgs a, CutList cl, const R *__restrict__ rec,
                                                     R *__restrict__ F, R *__restrict__ cbar) {
     constexpr int RS = CBAR ? 4 + K : 4;
@@ -531,8 +505,24 @@ __global__ __launch_bounds__(256) void k_adj_gather(EdgeArgs a, CutList cl, cons
     const int pc = part < NP ? 4 * part : 0;
     for (int e0 = eg; e0 < cnt; e0 += U * EPP) {
         int32_t rv[U];
+        if constexpr (MAKE) {
+            // first gather of a step: the reverse compacted slot from the list slot, its
+            // reverse and that one's compacted slot, kept in rslot for the later gathers
 #pragma unroll
-        for (int u = 0; u < U; ++u) rv[u] = cl.rslot[lo + min(e0 + u * EPP, last)];
+            for (int u = 0; u < U; ++u) rv[u] = cl.fslot[lo + min(e0 + u * EPP, last)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rv[u] = cl.rev[rv[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rv[u] = cl.cpos[rv[u]];
+            if (part == 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (e0 + u * EPP < cnt) cl.rslot[lo + e0 + u * EPP] = rv[u];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) rv[u] = cl.rslot[lo + min(e0 + u * EPP, last)];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             R v[4] = {R(0), R(0), R(0), R(0)};
@@ -572,11 +562,6 @@ void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl) 
     LAUNCH_OK("k_compact");
 }
 
-void reverse_slots(hipStream_t st, const EdgeArgs &a, const CutList &cl) {
-    hipLaunchKernelGGL(k_rslot, dim3(grid_for(a.n_ext * 16, 256)), dim3(256), 0, st, a.n_ext, cl.row, cl.nloc,
-                       cl.fslot, cl.rev, cl.cpos, cl.rslot);
-    LAUNCH_OK("k_rslot");
-}
 
 void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
                   const void *c, void *S) {
@@ -619,11 +604,15 @@ int edge_adjoint_centre(hipStream_t st, bool fp64, int L, int K, const EdgeArgs 
 }
 
 void edge_adjoint_gather(hipStream_t st, bool fp64, int K, const EdgeArgs &a, const CutList &cl, bool want_cbar,
-                         const void *rec, void *F, void *cbar) {
+                         bool make_rslot, const void *rec, void *F, void *cbar) {
     const int nbn = grid_for(a.n_ext, kRowsPerBlock);
-#define GAT_T(KK, R, CB)                                                                                         \
-    hipLaunchKernelGGL((k_adj_gather<KK, R, CB>), dim3(nbn), dim3(256), 0, st, a, cl, (const R *)rec, (R *)F,     \
-                       (R *)cbar);
+#define GAT_T(KK, R, CB)                                                                                          \
+    if (make_rslot)                                                                                               \
+        hipLaunchKernelGGL((k_adj_gather<KK, R, CB, true>), dim3(nbn), dim3(256), 0, st, a, cl, (const R *)rec,   \
+                           (R *)F, (R *)cbar);                                                                    \
+    else                                                                                                          \
+        hipLaunchKernelGGL((k_adj_gather<KK, R, CB, false>), dim3(nbn), dim3(256), 0, st, a, cl, (const R *)rec,  \
+                           (R *)F, (R *)cbar);
 #define GAT(KK)                                                 \
     if (fp64) {                                                 \
         if (want_cbar) { GAT_T(KK, double, true) }              \

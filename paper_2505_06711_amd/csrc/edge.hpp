@@ -27,7 +27,8 @@ struct EdgeArgs {
 // ghost neighbours at col[row[x+1] - ngh[x] .. row[x+1]).
 // fslot[s]: the list slot of the entry compacted into s; cpos[f]: the compacted slot of the
 // in-cutoff list entry f; rev: the list's reverse slots; rslot[s] (for the in-cutoff local
-// neighbours of each row): the compacted slot of the reverse of entry s.
+// neighbours of each row, filled by the step's first adjoint gather): the compacted slot of
+// the reverse of entry s.
 struct CutList {
     const int64_t *row;
     int32_t *col;
@@ -36,8 +37,6 @@ struct CutList {
     const int32_t *rev;
 };
 void compact_cutoff(hipStream_t st, const EdgeArgs &a, double r_c, CutList &cl);
-// rslot from fslot, rev and cpos (after compact_cutoff; needed by edge_adjoint_gather)
-void reverse_slots(hipStream_t st, const EdgeArgs &a, const CutList &cl);
 
 // S[i][lambda][m] for the n local rows.  c: messages of all ext atoms, [n_ext][K].
 void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl, const EdgeConsts &ec,
@@ -55,8 +54,9 @@ void edge_forward(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, co
 int edge_adjoint_centre(hipStream_t st, bool fp64, int L, int K, const EdgeArgs &a, const CutList &cl,
                         const EdgeConsts &ec, const void *c, const void *Sbar, bool want_cbar, void *F, double *Wpart,
                         void *rec);
+// make_rslot: the first gather after compact_cutoff (fills rslot; later gathers read it).
 void edge_adjoint_gather(hipStream_t st, bool fp64, int K, const EdgeArgs &a, const CutList &cl, bool want_cbar,
-                         const void *rec, void *F, void *cbar);
+                         bool make_rslot, const void *rec, void *F, void *cbar);
 // Values per edge record: the edge gradient (3, padded to 4) and K adjoint-message terms.
 inline int edge_record_elems(int K) { return 4 + K; }
 int edge_backward_blocks(int64_t n_ext);

@@ -504,7 +504,6 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     fill_energy_seed(st, fp64, n, m->energy_scale, d_g, ybar.p);
     zero(st, this->F.p, (size_t)nl.n_ext * 3 * rs);
     zero(st, Wacc.p, 9 * 8);
-    reverse_slots(st, ea, cl);
     mark(st, PH_OTHER);
     mark(st, PH_NN_BWD, nn_vjp(st, T - 1, true, ybar.as<char>(), 1));
     if (!fused()) {
@@ -515,7 +514,7 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
         const int nb = edge_adjoint_centre(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sbar.p, t > 0, this->F.p,
                                            Wpart.as<double>(), erec.p);
         mark(st, PH_ADJ_CENTRE, 1);
-        edge_adjoint_gather(st, fp64, K, ea, cl, t > 0, erec.p, this->F.p, cbar.p);
+        edge_adjoint_gather(st, fp64, K, ea, cl, t > 0, t == T - 1, erec.p, this->F.p, cbar.p);
         mark(st, PH_ADJ_GATHER, 1);
         sum_rows(st, Wpart.as<double>(), nb, 9, Wacc.as<double>(), true);
         mark(st, PH_OTHER);
