@@ -405,3 +405,48 @@ def test_water1207296_decomposed_equals_whole_fp64(rn, ctx, T):
                                atol=1e-11 * np.abs(g["sample_atom_energy"]).max())
     np.testing.assert_allclose(b[2][idx], np.array(g["sample_forces"]).reshape(-1, 3), rtol=0,
                                atol=1e-10 * np.abs(b[2]).max())
+
+
+def _degenerate_cases():
+    rng = np.random.default_rng(51)
+    one_open = dict(pos=np.array([[3.0, 4.0, 5.0]]), species=np.array([1], np.int32), cell=np.eye(3) * 20.0,
+                    pbc=np.zeros(3, np.int32), elements=["H", "O"])
+    one_big_box = dict(pos=np.array([[1.0, 2.0, 3.0]]), species=np.array([0], np.int32), cell=np.eye(3) * 14.0,
+                       pbc=np.ones(3, np.int32), elements=["H", "O"])
+    one_small_box = dict(pos=np.array([[0.3, 2.9, 1.7]]), species=np.array([1], np.int32),
+                         cell=np.diag([3.1, 3.4, 3.7]), pbc=np.ones(3, np.int32), elements=["H", "O"])
+    # two atoms inside r_c + skin but outside r_c: list entries, no edges
+    pair_in_skin = dict(pos=np.array([[1.0, 1.0, 1.0], [6.5, 1.0, 1.0]]), species=np.array([0, 1], np.int32),
+                        cell=np.eye(3) * 30.0, pbc=np.zeros(3, np.int32), elements=["H", "O"])
+    # one element of the two-element model absent
+    pts = [rng.uniform(0, 8, 3)]
+    while len(pts) < 12:
+        p = rng.uniform(0, 8, 3)
+        if min(np.linalg.norm(p - q) for q in pts) > 1.4:
+            pts.append(p)
+    h_only = dict(pos=np.array(pts), species=np.zeros(12, np.int32), cell=np.eye(3) * 8.0,
+                  pbc=np.ones(3, np.int32), elements=["H", "O"])
+    return {"one_atom_open": one_open, "one_atom_14A_box": one_big_box, "one_atom_3A_box_self_images": one_small_box,
+            "pair_in_skin_only": pair_in_skin, "one_element_absent": h_only}
+
+
+@pytest.mark.parametrize("case", list(_degenerate_cases()))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_degenerate_systems(rn, ctx, oracle_lib, case, prec):
+    """Degenerate inputs against the oracle: a lone atom (open; periodic with no copy in
+    range; periodic with many of its own copies in range), a pair that is in the list but not
+    in cutoff, and a system without one of the model's elements."""
+    s = _degenerate_cases()[case]
+    m = models.water_model(T_max=3, seed=51)
+    skin = 2.0
+    mr = m if prec == "fp64" else fp32_params(m)
+    ref = oracle_lib.evaluate(mr, s, T=3, skin=skin)
+    E, F, W = _eval(rn, ctx, m, s, 3, prec, skin=skin)
+    tol_e, tol_f = (1e-12, 1e-10) if prec == "fp64" else (1e-6, 1e-5)
+    assert rel_energy(E, ref) <= tol_e, (E, ref["energy"])
+    fmax = np.abs(ref["forces"]).max()
+    assert np.abs(F - ref["forces"]).max() <= tol_f * max(fmax, 1.0)
+    wmax = np.abs(ref["virial"]).max()
+    assert np.abs(W - ref["virial"]).max() <= (1e-10 if prec == "fp64" else 1e-4) * max(wmax, 1.0)
+    if case in ("one_atom_open", "one_atom_14A_box", "pair_in_skin_only"):
+        assert np.abs(F).max() == 0.0 and np.abs(W).max() == 0.0
