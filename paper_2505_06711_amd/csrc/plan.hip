@@ -266,7 +266,7 @@ void Plan::alloc_buffers() {
     }
     cbar.ensure((size_t)ne * K * rs);
     this->F.ensure((size_t)ne * 3 * rs);
-    Wpart.ensure((size_t)(edge_backward_blocks(ne) + 1) * 9 * 8);
+    Wpart.ensure((size_t)T * (edge_backward_blocks(ne) + 1) * 9 * 8);   // per layer, summed once
     Wacc.ensure(16 * 8);
     disp.ensure(1025 * 8);
     col2.ensure((size_t)(nl.n_pairs + 1) * 4);
@@ -503,21 +503,21 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     mark(st, -1);
     fill_energy_seed(st, fp64, n, m->energy_scale, d_g, ybar.p);
     zero(st, this->F.p, (size_t)nl.n_ext * 3 * rs);
-    zero(st, Wacc.p, 9 * 8);
     mark(st, PH_OTHER);
     mark(st, PH_NN_BWD, nn_vjp(st, T - 1, true, ybar.as<char>(), 1));
     if (!fused()) {
         density_vjp(st, fp64, m->L, K, n, dc, Sptr(T - 1), rhobar.p, Sbar.p);
         mark(st, PH_DENSITY_ADJ, 1);
     }
+    // the centre role's per-block virial partials of the T layers side by side, summed once
+    int nbw = 0;
     for (int t = T - 1; t >= 0; --t) {
         const int nb = edge_adjoint_centre(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sbar.p, t > 0, this->F.p,
-                                           Wpart.as<double>(), erec.p);
+                                           Wpart.as<double>() + (size_t)nbw * 9, erec.p);
+        nbw += nb;
         mark(st, PH_ADJ_CENTRE, 1);
         edge_adjoint_gather(st, fp64, K, ea, cl, t > 0, t == T - 1, erec.p, this->F.p, cbar.p);
         mark(st, PH_ADJ_GATHER, 1);
-        sum_rows(st, Wpart.as<double>(), nb, 9, Wacc.as<double>(), true);
-        mark(st, PH_OTHER);
         if (t > 0) {
             ghost_reduce(st, fp64, n, K, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), cbar.p);
             mark(st, PH_GHOST);
@@ -530,6 +530,7 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     }
     ghost_reduce(st, fp64, n, 3, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), this->F.p);
     mark(st, PH_GHOST);
+    sum_rows(st, Wpart.as<double>(), nbw, 9, Wacc.as<double>(), false);
     // the seed carried g; forces are -dE/dx already scaled
     forces_out(st, fp64, n, this->F.p, nl.perm.ptr(), nullptr, d_forces, Wacc.as<double>(), d_virial);
     mark(st, PH_OTHER);
