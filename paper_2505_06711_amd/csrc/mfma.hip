@@ -453,8 +453,10 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
     const int64_t m0 = (int64_t)blockIdx.x * BM;
-    const int F = p.F, H = p.H, Fp = pad_k(F);
-    const int ldx = (Fp > H ? Fp : H) + Fuse<OP>::PAD, ldf = H + 4;
+    // layer 0 contracts over F rounded up to the chunk size only (the weight rows are padded
+    // further, with zeros, which the product does not need)
+    const int F = p.F, H = p.H, Fk = (F + Fuse<OP>::KC - 1) / Fuse<OP>::KC * Fuse<OP>::KC;
+    const int ldx = (Fk > H ? Fk : H) + Fuse<OP>::PAD, ldf = H + 4;
     // LDS, addressed from `smem` by offset arithmetic only (a pointer picked from an array
     // would lose its address space and turn every LDS access into a flat one): X [BM][ldx]
     // holds the layer-0 input and then, in place, every hidden layer's output; non-FP32
@@ -467,7 +469,7 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
     float *wo = reinterpret_cast<float *>(smem + offw);
     for (int e = tid; e < p.dout * H; e += 256) wo[e] = p.Wout[e];
     // layer-0 input: the density of this tile's orbital sums, rounded to the operand type and
-    // zero padded to Fp columns.  One task per wave (lanes 0..31 take the tile's rows): the
+    // zero padded to Fk columns.  One task per wave (lanes 0..31 take the tile's rows): the
     // orders l < L whole, and order L (the most components) split in two halves of its pairs,
     // so that no wave runs divergent code and the longest task is about half of order L.
     static_assert(L == 1 || L == 2, "density tasks are laid out for L = 1, 2");
@@ -483,15 +485,15 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
             if (wave == 2) density_part<OP, L, K, 1, AS, K>(p, X, ldx, m0, lane);
         }
     }
-    for (int it = tid; it < BM * (Fp - F); it += 256)
-        X[(it / (Fp - F)) * ldx + F + it % (Fp - F)] = to_op<OP>(0.0f, 1.0f);
+    for (int it = tid; it < BM * (Fk - F); it += 256)
+        X[(it / (Fk - F)) * ldx + F + it % (Fk - F)] = to_op<OP>(0.0f, 1.0f);
     __syncthreads();
     for (int k = 0; k < p.nh; ++k) {
         float bias[NCB];
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) bias[cb] = p.b[k][16 * (wave + kFuseWaves * cb) + li];
         f4 acc[RB][NCB];
-        fused_layer<OP, NCB>(X, ldx, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], k == 0 ? Fp : H, H, wave, lane,
+        fused_layer<OP, NCB>(X, ldx, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], k == 0 ? Fk : H, H, wave, lane,
                              acc);
         __syncthreads();   // every wave has read this layer's input
         const bool last = k + 1 == p.nh;
@@ -690,7 +692,8 @@ static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout, int NLK) {
         const size_t a = std::max<size_t>(kFuseBM * ldh * eb, (size_t)kFuseBM * (F + 4) * 4);
         return a + (size_t)(dout * H + kFuseBM * dout) * 4;
     }
-    const size_t ldx = std::max<size_t>(Fp, H) + pad;
+    const size_t kc = op == OpType::F32 ? 16 : 32, Fk = (F + kc - 1) / kc * kc;
+    const size_t ldx = std::max<size_t>(Fk, H) + pad;
     size_t b = kFuseBM * ldx * eb;
     if (op != OpType::F32) b += (size_t)kFuseBM * (H + 4) * 4;
     return b + (size_t)dout * H * 4;
