@@ -86,10 +86,16 @@ __device__ inline void angular(R ux, R uy, R uz, R s, R *A, R (*dA)[3]) {
 // ghost neighbours at the back (reverse order).  Every later pass of the step reads only
 // these entries.  fslot maps a compacted slot to its list slot and cpos the other way (cpos
 // is written for in-cutoff entries only).
+constexpr int kCompactPasses = 8;   // passes of 16 entries whose loads are issued together
+
 __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, int32_t *__restrict__ fslot,
                           int32_t *__restrict__ cpos, int32_t *__restrict__ nloc, int32_t *__restrict__ ngh) {
-    // 16 lanes per row take the row's entries 16 at a time; a ballot gives each in-cutoff
-    // entry its rank, so the packed order equals a sequential scan of the row
+    // 16 lanes per row take the row's entries 16 at a time (a pass); a ballot gives each
+    // in-cutoff entry its rank, so the packed order equals a sequential scan of the row.  The
+    // entries of up to kCompactPasses passes are loaded at once, then their neighbours'
+    // positions, and only then are the passes tested in order, so that a lane has that many
+    // independent loads in flight instead of one dependent load per pass.
+    constexpr int CH = kCompactPasses;
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t x = t >> 4;
     const int g = threadIdx.x & 15, gbase = threadIdx.x & 48;
@@ -99,41 +105,40 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     int64_t front = lo, back = hi;
     const uint32_t below = (1u << g) - 1u;
-    // two-stage pipeline (indices clamped to the row's last entry): the positions of the next
-    // pass and the entries of the pass after it are loaded while this pass is tested
-    const int64_t last = hi - 1;
-    int32_t jc = 0, jn = 0;
-    double xc = 0.0, yc = 0.0, zc = 0.0;
-    if (lo < hi) {
-        jc = a.col[min(lo + g, last)];
-        jn = a.col[min(lo + 16 + g, last)];
-        { const double4 q = a.p4[jc]; xc = q.x; yc = q.y; zc = q.z; }
-    }
-    for (int64_t base = lo; base < hi; base += 16) {
-        const int64_t k = base + g;
-        const int32_t j = jc;
-        const double dx = xc - xi, dy = yc - yi, dz = zc - zi;
-        jc = jn;
-        { const double4 q = a.p4[jn]; xc = q.x; yc = q.y; zc = q.z; }
-        jn = a.col[min(base + 32 + g, last)];
-        const bool in = k < hi && dx * dx + dy * dy + dz * dz < rc2;
-        const bool isl = in && j < a.n, isg = in && j >= a.n;
-        const uint32_t ml = (uint32_t)(__ballot(isl) >> gbase) & 0xffffu;
-        const uint32_t mg = (uint32_t)(__ballot(isg) >> gbase) & 0xffffu;
-        if (isl) {
-            const int64_t d = front + __popc(ml & below);
-            col2[d] = j;
-            fslot[d] = (int32_t)k;
-            cpos[k] = (int32_t)d;
+    const int64_t last = hi - 1;   // indices past the row's end are clamped to its last entry
+    for (int64_t base = lo; base < hi; base += 16 * CH) {
+        int32_t j[CH];
+        double dx[CH], dy[CH], dz[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) j[u] = base + 16 * u < hi ? a.col[min(base + 16 * u + g, last)] : 0;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const double4 q = base + 16 * u < hi ? a.p4[j[u]] : pi;
+            dx[u] = q.x - xi; dy[u] = q.y - yi; dz[u] = q.z - zi;
         }
-        if (isg) {
-            const int64_t d = back - 1 - __popc(mg & below);
-            col2[d] = j;
-            fslot[d] = (int32_t)k;
-            cpos[k] = (int32_t)d;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (base + 16 * u >= hi) break;   // uniform over the row's lanes
+            const int64_t k = base + 16 * u + g;
+            const bool in = k < hi && dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u] < rc2;
+            const bool isl = in && j[u] < a.n, isg = in && j[u] >= a.n;
+            const uint32_t ml = (uint32_t)(__ballot(isl) >> gbase) & 0xffffu;
+            const uint32_t mg = (uint32_t)(__ballot(isg) >> gbase) & 0xffffu;
+            if (isl) {
+                const int64_t d = front + __popc(ml & below);
+                col2[d] = j[u];
+                fslot[d] = (int32_t)k;
+                cpos[k] = (int32_t)d;
+            }
+            if (isg) {
+                const int64_t d = back - 1 - __popc(mg & below);
+                col2[d] = j[u];
+                fslot[d] = (int32_t)k;
+                cpos[k] = (int32_t)d;
+            }
+            front += __popc(ml);
+            back -= __popc(mg);
         }
-        front += __popc(ml);
-        back -= __popc(mg);
     }
     if (active && g == 0) {
         nloc[x] = (int32_t)(front - lo);
