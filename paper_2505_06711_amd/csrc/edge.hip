@@ -506,7 +506,7 @@ __global__ __launch_bounds__(256) void k_adj_gather(EdgeArgs a, CutList cl, cons
     // U passes at a time, so that each lane has U independent (reverse slot -> record) loads
     // in flight; indices past the row's end are clamped to its last edge and their records
     // are not added
-    constexpr int U = 4;
+    constexpr int U = 8;
     const int pc = part < NP ? 4 * part : 0;
     for (int e0 = eg; e0 < cnt; e0 += U * EPP) {
         int32_t rv[U];
