@@ -164,7 +164,10 @@ constexpr int kFwdLanes = 4;
 
 // value of lane SRC of this lane's quad (all 4 lanes must be active)
 template <int SRC> __device__ inline int quad_bcast(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, SRC * 0x55, 0xF, 0xF, false);
+    // every lane of the quad reads a lane of the same quad, so no lane keeps an old value
+    // (and none reads an out-of-range lane, which would give 0): the move needs no prior
+    // register initialisation and can be folded into the instruction that uses it
+    return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, true);
 }
 template <int SRC> __device__ inline float quad_bcast(float v) { return __int_as_float(quad_bcast<SRC>(__float_as_int(v))); }
 template <int SRC> __device__ inline double quad_bcast(double v) {

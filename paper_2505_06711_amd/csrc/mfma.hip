@@ -267,11 +267,13 @@ template <> struct Fuse<OpType::BF16> {
 
 typedef float fl4 __attribute__((ext_vector_type(4)));
 
-// Lane permutations within rows of 16 lanes (DPP; registers only, no LDS round trip).
+// Lane permutations within rows of 16 lanes (DPP; registers only, no LDS round trip).  The
+// permutations used here read an active lane of the same row for every lane, so the moves
+// need no old value.
 template <int CTRL> __device__ inline double dpp_f64(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
@@ -279,7 +281,7 @@ constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141;  // lane i <- lane 7 - i within each group of 8
 
 template <int CTRL> __device__ inline float dpp_f32(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 // Sum over each group of 8 consecutive lanes (every lane gets the same value: the quad sums
