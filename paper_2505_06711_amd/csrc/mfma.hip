@@ -303,23 +303,22 @@ template <typename A> __device__ inline A sum8(A v) {
 // each takes H / kOutParts hidden units for all DOUT outputs, and the partial sums are
 // combined across the row's threads; thread `part` writes outputs part, part + kOutParts, ...
 // The energy NN (one output) accumulates in FP64, the message NNs in FP32 like their hidden
-// layers.
-template <int DOUT, typename A>
+// layers.  H (the hidden width) is a compile-time constant, so the loops unroll without
+// branches.
+template <int DOUT, typename A, int H>
 __device__ inline void out_layer(const float *hl, int ldl, const float *wo, const FusedNN &p, int64_t m0, int tid) {
-    constexpr int QM = kFuseMaxH / kOutParts;
-    const int H = p.H;
-    const int row = tid / kOutParts, part = tid % kOutParts, qn = H / kOutParts;
-    A hv[QM];
+    constexpr int QN = H / kOutParts;
+    const int row = tid / kOutParts, part = tid % kOutParts;
+    A hv[QN];
 #pragma unroll
-    for (int j = 0; j < QM; ++j) hv[j] = j < qn ? (A)hl[row * ldl + part * qn + j] : A(0);
+    for (int j = 0; j < QN; ++j) hv[j] = (A)hl[row * ldl + part * QN + j];
     A s[DOUT];
 #pragma unroll
     for (int o = 0; o < DOUT; ++o) {
-        const float *w = wo + o * H + part * qn;
+        const float *w = wo + o * H + part * QN;
         A a = A(0);
 #pragma unroll
-        for (int j = 0; j < QM; ++j)
-            if (j < qn) a += hv[j] * (A)w[j];
+        for (int j = 0; j < QN; ++j) a += hv[j] * (A)w[j];
         s[o] = a;
     }
 #pragma unroll
@@ -521,23 +520,25 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
     // output layer: dout is K (message NNs) or 1 (energy NN)
     const float *hl = (OP == OpType::F32) ? reinterpret_cast<const float *>(X) : hf;
     const int ldl = (OP == OpType::F32) ? ldx : ldf;
-    if (p.dout == K) out_layer<K, float>(hl, ldl, wo, p, m0, tid);
-    else out_layer<1, double>(hl, ldl, wo, p, m0, tid);
+    if (p.dout == K) out_layer<K, float, 64 * NCB>(hl, ldl, wo, p, m0, tid);
+    else out_layer<1, double, 64 * NCB>(hl, ldl, wo, p, m0, tid);
 }
 
 // Output layer of the adjoint: Ga[r][q] = (sum_o G[r][o] Wout[o][q]) * SiLU'(z) for column
-// q = tid % H of rows r0, r0 + 256 / H, ... (z holds those rows' pre-activations); the
-// thread keeps its column of Wout in registers and reads each G row as vectors.
-template <OpType OP, int DOUT, int NR>
-__device__ inline void out_adjoint(const FusedNN &p, const float *wo, const float *gs, const float (&z)[NR],
-                                   typename Fuse<OP>::T *Ga, int ldh, int64_t m0, int tid) {
-    const int H = p.H, q = tid % H, r0 = tid / H, rstep = 256 / H, nr = kFuseBM / rstep;
+// q = tid % H of rows r0, r0 + 256 / H, ... (z holds those NR = kFuseBM H / 256 rows'
+// pre-activations); the thread keeps its column of Wout in registers and reads each G row as
+// vectors.  H is a compile-time constant.
+template <OpType OP, int DOUT, int H>
+__device__ inline void out_adjoint(const FusedNN &p, const float *wo, const float *gs,
+                                   const float (&z)[kFuseBM * H / 256], typename Fuse<OP>::T *Ga, int ldh, int64_t m0,
+                                   int tid) {
+    constexpr int NR = kFuseBM * H / 256, rstep = 256 / H;
+    const int q = tid % H, r0 = tid / H;
     float wq[DOUT];
 #pragma unroll
     for (int o = 0; o < DOUT; ++o) wq[o] = wo[o * H + q];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        if (i >= nr) continue;
         const int r = r0 + rstep * i;
         float s = 0.0f;
         if constexpr (DOUT % 4 == 0) {
@@ -583,18 +584,18 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
             const int r = e / dout, o = e % dout;
             gs[e] = m0 + r < p.rows ? p.G[(m0 + r) * p.ldg + o] : 0.0f;
         }
-        constexpr int NR = BM * kFuseMaxH / 256;
-        const int q = tid % H, r0 = tid / H, rstep = 256 / H, nr = BM / rstep;
+        constexpr int HC = 64 * NCB, NR = BM * HC / 256, rstep = 256 / HC;   // HC = H
+        const int q = tid % HC, r0 = tid / HC;
         const float *Zl = p.Z[p.nh - 1];
         float z[NR];
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             const int64_t row = m0 + r0 + rstep * i;
-            z[i] = (i < nr && row < p.rows) ? Zl[row * p.ldz + q] : 0.0f;
+            z[i] = row < p.rows ? Zl[row * p.ldz + q] : 0.0f;
         }
         __syncthreads();
-        if (dout == K) out_adjoint<OP, K, NR>(p, wo, gs, z, Ga, ldh, m0, tid);
-        else out_adjoint<OP, 1, NR>(p, wo, gs, z, Ga, ldh, m0, tid);
+        if (dout == K) out_adjoint<OP, K, HC>(p, wo, gs, z, Ga, ldh, m0, tid);
+        else out_adjoint<OP, 1, HC>(p, wo, gs, z, Ga, ldh, m0, tid);
     }
     __syncthreads();
     for (int k = p.nh - 1; k >= 1; --k) {
@@ -709,7 +710,7 @@ void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
         fail(REANN_E_DEVICE, "mlp_fused: unsupported layer shape");
     const size_t smem = fused_smem(op, fwd, p.F, p.H, p.dout, NLK);
     const dim3 grid((unsigned)((p.rows + kFuseBM - 1) / kFuseBM));
-    const bool h128 = p.H == 128;
+    const bool h128 = p.H == 128;   // the kernels take H = 64 NCB as a compile-time constant
 #define LK_(OPV, NC, LL, KK)                                                                          \
     if (fwd) hipLaunchKernelGGL((k_mlp_fwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);        \
     else hipLaunchKernelGGL((k_mlp_bwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);
