@@ -409,19 +409,21 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
 
 // Density features of order l of tile row r for the pairs (a, b >= a) with a in [A0, A1):
 // X[r][l P + idx(a, b)] = sum over the components q of order l of w_q S[q][a] S[q][b].
+// A tile row past the segment's end takes the segment's last row (its results are never
+// stored), so every load is unconditional.
 template <OpType OP, int L, int K, int l, int A0, int A1>
 __device__ inline void density_part(const FusedNN &p, typename Fuse<OP>::T *X, int ldx, int64_t m0, int r) {
     constexpr int NLK = n_lambda(L) * K, P = K * (K + 1) / 2;
     constexpr int q0 = l * (l + 1) * (l + 2) / 6, nq = (l + 1) * (l + 2) / 2;
-    const bool ok = m0 + r < p.rows;
-    const float4 *Sg = reinterpret_cast<const float4 *>(p.S + (m0 + r) * NLK + q0 * K);
+    const int64_t row = min(m0 + r, p.rows - 1);
+    const float4 *Sg = reinterpret_cast<const float4 *>(p.S + row * NLK + q0 * K);
     float sv[nq][K], w[nq];
 #pragma unroll
     for (int q = 0; q < nq; ++q) {
         w[q] = (float)p.dc.w[q0 + q];
 #pragma unroll
         for (int m4 = 0; m4 < K / 4; ++m4) {
-            const float4 v4 = ok ? Sg[q * (K / 4) + m4] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 v4 = Sg[q * (K / 4) + m4];
             sv[q][4 * m4] = v4.x; sv[q][4 * m4 + 1] = v4.y; sv[q][4 * m4 + 2] = v4.z; sv[q][4 * m4 + 3] = v4.w;
         }
     }
@@ -589,9 +591,9 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
         const float *Zl = p.Z[p.nh - 1];
         float z[NR];
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const int64_t row = m0 + r0 + rstep * i;
-            z[i] = row < p.rows ? Zl[row * p.ldz + q] : 0.0f;
+        for (int i = 0; i < NR; ++i) {   // rows past the end: as above (out_adjoint zeroes them)
+            const int64_t row = min(m0 + r0 + rstep * i, p.rows - 1);
+            z[i] = Zl[row * p.ldz + q];
         }
         __syncthreads();
         if (dout == K) out_adjoint<OP, K, HC>(p, wo, gs, z, Ga, ldh, m0, tid);
@@ -607,9 +609,10 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int64_t row = m0 + 16 * rb + 4 * lg + r;
+                    // rows past the end read the last row; their adjoints are set to 0 below
+                    const int64_t row = min(m0 + 16 * rb + 4 * lg + r, p.rows - 1);
                     const int col = 16 * (wave + kFuseWaves * cb) + li;
-                    zp[rb][cb][r] = row < p.rows ? Zk[row * p.ldz + col] : 0.0f;
+                    zp[rb][cb][r] = Zk[row * p.ldz + col];
                 }
         f4 acc[RB][NCB];
         fused_layer<OP, NCB>(Ga, ldh, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], H, H, wave, lane, acc);
