@@ -162,19 +162,23 @@ __device__ inline int64_t cut_slot(const CutList &cl, int64_t x, int e) {
 // evaluated (indices clamped to the row's last edge; a lane past the end contributes 0).
 constexpr int kFwdLanes = 4;
 
-// value of lane SRC of this lane's quad (all 4 lanes must be active)
-template <int SRC> __device__ inline int quad_bcast(int v) {
-    // every lane of the quad reads a lane of the same quad, so no lane keeps an old value
-    // (and none reads an out-of-range lane, which would give 0): the move needs no prior
-    // register initialisation and can be folded into the instruction that uses it
-    return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, true);
-}
-template <int SRC> __device__ inline float quad_bcast(float v) { return __int_as_float(quad_bcast<SRC>(__float_as_int(v))); }
-template <int SRC> __device__ inline double quad_bcast(double v) {
+// DPP lane moves within rows of 16 lanes.  The controls used here make every lane read an
+// active lane of its own row, so no lane keeps an old value (and none reads an out-of-range
+// lane, which would give 0): the move needs no prior register initialisation.
+template <int CTRL> __device__ inline int dpp_move(int v) { return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true); }
+template <int CTRL> __device__ inline float dpp_move(float v) { return __int_as_float(dpp_move<CTRL>(__float_as_int(v))); }
+template <int CTRL> __device__ inline double dpp_move(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = quad_bcast<SRC>((int)(uint32_t)(b & 0xffffffffll)), hi = quad_bcast<SRC>((int)(b >> 32));
+    const int lo = dpp_move<CTRL>((int)(uint32_t)(b & 0xffffffffll)), hi = dpp_move<CTRL>((int)(b >> 32));
     return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
+constexpr int kDppQuadXor1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowHalfMirror = 0x141;   // lane i <- lane 7 - i within each group of 8
+constexpr int kDppRowMirror = 0x140;       // lane i <- lane 15 - i within each row of 16
+
+// value of lane SRC of this lane's quad (all 4 lanes must be active)
+template <int SRC, typename V> __device__ inline V quad_bcast(V v) { return dpp_move<SRC * 0x55>(v); }
 
 template <int L, int K, typename R>
 __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeConsts ec, const R *__restrict__ c,
@@ -334,10 +338,15 @@ constexpr int kRowsPerBlock = 8;   // 256 threads = 8 half-waves, one row each
 constexpr int kCentreLanes = 16;
 constexpr int kCentreRows = 256 / kCentreLanes;
 
-template <typename R> __device__ inline R row_sum(R v) {   // over the kCentreLanes lanes of a row
-#pragma unroll
-    for (int o = kCentreLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kCentreLanes);
-    return v;
+// Sum over the kCentreLanes = 16 lanes of a row (one DPP row, all lanes active): the quad
+// sums, then each lane adds the mirrored lane's value within its group of 8 (the other quad)
+// and within the row (the other half), so every lane ends with the row's total.
+static_assert(kCentreLanes == 16, "row sums are formed within a DPP row of 16 lanes");
+template <typename R> __device__ inline R row_sum(R v) {
+    v += dpp_move<kDppQuadXor1>(v);
+    v += dpp_move<kDppQuadXor2>(v);
+    v += dpp_move<kDppRowHalfMirror>(v);
+    return v + dpp_move<kDppRowMirror>(v);
 }
 
 template <int L, int K, typename R, bool CBAR>
