@@ -146,12 +146,6 @@ __global__ void k_compact(EdgeArgs a, double rc2, int32_t *__restrict__ col2, in
     }
 }
 
-// e-th in-cutoff neighbour of row x (locals first, then ghosts)
-__device__ inline int64_t cut_slot(const CutList &cl, int64_t x, int e) {
-    const int nl = cl.nloc[x];
-    return e < nl ? cl.row[x] + e : cl.row[x + 1] - cl.ngh[x] + (e - nl);
-}
-
 // Forward edge pass: the 4 lanes of a quad own one row, lane q the channels
 // m = q K/4 .. (q+1) K/4 - 1 (a contiguous block, so a neighbour's message block is one
 // vector load and the lane's part of S is written with vector stores).
@@ -314,12 +308,6 @@ __device__ inline void add4(const float *p, float (&v)[4]) {
 __device__ inline void add4(const double *p, double (&v)[4]) {
     const double2 t0 = reinterpret_cast<const double2 *>(p)[0], t1 = reinterpret_cast<const double2 *>(p)[1];
     v[0] += t0.x; v[1] += t0.y; v[2] += t1.x; v[3] += t1.y;
-}
-
-template <typename R> __device__ inline R hw_sum(R v) {   // sum over the 32 lanes of a half-wave
-#pragma unroll
-    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
-    return v;
 }
 
 constexpr int kRowsPerBlock = 8;   // 256 threads = 8 half-waves, one row each
