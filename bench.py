@@ -361,7 +361,7 @@ def main():
                          "kernel that scales rocprofv3's FETCH_SIZE / WRITE_SIZE readings)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the subdomain exchange is "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the subdomain exchange is "
               "emulated inside one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
