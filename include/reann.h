@@ -100,6 +100,10 @@ reann_status reann_model_create(const reann_model_desc *desc, reann_model **out)
  * en, laid out as in reann_model_desc; its size must match the dimensions exactly.
  * REANN_E_INVALID for an unreadable or malformed spec or weight file. */
 reann_status reann_model_load(const char *spec_json_path, reann_model **out);
+/* Frees the model.  Plans (reann_plan_create) and servers made from it must be freed
+ * first.  A context's cached state for reann_energy_forces may outlive the model: it is
+ * never used again, since every model gets an id no later model reuses, even one created
+ * at the same address. */
 void reann_model_free(reann_model *m);
 
 /* ---------------------------------------------------------------- context --

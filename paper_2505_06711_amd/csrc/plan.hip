@@ -159,6 +159,7 @@ void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const doubl
                 int TT, const reann_opts *opt) {
     ctx = c_;
     m = mm;
+    model_id = mm->id;
     if (nn <= 0) fail(REANN_E_INVALID, "n must be > 0");
     if (TT < 1 || TT > m->T_max) fail(REANN_E_INVALID, "T must be in [1, T_max]");
     T = TT;
@@ -193,7 +194,9 @@ void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const doubl
 
 bool Plan::same_system(const Model *mm, const int32_t *spec, int64_t nn, const double cell_[9], const int32_t pbc_[3],
                        int TT, const reann_opts *opt) const {
-    if (mm != m || nn != n || TT != T) return false;
+    // the id, not only the address: a model created after this plan's model was freed can
+    // have the same address (m itself is not read, it may be dangling)
+    if (mm != m || mm->id != model_id || nn != n || TT != T) return false;
     const int pr = opt ? opt->precision : REANN_FP32;
     const double sk = opt ? opt->skin : 0.0;
     if (pr != prec || sk != skin) return false;

@@ -2,6 +2,7 @@
 // stream), and a plan that evaluates one system (neighbour list, layer buffers, kernels).
 #pragma once
 
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -40,7 +41,16 @@ struct DeviceWeights {
     std::unique_ptr<MfmaSet> mf[2][3];      // [msg, energy][OpType]
 };
 
+// A number no other model of this process has had: a freed model's address can be reused
+// by the next one, so a plan cached for a system records the id of its model, not only the
+// address.
+inline uint64_t next_model_id() {
+    static std::atomic<uint64_t> counter{0};
+    return ++counter;
+}
+
 struct Model {
+    const uint64_t id = next_model_id();
     int n_species, L, K, T_max, nh, H, F, NL;
     double r_c, ang_scale, energy_scale;
     std::vector<double> centres, alphas, c0, msg, en;
@@ -78,6 +88,7 @@ static_assert(PH_OTHER + 1 == REANN_N_PHASES, "phase count");
 struct Plan {
     Ctx *ctx = nullptr;
     Model *m = nullptr;
+    uint64_t model_id = 0;   // m->id when the plan was made (m may since have been freed)
     int T = 1, prec = REANN_FP32;
     bool fp64 = false;
     size_t rs = 4;   // bytes of the working type

@@ -157,6 +157,58 @@ def test_cu_small_with_skin(rn, ctx, oracle_lib, prec):
         check_fp32(*_eval(rn, ctx, m, s, 3, prec, skin=1.0), ref, "cu 5x5x4", tol_e=2e-6)
 
 
+# Every compiled (L, K) pair, 1 to 4 hidden layers, and hidden widths on the fused NN kernels
+# (64 and 128, with one or two column blocks per wave at K = 8 and 12) and on the per-layer
+# path (96 and 200, which the fused kernels do not take).
+MODEL_SHAPES = {
+    "L1_K4_1x64": dict(L=1, K=4, n_hidden=1, hidden=64),
+    "L2_K4_4x128": dict(L=2, K=4, n_hidden=4, hidden=128),
+    "L2_K8_3x128": dict(L=2, K=8, n_hidden=3, hidden=128),
+    "L2_K12_1x64": dict(L=2, K=12, n_hidden=1, hidden=64),
+    "L2_K8_2x96_per_layer": dict(L=2, K=8, n_hidden=2, hidden=96),
+    "L2_K12_2x200_per_layer": dict(L=2, K=12, n_hidden=2, hidden=200),
+}
+
+
+@pytest.mark.parametrize("shape", list(MODEL_SHAPES))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_model_shapes(rn, ctx, oracle_lib, shape, prec):
+    """Two elements, T = 3, 0.5 A skin, 2x1x1 subdomains, on the 192-molecule water box."""
+    s = systems.water_box(seed=60)
+    m = models.make_model(["H", "O"], r_c=5.0, width=0.5, T_max=3, seed=61, **MODEL_SHAPES[shape])
+    if prec == "fp64":
+        ref = oracle_lib.evaluate(m, s, T=3, skin=0.5)
+        E, F, W = _eval(rn, ctx, m, s, 3, prec, skin=0.5, decomp=(2, 1, 1))
+        print("fp64 %s: rel E %.2e" % (shape, rel_energy(E, ref)), flush=True)
+        assert rel_energy(E, ref) <= 1e-12
+        assert np.abs(F - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max()
+        assert np.abs(W - ref["virial"]).max() <= 1e-10 * np.abs(ref["virial"]).max()
+    else:
+        # random models: a single hidden layer fed by 234 density features contracts them in
+        # one FP32 sum per unit, so the energy's rounding reaches ~1.2e-6 (the bound of the
+        # random Cu model); forces and virial keep the common bounds
+        ref = oracle_lib.evaluate(fp32_params(m), s, T=3, skin=0.5)
+        check_fp32(*_eval(rn, ctx, m, s, 3, prec, skin=0.5, decomp=(2, 1, 1)), ref, shape, tol_e=2e-6)
+
+
+def test_new_model_on_same_system_gets_its_own_plan(rn, ctx, oracle_lib):
+    """Models of different shapes evaluated one after another on the same system through one
+    context, each freed after use: a new model (which can occupy a freed model's address)
+    must not reuse the evaluation state cached for the freed one."""
+    import gc
+    s = systems.water_box(seed=62)
+    small = models.make_model(["H", "O"], r_c=5.0, width=0.5, T_max=3, seed=63, L=1, K=4, n_hidden=1, hidden=64)
+    big = models.make_model(["H", "O"], r_c=5.0, width=0.5, T_max=3, seed=64, L=2, K=12, n_hidden=3, hidden=128)
+    for m in (small, big, small):
+        model = rn.Model(m)
+        E, F, W = rn.energy_forces(ctx, model, s, T=3, precision="fp64", skin=0.5)
+        del model
+        gc.collect()
+        ref = oracle_lib.evaluate(m, s, T=3, skin=0.5)
+        assert rel_energy(E, ref) <= 1e-12
+        assert np.abs(F - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max()
+
+
 def test_layer_intermediates_fp64(rn, ctx, oracle_lib):
     """Orbital sums S^t, messages c^t and atomic energies, layer by layer."""
     import torch
