@@ -171,7 +171,7 @@ MODEL_SHAPES = {
 
 
 @pytest.mark.parametrize("shape", list(MODEL_SHAPES))
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_model_shapes(rn, ctx, oracle_lib, shape, prec):
     """Two elements, T = 3, 0.5 A skin, 2x1x1 subdomains, on the 192-molecule water box."""
     s = systems.water_box(seed=60)
@@ -183,6 +183,19 @@ def test_model_shapes(rn, ctx, oracle_lib, shape, prec):
         assert rel_energy(E, ref) <= 1e-12
         assert np.abs(F - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max()
         assert np.abs(W - ref["virial"]).max() <= 1e-10 * np.abs(ref["virial"]).max()
+    elif prec == "bf16":
+        # BF16 operands approximate the model (8 significant bits per operand, and every
+        # layer of the T NN evaluations adds its rounding), so this checks the BF16 kernels'
+        # layouts at every shape rather than a precision: an operand or tile mistake gives
+        # errors of order one, while rounding grows with the depth (0.4% for one hidden
+        # layer, 1.8% for four on these models)
+        ref = oracle_lib.evaluate(m, s, T=3, skin=0.5)
+        E, F, W = _eval(rn, ctx, m, s, 3, prec, skin=0.5, decomp=(2, 1, 1))
+        re, rf = rel_energy(E, ref), rel_force_rmse(F, ref)
+        print("bf16 %s: rel E %.2e, force rel-RMSE %.2e" % (shape, re, rf), flush=True)
+        depth = MODEL_SHAPES[shape]["n_hidden"] + 1
+        assert re <= 1e-2 * depth
+        assert rf <= 2e-2 * depth
     else:
         # random models: a single hidden layer fed by 234 density features contracts them in
         # one FP32 sum per unit, so the energy's rounding reaches ~1.2e-6 (the bound of the
