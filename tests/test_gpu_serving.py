@@ -82,6 +82,33 @@ def test_server_matches_plan_path(rn, model_params):
             np.testing.assert_allclose(r["forces"], F, rtol=0, atol=1e-9 * np.abs(F).max())
 
 
+# Other model shapes through the server (its graphs capture the same kernels as the plan
+# path): K = 8 and K = 4 edge passes, one and two hidden layers, and a hidden width that the
+# fused NN kernels do not take (the per-layer path).
+SERVE_SHAPES = {
+    "L2_K8_2x64": dict(L=2, K=8, n_hidden=2, hidden=64),
+    "L1_K4_1x64": dict(L=1, K=4, n_hidden=1, hidden=64),
+    "L2_K12_2x96_per_layer": dict(L=2, K=12, n_hidden=2, hidden=96),
+}
+
+
+@pytest.mark.parametrize("shape", list(SERVE_SHAPES))
+def test_server_matches_plan_path_other_models(rn, shape):
+    m = models.make_model(["H", "O"], r_c=5.0, width=0.5, T_max=3, seed=7, **SERVE_SHAPES[shape])
+    model = rn.Model(m)
+    ctx = rn.Context(0)
+    srv = rn.Server(model, T=3, precision="fp32", skin=1.0, use_graph=True)
+    for k, n in enumerate([300, 1200]):
+        s = systems.remap_species(systems.water_box_n(n, seed=40 + k), ["H", "O"])
+        sid = srv.add_system(s)
+        for rep in range(2):
+            r = wait(srv, srv.submit_eval(sid, s["pos"]), sid)
+            E, F, W = rn.energy_forces(ctx, model, s, T=3, precision="fp32", skin=1.0)
+            assert r["energy"] == pytest.approx(E, rel=1e-12, abs=1e-12), rep
+            np.testing.assert_allclose(r["forces"], F, rtol=0, atol=1e-9 * np.abs(F).max())
+    srv.close()
+
+
 def test_velocity_verlet_steps_and_rebuilds(rn, model_params):
     s = mix(300, [1500])[0]
     model = rn.Model(model_params)
