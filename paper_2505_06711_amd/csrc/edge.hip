@@ -56,6 +56,18 @@ __device__ inline double d_sinpi(double x) { return sinpi(x); }
 __device__ inline float d_sqrt(float x) { return sqrtf(x); }
 __device__ inline double d_sqrt(double x) { return sqrt(x); }
 
+// r / r_c, the argument of the cutoff function.  FP32: a product with 1/r_c rounded to FP32
+// would carry that constant's rounding (a relative bias of up to 3e-8, the same sign for every
+// edge), which the steep tail of f_c amplifies ~10x near r_c and every atom of a crystal repeats
+// coherently; 1/r_c is taken as a sum of two floats instead, so the quotient is within about one
+// rounding of the exact one.  FP64: the product with 1/r_c.
+__device__ inline float over_rc(float r, double r_c) {
+    const double inv = 1.0 / r_c;
+    const float hi = (float)inv, lo = (float)(inv - (double)hi);
+    return fmaf(r, hi, r * lo);
+}
+__device__ inline double over_rc(double r, double r_c) { return r * (1.0 / r_c); }
+
 // A_lambda(u) with u = s d, and optionally dA_lambda/dd (= s * dA/du).
 template <int L, typename R, bool GRAD>
 __device__ inline void angular(R ux, R uy, R uz, R s, R *A, R (*dA)[3]) {
@@ -194,7 +206,6 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
     for (int u = 0; u < KG; ++u) { cen[u] = R(ec.centres[KG * q + u]); alp[u] = gauss_const<R>(ec, KG * q + u); }
     const double4 pi = a.p4[i];
     const double xi = pi.x, yi = pi.y, zi = pi.z;
-    const R inv_rc = R(1.0 / ec.r_c);
     const R s = R(ec.ang_scale);
     const int nl = cl.nloc[i], cnt = nl + cl.ngh[i], last = cnt - 1;
     const int64_t lo = cl.row[i], gb = cl.row[i + 1] - cl.ngh[i];
@@ -235,7 +246,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(EdgeArgs a, CutList cl, EdgeCo
         // own edge: geometry
         const double d2 = dx * dx + dy * dy + dz * dz;
         const R r = d_sqrt(R(d2));
-        const R uc = R(0.5) * d_cospi(r * inv_rc) + R(0.5);
+        const R uc = R(0.5) * d_cospi(over_rc(r, ec.r_c)) + R(0.5);
         const R fc = live ? uc * uc : R(0);
         R A[NL];
         angular<L, R, false>(R(ec.ang_scale * dx), R(ec.ang_scale * dy), R(ec.ang_scale * dz), s, A, nullptr);
@@ -279,7 +290,7 @@ __device__ inline void edge_geo(const EdgeConsts &ec, double dx, double dy, doub
     const double d2 = dx * dx + dy * dy + dz * dz;
     g.r = d_sqrt(R(d2));
     const R rinv = R(1) / g.r;
-    const R t = g.r * R(1.0 / ec.r_c);
+    const R t = over_rc(g.r, ec.r_c);
     const R u = R(0.5) * d_cospi(t) + R(0.5);
     g.fc = u * u;
     g.dfc = -u * R(M_PI / ec.r_c) * d_sinpi(t);

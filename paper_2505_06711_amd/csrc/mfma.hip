@@ -47,6 +47,10 @@ __device__ inline float sigm_f(float z) {
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
 __device__ inline float silu_f(float z) { return z * sigm_f(z); }
+// The forward's SiLU with the exponential of the library (argument reduction in extended
+// precision, so the rounding of -z log2(e) is not amplified by |z|); the activation is rounded
+// once more than an exact SiLU, not several times.
+__device__ inline float silu_fwd(float z) { return z * __builtin_amdgcn_rcpf(1.0f + expf(-z)); }
 __device__ inline float dsilu_f(float z) {
     const float s = sigm_f(z);
     return s * (1.0f + z * (1.0f - s));
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t rows, int in, int out, con
                 if (EPI == EPI_BIAS_SILU) {
                     v += bias[col];
                     Z[row * ldz + col] = v;
-                    v = silu_f(v);
+                    v = silu_fwd(v);
                 } else if (EPI == EPI_BIAS) {
                     v += bias[col];
                 } else if (EPI == EPI_DSILU) {
@@ -302,11 +306,14 @@ template <typename A> __device__ inline A sum8(A v) {
 // Output layer of the forward (FP32 data, accumulation in A): kOutParts threads share a row,
 // each takes H / kOutParts hidden units for all DOUT outputs, and the partial sums are
 // combined across the row's threads; thread `part` writes outputs part, part + kOutParts, ...
-// The energy NN (one output) accumulates in FP64, the message NNs in FP32 like their hidden
-// layers.  H (the hidden width) is a compile-time constant, so the loops unroll without
-// branches.
-template <int DOUT, typename A, int H>
-__device__ inline void out_layer(const float *hl, int ldl, const float *wo, const FusedNN &p, int64_t m0, int tid) {
+// The energy NN (one output) accumulates in FP64 with FP64 weights and bias: its output is a
+// sum of H terms that can cancel to a small atomic energy, so the FP32 rounding of its weights
+// would be amplified by that cancellation.  The message NNs accumulate in FP32 with FP32 weights,
+// like their hidden layers.  H (the hidden width) is a compile-time constant, so the loops
+// unroll without branches.
+template <int DOUT, typename A, int H, typename WT>
+__device__ inline void out_layer(const float *hl, int ldl, const WT *wo, const WT *bo, const FusedNN &p, int64_t m0,
+                                 int tid) {
     constexpr int QN = H / kOutParts;
     const int row = tid / kOutParts, part = tid % kOutParts;
     A hv[QN];
@@ -315,7 +322,7 @@ __device__ inline void out_layer(const float *hl, int ldl, const float *wo, cons
     A s[DOUT];
 #pragma unroll
     for (int o = 0; o < DOUT; ++o) {
-        const float *w = wo + o * H + part * QN;
+        const WT *w = wo + o * H + part * QN;
         A a = A(0);
 #pragma unroll
         for (int j = 0; j < QN; ++j) a += hv[j] * (A)w[j];
@@ -327,13 +334,13 @@ __device__ inline void out_layer(const float *hl, int ldl, const float *wo, cons
     if (grow < p.rows) {
 #pragma unroll
         for (int o = 0; o < DOUT; ++o)
-            if (o % kOutParts == part) p.C[grow * p.ldc + o] = (float)(s[o] + (A)p.bout[o]);
+            if (o % kOutParts == part) p.C[grow * p.ldc + o] = (float)(s[o] + (A)bo[o]);
     }
 }
 
 // acc[rb][cb] = sum_k X[16 rb + i][k] Wt[16 (wave + 4 cb) + j][k] over k < kin (a multiple of
 // the chunk).  Columns at or past `out` read row 0 of Wt; the caller never stores them.
-template <OpType OP, int NCB>
+template <OpType OP, int NCB, bool SPLIT>
 __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const typename Fuse<OP>::T *__restrict__ Wt,
                                    int ldw, int kin, int out, int wave, int lane, f4 (&acc)[kFuseBM / 16][NCB]) {
     constexpr int RB = kFuseBM / 16, KC = Fuse<OP>::KC;
@@ -362,7 +369,17 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) a[rb] = *reinterpret_cast<const V *>(X + (16 * rb + li) * ldx + k0 + RUN * lg);
     };
-    auto mma = [&](const V (&a)[RB], const V (&b)[NCB]) {
+    // SPLIT (the forward, whose rounding reaches the energy): even chunks accumulate into acc,
+    // odd chunks into acc2, summed at the end, so each FP32 accumulation chain is half as long.
+    // The adjoint keeps one chain (its rounding reaches only the forces, and the registers of a
+    // second chain would spill).
+    f4 acc2[RB][NCB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc2[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+    f4 (&accb)[RB][NCB] = SPLIT ? acc2 : acc;
+    auto mma = [&](f4 (&c)[RB][NCB], const V (&a)[RB], const V (&b)[NCB]) {
         if constexpr (OP == OpType::F32) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
@@ -370,14 +387,14 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                     for (int cb = 0; cb < NCB; ++cb)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s], b[cb][s], acc[rb][cb], 0, 0, 0);
+                        c[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s], b[cb][s], c[rb][cb], 0, 0, 0);
         } else {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        __builtin_bit_cast(bf16x8, a[rb]), __builtin_bit_cast(bf16x8, b[cb]), acc[rb][cb], 0, 0, 0);
+                    c[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, a[rb]), __builtin_bit_cast(bf16x8, b[cb]), c[rb][cb], 0, 0, 0);
         }
     };
     // pairs of chunks per trip, so that a trip is one basic block and the requests cannot be
@@ -392,17 +409,23 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
         load_b(b1, k0 + KC);
         load_a(a1, k0 + KC);
         __builtin_amdgcn_sched_barrier(0);
-        mma(a0, b0);
+        mma(acc, a0, b0);
         __builtin_amdgcn_sched_barrier(0);
         const int k2 = min(k0 + 2 * KC, klast);
         load_b(b0, k2);
         load_a(a0, k2);
         __builtin_amdgcn_sched_barrier(0);
-        mma(a1, b1);
+        mma(accb, a1, b1);
         __builtin_amdgcn_sched_barrier(0);
         k0 += 2 * KC;
     }
-    if (nck & 1) mma(a0, b0);   // a0, b0 hold the last chunk
+    if (nck & 1) mma(acc, a0, b0);   // a0, b0 hold the last chunk
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] += acc2[rb][cb];
+    }
 }
 
 }  // namespace
@@ -470,7 +493,11 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
     T *X = reinterpret_cast<T *>(smem);
     float *hf = reinterpret_cast<float *>(smem + offf);
     float *wo = reinterpret_cast<float *>(smem + offw);
-    for (int e = tid; e < p.dout * H; e += 256) wo[e] = p.Wout[e];
+    double *wo64 = reinterpret_cast<double *>(smem + offw);   // the energy NN's FP64 W_out instead
+    if (p.dout == 1)
+        for (int e = tid; e < H; e += 256) wo64[e] = p.Wout64[e];
+    else
+        for (int e = tid; e < p.dout * H; e += 256) wo[e] = p.Wout[e];
     // layer-0 input: the density of this tile's orbital sums, rounded to the operand type and
     // zero padded to Fk columns.  One task per wave (lanes 0..31 take the tile's rows): the
     // orders l < L whole, and order L (the most components) split in two halves of its pairs,
@@ -496,7 +523,7 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) bias[cb] = p.b[k][16 * (wave + kFuseWaves * cb) + li];
         f4 acc[RB][NCB];
-        fused_layer<OP, NCB>(X, ldx, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], k == 0 ? Fk : H, H, wave, lane,
+        fused_layer<OP, NCB, true>(X, ldx, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], k == 0 ? Fk : H, H, wave, lane,
                              acc);
         __syncthreads();   // every wave has read this layer's input
         const bool last = k + 1 == p.nh;
@@ -512,7 +539,7 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
                     const int64_t row = m0 + rr;
                     const float z = acc[rb][cb][r] + bias[cb];
                     if (row < p.rows) Zk[row * p.ldz + col] = z;
-                    const float h = silu_f(z);
+                    const float h = silu_fwd(z);
                     X[rr * ldx + col] = to_op<OP>(h, 1.0f);
                     if (OP != OpType::F32 && last) hf[rr * ldf + col] = h;
                 }
@@ -522,8 +549,8 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
     // output layer: dout is K (message NNs) or 1 (energy NN)
     const float *hl = (OP == OpType::F32) ? reinterpret_cast<const float *>(X) : hf;
     const int ldl = (OP == OpType::F32) ? ldx : ldf;
-    if (p.dout == K) out_layer<K, float, 64 * NCB>(hl, ldl, wo, p, m0, tid);
-    else out_layer<1, double, 64 * NCB>(hl, ldl, wo, p, m0, tid);
+    if (p.dout == K) out_layer<K, float, 64 * NCB, float>(hl, ldl, wo, p.bout, p, m0, tid);
+    else out_layer<1, double, 64 * NCB, double>(hl, ldl, wo64, p.bout64, p, m0, tid);
 }
 
 // Output layer of the adjoint: Ga[r][q] = (sum_o G[r][o] Wout[o][q]) * SiLU'(z) for column
@@ -615,7 +642,7 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
                     zp[rb][cb][r] = Zk[row * p.ldz + col];
                 }
         f4 acc[RB][NCB];
-        fused_layer<OP, NCB>(Ga, ldh, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], H, H, wave, lane, acc);
+        fused_layer<OP, NCB, false>(Ga, ldh, reinterpret_cast<const T *>(p.W[k]), p.ldw[k], H, H, wave, lane, acc);
         __syncthreads();   // every wave has read the tile
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -634,7 +661,7 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
     // first layer: dE/drho = zbar_0 W_0 (F columns), into region A once every wave is done
     // reading the adjoint tile
     f4 acc[RB][NCBF];
-    fused_layer<OP, NCBF>(Ga, ldh, reinterpret_cast<const T *>(p.W[0]), p.ldw[0], H, F, wave, lane, acc);
+    fused_layer<OP, NCBF, false>(Ga, ldh, reinterpret_cast<const T *>(p.W[0]), p.ldw[0], H, F, wave, lane, acc);
     __syncthreads();
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -702,7 +729,7 @@ static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout, int NLK) {
     const size_t ldx = std::max<size_t>(Fk, H) + pad;
     size_t b = kFuseBM * ldx * eb;
     if (op != OpType::F32) b += (size_t)kFuseBM * (H + 4) * 4;
-    return b + (size_t)dout * H * 4;
+    return b + (size_t)dout * H * (dout == 1 ? 8 : 4);   // W_out: FP64 for the energy NN
 }
 
 void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {

@@ -50,6 +50,7 @@ struct FusedNN {
     float *Z[kFuseMaxNh];         // pre-activations [rows][ldz]: written by forward, read by adjoint
     int ldz;
     const float *Wout, *bout;     // output layer [dout][H], [dout] (FP32)
+    const double *Wout64, *bout64;   // forward with dout = 1 (the energy NN): the same in FP64
     const float *G;               // adjoint: output adjoint [rows][ldg]
     int ldg;
     float *C;                     // forward: outputs [rows][ldc]; adjoint: dE/dS [rows][NL*K]

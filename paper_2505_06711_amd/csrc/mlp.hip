@@ -303,11 +303,12 @@ void sum_rows(hipStream_t st, const double *partials, int nb, int width, double 
 // every output accumulates in FP64 (these are sums of large terms with cancellation).
 constexpr int kOutRows = 64, kOutMaxIn = 128, kOutMaxOut = 16;
 
+template <typename WT>
 __global__ __launch_bounds__(256) void k_out_fwd(int64_t rows, int in, int out, const float *__restrict__ A, int lda,
-                                                 const float *__restrict__ W, const float *__restrict__ b,
+                                                 const WT *__restrict__ W, const WT *__restrict__ b,
                                                  float *__restrict__ C, int ldc) {
     __shared__ float sA[kOutRows][kOutMaxIn + 1];
-    __shared__ float sW[kOutMaxOut][kOutMaxIn];
+    __shared__ WT sW[kOutMaxOut][kOutMaxIn];
     const int64_t r0 = (int64_t)blockIdx.x * kOutRows;
     for (int e = threadIdx.x; e < kOutRows * in; e += 256) {
         const int rr = e / in, k = e % in;
@@ -323,6 +324,22 @@ __global__ __launch_bounds__(256) void k_out_fwd(int64_t rows, int in, int out, 
         for (int k = 0; k < in; ++k) s += (double)sA[rr][k] * (double)sW[o][k];
         C[r * ldc + o] = (float)(s + (double)b[o]);
     }
+}
+
+// The energy NN's output layer on the per-layer path: one output per row, FP64 weights and
+// bias, FP64 accumulation in order k = 0 .. in - 1 (one thread per row; any width up to 1024).
+constexpr int kOutEnMaxIn = 1024;
+__global__ __launch_bounds__(256) void k_out_energy(int64_t rows, int in, const float *__restrict__ A, int lda,
+                                                    const double *__restrict__ W, const double *__restrict__ b,
+                                                    float *__restrict__ C, int ldc) {
+    __shared__ double sW[kOutEnMaxIn];
+    for (int k = threadIdx.x; k < in; k += 256) sW[k] = W[k];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= rows) return;
+    double s = 0.0;
+    for (int k = 0; k < in; ++k) s += (double)A[r * lda + k] * sW[k];
+    C[r * ldc] = (float)(s + b[0]);
 }
 
 // zbar[r][q] = (sum_o ybar[r][o] W[o][q]) * SiLU'(Z[r][q])
@@ -345,8 +362,17 @@ void out_layer_fwd(hipStream_t st, int64_t rows, int in, int out, const float *A
         dense(st, false, EPI_BIAS, true, rows, in, out, A, lda, W, b, nullptr, 0, C, ldc);
         return;
     }
-    hipLaunchKernelGGL(k_out_fwd, dim3(grid_for(rows, kOutRows)), dim3(256), 0, st, rows, in, out, A, lda, W, b, C, ldc);
+    hipLaunchKernelGGL(k_out_fwd<float>, dim3(grid_for(rows, kOutRows)), dim3(256), 0, st, rows, in, out, A, lda, W, b,
+                       C, ldc);
     LAUNCH_OK("k_out_fwd");
+}
+
+void out_layer_energy(hipStream_t st, int64_t rows, int in, const float *A, int lda, const double *W, const double *b,
+                      float *C, int ldc) {
+    if (rows <= 0) return;
+    if (in > kOutEnMaxIn) fail(REANN_E_UNSUPPORTED, "energy NN output layer wider than 1024");
+    hipLaunchKernelGGL(k_out_energy, dim3(grid_for(rows, 256)), dim3(256), 0, st, rows, in, A, lda, W, b, C, ldc);
+    LAUNCH_OK("k_out_energy");
 }
 
 void out_layer_vjp(hipStream_t st, int64_t rows, int out, int in, const float *G, int ldg, const float *W,

@@ -30,6 +30,9 @@ void dense(hipStream_t st, bool fp64, Epi epi, bool trans_w, int64_t rows, int i
 // Output layer of an atomic NN (FP32 data, FP64 accumulation): C = A W^T + b, W [out][in].
 void out_layer_fwd(hipStream_t st, int64_t rows, int in, int out, const float *A, int lda, const float *W,
                    const float *b, float *C, int ldc);
+// The energy NN's output layer (one output): FP64 weights [in] and bias, FP64 accumulation.
+void out_layer_energy(hipStream_t st, int64_t rows, int in, const float *A, int lda, const double *W, const double *b,
+                      float *C, int ldc);
 // Its adjoint into the last hidden layer: C[r][q] = (sum_o G[r][o] W[o][q]) * SiLU'(Z[r][q]).
 void out_layer_vjp(hipStream_t st, int64_t rows, int out, int in, const float *G, int ldg, const float *W,
                    const float *Z, int ldz, float *C, int ldc);

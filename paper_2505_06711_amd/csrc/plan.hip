@@ -343,6 +343,11 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
             f.ldz = H;
             f.Wout = (const float *)(p + lay.w_off[nh] * rs);
             f.bout = (const float *)(p + lay.b_off[nh] * rs);
+            if (energy) {   // the energy readout takes its weights and bias in FP64
+                const double *p64 = w.en64.as<double>() + (size_t)nn_index * lay.size;
+                f.Wout64 = p64 + lay.w_off[nh];
+                f.bout64 = p64 + lay.b_off[nh];
+            }
             f.C = (float *)out; f.ldc = dout;
             mlp_fused(st, op, true, f);
             ++nfused;
@@ -368,7 +373,11 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
         if (fp64)
             dense(st, fp64, EPI_BIAS, true, rows, H, dout, A, lda, p + lay.w_off[nh] * rs, p + lay.b_off[nh] * rs,
                   nullptr, 0, out, dout);
-        else
+        else if (energy) {   // FP64 weights and bias, as in the fused kernel
+            const double *p64 = w.en64.as<double>() + (size_t)nn_index * lay.size;
+            out_layer_energy(st, rows, H, (const float *)A, lda, p64 + lay.w_off[nh], p64 + lay.b_off[nh], (float *)out,
+                             dout);
+        } else
             out_layer_fwd(st, rows, H, dout, (const float *)A, lda, (const float *)(p + lay.w_off[nh] * rs),
                           (const float *)(p + lay.b_off[nh] * rs), (float *)out, dout);
     }

@@ -1,18 +1,15 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
+Every reference is the oracle evaluated in FP64 on the model's exact (FP64) parameters.
 Tolerances:
   neighbour lists  bit-exact sets in canonical (i, owner, shift) order
   FP64 path        |dE| <= 1e-12 * max(|E|, sum|E_i|); forces and virial <= 1e-10 (relative to max)
-  FP32 path        |dE| <= 1e-6 * max(|E|, sum|E_i|); force RMSE <= 1e-5 * force RMS;
+  FP32 path        |dE| <= 1e-6 * max(|E|, sum|E_i|) (random weights can make E ~ 0, so the
+                   scale of the atomic energies is the denominator when it is larger);
+                   force RMSE <= 1e-5 * force RMS and every force component within 1e-5 * max|F|;
                    virial <= 1e-4 * max|W| (W sums ~1e7 edge terms d (x) f whose magnitudes
                    exceed |W| by ~1e3, so per-edge FP32 rounding is amplified that much).
-                   On the named workloads (192-atom water, 100,800-atom Cu) the FP32 path is
-                   held to these bounds against the FP64 model.  On the other random models
-                   the reference is the oracle evaluated on the same parameters rounded to
-                   FP32, which isolates the arithmetic: storing weights in FP32 alone moves the
-                   energy of a small-energy random model by ~1e-6.
 """
-import copy
 import json
 import os
 
@@ -49,21 +46,18 @@ def rel_force_rmse(F, ref):
     return np.sqrt(((F - ref["forces"]) ** 2).mean()) / np.sqrt((ref["forces"] ** 2).mean())
 
 
-def fp32_params(m):
-    """The model with every parameter rounded to FP32 (what the FP32 path evaluates)."""
-    m2 = copy.deepcopy(m)
-    for k in ("centres", "alphas", "c0", "msg_blob", "energy_blob"):
-        setattr(m2, k, np.asarray(getattr(m, k), np.float32).astype(np.float64))
-    return m2
-
-
-def check_fp32(E, F, W, ref, tag="", tol_e=1e-6):
+def check_fp32(E, F, W, ref, tag=""):
     re, rf = rel_energy(E, ref), rel_force_rmse(F, ref)
-    rw = np.abs(W - ref["virial"]).max() / np.abs(ref["virial"]).max()
-    print("fp32 %s: rel E %.2e, force rel-RMSE %.2e, virial rel %.2e" % (tag, re, rf, rw), flush=True)
-    assert re <= tol_e
+    fmax = np.abs(ref["forces"]).max()
+    rfe = np.abs(F - ref["forces"]).max() / max(fmax, 1e-300)
+    wmax = np.abs(ref["virial"]).max()
+    rw = np.abs(W - ref["virial"]).max() / max(wmax, 1e-300)
+    print("fp32 %s: rel E %.2e (|dE|/|E| %.2e), force rel-RMSE %.2e, max component %.2e, virial rel %.2e"
+          % (tag, re, abs(E - ref["energy"]) / max(abs(ref["energy"]), 1e-300), rf, rfe, rw), flush=True)
+    assert re <= 1e-6
     assert rf <= 1e-5
-    assert rw <= 1e-4
+    assert np.abs(F - ref["forces"]).max() <= 1e-5 * (fmax if fmax > 0 else 1.0)
+    assert np.abs(W - ref["virial"]).max() <= 1e-4 * (wmax if wmax > 0 else 1.0)
 
 
 def canon(row, j, sh):
@@ -136,7 +130,7 @@ def test_fp32_water192_workload(rn, ctx, oracle_lib):
 def test_fp32_matches_oracle_water(rn, ctx, oracle_lib, T):
     s = systems.water_box(seed=31)
     m = models.water_model(T_max=3, seed=31)
-    ref = oracle_lib.evaluate(fp32_params(m), s, T=T)
+    ref = oracle_lib.evaluate(m, s, T=T)
     check_fp32(*_eval(rn, ctx, m, s, T, "fp32"), ref, "water T=%d" % T)
 
 
@@ -150,11 +144,11 @@ def test_cu_small_with_skin(rn, ctx, oracle_lib, prec):
         assert rel_energy(E, ref) <= 1e-12
         assert np.abs(F - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max()
     else:
-        # every atom of a crystal repeats nearly the same arithmetic, so FP32 rounding is
-        # coherent across atoms instead of averaging out; on this random model with 48 eV
-        # atomic energies it reaches ~1.1e-6 (the named workloads stay below 1e-6)
-        ref = oracle_lib.evaluate(fp32_params(m), s, T=3, skin=1.0)
-        check_fp32(*_eval(rn, ctx, m, s, 3, prec, skin=1.0), ref, "cu 5x5x4", tol_e=2e-6)
+        # every atom of a crystal repeats nearly the same arithmetic, so its FP32 rounding is
+        # coherent across atoms instead of averaging out (a systematic rounding, such as that of
+        # 1/r_c in the cutoff argument, shows here first)
+        ref = oracle_lib.evaluate(m, s, T=3, skin=1.0)
+        check_fp32(*_eval(rn, ctx, m, s, 3, prec, skin=1.0), ref, "cu 5x5x4")
 
 
 # Every compiled (L, K) pair, 1 to 4 hidden layers, and hidden widths on the fused NN kernels
@@ -207,11 +201,8 @@ def test_model_shapes(rn, ctx, oracle_lib, shape, prec):
         assert re <= 1e-2 * depth
         assert rf <= 2e-2 * depth
     else:
-        # random models: a single hidden layer fed by 234 density features contracts them in
-        # one FP32 sum per unit, so the energy's rounding reaches ~1.2e-6 (the bound of the
-        # random Cu model); forces and virial keep the common bounds
-        ref = oracle_lib.evaluate(fp32_params(m), s, T=3, skin=0.5)
-        check_fp32(*_eval(rn, ctx, m, s, 3, prec, skin=0.5, decomp=(2, 1, 1)), ref, shape, tol_e=2e-6)
+        ref = oracle_lib.evaluate(m, s, T=3, skin=0.5)
+        check_fp32(*_eval(rn, ctx, m, s, 3, prec, skin=0.5, decomp=(2, 1, 1)), ref, shape)
 
 
 def test_new_model_on_same_system_gets_its_own_plan(rn, ctx, oracle_lib):
@@ -387,9 +378,11 @@ def test_cu100800_full_size_against_oracle_golden(rn, ctx, prec):
     Fref = np.array(g["sample_forces"]).reshape(-1, 3)
     frms = g["force_rms"]
     tol_e, tol_f = (1e-12, 1e-10) if prec == "fp64" else (1e-6, 1e-5)
-    print(prec, "E", E, "ref", g["energy"], "relE", abs(E - g["energy"]) / den, flush=True)
+    print(prec, "E", E, "ref", g["energy"], "relE", abs(E - g["energy"]) / den, "max force component",
+          np.abs(Fs - Fref).max() / np.abs(Fref).max(), flush=True)
     assert abs(E - g["energy"]) / den <= tol_e
     assert np.sqrt(((Fs - Fref) ** 2).mean()) / frms <= tol_f
+    assert np.abs(Fs - Fref).max() <= tol_f * np.abs(Fref).max()
     np.testing.assert_allclose(ae.cpu().numpy()[idx], g["sample_atom_energy"], rtol=0,
                                atol=(tol_f * 10) * np.abs(g["sample_atom_energy"]).max())
     Wref = np.array(g["virial"]).reshape(3, 3)
@@ -482,6 +475,39 @@ def test_water1207296_decomposed_equals_whole_fp64(rn, ctx, T):
                                atol=1e-10 * np.abs(b[2]).max())
 
 
+@pytest.mark.parametrize("T", [2, 3])
+def test_water1207296_fp32_decomposed_against_oracle_golden(rn, ctx, T):
+    """The FP32 path on the 1,207,296-atom water box split 2x2x2 (the decomposed workload
+    that the throughput figures quote) against the oracle's stored FP64 values: energy within
+    1e-6 relative, the 256 sampled forces within 1e-5 of the force scale (RMSE and every
+    component)."""
+    import torch
+    from tests.golden.make_golden import positions_digest
+    g = _golden("water1207296", T)
+    w = synth.workload("water1207296")
+    s, m = w["system"], w["model"]
+    assert positions_digest(s["pos"]) == g["positions_sha256"]
+    plan = rn.Plan(ctx, rn.Model(m), s, T=T, precision="fp32", decomp=(2, 2, 2), skin=w["skin"])
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
+    e = torch.zeros((), dtype=torch.float64, device="cuda")
+    F = torch.zeros_like(pos)
+    plan.forward(pos, e)
+    plan.backward(F)
+    torch.cuda.synchronize()
+    E = float(e)
+    idx = np.array(g["sample_index"])
+    Fs = F.cpu().numpy()[idx]
+    Fref = np.array(g["sample_forces"]).reshape(-1, 3)
+    den = max(abs(g["energy"]), g["sum_abs_atom_energy"])
+    print("water 2x2x2 fp32 T=%d: rel E %.2e (|dE|/|E| %.2e), sampled force RMSE/RMS %.2e, max component %.2e"
+          % (T, abs(E - g["energy"]) / den, abs(E - g["energy"]) / abs(g["energy"]),
+             np.sqrt(((Fs - Fref) ** 2).mean()) / g["force_rms"], np.abs(Fs - Fref).max() / np.abs(Fref).max()),
+          flush=True)
+    assert abs(E - g["energy"]) <= 1e-6 * den
+    assert np.sqrt(((Fs - Fref) ** 2).mean()) <= 1e-5 * g["force_rms"]
+    assert np.abs(Fs - Fref).max() <= 1e-5 * np.abs(Fref).max()
+
+
 def _degenerate_cases():
     rng = np.random.default_rng(51)
     one_open = dict(pos=np.array([[3.0, 4.0, 5.0]]), species=np.array([1], np.int32), cell=np.eye(3) * 20.0,
@@ -514,8 +540,7 @@ def test_degenerate_systems(rn, ctx, oracle_lib, case, prec):
     s = _degenerate_cases()[case]
     m = models.water_model(T_max=3, seed=51)
     skin = 2.0
-    mr = m if prec == "fp64" else fp32_params(m)
-    ref = oracle_lib.evaluate(mr, s, T=3, skin=skin)
+    ref = oracle_lib.evaluate(m, s, T=3, skin=skin)
     E, F, W = _eval(rn, ctx, m, s, 3, prec, skin=skin)
     tol_e, tol_f = (1e-12, 1e-10) if prec == "fp64" else (1e-6, 1e-5)
     assert rel_energy(E, ref) <= tol_e, (E, ref["energy"])
