@@ -181,6 +181,12 @@ reann_status reann_plan_backward(reann_plan *p, const double *d_grad_energy, dou
                                  void *hip_stream);
 void reann_plan_free(reann_plan *p);
 
+/* Number of forwards run on the plan so far (0 before the first).  A backward always uses the
+ * state of the plan's most recent forward; a caller that keeps several forwards alive (e.g. an
+ * autograd graph) records the number after each forward and compares it before the backward
+ * to detect that another forward has replaced that state.  gen: host scalar. */
+reann_status reann_plan_generation(const reann_plan *p, uint64_t *gen);
+
 /* Intermediate values of the last forward, for layer-by-layer checks, copied to host in
  * the caller's atom order:  what = 0: orbital sums S^t [n][NL][K] (NL = (L+1)(L+2)(L+3)/6,
  * components ordered by l, then lx descending, then ly descending); 1: messages c^t [n][K];

@@ -77,6 +77,7 @@ _SIGS = {
     "reann_plan_free": (None, [_vp]),
     "reann_plan_get": (_i32, [_vp, _i32, _i32, _vp]),
     "reann_plan_set_timing": (_i32, [_vp, _i32]),
+    "reann_plan_generation": (_i32, [_vp, C.POINTER(C.c_uint64)]),
     "reann_plan_timing": (_i32, [_vp, _vp, _vp, C.POINTER(_i64)]),
     "reann_server_create": (_i32, [_vp, C.POINTER(_ServerOpts), C.POINTER(_vp)]),
     "reann_server_set_masses": (_i32, [_vp, _vp]),
@@ -343,6 +344,12 @@ class Plan:
             _require_device_f64(virial, (3, 3))
             w = virial.data_ptr()
         check(load().reann_plan_backward(self.handle, g, forces.data_ptr(), w, self._stream(stream)))
+
+    def generation(self) -> int:
+        """Number of forwards run on this plan (a backward uses the latest one's state)."""
+        g = C.c_uint64(0)
+        check(load().reann_plan_generation(self.handle, C.byref(g)))
+        return g.value
 
     def get(self, what: str, t: int = 0) -> np.ndarray:
         """Intermediates of the last forward in caller atom order: 'S' [n,NL,K], 'c' [n,K],

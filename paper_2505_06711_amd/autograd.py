@@ -7,7 +7,9 @@ from __future__ import annotations
 
 import torch
 
-from ._binding import Plan
+from ._binding import Plan, ReannError
+
+REANN_E_STATE = -7
 
 
 class _REANNEnergy(torch.autograd.Function):
@@ -17,12 +19,19 @@ class _REANNEnergy(torch.autograd.Function):
         energy = torch.empty((), dtype=torch.float64, device=pos.device)
         plan.forward(pos, energy)
         ctx.plan = plan
+        # the plan keeps the state of its latest forward only; the backward checks that no
+        # other forward has run on it since this one
+        ctx.generation = plan.generation()
         ctx.n = pos.shape[0]
         ctx.device = pos.device
         return energy
 
     @staticmethod
     def backward(ctx, grad_energy: torch.Tensor):
+        if ctx.plan.generation() != ctx.generation:
+            raise ReannError(REANN_E_STATE, "backward of a REANN energy whose plan has run another forward since: "
+                                            "the plan holds only its latest forward's state (use one plan per "
+                                            "energy that is kept for a backward)")
         g = grad_energy.detach().to(torch.float64).contiguous().reshape(())
         forces = torch.empty((ctx.n, 3), dtype=torch.float64, device=ctx.device)
         ctx.plan.backward(forces, grad_energy=g)
@@ -31,5 +40,6 @@ class _REANNEnergy(torch.autograd.Function):
 
 def reann_energy(pos: torch.Tensor, plan: Plan) -> torch.Tensor:
     """Total energy (eV, float64 scalar tensor) of the plan's system at ``pos``; its
-    gradient w.r.t. ``pos`` is -F.  One backward per forward."""
+    gradient w.r.t. ``pos`` is -F.  A backward must follow the plan's latest forward: a
+    backward after another forward on the same plan raises ReannError (REANN_E_STATE)."""
     return _REANNEnergy.apply(pos, plan)

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <sstream>
@@ -505,6 +506,13 @@ reann_status reann_plan_get(reann_plan *p, int32_t what, int32_t t, double *host
         REQUIRE(p && host_out, "NULL argument");
         HIP_OK(hipSetDevice(p->impl.ctx->device));
         p->impl.get(what, t, host_out);
+    });
+}
+
+reann_status reann_plan_generation(const reann_plan *p, uint64_t *gen) {
+    return guarded([&] {
+        REQUIRE(p && gen, "NULL argument");
+        *gen = p->impl.generation;
     });
 }
 

@@ -503,6 +503,7 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
     sum_rows(st, Epart.as<double>(), nb, 1, d_energy, false);
     mark(st, PH_OTHER);
     have_forward = true;
+    ++generation;
 }
 
 void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipStream_t st) {

@@ -110,6 +110,7 @@ struct Plan {
     DevBuf fp8s, fp8tmp;      // per-call activation scale for FP8 products
     OpType op = OpType::F32;
     bool have_forward = false;
+    uint64_t generation = 0;   // forwards launched on this plan (reann_plan_generation)
     bool timing = false;
     // events recorded at phase boundaries while timing is on; intervals are attributed to
     // the phase named by the event that closes them (phase -1: not attributed)

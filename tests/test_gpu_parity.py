@@ -550,3 +550,27 @@ def test_degenerate_systems(rn, ctx, oracle_lib, case, prec):
     assert np.abs(W - ref["virial"]).max() <= (1e-10 if prec == "fp64" else 1e-4) * max(wmax, 1.0)
     if case in ("one_atom_open", "one_atom_14A_box", "pair_in_skin_only"):
         assert np.abs(F).max() == 0.0 and np.abs(W).max() == 0.0
+
+
+def test_autograd_backward_after_another_forward_is_refused(rn, ctx, oracle_lib):
+    """A plan keeps only its latest forward's state: the backward of an energy whose plan has
+    run another forward since raises REANN_E_STATE instead of returning the other
+    configuration's forces; the latest energy's backward still matches the oracle."""
+    import torch
+    from paper_2505_06711_amd.autograd import reann_energy
+    s = systems.water_box(seed=38)
+    m = models.water_model(T_max=2, seed=38)
+    plan = rn.Plan(ctx, rn.Model(m), s, T=2, precision="fp64")
+    p1 = torch.tensor(s["pos"], dtype=torch.float64, device="cuda", requires_grad=True)
+    moved = s["pos"] + 0.05
+    p2 = torch.tensor(moved, dtype=torch.float64, device="cuda", requires_grad=True)
+    e1 = reann_energy(p1, plan)
+    e2 = reann_energy(p2, plan)
+    with pytest.raises(rn.ReannError) as err:
+        e1.backward()
+    assert err.value.status == -7
+    e2.backward()
+    torch.cuda.synchronize()
+    ref = oracle_lib.evaluate(m, dict(s, pos=moved), T=2)
+    np.testing.assert_allclose(-p2.grad.cpu().numpy(), ref["forces"], rtol=0,
+                               atol=1e-10 * np.abs(ref["forces"]).max())
