@@ -160,6 +160,25 @@ reann_status reann_energy_forces(reann_ctx *ctx, const reann_model *m, const dou
                                  int64_t n, const double cell[9], const int32_t pbc[3], double r_c, int32_t T,
                                  const reann_opts *opt, double *energy, double *forces, double *virial);
 
+/* reann_energy_forces_noalloc: reann_energy_forces for callers that cannot allocate device
+ * memory (code that must not call hipMalloc, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and host-pointer conventions, but no device allocation
+ * and no caching between calls: every device buffer of the evaluation (positions, neighbour
+ * list, layer state, adjoint records, outputs) is carved from a static device array of 64 MiB
+ * per GPU that the library holds from its load until the process ends.  That bounds the system
+ * size: roughly 3,500 atoms at the Cu workload's shapes (r_c 6 A + 1 A skin, K = 12, T = 3) and
+ * ~10,000 water atoms at r_c = 5 A, K = 8; larger inputs return REANN_E_CAPACITY.  Each call
+ * builds the neighbour list afresh.  The model's device copies must already exist for this GPU
+ * and precision (created by an earlier reann_energy_forces or reann_plan_create with the same
+ * model), else REANN_E_STATE.  All calls on one GPU share its array: the library serialises
+ * them within the process, and the array keeps the last call's contents (every buffer is
+ * rewritten or cleared before use).  Calls on one GPU from several processes, or overlapping
+ * work that another library places in the same array, race. */
+reann_status reann_energy_forces_noalloc(reann_ctx *ctx, const reann_model *m, const double *pos,
+                                         const int32_t *species, int64_t n, const double cell[9],
+                                         const int32_t pbc[3], double r_c, int32_t T, const reann_opts *opt,
+                                         double *energy, double *forces, double *virial);
+
 /* Device-pointer path (used by the PyTorch autograd binding).  A plan fixes the system
  * (n, species, cell, pbc), the model, T and the options.  species is host [n].
  *   reann_plan_forward:  d_pos device FP64 [n][3]; writes d_energy (device FP64 scalar) and,

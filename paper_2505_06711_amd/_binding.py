@@ -71,6 +71,8 @@ _SIGS = {
     "reann_nlist_info": (_i32, [_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
     "reann_nlist_free": (None, [_vp]),
     "reann_energy_forces": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _d, _i32, C.POINTER(_Opts), _vp, _vp, _vp]),
+    "reann_energy_forces_noalloc": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _d, _i32, C.POINTER(_Opts), _vp, _vp,
+                                           _vp]),
     "reann_plan_create": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _i32, C.POINTER(_Opts), C.POINTER(_vp)]),
     "reann_plan_forward": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "reann_plan_backward": (_i32, [_vp, _vp, _vp, _vp, _vp]),
@@ -277,8 +279,9 @@ def build_neighbors(ctx: Context, system: dict, r_c: float, skin: float = 0.0, d
 
 
 def energy_forces(ctx: Context, model: Model, system: dict, T: int, precision="fp32", decomp=(1, 1, 1),
-                  skin: float = 0.0, forces: bool = True):
-    """Host-pointer evaluation: returns (E, F[n,3] or None, W[3,3] or None)."""
+                  skin: float = 0.0, forces: bool = True, noalloc: bool = False):
+    """Host-pointer evaluation: returns (E, F[n,3] or None, W[3,3] or None).  noalloc=True
+    calls reann_energy_forces_noalloc (no device allocation; bounded system size)."""
     pos = _f64(system["pos"])
     spec = _i32a(system["species"])
     cell = _f64(system["cell"], (9,))
@@ -288,8 +291,9 @@ def energy_forces(ctx: Context, model: Model, system: dict, T: int, precision="f
     F = np.zeros((n, 3)) if forces else None
     W = np.zeros(9) if forces else None
     o = _opts(precision, decomp, skin)
-    check(load().reann_energy_forces(ctx.handle, model.handle, _p(pos), _p(spec), n, _p(cell), _p(pbc),
-                                     float(model.r_c), int(T), C.byref(o), _p(E), _p(F), _p(W)))
+    fn = load().reann_energy_forces_noalloc if noalloc else load().reann_energy_forces
+    check(fn(ctx.handle, model.handle, _p(pos), _p(spec), n, _p(cell), _p(pbc), float(model.r_c), int(T),
+             C.byref(o), _p(E), _p(F), _p(W)))
     return float(E[0]), F, (W.reshape(3, 3) if forces else None)
 
 

@@ -455,6 +455,88 @@ reann_status reann_energy_forces(reann_ctx *ctx, const reann_model *m, const dou
     });
 }
 
+// ---------------------------------------------------------- allocation-free --
+// Device memory of reann_energy_forces_noalloc: one static array per GPU, held from the load of
+// the library's code object on that GPU until the process ends.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+struct ScratchSlot {
+    std::mutex mu;            // one call at a time per GPU: every call shares the array
+    char *ptr = nullptr;      // device address of `scratch` on this GPU
+};
+std::mutex g_scratch_mu;
+std::map<int, std::unique_ptr<ScratchSlot>> g_scratch;
+
+// The slot of `device` (current device), resolving the array's device address on the first
+// call for that device.  In host code `scratch` names a host-side stand-in, never usable as a
+// device address: every kernel and copy gets `ptr`.
+ScratchSlot &scratch_slot(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto &slot = g_scratch[device];
+    if (!slot) {
+        auto s = std::make_unique<ScratchSlot>();
+        void *p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(REANN_E_DEVICE, "no device address for the static scratch array");
+        s->ptr = static_cast<char *>(p);
+        slot = std::move(s);
+    }
+    return *slot;
+}
+
+// Installs an arena over the scratch for the current thread; uninstalls it on scope exit.
+struct ArenaScope {
+    Arena a;
+    ArenaScope(char *base, size_t cap) { a.base = base; a.cap = cap; a.used = 0; current_arena() = &a; }
+    ~ArenaScope() { current_arena() = nullptr; }
+};
+}  // namespace
+
+reann_status reann_energy_forces_noalloc(reann_ctx *ctx, const reann_model *m, const double *pos,
+                                         const int32_t *species, int64_t n, const double cell[9], const int32_t pbc[3],
+                                         double r_c, int32_t T, const reann_opts *opt, double *energy, double *forces,
+                                         double *virial) {
+    return guarded([&] {
+        REQUIRE(ctx && pos && energy, "NULL argument");
+        check_eval_args(m, pos, species, n, cell, pbc, T, opt);
+        REQUIRE(r_c == m->impl.r_c, "r_c must equal the model's cutoff");
+        Ctx &c = ctx->impl;
+        HIP_OK(hipSetDevice(c.device));
+        const int prec = opt ? opt->precision : REANN_FP32;
+        if (!const_cast<Model &>(m->impl).on_device(c.device, prec))
+            fail(REANN_E_STATE, "reann_energy_forces_noalloc: the model's weights are not on this GPU at this "
+                                "precision yet (run one reann_energy_forces or reann_plan_create with the same model, "
+                                "GPU and precision first; those allocate them)");
+        ScratchSlot &slot = scratch_slot(c.device);
+        std::lock_guard<std::mutex> lk(slot.mu);
+        hipStream_t st = c.stream;
+        try {
+            ArenaScope arena(slot.ptr, kScratchBytes);
+            Plan p;   // every device buffer below comes from the arena
+            p.init(&c, const_cast<Model *>(&m->impl), species, n, cell, pbc, T, opt);
+            DevBuf bpos, bF, bsc;
+            double *dpos = static_cast<double *>(bpos.ensure(n * 24));
+            double *dF = static_cast<double *>(bF.ensure(n * 24));
+            double *dsc = static_cast<double *>(bsc.ensure(16 * 8));
+            HIP_OK(hipMemcpyAsync(dpos, pos, n * 24, hipMemcpyHostToDevice, st));
+            p.forward(dpos, dsc, nullptr, st);
+            if (forces || virial) p.backward(nullptr, dF, dsc + 1, st);
+            double h[10];
+            HIP_OK(hipMemcpyAsync(h, dsc, 10 * 8, hipMemcpyDeviceToHost, st));
+            if (forces) HIP_OK(hipMemcpyAsync(forces, dF, n * 24, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            *energy = h[0];
+            if (virial) std::memcpy(virial, h + 1, 9 * 8);
+        } catch (...) {
+            // work already queued may still write the scratch: drain it before the next call
+            (void)hipStreamSynchronize(st);
+            throw;
+        }
+    });
+}
+
 reann_status reann_plan_create(reann_ctx *ctx, const reann_model *m, const int32_t *species, int64_t n,
                                const double cell[9], const int32_t pbc[3], int32_t T, const reann_opts *opt,
                                reann_plan **out) {

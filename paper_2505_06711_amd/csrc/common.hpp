@@ -32,29 +32,58 @@ inline void hip_check(hipError_t e, const char *what, const char *file, int line
 #define HIP_OK(x) ::reann::hip_check((x), #x, __FILE__, __LINE__)
 #define LAUNCH_OK(name) ::reann::hip_check(hipGetLastError(), name, __FILE__, __LINE__)
 
+// Bump allocator over device memory the library does not allocate (the static scratch of the
+// allocation-free entry point).  While one is installed on a thread, every DevBuf that grows on
+// that thread takes its memory from it, 256-byte aligned, instead of hipMalloc, and never frees
+// it; running out throws REANN_E_CAPACITY.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+};
+inline Arena *&current_arena() {
+    static thread_local Arena *a = nullptr;
+    return a;
+}
+
 // Owning device allocation that only grows.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = true;   // false: memory of an Arena, not freed here
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned) { o.p = nullptr; o.bytes = 0; }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; bytes = o.bytes; owned = o.owned;
+            o.p = nullptr; o.bytes = 0;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        owned = true;
     }
     void *ensure(size_t n) {
         if (n == 0) n = 256;
         if (n > bytes) {
             release();
-            HIP_OK(hipMalloc(&p, n));
+            if (Arena *a = current_arena()) {
+                const size_t off = (a->used + 255) & ~(size_t)255;
+                if (off > a->cap || n > a->cap - off)
+                    throw Error(REANN_E_CAPACITY, "the evaluation needs more device memory than the " +
+                                                      std::to_string(a->cap >> 20) + " MiB of static scratch");
+                p = a->base + off;
+                a->used = off + n;
+                owned = false;
+            } else {
+                HIP_OK(hipMalloc(&p, n));
+            }
             bytes = n;
         }
         return p;

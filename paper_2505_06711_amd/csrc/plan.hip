@@ -119,6 +119,15 @@ const MfmaSet &Model::mfma(int device, hipStream_t st, bool energy, OpType op) {
     return *slot;
 }
 
+bool Model::on_device(int device, int prec) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = dev.find(device);
+    if (it == dev.end()) return false;
+    if (prec == REANN_FP64) return true;
+    const int op = (int)(prec == REANN_BF16 ? OpType::BF16 : (prec == REANN_FP8 ? OpType::FP8 : OpType::F32));
+    return it->second->mf[0][op] && it->second->mf[1][op];
+}
+
 EdgeConsts Model::edge_consts() const {
     EdgeConsts e{};
     for (int m = 0; m < K; ++m) {

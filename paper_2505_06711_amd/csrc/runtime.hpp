@@ -61,6 +61,8 @@ struct Model {
     DeviceWeights &weights(int device, hipStream_t st);
     // matrix-core operands of the message (energy = false) or energy NNs for `op`
     const MfmaSet &mfma(int device, hipStream_t st, bool energy, OpType op);
+    // whether the device copies an evaluation at `prec` reads already exist on `device`
+    bool on_device(int device, int prec);
     EdgeConsts edge_consts() const;
     DensityConsts density_consts() const;
 };
