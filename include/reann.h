@@ -262,7 +262,27 @@ typedef struct {
     int32_t device;
     double thermostat_K;
     double thermostat_tau_fs;
+    int32_t decomp[3];       /* subdomains per axis for every system ({0,0,0} or {1,1,1} = whole
+                                system), as in reann_opts: each system is evaluated split, with the
+                                per-layer ghost exchange, and every skin-rule rebuild reassigns its
+                                atoms to subdomains by their current positions (atom migration) */
+    int32_t thermostat;      /* REANN_THERMO_BERENDSEN or REANN_THERMO_CSVR (used when
+                                thermostat_K > 0 and thermostat_tau_fs > 0)                     */
+    uint64_t seed;           /* CSVR: seed of each system's random stream (mixed with its id)   */
 } reann_server_opts;
+
+/* Thermostats of REANN_REQ_VV_STEP (applied at the end of the step, from the kinetic energy K
+ * after it, N_f = 3 n, K_0 = N_f k_B thermostat_K / 2, c = exp(-dt / thermostat_tau_fs)):
+ *  BERENDSEN  v *= sqrt(1 + (dt / tau)(K_0 / K - 1))   (Berendsen et al., J. Chem. Phys. 81, 3684
+ *             (1984)); relaxes K to K_0 but suppresses its fluctuations, so it does not sample the
+ *             canonical ensemble.
+ *  CSVR       stochastic velocity rescaling (Bussi, Donadio and Parrinello, J. Chem. Phys. 126,
+ *             014101 (2007)): v *= sqrt(K' / K) with
+ *             K' = K + (1 - c)(K_0 (R^2 + S) / N_f - K) + 2 R sqrt(c (1 - c) K K_0 / N_f),
+ *             R ~ N(0, 1) and S ~ chi^2 with N_f - 1 degrees of freedom drawn on the host from the
+ *             system's seeded stream; samples the canonical (NVT) ensemble. */
+#define REANN_THERMO_BERENDSEN 0
+#define REANN_THERMO_CSVR 1
 
 #define REANN_REQ_EVAL 0      /* evaluate E, F, W at the given positions (pos required)        */
 #define REANN_REQ_VV_STEP 1   /* one velocity-Verlet step of dt_fs (pos ignored), then E, F, W  */
@@ -283,6 +303,8 @@ typedef struct {
     reann_status status;      /* status of the request itself                              */
     double kinetic;           /* REANN_REQ_VV_STEP: kinetic energy (eV) of the velocities after
                                  the step (after any rescaling); 0 for REANN_REQ_EVAL        */
+    double *velocities;       /* caller-owned host [n][3] (A/fs), or NULL: the system's velocities
+                                 after the request (after any rescaling)                     */
 } reann_result;
 
 reann_status reann_server_create(const reann_model *m, const reann_server_opts *opt, reann_server **out);

@@ -43,7 +43,8 @@ class _Opts(C.Structure):
 class _ServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_batch_atoms", C.c_int64), ("precision", C.c_int32),
                 ("T", C.c_int32), ("skin", C.c_double), ("use_graph", C.c_int32), ("device", C.c_int32),
-                ("thermostat_K", C.c_double), ("thermostat_tau_fs", C.c_double)]
+                ("thermostat_K", C.c_double), ("thermostat_tau_fs", C.c_double), ("decomp", C.c_int32 * 3),
+                ("thermostat", C.c_int32), ("seed", C.c_uint64)]
 
 
 class _Request(C.Structure):
@@ -53,7 +54,7 @@ class _Request(C.Structure):
 class _Result(C.Structure):
     _fields_ = [("energy", C.c_double), ("virial", C.c_double * 9), ("forces", C.c_void_p),
                 ("positions", C.c_void_p), ("t_submit_ns", C.c_int64), ("t_done_ns", C.c_int64),
-                ("status", C.c_int32), ("kinetic", C.c_double)]
+                ("status", C.c_int32), ("kinetic", C.c_double), ("velocities", C.c_void_p)]
 
 
 _vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
@@ -402,7 +403,7 @@ class Server:
 
     def __init__(self, model: Model, T: int, precision="bf16", skin: float = 1.0, hbm_budget_bytes: int = 0,
                  max_batch_atoms: int = 0, use_graph: bool = True, device: int = 0, thermostat_K: float = 0.0,
-                 thermostat_tau_fs: float = 0.0):
+                 thermostat_tau_fs: float = 0.0, decomp=(1, 1, 1), thermostat: str = "berendsen", seed: int = 0):
         lib = load()
         o = _ServerOpts()
         o.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -414,6 +415,10 @@ class Server:
         o.device = int(device)
         o.thermostat_K = float(thermostat_K)
         o.thermostat_tau_fs = float(thermostat_tau_fs)
+        for a in range(3):
+            o.decomp[a] = int(decomp[a])
+        o.thermostat = {"berendsen": 0, "csvr": 1}[thermostat]
+        o.seed = int(seed)
         h = _vp()
         check(lib.reann_server_create(model.handle, C.byref(o), C.byref(h)))
         self.handle = h
@@ -456,21 +461,23 @@ class Server:
     def submit_vv(self, sys_id: int, dt_fs: float) -> int:
         return self._submit(sys_id, REQ_VV_STEP, dt=dt_fs)
 
-    def poll(self, ticket: int, sys_id: int, forces: bool = True, positions: bool = False):
-        """None while pending; else a dict with energy, virial, forces, positions, kinetic
-        (eV, velocity-Verlet steps), latency_s."""
+    def poll(self, ticket: int, sys_id: int, forces: bool = True, positions: bool = False, velocities: bool = False):
+        """None while pending; else a dict with energy, virial, forces, positions, velocities,
+        kinetic (eV, velocity-Verlet steps), latency_s."""
         n = self.n_atoms[sys_id]
         res = _Result()
         F = np.zeros((n, 3)) if forces else None
         P = np.zeros((n, 3)) if positions else None
+        V = np.zeros((n, 3)) if velocities else None
         res.forces = None if F is None else F.ctypes.data
         res.positions = None if P is None else P.ctypes.data
+        res.velocities = None if V is None else V.ctypes.data
         st = load().reann_poll(self.handle, C.c_uint64(ticket), C.byref(res))
         if st == PENDING:
             return None
         check(st)
         return dict(energy=res.energy, virial=np.array(res.virial[:]).reshape(3, 3), forces=F, positions=P,
-                    kinetic=res.kinetic, latency_s=(res.t_done_ns - res.t_submit_ns) * 1e-9, t_done_ns=res.t_done_ns)
+                    velocities=V, kinetic=res.kinetic, latency_s=(res.t_done_ns - res.t_submit_ns) * 1e-9, t_done_ns=res.t_done_ns)
 
     def stats(self) -> dict:
         keys = ("admission_rounds", "completed", "atoms", "graph_replays", "deferred", "resident_bytes",

@@ -19,6 +19,7 @@
 #include <list>
 #include <map>
 #include <mutex>
+#include <random>
 #include <thread>
 
 #include "runtime.hpp"
@@ -57,11 +58,13 @@ constexpr int kKeBlock = 256;
 // Kinetic energy K = (1/2) sum m v^2 of one system in a fixed order: per-block partial sums of
 // m v^2 over consecutive components (a tree in LDS), then one block sums the partials in
 // block order.  The blocks also take the largest velocity and acceleration components
-// (|v_c| and |F_c / m| in A/fs and A/fs^2).  The final block forms the Berendsen factor
-// lambda = sqrt(1 + (dt / tau)(T0 / T - 1)), T = 2 K / (3 n k_B), when T0 > 0 and tau > 0
-// (else 1), and writes aux[0] = lambda and, to the result head, lambda^2 K (eV: the kinetic
-// energy after the rescaling that k_vv_post applies), the squared largest displacement
-// since the list was built (aux[1], from max_displacement2), lambda max|v_c| and max|a_c|.
+// (|v_c| and |F_c / m| in A/fs and A/fs^2).  When T0 > 0 and tau > 0 the final block forms the
+// thermostat's velocity factor lambda (else 1): Berendsen, lambda^2 = 1 + (dt / tau)(T0 / T - 1)
+// with T = 2 K / (3 n k_B); CSVR, lambda^2 = K' / K with K' the kinetic energy resampled from the
+// host-drawn normal r1 and chi-square s (see include/reann.h).  It writes aux[0] = lambda and,
+// to the result head, lambda^2 K (eV: the kinetic energy after the rescaling that k_vv_post
+// applies), the squared largest displacement since the list was built (aux[1], from
+// max_displacement2), lambda max|v_c| and max|a_c|.
 constexpr int kAuxDisp = 1;      // max_displacement2 output and its partials (<= 1025 values)
 constexpr int kAuxKe = 1100;     // kinetic partials, 3 per block
 
@@ -95,6 +98,7 @@ __global__ __launch_bounds__(kKeBlock) void k_ke_part(int64_t n3, const int32_t 
 }
 
 __global__ __launch_bounds__(kKeBlock) void k_ke_final(int64_t n, int nb, double dt, double T0, double tau,
+                                                        int kind, double r1, double s_chi2,
                                                         double *__restrict__ aux, double *__restrict__ head) {
     __shared__ double sh[3][kKeBlock];
     const double *part = aux + kAuxKe;
@@ -118,8 +122,16 @@ __global__ __launch_bounds__(kKeBlock) void k_ke_final(int64_t n, int nb, double
         const double K = 0.5 * sh[0][0] / kAccel;   // amu A^2 / fs^2 -> eV
         double lam2 = 1.0;
         if (T0 > 0.0 && tau > 0.0 && K > 0.0) {
-            const double Tcur = 2.0 * K / (3.0 * (double)n * kBoltzmann);
-            lam2 = fmax(0.0, 1.0 + dt / tau * (T0 / Tcur - 1.0));
+            const double nf = 3.0 * (double)n;
+            if (kind == REANN_THERMO_CSVR) {
+                const double K0 = 0.5 * nf * kBoltzmann * T0, c = exp(-dt / tau);
+                const double Kn = K + (1.0 - c) * (K0 * (r1 * r1 + s_chi2) / nf - K) +
+                                  2.0 * r1 * sqrt(c * (1.0 - c) * K * K0 / nf);
+                lam2 = fmax(0.0, Kn / K);
+            } else {
+                const double Tcur = 2.0 * K / (nf * kBoltzmann);
+                lam2 = fmax(0.0, 1.0 + dt / tau * (T0 / Tcur - 1.0));
+            }
         }
         const double lam = sqrt(lam2);
         aux[0] = lam;
@@ -130,16 +142,21 @@ __global__ __launch_bounds__(kKeBlock) void k_ke_final(int64_t n, int nb, double
     }
 }
 
-// After a step: the new forces become the old ones, the positions go to the output block,
-// and (velocity-Verlet steps) the velocities take the factor aux[0].
+// After a step: the new forces become the old ones, the positions and velocities go to the
+// output block, and (velocity-Verlet steps, scale_v) the velocities first take the factor aux[0].
 __global__ void k_vv_post(int64_t n3, const double *__restrict__ F, double *__restrict__ Fold,
                           const double *__restrict__ x, double *__restrict__ xout, double *__restrict__ v,
-                          const double *__restrict__ aux) {
+                          double *__restrict__ vout, const double *__restrict__ aux, int scale_v) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n3) return;
     Fold[t] = F[t];
     xout[t] = x[t];
-    if (v) v[t] *= aux[0];
+    double vt = v[t];
+    if (scale_v) {
+        vt *= aux[0];
+        v[t] = vt;
+    }
+    vout[t] = vt;
 }
 
 __global__ void k_copy_d(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
@@ -157,9 +174,9 @@ struct Sys {
     bool have_forces = false;               // forces of the current positions are known
     // residency
     std::unique_ptr<Plan> plan;
-    // d_out = [E, W (9), K, d^2, vmax, amax, F (3n), positions (3n)]: the step writes E, W and
-    // F in place, the motion figures and positions are written after it, and one
-    // device-to-host copy returns the lot
+    // d_out = [E, W (9), K, d^2, vmax, amax, F (3n), positions (3n), velocities (3n)]: the step
+    // writes E, W and F in place, the motion figures, positions and velocities are written after
+    // it, and one device-to-host copy returns the lot
     DevBuf d_pos, d_vel, d_Fold, d_out, d_aux;   // d_aux: [lambda, displacement scratch, kinetic partials]
     // motion after the last velocity-Verlet step (largest displacement since the list was
     // built, largest velocity and acceleration components): bound the next step's
@@ -171,6 +188,8 @@ struct Sys {
     double *KE() { return d_out.as<double>() + 10; }
     double *F() { return d_out.as<double>() + kOutHead; }
     double *P() { return d_out.as<double>() + kOutHead + 3 * n; }
+    double *V() { return d_out.as<double>() + kOutHead + 6 * n; }
+    std::mt19937_64 rng;   // CSVR draws
     DArr<int32_t> d_spec;
     hipGraphExec_t graph = nullptr;
     int64_t graph_rebuilds = -1;   // plan rebuild count the graph was captured for
@@ -192,7 +211,7 @@ struct Req {
 
 struct Done {
     double energy = 0, virial[9]{}, kinetic = 0;
-    std::vector<double> forces, positions;
+    std::vector<double> forces, positions, velocities;
     int64_t t_submit = 0, t_done = 0;
     reann_status status = REANN_OK;
     std::string error;
@@ -204,7 +223,7 @@ struct Slot {
     bool active = false;
     Req req;
     Sys *sys = nullptr;
-    double *h_out = nullptr;          // pinned: energy, virial[9], forces [n][3], positions [n][3]
+    double *h_out = nullptr;          // pinned: the result head, forces, positions, velocities
     size_t h_cap = 0;
 };
 
@@ -297,10 +316,10 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
     reann_opts o{};
     o.precision = opt.precision;
     o.skin = opt.skin;
-    o.decomp[0] = o.decomp[1] = o.decomp[2] = 1;
+    for (int a = 0; a < 3; ++a) o.decomp[a] = opt.decomp[a] > 0 ? opt.decomp[a] : 1;
     p->init(&ctx, m, sy.species.data(), sy.n, sy.cell, sy.pbc, opt.T, &o);
     sy.d_pos.ensure(sy.n * 24); sy.d_vel.ensure(sy.n * 24); sy.d_Fold.ensure(sy.n * 24);
-    sy.d_out.ensure((kOutHead + 6 * sy.n) * 8);
+    sy.d_out.ensure((kOutHead + 9 * sy.n) * 8);
     sy.d_aux.ensure((size_t)(kAuxKe + 3 * grid_for(sy.n * 3, kKeBlock)) * 8);
     sy.motion_known = false;
     int32_t *ds = sy.d_spec.resize(sy.n);
@@ -382,7 +401,7 @@ bool reann_server::admit(Req &r) {
             return false;
         }
     }
-    const size_t need_host = (size_t)(kOutHead + 6 * sy.n) * 8;
+    const size_t need_host = (size_t)(kOutHead + 9 * sy.n) * 8;
     if (s->h_cap < need_host) {
         if (s->h_out) (void)hipHostFree(s->h_out);
         HIP_OK(hipHostMalloc((void **)&s->h_out, need_host, hipHostMallocDefault));
@@ -425,15 +444,21 @@ bool reann_server::admit(Req &r) {
         hipLaunchKernelGGL(k_ke_part, dim3(nb), dim3(kKeBlock), 0, st, n3, sy.d_spec.ptr(), d_minv.as<double>(),
                            sy.d_vel.as<double>(), sy.F(), aux + kAuxKe);
         LAUNCH_OK("k_ke_part");
+        // CSVR: one normal and one chi-square (N_f - 1 degrees of freedom) per step from the
+        // system's stream; drawn every step so that the stream does not depend on the thermostat
+        std::normal_distribution<double> nd(0.0, 1.0);
+        std::gamma_distribution<double> gd(0.5 * (3.0 * (double)sy.n - 1.0), 2.0);
+        const double r1 = nd(sy.rng), s_chi2 = sy.n * 3 > 1 ? gd(sy.rng) : 0.0;
         hipLaunchKernelGGL(k_ke_final, dim3(1), dim3(kKeBlock), 0, st, sy.n, nb, r.dt, opt.thermostat_K,
-                           opt.thermostat_tau_fs, aux, sy.KE());
+                           opt.thermostat_tau_fs, (int)opt.thermostat, r1, s_chi2, aux, sy.KE());
         LAUNCH_OK("k_ke_final");
     }
     hipLaunchKernelGGL(k_vv_post, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.F(), sy.d_Fold.as<double>(),
-                       sy.d_pos.as<double>(), sy.P(), vv ? sy.d_vel.as<double>() : nullptr, sy.d_aux.as<double>());
+                       sy.d_pos.as<double>(), sy.P(), sy.d_vel.as<double>(), sy.V(), sy.d_aux.as<double>(),
+                       vv ? 1 : 0);
     LAUNCH_OK("k_vv_post");
     sy.have_forces = true;
-    HIP_OK(hipMemcpyAsync(s->h_out, sy.d_out.p, (kOutHead + 2 * n3) * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(s->h_out, sy.d_out.p, (kOutHead + 3 * n3) * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipEventRecord(s->ev, st));
     sy.busy = true;
     sy.last_used = now_ns();
@@ -460,6 +485,7 @@ void reann_server::finish(Slot &s) {
     }
     d.forces.assign(s.h_out + kOutHead, s.h_out + kOutHead + n3);
     d.positions.assign(s.h_out + kOutHead + n3, s.h_out + kOutHead + 2 * n3);
+    d.velocities.assign(s.h_out + kOutHead + 2 * n3, s.h_out + kOutHead + 3 * n3);
     d.t_submit = s.req.t_submit;
     d.t_done = now_ns();
     sy.busy = false;
@@ -562,6 +588,10 @@ reann_status reann_server_create(const reann_model *m, const reann_server_opts *
         int nd = 0;
         HIP_OK(hipGetDeviceCount(&nd));
         if (o->device < 0 || o->device >= nd) fail(REANN_E_INVALID, "device index out of range");
+        for (int a = 0; a < 3; ++a)
+            if (o->decomp[a] < 0 || o->decomp[a] > kMaxSplit) fail(REANN_E_INVALID, "decomp must be in [0, 16]");
+        if (o->thermostat != REANN_THERMO_BERENDSEN && o->thermostat != REANN_THERMO_CSVR)
+            fail(REANN_E_INVALID, "unknown thermostat");
         HIP_OK(hipSetDevice(o->device));
         auto s = std::make_unique<reann_server>();
         s->m = const_cast<Model *>(&m->impl);
@@ -615,7 +645,7 @@ reann_status reann_system_add(reann_server *s, const int32_t *species, int64_t n
         for (int64_t i = 0; i < 3 * n; ++i)
             if (!std::isfinite(pos[i]) || (vel && !std::isfinite(vel[i]))) fail(REANN_E_INVALID, "non-finite input");
         Geom g{};
-        geom_init(g, cell, pbc, nullptr, s->m->r_c, s->opt.skin);   // validates the cell
+        geom_init(g, cell, pbc, s->opt.decomp, s->m->r_c, s->opt.skin);   // validates the cell and split
         auto sy = std::make_unique<Sys>();
         sy->n = n;
         sy->species.assign(species, species + n);
@@ -628,6 +658,7 @@ reann_status reann_system_add(reann_server *s, const int32_t *species, int64_t n
         if (s->estimate_bytes(*sy) > s->budget) fail(REANN_E_CAPACITY, "system larger than the server's HBM budget");
         std::lock_guard<std::mutex> lk(s->mu);
         sy->id = s->next_sys++;
+        sy->rng.seed(s->opt.seed ^ (0x9E3779B97F4A7C15ull * sy->id));
         *sys_id = sy->id;
         s->systems[sy->id] = std::move(sy);
     });
@@ -678,6 +709,8 @@ reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res) {
     std::memcpy(res->virial, d.virial, sizeof d.virial);
     if (res->forces && !d.forces.empty()) std::memcpy(res->forces, d.forces.data(), d.forces.size() * 8);
     if (res->positions && !d.positions.empty()) std::memcpy(res->positions, d.positions.data(), d.positions.size() * 8);
+    if (res->velocities && !d.velocities.empty())
+        std::memcpy(res->velocities, d.velocities.data(), d.velocities.size() * 8);
     res->t_submit_ns = d.t_submit;
     res->t_done_ns = d.t_done;
     res->kinetic = d.kinetic;

@@ -44,11 +44,12 @@ def wait(srv, ticket, sid, timeout=60.0, **kw):
         time.sleep(0.0005)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("use_graph", [True, False])
-def test_result_alone_equals_result_in_mix(rn, model_params, use_graph):
+def test_result_alone_equals_result_in_mix(rn, model_params, use_graph, prec):
     sys_list = mix(100, [300, 500, 2000, 96, 4000, 864, 1500, 200, 3000, 108])
     model = rn.Model(model_params)
-    srv = rn.Server(model, T=3, precision="fp32", skin=1.0, use_graph=use_graph)
+    srv = rn.Server(model, T=3, precision=prec, skin=1.0, use_graph=use_graph)
     ids = [srv.add_system(s) for s in sys_list]
     alone = wait(srv, srv.submit_eval(ids[2], sys_list[2]["pos"]), ids[2])
     tickets = [(srv.submit_eval(i, s["pos"]), i) for i, s in zip(ids, sys_list)]
@@ -67,19 +68,42 @@ def test_result_alone_equals_result_in_mix(rn, model_params, use_graph):
     srv.close()
 
 
-def test_server_matches_plan_path(rn, model_params):
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_server_matches_plan_path(rn, model_params, prec):
     sys_list = mix(200, [600, 1372])
     model = rn.Model(model_params)
     ctx = rn.Context(0)
-    srv = rn.Server(model, T=3, precision="fp32", skin=1.0, use_graph=True)
+    srv = rn.Server(model, T=3, precision=prec, skin=1.0, use_graph=True)
     for s in sys_list:
         sid = srv.add_system(s)
         # several replays of the same graph with eager work in between
         for rep in range(3):
             r = wait(srv, srv.submit_eval(sid, s["pos"]), sid)
-            E, F, W = rn.energy_forces(ctx, model, s, T=3, precision="fp32", skin=1.0)
+            E, F, W = rn.energy_forces(ctx, model, s, T=3, precision=prec, skin=1.0)
             assert r["energy"] == pytest.approx(E, rel=1e-12, abs=1e-12), rep
             np.testing.assert_allclose(r["forces"], F, rtol=0, atol=1e-9 * np.abs(F).max())
+
+
+def test_bf16_server_against_fp64_oracle(rn, model_params, oracle_lib):
+    """The serving precision (BF16 atomic-NN products) on a water box and an FCC crystal of the
+    serving mix, through the server's captured graphs, against the FP64 oracle: errors in
+    meV/atom and meV/A.  The bounds are sanity limits (a layout mistake gives errors of the
+    order of the energies themselves); the printed values are the measurement."""
+    sys_list = mix(250, [600, 1372])
+    srv = rn.Server(rn.Model(model_params), T=3, precision="bf16", skin=1.0, use_graph=True)
+    for s in sys_list:
+        sid = srv.add_system(s)
+        r = wait(srv, srv.submit_eval(sid, s["pos"]), sid)
+        ref = oracle_lib.evaluate(model_params, s, T=3, skin=1.0)
+        n = len(s["pos"])
+        de = abs(r["energy"] - ref["energy"]) / n * 1e3
+        frmse = np.sqrt(((r["forces"] - ref["forces"]) ** 2).mean()) * 1e3
+        frms = np.sqrt((ref["forces"] ** 2).mean())
+        print("serving bf16, %d atoms: |dE| = %.3f meV/atom (E/N = %.3f eV), force RMSE = %.2f meV/A "
+              "(force RMS %.3f eV/A)" % (n, de, ref["energy"] / n, frmse, frms), flush=True)
+        assert de / 1e3 <= 2e-2 * np.abs(ref["atom_energy"]).mean()
+        assert frmse / 1e3 <= 5e-2 * frms
+    srv.close()
 
 
 # Other model shapes through the server (its graphs capture the same kernels as the plan
