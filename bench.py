@@ -398,6 +398,42 @@ def decomposed_water(rn, torch, ctx, steps=10, warmup=2, Ts=(1, 2, 3, 4, 6)):
                 atom_steps_per_s_T3=t3["atom_steps_per_s"], steps_per_T=steps, tsweep=sw)
 
 
+def halo_ablation(rn, torch, ctx, exchange_rows, Ts=(1, 2, 3, 4), steps=3, warmup=1):
+    """The redundancy the per-layer exchange avoids (Sec. 2.2, Fig. 2): the 1,207,296-atom
+    water box split 2x2x2 evaluated by the extended-halo scheme (each subdomain an open cluster
+    of every copy within T (r_c + skin) of its box, recomputed at every layer, no exchange
+    between layers; paper_2505_06711_amd.halo) against the per-layer exchange at the same
+    split (`exchange_rows`, the decomposed_water sweep).  FP32, ms per energy+force+virial step."""
+    import synth
+    from paper_2505_06711_amd.halo import HaloEvaluator
+    w = synth.workload("water1207296")
+    s, m = w["system"], w["model"]
+    n = len(s["pos"])
+    model = rn.Model(m)
+    ex = {r["T"]: r["ms_per_step"] for r in exchange_rows}
+    rows = []
+    for T in Ts:
+        h = HaloEvaluator(ctx, model, m, s, T=T, precision="fp32", decomp=w["decomp"], skin=w["skin"])
+        h.device_inputs(torch)
+        for _ in range(1 + warmup):
+            h.step(torch)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            h.step(torch)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        rows.append(dict(T=T, halo_ms_per_step=round(ms, 3), exchange_ms_per_step=ex.get(T),
+                         halo_over_exchange=round(ms / ex[T], 3) if T in ex else None,
+                         cluster_atoms=h.cluster_atoms(), cluster_atoms_per_atom=round(h.cluster_atoms() / n, 3)))
+        print("halo ablation T=%d %.2f ms (%d cluster atoms)" % (T, ms, h.cluster_atoms()), file=sys.stderr, flush=True)
+        del h
+    return dict(workload=describe("water1207296", w), precision="fp32", scheme="extended halo T (r_c + skin), "
+                "every layer over the whole cluster, vs per-layer ghost exchange", rows=rows)
+
+
 def precision_ladder(rn, torch, ctx, w, name, steps=20, warmup=3):
     """The Cu workload with the atomic-NN products in FP32, BF16 and FP8 e4m3 (FP32
     accumulation): atom-steps/s and the errors against the FP64 oracle's stored energy and 256
@@ -566,6 +602,8 @@ def main():
         out["precision_ladder"] = precision_ladder(rn, torch, ctx, w, a.workload)
         print("bench: decomposed water", file=sys.stderr, flush=True)
         out["decomposed_water"] = decomposed_water(rn, torch, ctx)
+        print("bench: halo ablation", file=sys.stderr, flush=True)
+        out["halo_ablation"] = halo_ablation(rn, torch, ctx, out["decomposed_water"]["tsweep"]["rows"])
     if not a.no_serve:
         print("bench: MD-amortised run", file=sys.stderr, flush=True)
         out["md_amortised"] = md_amortised(rn, w, a.precision)

@@ -200,6 +200,13 @@ reann_status reann_plan_backward(reann_plan *p, const double *d_grad_energy, dou
                                  void *hip_stream);
 void reann_plan_free(reann_plan *p);
 
+/* Weights of the atomic energies in the plan's energy: E = sum_i w_i E_i, and the backward
+ * gives the gradient of that weighted sum (forces, virial).  w: host [n] in caller order,
+ * copied; NULL restores w_i = 1.  Atomic energies (d_atom_energy) stay unweighted.  Used to
+ * evaluate a subdomain together with copies of atoms it does not own, counting only its own
+ * atoms' energies (the extended-halo scheme, where each subdomain recomputes its halo). */
+reann_status reann_plan_set_energy_weights(reann_plan *p, const double *w);
+
 /* Number of forwards run on the plan so far (0 before the first).  A backward always uses the
  * state of the plan's most recent forward; a caller that keeps several forwards alive (e.g. an
  * autograd graph) records the number after each forward and compares it before the backward

@@ -55,6 +55,10 @@ def _load():
         lib.oracle_eval.argtypes = [C.POINTER(_Model), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.oracle_eval_halo.restype = C.c_int
+        lib.oracle_eval_halo.argtypes = [C.POINTER(_Model), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_int32,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         _lib = lib
     return _lib
 
@@ -90,6 +94,44 @@ def neighbors(system: dict, rcut: float, decomp=(1, 1, 1)):
 
 def n_lambda(L: int) -> int:
     return (L + 1) * (L + 2) * (L + 3) // 6
+
+
+def _model_struct(model):
+    keep = [np.ascontiguousarray(a, dtype=np.float64) for a in
+            (model.centres, model.alphas, model.c0, model.msg_blob, model.energy_blob)]
+    if keep[3].size == 0:
+        keep[3] = np.zeros(1)
+    mm = _Model(model.n_species, model.L, model.K, model.T_max, model.n_hidden, model.hidden, model.r_c,
+                model.ang_scale, model.energy_scale, *[_p(a) for a in keep])
+    return mm, keep
+
+
+def evaluate_halo(model, system: dict, T: int, skin: float = 0.0, decomp=(1, 1, 1), forces: bool = True,
+                  threads: int = 0) -> dict:
+    """The extended-halo scheme (every subdomain evaluates all copies within T (r_c + skin) of
+    its box, no exchange between layers; see oracle_eval_halo).  Returns energy, atom_energy,
+    forces, virial and work [T, 2] (rows and in-cutoff edges evaluated per layer, summed over
+    subdomains)."""
+    lib = _load()
+    pos, cell, pbc = _sys_arrays(system)
+    spec = np.ascontiguousarray(system["species"], dtype=np.int32)
+    n = pos.shape[0]
+    mm, keep = _model_struct(model)
+    E = np.zeros(1)
+    Ei = np.zeros(n)
+    F = np.zeros((n, 3)) if forces else None
+    W = np.zeros(9) if forces else None
+    work = np.zeros((T, 2), np.int64)
+    dec = np.ascontiguousarray(decomp, dtype=np.int32)
+    rc = lib.oracle_eval_halo(C.byref(mm), n, _p(pos), _p(spec), _p(cell), _p(pbc), float(skin), int(T), _p(dec),
+                              int(threads), _p(E), _p(Ei), _p(F), _p(W), _p(work))
+    if rc != 0:
+        raise ValueError("oracle_eval_halo failed: %d" % rc)
+    out = dict(energy=float(E[0]), atom_energy=Ei, work=work)
+    if forces:
+        out["forces"] = F
+        out["virial"] = W.reshape(3, 3)
+    return out
 
 
 def evaluate(model, system: dict, T: int, skin: float = 0.0, decomp=(1, 1, 1), naive: bool = False,

@@ -319,13 +319,14 @@ static int om_nmax(const om_geom *g, int a, double shell) {
     return g->per[a] ? (int)floor(shell / g->L[a]) + 1 : 0;
 }
 
-/* Locals and ghosts of subdomain p (reading R9), then the neighbour rows of its locals
-   (and of its ghosts when all_rows is set), each row sorted by ext index. */
-static int om_domain_build(const om_geom *g, const int32_t *species, int p, double rcut, int all_rows,
+/* Locals and ghosts of subdomain p (reading R9; ghost shell `gshell` + 1e-6 around the box,
+   gshell = rcut for the per-layer exchange), then the neighbour rows (cutoff rcut) of its
+   locals (and of its ghosts when all_rows is set), each row sorted by ext index. */
+static int om_domain_build(const om_geom *g, const int32_t *species, int p, double rcut, double gshell, int all_rows,
                            om_domain *D) {
     memset(D, 0, sizeof(*D));
     int pc[3] = { p / (g->P[1] * g->P[2]), (p / g->P[2]) % g->P[1], p % g->P[2] };
-    double shell = rcut + 1e-6;
+    double shell = gshell + 1e-6;
     int nm[3]; for (int a = 0; a < 3; ++a) nm[a] = om_nmax(g, a, shell);
     int64_t cap = 1024, n_ext = 0;
     D->gid = malloc(sizeof(int64_t) * cap); D->shift = malloc(sizeof(int32_t) * 3 * cap);
@@ -466,7 +467,7 @@ int64_t oracle_neighbors(int64_t n, const double *pos, const double *cell, const
     om_pair **rows = calloc(n > 0 ? n : 1, sizeof(om_pair *));
     for (int p = 0; p < np; ++p) {
         om_domain D;
-        rc = om_domain_build(&g, zero_spec, p, rcut, 0, &D);
+        rc = om_domain_build(&g, zero_spec, p, rcut, rcut, 0, &D);
         if (rc) { om_domain_free(&D); break; }
         for (int64_t i = 0; i < D.n_loc; ++i) {
             int64_t gi = D.gid[i], nb = D.row[i + 1] - D.row[i];
@@ -592,7 +593,7 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
     int np = g.P[0] * g.P[1] * g.P[2];
     double rcut = m->r_c + skin;
     om_domain *D = calloc(np, sizeof(om_domain));
-    for (int p = 0; p < np && rc == OM_OK; ++p) rc = om_domain_build(&g, species, p, rcut, naive, &D[p]);
+    for (int p = 0; p < np && rc == OM_OK; ++p) rc = om_domain_build(&g, species, p, rcut, rcut, naive, &D[p]);
     if (rc) goto done;
 
     /* per domain, per layer: messages of every ext atom; orbital sums of locals */
@@ -757,6 +758,162 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
 done:
     for (int p = 0; p < np; ++p) om_domain_free(&D[p]);
     free(D);
+    om_geom_free(&g);
+    return rc;
+}
+
+/* ------------------------------------------------- extended-halo scheme -- */
+
+/* Halo level of ext copy e of subdomain p: 0 for the locals, else the smallest k >= 1 such
+   that the copy lies within k rcut + 1e-6 of the box on every split or periodic axis (the shell
+   test of reading R9 with k rcut for r_c + skin).  A neighbour (distance < rcut) of a copy of
+   level k has level <= k + 1. */
+static int om_halo_level(const om_geom *g, const om_domain *D, int p, int64_t e, double rcut) {
+    if (e < D->n_loc) return 0;
+    int pc[3] = { p / (g->P[1] * g->P[2]), (p / g->P[2]) % g->P[1], p % g->P[2] };
+    for (int k = 1;; ++k) {
+        double s = k * rcut + 1e-6;
+        int in = 1;
+        for (int a = 0; a < 3; ++a) {
+            double y = D->pos[3 * e + a];
+            if (g->per[a] && !(y >= g->lo[a][pc[a]] - s && y < g->hi[a][pc[a]] + s)) in = 0;
+        }
+        if (in) return k;
+    }
+}
+
+/* Energy, forces and virial by the extended-halo scheme: the alternative to the per-layer
+ * exchange that the paper argues against (Sec. 2.2, Fig. 2(a): the receptive field of T layers
+ * reaches T r_c).  Each subdomain takes every copy within T (r_c + skin) of its box and runs the
+ * T layers with no exchange between them: layer t evaluates every copy of halo level at most
+ * T - 1 - t (those are the atoms whose layer-t output reaches a local's energy), reading its
+ * neighbours' layer-t messages from the same subdomain.  E_p sums the locals' atomic energies
+ * and E = sum_p E_p; the reverse sweep runs inside each subdomain over the same copies, the
+ * message adjoints staying there, and the copies' forces are summed onto their owners once at
+ * the end.  It must give the whole-system E, F and W; the cost is the redundant evaluation of
+ * the halo copies.
+ *   work (optional) [T][2]: rows evaluated and in-cutoff edges summed, per layer, over all
+ *   subdomains (the per-layer exchange evaluates n rows and the locals' edges per layer). */
+int oracle_eval_halo(const om_model *m, int64_t n, const double *pos, const int32_t *species, const double *cell,
+                     const int32_t *pbc, double skin, int32_t T, const int32_t *decomp, int32_t n_threads,
+                     double *energy, double *atom_energy, double *forces, double *virial, int64_t *work) {
+    if (!m || !pos || !species || !cell || !pbc || !energy || n <= 0) return OM_EINVAL;
+    if (T < 1 || T > m->T_max || m->K < 1 || m->K > 64 || m->L < 0 || m->L > 4 || !(m->r_c > 0.0) ||
+        skin < 0.0 || m->hidden > 1024 || m->n_hidden > 7 || m->n_hidden < 0)
+        return OM_EINVAL;
+    for (int64_t i = 0; i < n; ++i) if (species[i] < 0 || species[i] >= m->n_species) return OM_EINVAL;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    om_ctx C; C.m = m; om_lambda_init(m->L, &C.q);
+    C.K = m->K; C.F = om_nfeat(m->L, m->K); C.NL = C.q.n;
+    const int K = C.K, F = C.F, NL = C.NL, H = m->hidden, nh = m->n_hidden;
+    if (F > 1024) return OM_EINVAL;
+    om_geom g; memset(&g, 0, sizeof g);
+    int rc = om_geom_init(&g, n, pos, cell, pbc, decomp);
+    if (rc) { om_geom_free(&g); return rc; }
+    int np = g.P[0] * g.P[1] * g.P[2];
+    double rcut = m->r_c + skin;
+    double *Eat = calloc(n, sizeof(double));
+    double Wtot[9] = { 0 };
+    if (forces) memset(forces, 0, sizeof(double) * n * 3);
+    if (work) memset(work, 0, sizeof(int64_t) * 2 * T);
+    for (int p = 0; p < np && rc == OM_OK; ++p) {
+        om_domain D;
+        rc = om_domain_build(&g, species, p, rcut, T * rcut, 1, &D);
+        if (rc) { om_domain_free(&D); break; }
+        const int64_t ne = D.n_ext;
+        int *lev = malloc(sizeof(int) * (ne + 1));
+        for (int64_t e = 0; e < ne; ++e) lev[e] = om_halo_level(&g, &D, p, e, rcut);
+        double **c = calloc(T, sizeof(double *)), **S = calloc(T, sizeof(double *));
+        for (int t = 0; t < T; ++t) {
+            c[t] = calloc((size_t)ne * K + 1, sizeof(double));
+            S[t] = calloc((size_t)ne * NL * K + 1, sizeof(double));
+        }
+        for (int64_t e = 0; e < ne; ++e)
+            for (int k = 0; k < K; ++k) c[0][e * K + k] = m->c0[D.spec[e] * K + k];
+        for (int t = 0; t < T; ++t) {
+            const int top = T - 1 - t;   /* rows of level <= top are evaluated at layer t */
+#pragma omp parallel for schedule(dynamic, 64)
+            for (int64_t e = 0; e < ne; ++e) {
+                if (lev[e] > top) continue;
+                om_edge_sum(&C, &D, e, c[t], S[t] + e * NL * K);
+                if (t < T - 1) {
+                    double rho[1024];
+                    om_density(&C.q, m->L, K, S[t] + e * NL * K, rho);
+                    om_mlp_forward(om_msg_params(m, t, D.spec[e]), F, H, nh, K, rho, c[t + 1] + e * K);
+                }
+            }
+            if (work)
+                for (int64_t e = 0; e < ne; ++e) {
+                    if (lev[e] > top) continue;
+                    work[2 * t] += 1;
+                    for (int64_t k = D.row[e]; k < D.row[e + 1]; ++k) {
+                        int64_t j = D.col[k];
+                        double d[3] = { D.pos[3 * j] - D.pos[3 * e], D.pos[3 * j + 1] - D.pos[3 * e + 1],
+                                        D.pos[3 * j + 2] - D.pos[3 * e + 2] };
+                        if (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) < m->r_c) work[2 * t + 1] += 1;
+                    }
+                }
+        }
+        for (int64_t i = 0; i < D.n_loc; ++i) {
+            double rho[1024], y;
+            om_density(&C.q, m->L, K, S[T - 1] + i * NL * K, rho);
+            om_mlp_forward(om_en_params(m, D.spec[i]), F, H, nh, 1, rho, &y);
+            Eat[D.gid[i]] = m->energy_scale * y;
+        }
+        if (forces || virial) {
+            double *Sbar = calloc((size_t)ne * NL * K + 1, sizeof(double));
+            double *Fext = calloc((size_t)ne * 3 + 1, sizeof(double));
+            double *cbar = calloc((size_t)ne * K + 1, sizeof(double));
+            for (int64_t i = 0; i < D.n_loc; ++i) {
+                double rho[1024], rhobar[1024], ybar = m->energy_scale;
+                om_density(&C.q, m->L, K, S[T - 1] + i * NL * K, rho);
+                om_mlp_vjp(om_en_params(m, D.spec[i]), F, H, nh, 1, rho, &ybar, rhobar);
+                om_density_vjp(&C.q, m->L, K, S[T - 1] + i * NL * K, rhobar, Sbar + i * NL * K);
+            }
+            for (int t = T - 1; t >= 0; --t) {
+                const int top = T - 1 - t;
+                memset(cbar, 0, sizeof(double) * ne * K);
+                /* serial over rows: every edge adds to both ends, in row order */
+                for (int64_t e = 0; e < ne; ++e) {
+                    if (lev[e] > top) continue;
+                    for (int64_t k = D.row[e]; k < D.row[e + 1]; ++k) {
+                        int64_t j = D.col[k];
+                        om_edge_adjoint(&C, D.pos + 3 * e, D.pos + 3 * j, Sbar + e * NL * K, c[t] + j * K, Fext + 3 * e,
+                                        Fext + 3 * j, t > 0 ? cbar + j * K : NULL, Wtot);
+                    }
+                }
+                if (t == 0) break;                   /* dc^0/dr = 0 */
+                /* message adjoints stay in the subdomain: through layer t-1's message NN of
+                   every row evaluated there */
+                memset(Sbar, 0, sizeof(double) * ne * NL * K);
+#pragma omp parallel for schedule(dynamic, 64)
+                for (int64_t e = 0; e < ne; ++e) {
+                    if (lev[e] > T - t) continue;
+                    double rho[1024], rhobar[1024];
+                    om_density(&C.q, m->L, K, S[t - 1] + e * NL * K, rho);
+                    om_mlp_vjp(om_msg_params(m, t - 1, D.spec[e]), F, H, nh, K, rho, cbar + e * K, rhobar);
+                    om_density_vjp(&C.q, m->L, K, S[t - 1] + e * NL * K, rhobar, Sbar + e * NL * K);
+                }
+            }
+            if (forces)                                /* copies' forces summed onto their owners */
+                for (int64_t e = 0; e < ne; ++e)
+                    for (int k = 0; k < 3; ++k) forces[D.gid[e] * 3 + k] += Fext[e * 3 + k];
+            free(Sbar); free(Fext); free(cbar);
+        }
+        for (int t = 0; t < T; ++t) { free(c[t]); free(S[t]); }
+        free(c); free(S); free(lev);
+        om_domain_free(&D);
+    }
+    if (rc == OM_OK) {
+        double Etot = 0.0;
+        for (int64_t i = 0; i < n; ++i) Etot += Eat[i];
+        *energy = Etot;
+        if (atom_energy) memcpy(atom_energy, Eat, sizeof(double) * n);
+        if (virial) memcpy(virial, Wtot, sizeof(Wtot));
+    }
+    free(Eat);
     om_geom_free(&g);
     return rc;
 }

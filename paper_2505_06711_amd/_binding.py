@@ -81,6 +81,7 @@ _SIGS = {
     "reann_plan_get": (_i32, [_vp, _i32, _i32, _vp]),
     "reann_plan_set_timing": (_i32, [_vp, _i32]),
     "reann_plan_generation": (_i32, [_vp, C.POINTER(C.c_uint64)]),
+    "reann_plan_set_energy_weights": (_i32, [_vp, _vp]),
     "reann_plan_timing": (_i32, [_vp, _vp, _vp, C.POINTER(_i64)]),
     "reann_server_create": (_i32, [_vp, C.POINTER(_ServerOpts), C.POINTER(_vp)]),
     "reann_server_set_masses": (_i32, [_vp, _vp]),
@@ -349,6 +350,14 @@ class Plan:
             _require_device_f64(virial, (3, 3))
             w = virial.data_ptr()
         check(load().reann_plan_backward(self.handle, g, forces.data_ptr(), w, self._stream(stream)))
+
+    def set_energy_weights(self, w=None):
+        """E = sum_i w_i E_i (w: [n] in caller order; None = all 1); the backward follows."""
+        if w is None:
+            check(load().reann_plan_set_energy_weights(self.handle, None))
+            return
+        wa = _f64(w, (self.n,))
+        check(load().reann_plan_set_energy_weights(self.handle, _p(wa)))
 
     def generation(self) -> int:
         """Number of forwards run on this plan (a backward uses the latest one's state)."""

@@ -591,6 +591,23 @@ reann_status reann_plan_get(reann_plan *p, int32_t what, int32_t t, double *host
     });
 }
 
+reann_status reann_plan_set_energy_weights(reann_plan *p, const double *w) {
+    return guarded([&] {
+        REQUIRE(p, "NULL argument");
+        Plan &P = p->impl;
+        HIP_OK(hipSetDevice(P.ctx->device));
+        if (!w) {
+            P.have_ew = false;
+            return;
+        }
+        for (int64_t i = 0; i < P.n; ++i) REQUIRE(std::isfinite(w[i]), "non-finite energy weight");
+        double *d = P.d_ew.resize(P.n);
+        HIP_OK(hipMemcpyAsync(d, w, P.n * 8, hipMemcpyHostToDevice, P.ctx->stream));
+        HIP_OK(hipStreamSynchronize(P.ctx->stream));
+        P.have_ew = true;
+    });
+}
+
 reann_status reann_plan_generation(const reann_plan *p, uint64_t *gen) {
     return guarded([&] {
         REQUIRE(p && gen, "NULL argument");

@@ -245,15 +245,16 @@ constexpr int kRedBlock = 256;
 
 template <typename R>
 __global__ void k_energy(int64_t n, double scale, const R *__restrict__ y, const int32_t *__restrict__ perm,
-                         double *__restrict__ Eat, double *__restrict__ part) {
+                         const double *__restrict__ w, double *__restrict__ Eat, double *__restrict__ part) {
     __shared__ double sm[kRedBlock];
     const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
-    double e = 0.0;
+    double e = 0.0, we = 0.0;
     if (i < n) {
         e = scale * (double)y[i];
         if (Eat) Eat[perm[i]] = e;
+        we = w ? w[perm[i]] * e : e;
     }
-    sm[threadIdx.x] = e;
+    sm[threadIdx.x] = we;
     __syncthreads();
     for (int h = kRedBlock / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
@@ -263,10 +264,10 @@ __global__ void k_energy(int64_t n, double scale, const R *__restrict__ y, const
 }
 
 int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const void *y, const int32_t *perm,
-                    double *Eat_user, double *partials) {
+                    const double *w_user, double *Eat_user, double *partials) {
     const int nb = grid_for(n, kRedBlock);
-    if (fp64) hipLaunchKernelGGL(k_energy<double>, dim3(nb), dim3(kRedBlock), 0, st, n, scale, (const double *)y, perm, Eat_user, partials);
-    else hipLaunchKernelGGL(k_energy<float>, dim3(nb), dim3(kRedBlock), 0, st, n, scale, (const float *)y, perm, Eat_user, partials);
+    if (fp64) hipLaunchKernelGGL(k_energy<double>, dim3(nb), dim3(kRedBlock), 0, st, n, scale, (const double *)y, perm, w_user, Eat_user, partials);
+    else hipLaunchKernelGGL(k_energy<float>, dim3(nb), dim3(kRedBlock), 0, st, n, scale, (const float *)y, perm, w_user, Eat_user, partials);
     LAUNCH_OK("k_energy");
     return nb;
 }
@@ -384,14 +385,16 @@ void out_layer_vjp(hipStream_t st, int64_t rows, int out, int in, const float *G
 }
 
 template <typename R>
-__global__ void k_seed(int64_t n, double scale, const double *__restrict__ g, R *__restrict__ ybar) {
+__global__ void k_seed(int64_t n, double scale, const double *__restrict__ g, const int32_t *__restrict__ perm,
+                       const double *__restrict__ w, R *__restrict__ ybar) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) ybar[i] = R(scale * (g ? *g : 1.0));
+    if (i < n) ybar[i] = R(scale * (g ? *g : 1.0) * (w ? w[perm[i]] : 1.0));
 }
 
-void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const double *g, void *ybar) {
-    if (fp64) hipLaunchKernelGGL(k_seed<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, scale, g, (double *)ybar);
-    else hipLaunchKernelGGL(k_seed<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, scale, g, (float *)ybar);
+void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const double *g, const int32_t *perm,
+                      const double *w_user, void *ybar) {
+    if (fp64) hipLaunchKernelGGL(k_seed<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, scale, g, perm, w_user, (double *)ybar);
+    else hipLaunchKernelGGL(k_seed<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, scale, g, perm, w_user, (float *)ybar);
     LAUNCH_OK("k_seed");
 }
 

@@ -37,13 +37,16 @@ void out_layer_energy(hipStream_t st, int64_t rows, int in, const float *A, int 
 void out_layer_vjp(hipStream_t st, int64_t rows, int out, int in, const float *G, int ldg, const float *W,
                    const float *Z, int ldz, float *C, int ldc);
 
-// Eat[perm[i]] = scale * y[i] (FP64), and per-block partial sums of Eat in local order.
+// Eat[perm[i]] = scale * y[i] (FP64), and per-block partial sums of w[perm[i]] Eat[perm[i]] in
+// local order (w_user: caller-order weights, NULL = 1).
 int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const void *y, const int32_t *perm,
-                    double *Eat_user, double *partials);
+                    const double *w_user, double *Eat_user, double *partials);
 // out[0] = sum of partials[0..nb) (single block, fixed order); if accumulate, out[q] += ...
 void sum_rows(hipStream_t st, const double *partials, int nb, int width, double *out, bool accumulate);
-// ybar[i] = scale * g  (g = device scalar or NULL = 1)
-void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const double *g, void *ybar);
+// ybar[i] = scale * g * w[perm[i]]  (g = device scalar or NULL = 1; w_user = caller-order weights
+// or NULL = 1)
+void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const double *g, const int32_t *perm,
+                      const double *w_user, void *ybar);
 // forces_user[perm[i]][a] = gscale * F[i][a]; virial_out[q] = gscale * W[q]
 void forces_out(hipStream_t st, bool fp64, int64_t n, const void *F, const int32_t *perm, const double *g,
                 double *forces_user, const double *W, double *virial_out);

@@ -508,7 +508,8 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
         }
     }
     mark(st, PH_NN_FWD, nn_forward(st, T - 1, true));
-    const int nb = energy_finalize(st, fp64, n, m->energy_scale, y.p, nl.perm.ptr(), d_atom_energy, Epart.as<double>());
+    const int nb = energy_finalize(st, fp64, n, m->energy_scale, y.p, nl.perm.ptr(), have_ew ? d_ew.ptr() : nullptr,
+                                   d_atom_energy, Epart.as<double>());
     sum_rows(st, Epart.as<double>(), nb, 1, d_energy, false);
     mark(st, PH_OTHER);
     have_forward = true;
@@ -523,7 +524,7 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     const EdgeConsts ec = m->edge_consts();
     const DensityConsts dc = m->density_consts();
     mark(st, -1);
-    fill_energy_seed(st, fp64, n, m->energy_scale, d_g, ybar.p);
+    fill_energy_seed(st, fp64, n, m->energy_scale, d_g, nl.perm.ptr(), have_ew ? d_ew.ptr() : nullptr, ybar.p);
     zero(st, this->F.p, (size_t)nl.n_ext * 3 * rs);
     mark(st, PH_OTHER);
     mark(st, PH_NN_BWD, nn_vjp(st, T - 1, true, ybar.as<char>(), 1));

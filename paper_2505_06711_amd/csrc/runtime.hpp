@@ -113,6 +113,9 @@ struct Plan {
     OpType op = OpType::F32;
     bool have_forward = false;
     uint64_t generation = 0;   // forwards launched on this plan (reann_plan_generation)
+    // weights of the atomic energies in E (caller order; reann_plan_set_energy_weights)
+    DArr<double> d_ew;
+    bool have_ew = false;
     bool timing = false;
     // events recorded at phase boundaries while timing is on; intervals are attributed to
     // the phase named by the event that closes them (phase -1: not attributed)

@@ -430,3 +430,39 @@ def test_invalid_arguments(oracle_lib):
     with pytest.raises(ValueError):
         cell = s["cell"].copy(); cell[0, 1] = 0.5
         oracle_lib.evaluate(m, dict(s, cell=cell), T=2)
+
+
+# ---- the extended-halo scheme (Sec. 2.2, Fig. 2(a)): no exchange between layers, a T (r_c +
+# skin) halo recomputed in every subdomain.  It must give the whole-system result, and its work
+# counts show the redundancy the per-layer exchange avoids.
+
+@pytest.mark.parametrize("T", [1, 2, 3])
+@pytest.mark.parametrize("decomp", [(1, 1, 1), (2, 2, 2), (3, 2, 1)])
+def test_halo_scheme_equals_whole(oracle_lib, T, decomp):
+    s = systems.water_box(seed=30)
+    m = models.water_model(T_max=3, seed=30)
+    ref = oracle_lib.evaluate(m, s, T=T, skin=0.5)
+    h = oracle_lib.evaluate_halo(m, s, T=T, skin=0.5, decomp=decomp)
+    assert abs(h["energy"] - ref["energy"]) <= 1e-12 * np.abs(ref["atom_energy"]).sum()
+    np.testing.assert_allclose(h["atom_energy"], ref["atom_energy"], rtol=0, atol=1e-12 * np.abs(ref["atom_energy"]).max())
+    assert np.abs(h["forces"] - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max()
+    assert np.abs(h["virial"] - ref["virial"]).max() <= 1e-10 * np.abs(ref["virial"]).max()
+
+
+def test_halo_scheme_work_counts(oracle_lib):
+    """At T = 1 the halo scheme evaluates exactly the locals and their in-cutoff edges, like the
+    per-layer exchange; for T > 1 its layer t evaluates more rows the earlier the layer (the
+    halo shrinks by one cutoff per layer), its last layer only the locals, and in total more
+    than the T n rows of the exchange."""
+    s = systems.water_box(grid=(6, 6, 6), spacing=systems.WATER_BOX_L / 4, seed=83)
+    m = models.water_model(T_max=4, seed=83)
+    n = len(s["pos"])
+    row, _, _ = oracle_lib.neighbors(s, m.r_c)
+    n_edges = int(row[-1])
+    for T in (1, 2, 3):
+        w = oracle_lib.evaluate_halo(m, s, T=T, skin=0.0, decomp=(2, 2, 2), forces=False)["work"]
+        assert w[-1, 0] == n and w[-1, 1] == n_edges
+        if T == 1:
+            continue
+        assert all(w[t, 0] > w[t + 1, 0] for t in range(T - 1))
+        assert w[:, 0].sum() > T * n and w[:, 1].sum() > T * n_edges
