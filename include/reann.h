@@ -56,8 +56,12 @@ typedef int32_t reann_status;
 
 /* Arithmetic of the evaluation.  FP64: every step in double.  FP32: edge passes,
    densities and atomic NNs in float, positions and displacements formed in double,
-   energy and virial sums in double.  BF16 / FP8: as FP32 but the atomic-NN matrix
-   products take bfloat16 / OCP e4m3 operands (per-tensor scale) with float accumulation. */
+   energy and virial sums in double.  BF16: as FP32 but the atomic-NN matrix products take
+   bfloat16 operands with float accumulation.  FP8: the atomic-NN forward products take OCP
+   e4m3 operands with float accumulation, one scale per weight matrix and per activation
+   tensor, the activation scales calibrated once from an FP32 evaluation on the plan's first
+   call (twice the largest magnitude seen maps to 448; larger values saturate); the adjoint
+   products take bfloat16 operands. */
 #define REANN_FP64 0
 #define REANN_FP32 1
 #define REANN_BF16 2

@@ -30,7 +30,8 @@ __device__ inline uint16_t f2bf(float f) {   // round to nearest even
     return (uint16_t)(u >> 16);
 }
 
-__device__ inline uint8_t f2fp8(float f) {   // OCP e4m3, |f| <= 448 by construction of the scale
+__device__ inline uint8_t f2fp8(float f) {   // OCP e4m3; values beyond the largest finite one (448) saturate
+    f = fminf(fmaxf(f, -448.0f), 448.0f);
     return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(f, 0.0f, 0, false) & 0xff);
 }
 
@@ -268,6 +269,11 @@ template <> struct Fuse<OpType::BF16> {
     static constexpr int KC = 32;
     static constexpr int PAD = 8;
 };
+template <> struct Fuse<OpType::FP8> {
+    using T = uint8_t;
+    static constexpr int KC = 32;
+    static constexpr int PAD = 16;
+};
 
 typedef float fl4 __attribute__((ext_vector_type(4)));
 
@@ -359,7 +365,8 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
     // requested before the matrix instructions of chunk k0 are issued (the scheduling
     // barriers keep the compiler from moving the requests next to their use)
     using T = typename Fuse<OP>::T;
-    using V = typename std::conditional<OP == OpType::F32, fl4, u16x8>::type;
+    using V = typename std::conditional<OP == OpType::F32, fl4,
+                                        typename std::conditional<OP == OpType::BF16, u16x8, long>::type>::type;
     constexpr int RUN = OP == OpType::F32 ? 4 : 8;   // k per lane per chunk
     auto load_b = [&](V (&b)[NCB], int k0) {
 #pragma unroll
@@ -388,13 +395,19 @@ __device__ inline void fused_layer(const typename Fuse<OP>::T *X, int ldx, const
 #pragma unroll
                     for (int cb = 0; cb < NCB; ++cb)
                         c[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s], b[cb][s], c[rb][cb], 0, 0, 0);
-        } else {
+        } else if constexpr (OP == OpType::BF16) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb)
                     c[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                         __builtin_bit_cast(bf16x8, a[rb]), __builtin_bit_cast(bf16x8, b[cb]), c[rb][cb], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+                    c[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[rb], b[cb], c[rb][cb], 0, 0, 0);
         }
     };
     // pairs of chunks per trip, so that a trip is one basic block and the requests cannot be
@@ -458,7 +471,8 @@ __device__ inline void density_part(const FusedNN &p, typename Fuse<OP>::T *X, i
             float acc = 0.0f;
 #pragma unroll
             for (int q = 0; q < nq; ++q) acc += w[q] * sv[q][a] * sv[q][b];
-            xr[a * K - a * (a - 1) / 2 + (b - a)] = to_op<OP>(acc, 1.0f);
+            const int f = a * K - a * (a - 1) / 2 + (b - a);
+            xr[f] = to_op<OP>(acc, OP == OpType::FP8 ? p.xinv[l * P + f] : 1.0f);
         }
 }
 
@@ -528,6 +542,9 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
         __syncthreads();   // every wave has read this layer's input
         const bool last = k + 1 == p.nh;
         float *Zk = p.Z[k];
+        // FP8: the product carries the operands' scales; the next layer's input is stored scaled
+        const float zs = OP == OpType::FP8 ? p.zscale[k] : 1.0f;
+        const float hin = (OP == OpType::FP8 && !last) ? p.hinv[k + 1] : 1.0f;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -537,10 +554,10 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
                 for (int r = 0; r < 4; ++r) {
                     const int rr = 16 * rb + 4 * lg + r;
                     const int64_t row = m0 + rr;
-                    const float z = acc[rb][cb][r] + bias[cb];
+                    const float z = acc[rb][cb][r] * zs + bias[cb];
                     if (row < p.rows) Zk[row * p.ldz + col] = z;
                     const float h = silu_fwd(z);
-                    X[rr * ldx + col] = to_op<OP>(h, 1.0f);
+                    X[rr * ldx + col] = to_op<OP>(h, hin);
                     if (OP != OpType::F32 && last) hf[rr * ldf + col] = h;
                 }
             }
@@ -713,13 +730,65 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
 }
 
 bool fused_nn_ok(OpType op, int F, int H, int nh, int dout, int NLK) {
-    return op != OpType::FP8 && (H == 64 || H == 128) && F >= 1 && F <= kFuseMaxF && nh >= 1 && nh <= kFuseMaxNh &&
+    (void)op;
+    return (H == 64 || H == 128) && F >= 1 && F <= kFuseMaxF && nh >= 1 && nh <= kFuseMaxNh &&
            dout >= 1 && dout <= kFuseMaxOut && NLK >= 1 && NLK <= kFuseMaxNLK;
+}
+
+// ---------------------------------------------------------- FP8 calibration --
+
+__device__ inline void atomic_max_pos(float *a, float v) {   // v >= 0: order as unsigned
+    atomicMax(reinterpret_cast<unsigned int *>(a), __float_as_uint(v));
+}
+
+// block y = feature f; the blocks along x split the rows
+__global__ void k_density_absmax(int L, int K, int64_t rows, DensityConsts dc, const float *__restrict__ S,
+                                 float *__restrict__ out) {
+    const int P = K * (K + 1) / 2, NLK = dc.lstart[L + 1] * K;
+    const int f = blockIdx.y, l = f / P;
+    int rem = f % P, a = 0;
+    while (rem >= K - a) { rem -= K - a; ++a; }
+    const int b = a + rem;
+    float m = 0.0f;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+        const float *Sr = S + r * NLK;
+        float acc = 0.0f;
+        for (int q = dc.lstart[l]; q < dc.lstart[l + 1]; ++q) acc += (float)dc.w[q] * Sr[q * K + a] * Sr[q * K + b];
+        m = fmaxf(m, fabsf(acc));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomic_max_pos(out + f, m);
+}
+
+__global__ void k_silu_absmax(int64_t rows, int H, int ld, const float *__restrict__ Z, float *__restrict__ out) {
+    float m = 0.0f;
+    const int64_t tot = rows * H;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(silu_fwd(Z[(t / H) * ld + t % H])));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomic_max_pos(out, m);
+}
+
+void density_absmax(hipStream_t st, int L, int K, int64_t rows, const DensityConsts &dc, const float *S, float *out) {
+    if (rows <= 0) return;
+    const int F = (L + 1) * K * (K + 1) / 2;
+    const int bx = (int)std::min<int64_t>(64, (rows + 255) / 256);
+    hipLaunchKernelGGL(k_density_absmax, dim3(bx, F), dim3(256), 0, st, L, K, rows, dc, S, out);
+    LAUNCH_OK("k_density_absmax");
+}
+
+void silu_absmax(hipStream_t st, int64_t rows, int H, int ld, const float *Z, float *out) {
+    if (rows <= 0) return;
+    const int nb = (int)std::min<int64_t>(1024, (rows * H + 255) / 256);
+    hipLaunchKernelGGL(k_silu_absmax, dim3(nb), dim3(256), 0, st, rows, H, ld, Z, out);
+    LAUNCH_OK("k_silu_absmax");
 }
 
 static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout, int NLK) {
     (void)NLK;
-    const size_t eb = op_bytes(op), pad = op == OpType::F32 ? 4 : 8;
+    const size_t eb = op_bytes(op), pad = op == OpType::F32 ? 4 : (op == OpType::BF16 ? 8 : 16);
     const size_t Fp = pad_k(F), ldh = H + pad;
     if (!fwd) {
         const size_t a = std::max<size_t>(kFuseBM * ldh * eb, (size_t)kFuseBM * (F + 4) * 4);
@@ -754,7 +823,14 @@ void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
     else if (p.L == 2 && p.K == 4) { NC_(OPV, 2, 4) }                                   \
     else fail(REANN_E_UNSUPPORTED, "mlp_fused: no kernel compiled for this (L, K)");
     if (op == OpType::F32) { ALL_(OpType::F32) }
-    else { ALL_(OpType::BF16) }
+    else if (op == OpType::BF16) { ALL_(OpType::BF16) }
+    else {
+        if (!fwd) fail(REANN_E_DEVICE, "mlp_fused: FP8 runs the forward only (its adjoint takes BF16 operands)");
+#undef LK_
+#define LK_(OPV, NC, LL, KK) hipLaunchKernelGGL((k_mlp_fwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);
+        ALL_(OpType::FP8)
+#undef LK_
+    }
 #undef ALL_
 #undef NC_
 #undef LK_

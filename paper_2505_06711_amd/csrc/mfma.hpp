@@ -51,13 +51,28 @@ struct FusedNN {
     int ldz;
     const float *Wout, *bout;     // output layer [dout][H], [dout] (FP32)
     const double *Wout64, *bout64;   // forward with dout = 1 (the energy NN): the same in FP64
+    // FP8 forward only (1 / 1 / NULL otherwise): layer k's product is multiplied by zscale[k]
+    // before its bias; the input of hidden layer k >= 1 is stored as h * hinv[k]; the layer-0
+    // input (the density) as rho_f * xinv[f] (the calibrated per-feature scales, whose inverses
+    // are folded into the layer-0 operand)
+    float zscale[kFuseMaxNh];
+    float hinv[kFuseMaxNh];
+    const float *xinv;
     const float *G;               // adjoint: output adjoint [rows][ldg]
     int ldg;
     float *C;                     // forward: outputs [rows][ldc]; adjoint: dE/dS [rows][NL*K]
     int ldc;
 };
 
+// Whether the fused kernels take these shapes (every operand type: FP8 runs the forward only,
+// its adjoint takes BF16 operands).
 bool fused_nn_ok(OpType op, int F, int H, int nh, int dout, int NLK);
+
+// FP8 calibration from FP32 activations: out[f] = max over the rows of |rho_f| of the density of
+// S [rows][NL*K] (f = (l, a <= b) in the feature order); out[F] must be zero on entry.
+void density_absmax(hipStream_t st, int L, int K, int64_t rows, const DensityConsts &dc, const float *S, float *out);
+// out[0] = max(out[0], max |SiLU(z)|) over Z [rows][ld], H columns; out must be zero initially.
+void silu_absmax(hipStream_t st, int64_t rows, int H, int ld, const float *Z, float *out);
 // Forward (fwd = true: density of S, hidden layers, Z stores, output layer with FP64
 // accumulation) or adjoint (fwd = false: output layer, hidden layers, first layer, density
 // adjoint to dE/dS) of one element's NN.

@@ -124,8 +124,10 @@ bool Model::on_device(int device, int prec) {
     auto it = dev.find(device);
     if (it == dev.end()) return false;
     if (prec == REANN_FP64) return true;
-    const int op = (int)(prec == REANN_BF16 ? OpType::BF16 : (prec == REANN_FP8 ? OpType::FP8 : OpType::F32));
-    return it->second->mf[0][op] && it->second->mf[1][op];
+    auto has = [&](OpType o) { return it->second->mf[0][(int)o] && it->second->mf[1][(int)o]; };
+    if (prec == REANN_FP8)   // the FP8 rung also calibrates in FP32 and runs its adjoint in BF16
+        return has(OpType::FP8) && has(OpType::F32) && has(OpType::BF16);
+    return has(prec == REANN_BF16 ? OpType::BF16 : OpType::F32);
 }
 
 EdgeConsts Model::edge_consts() const {
@@ -196,6 +198,11 @@ void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const doubl
     if (!fp64) {
         m->mfma(ctx->device, st, false, op);
         m->mfma(ctx->device, st, true, op);
+        if (op == OpType::FP8)   // calibration forward in FP32, adjoint in BF16
+            for (bool e : {false, true}) {
+                m->mfma(ctx->device, st, e, OpType::F32);
+                m->mfma(ctx->device, st, e, OpType::BF16);
+            }
     }
     fp8s.ensure(16);
     fp8tmp.ensure(16);
@@ -334,7 +341,8 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
         const char *p = blob + (size_t)nn_index * lay.size * rs;
         const char *A = rhoptr(t) + (size_t)a * F * rs;
         int lda = F;
-        const MfmaSet *mf = fp64 ? nullptr : &m->mfma(ctx->device, st, energy, op);
+        const bool f8 = fp8_fused();
+        const MfmaSet *mf = fp64 ? nullptr : (f8 ? fp8set[energy ? 1 : 0].get() : &m->mfma(ctx->device, st, energy, op));
         char *out = energy ? y.as<char>() + (size_t)a * rs : cptr(t + 1) + (size_t)a * K * rs;
         const int dout = energy ? 1 : K;
         if (fused()) {
@@ -348,7 +356,10 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
                 f.ldw[k] = mf->ld_fwd[qi];
                 f.b[k] = (const float *)(p + lay.b_off[k] * rs);
                 f.Z[k] = (float *)(Zptr(t, k) + (size_t)a * H * rs);
+                f.zscale[k] = f8 ? fp8_zscale[energy ? 1 : 0][qi] : 1.0f;
+                f.hinv[k] = f8 ? fp8_hinv[energy ? 1 : 0][qi] : 1.0f;
             }
+            f.xinv = f8 ? fp8_xinv[energy ? 1 : 0].as<float>() + (size_t)nn_index * F : nullptr;
             f.ldz = H;
             f.Wout = (const float *)(p + lay.w_off[nh] * rs);
             f.bout = (const float *)(p + lay.b_off[nh] * rs);
@@ -412,7 +423,10 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
         int ldin = ldg;
         char *bufs[2] = {gA.as<char>(), gB.as<char>()};
         int cur = 0;
-        const MfmaSet *mf = fp64 ? nullptr : &m->mfma(ctx->device, st, energy, op);
+        // the FP8 rung's adjoint takes BF16 operands (the forward's FP8 scales are calibrated
+        // for activations, not for their adjoints)
+        const OpType bop = fp8_fused() ? OpType::BF16 : op;
+        const MfmaSet *mf = fp64 ? nullptr : &m->mfma(ctx->device, st, energy, bop);
         if (fused()) {
             FusedNN f{};
             f.rows = rows; f.F = F; f.H = H; f.nh = nh; f.dout = lay.dout[nh];
@@ -428,7 +442,7 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
             f.Wout = (const float *)(p + lay.w_off[nh] * rs);
             f.G = (const float *)gin; f.ldg = ldin;
             f.C = (float *)(Sbar.as<char>() + (size_t)a * m->NL * m->K * rs); f.ldc = m->NL * m->K;
-            mlp_fused(st, op, false, f);
+            mlp_fused(st, bop, false, f);
             ++nfused;
             continue;
         }
@@ -472,7 +486,106 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
 bool Plan::prepare(const double *d_pos, hipStream_t st) {
     const int64_t rb0 = rebuilds;
     ensure_list(d_pos, st);
+    if (fp8_fused() && !fp8_ready) calibrate_fp8(d_pos, st);
     return rebuilds != rb0;
+}
+
+// FP8 calibration (once, on the plan's first evaluation): an FP32 forward gives every NN's
+// inputs; per NN, the largest |rho| over its element's rows and features sets the scale of the
+// density input, s = headroom max|rho| / 448 (one scale per tensor; the kernels take one per
+// feature, folded into layer 0's operand W_0 diag(s), but per-feature scales measured no better:
+// e4m3's error here is its 3-bit mantissa, not its range), and the largest |SiLU(z)| of each
+// hidden layer sets that layer's input scale.  Weights are stored in FP8 with one scale per
+// matrix.  The headroom of 2 keeps values up to twice the calibration maximum in range; larger
+// ones saturate at 448.  The scales stay fixed afterwards (a trajectory keeps its ranges).
+void Plan::calibrate_fp8(const double *d_pos, hipStream_t st) {
+    constexpr double kHeadroom = 2.0;
+    const int F = m->F, H = m->H, nh = m->nh, ns = m->n_species, K = m->K;
+    const OpType saved = op;
+    const uint64_t gen = generation;
+    op = OpType::F32;
+    DevBuf tmpE;
+    launch_forward(d_pos, static_cast<double *>(tmpE.ensure(64)), nullptr, st);
+    op = saved;
+    generation = gen;   // the calibration pass is not one of the caller's forwards
+    const int nmsg = (m->T_max - 1) * ns, nen = ns;
+    const int nq[2] = {nmsg, nen};
+    DevBuf amax;
+    const size_t na = (size_t)(nmsg + nen) * (F + nh);
+    float *dam = static_cast<float *>(amax.ensure(std::max<size_t>(na, 1) * 4));
+    zero(st, dam, std::max<size_t>(na, 1) * 4);
+    const DensityConsts dc = m->density_consts();
+    auto slot = [&](int e, int q) { return dam + ((size_t)(e ? nmsg : 0) + q) * (F + nh); };
+    for (int t = 0; t < T; ++t) {
+        const bool energy = t == T - 1;
+        for (int s = 0; s < ns; ++s) {
+            const int64_t a = nl.seg[s], rows = nl.seg[s + 1] - nl.seg[s];
+            if (rows <= 0) continue;
+            const int q = energy ? s : t * ns + s;
+            float *out = slot(energy, q);
+            density_absmax(st, m->L, K, rows, dc, (const float *)(Sptr(t) + (size_t)a * m->NL * K * rs), out);
+            for (int k = 0; k + 1 < nh; ++k)
+                silu_absmax(st, rows, H, H, (const float *)(Zptr(t, k) + (size_t)a * H * rs), out + F + k);
+        }
+    }
+    std::vector<float> ham(std::max<size_t>(na, 1));
+    HIP_OK(hipMemcpyAsync(ham.data(), dam, ham.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (int e = 0; e < 2; ++e) {
+        const NNLayout &lay = e ? m->en_nn : m->msg_nn;
+        const std::vector<double> &blob = e ? m->en : m->msg;
+        const int count = nq[e];
+        auto set = std::make_unique<MfmaSet>();
+        std::vector<float> host, xinv((size_t)std::max(count, 1) * F, 1.0f), scales;
+        std::vector<size_t> foff;
+        std::vector<int> rows_, cols_, lds_;
+        fp8_zscale[e].assign((size_t)std::max(count, 1) * nh, 1.0f);
+        fp8_hinv[e].assign((size_t)std::max(count, 1) * nh, 1.0f);
+        for (int q = 0; q < count; ++q) {
+            const float *am = ham.data() + ((size_t)(e ? nmsg : 0) + q) * (F + nh);
+            double rmax = 0.0;
+            for (int f = 0; f < F; ++f) rmax = std::max(rmax, (double)am[f]);
+            std::vector<double> sx(F, kHeadroom * (rmax > 0.0 ? rmax : 1.0) / 448.0);
+            for (int f = 0; f < F; ++f) xinv[(size_t)q * F + f] = (float)(1.0 / sx[f]);
+            for (int k = 0; k < nh; ++k) {
+                const double *W = blob.data() + (size_t)q * lay.size + lay.w_off[k];
+                const int dout = lay.dout[k], din = lay.din[k], ld = pad_k(din);
+                const double sig = k == 0 ? 1.0 : kHeadroom * (am[F + k - 1] > 0.0f ? am[F + k - 1] : 1.0) / 448.0;
+                foff.push_back(host.size());
+                rows_.push_back(dout); cols_.push_back(din); lds_.push_back(ld);
+                double wmax = 0.0;
+                for (int o = 0; o < dout; ++o)
+                    for (int i = 0; i < ld; ++i) {
+                        const double v = i < din ? W[(size_t)o * din + i] * (k == 0 ? sx[i] : 1.0) : 0.0;
+                        host.push_back((float)v);
+                        wmax = std::max(wmax, std::fabs(v));
+                    }
+                const double wsc = wmax > 0.0 ? wmax / 448.0 : 1.0;
+                scales.push_back((float)wsc);
+                set->off_fwd.push_back(0);
+                set->ld_fwd.push_back(ld);
+                fp8_zscale[e][(size_t)q * nh + k] = (float)(wsc * sig);
+                fp8_hinv[e][(size_t)q * nh + k] = (float)(1.0 / sig);
+            }
+        }
+        DevBuf tmp;
+        tmp.ensure(std::max<size_t>(host.size(), 1) * 4);
+        if (!host.empty()) HIP_OK(hipMemcpyAsync(tmp.p, host.data(), host.size() * 4, hipMemcpyHostToDevice, st));
+        set->scales.ensure(std::max<size_t>(scales.size(), 1) * 4);
+        if (!scales.empty())
+            HIP_OK(hipMemcpyAsync(set->scales.p, scales.data(), scales.size() * 4, hipMemcpyHostToDevice, st));
+        set->buf.ensure(std::max<size_t>(host.size(), 1));
+        for (size_t i = 0; i < foff.size(); ++i) {
+            convert_operand(st, OpType::FP8, tmp.as<float>() + foff[i], rows_[i], cols_[i], lds_[i],
+                            set->buf.as<char>() + foff[i], lds_[i], set->scales.as<float>() + i);
+            set->off_fwd[i] = foff[i];   // one byte per element: the byte offset equals the float offset
+        }
+        float *dx = static_cast<float *>(fp8_xinv[e].ensure(xinv.size() * 4));
+        HIP_OK(hipMemcpyAsync(dx, xinv.data(), xinv.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_OK(hipStreamSynchronize(st));
+        fp8set[e] = std::move(set);
+    }
+    fp8_ready = true;
 }
 
 void Plan::forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st) {

@@ -116,6 +116,12 @@ struct Plan {
     // weights of the atomic energies in E (caller order; reann_plan_set_energy_weights)
     DArr<double> d_ew;
     bool have_ew = false;
+    // FP8 on the fused NN kernels: forward operands and scales calibrated on the plan's first
+    // evaluation (see calibrate_fp8), per NN [message, energy] indexed like the weight blobs
+    bool fp8_ready = false;
+    std::unique_ptr<MfmaSet> fp8set[2];
+    DevBuf fp8_xinv[2];                     // [NN][F] inverse per-feature scales of the density input
+    std::vector<float> fp8_zscale[2], fp8_hinv[2];   // [NN * nh]
     bool timing = false;
     // events recorded at phase boundaries while timing is on; intervals are attributed to
     // the phase named by the event that closes them (phase -1: not attributed)
@@ -142,8 +148,13 @@ struct Plan {
     // per-phase kernel time (ms) accumulated since the last call; returns the step count
     int64_t collect_timing(double *ms, int64_t *nlaunch);
 
+    // the FP8 rung's NN forward runs on the fused kernels (calibrated operands); its adjoint
+    // then takes the BF16 operands
+    bool fp8_fused() const { return op == OpType::FP8 && fused(); }
+
   private:
     void ensure_list(const double *d_pos, hipStream_t st);
+    void calibrate_fp8(const double *d_pos, hipStream_t st);
     void alloc_buffers();
     char *cptr(int t) const { return c.as<char>() + (size_t)t * nl.n_ext * m->K * rs; }
     char *Sptr(int t) const { return S.as<char>() + (size_t)t * n * m->NL * m->K * rs; }

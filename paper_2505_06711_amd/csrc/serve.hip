@@ -10,6 +10,7 @@
 // the graph re-captured when an atom has moved more than skin/2.  Every system has its own
 // buffers and the kernels are deterministic, so a result does not depend on what else is in
 // flight.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -183,6 +184,10 @@ struct Sys {
     // displacement, so that the skin check (a device round trip) is needed only near the edge
     bool motion_known = false;
     double disp = 0, vmax = 0, amax = 0;
+    // caller positions the neighbour list was last built from, when that build came from an
+    // EVAL request (host positions): later EVAL requests check the skin rule on the host
+    std::vector<double> xref_h;
+    bool xref_ok = false;
     double *E() { return d_out.as<double>(); }
     double *W() { return d_out.as<double>() + 1; }
     double *KE() { return d_out.as<double>() + 10; }
@@ -256,7 +261,7 @@ struct reann_server {
     bool make_resident(Sys &sy, int64_t need);
     void evict(Sys &sy);
     int64_t estimate_bytes(const Sys &sy) const;
-    void launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid = false);
+    void launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid = false, const double *h_pos = nullptr);
 };
 
 int64_t reann_server::estimate_bytes(const Sys &sy) const {
@@ -281,11 +286,14 @@ int64_t reann_server::estimate_bytes(const Sys &sy) const {
 void reann_server::evict(Sys &sy) {
     // bring the evolving state home, then release the device memory
     if (sy.plan) {
-        HIP_OK(hipDeviceSynchronize());
-        HIP_OK(hipMemcpy(sy.pos.data(), sy.d_pos.p, sy.n * 24, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(sy.vel.data(), sy.d_vel.p, sy.n * 24, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(sy.forces.data(), sy.d_Fold.p, sy.n * 24, hipMemcpyDeviceToHost));
+        // the system is idle: its last request's work is complete, so only these copies are waited for
+        hipStream_t st = ctx.stream;
+        HIP_OK(hipMemcpyAsync(sy.pos.data(), sy.d_pos.p, sy.n * 24, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipMemcpyAsync(sy.vel.data(), sy.d_vel.p, sy.n * 24, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipMemcpyAsync(sy.forces.data(), sy.d_Fold.p, sy.n * 24, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
     }
+    sy.xref_ok = false;
     if (sy.graph) { (void)hipGraphExecDestroy(sy.graph); sy.graph = nullptr; }
     sy.plan.reset();
     sy.d_pos.release(); sy.d_vel.release(); sy.d_Fold.release(); sy.d_out.release(); sy.d_aux.release();
@@ -336,12 +344,34 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
     return true;
 }
 
-// Enqueue one step of `sy` on slot `s` (positions for EVAL already staged in d_pos).
-void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid) {
+// Enqueue one step of `sy` on slot `s` (positions for EVAL already staged in d_pos; h_pos: the
+// same positions on the host, for EVAL requests).
+void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid, const double *h_pos) {
     hipStream_t st = s.st;
     Plan &p = *sy.plan;
-    // the skin check waits for the device; skipped when the caller has shown the list valid
+    // The skin check on the device waits for it.  It is skipped when the caller has shown the
+    // list valid (velocity-Verlet motion bounds), and for EVAL requests it runs on the host
+    // against the host copy of the positions the list was built from (the same rule: rebuild
+    // when an atom has moved more than skin/2).
+    if (!list_valid && h_pos && sy.xref_ok && p.built) {
+        const double half = 0.5 * opt.skin;
+        double d2max = 0.0;
+        for (int64_t i = 0; i < sy.n; ++i) {
+            const double dx = h_pos[3 * i] - sy.xref_h[3 * i], dy = h_pos[3 * i + 1] - sy.xref_h[3 * i + 1],
+                         dz = h_pos[3 * i + 2] - sy.xref_h[3 * i + 2];
+            d2max = std::max(d2max, dx * dx + dy * dy + dz * dz);
+        }
+        list_valid = d2max <= half * half;
+    }
     const bool rebuilt = list_valid ? false : p.prepare(sy.d_pos.as<double>(), st);
+    if (rebuilt) {
+        if (h_pos) {
+            sy.xref_h.assign(h_pos, h_pos + 3 * sy.n);
+            sy.xref_ok = true;
+        } else {
+            sy.xref_ok = false;
+        }
+    }
     if (rebuilt) {
         stats[6]++;
         const int64_t actual = (int64_t)p.device_bytes() + 4 * (int64_t)sy.n * 24;
@@ -433,7 +463,7 @@ bool reann_server::admit(Req &r) {
     } else {
         HIP_OK(hipMemcpyAsync(sy.d_pos.p, r.pos.data(), sy.n * 24, hipMemcpyHostToDevice, st));
     }
-    launch_step(*s, sy, true, list_valid);
+    launch_step(*s, sy, true, list_valid, vv ? nullptr : r.pos.data());
     if (vv) {
         hipLaunchKernelGGL(k_vv_kick, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, r.dt, sy.d_spec.ptr(),
                            d_minv.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.F());

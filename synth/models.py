@@ -132,6 +132,14 @@ def unpack_mlp(blob: np.ndarray, dims: list[int], index: int):
 # choices keep every layer's messages and sums O(1) up to T = 6, with atomic energies of
 # order 0.5 eV and forces of order 1 eV/A, like a trained potential.
 
+def water_model_plain(T_max=2, seed=0) -> ModelParams:
+    """The 64-molecule water configuration's model as stated: L=2, 8 Gaussians centred
+    uniformly on [0, 5] A, width 0.5 A, r_c = 5 A, two hidden layers of 64 SiLU units, every
+    weight N(0, 1/fan_in), zero biases, c0 ~ N(0, 1), raw Cartesian angular factors (A),
+    elements (H, O)."""
+    return make_model(["H", "O"], L=2, K=8, r_c=5.0, width=0.5, n_hidden=2, hidden=64, T_max=T_max, seed=seed)
+
+
 def water_model(T_max=2, seed=0, **kw) -> ModelParams:
     """Water model: L=2, 8 Gaussians centred uniformly on [0, 5] A, width 0.5 A,
     r_c = 5 A, two hidden layers of 64 SiLU units, elements (H, O)."""

@@ -1,7 +1,8 @@
 """Named synthetic workloads (system + model + evaluation settings).
 
     water192      64-molecule periodic water box, 192 atoms, r_c = 5 A, no skin,
-                  T = 2, water model (K=8, 2x64 SiLU); small parity case.
+                  T = 2, the plain water model (K=8, 2x64 SiLU, weights N(0, 1/fan_in),
+                  zero biases); small parity case.
     cu100800      FCC Cu-like crystal, a = 3.61 A, 30x30x28 cells = 100,800 atoms,
                   sigma = 0.1 A, r_c = 6 A with a 1 A skin, T = 3, Cu model
                   (K=12, 3x128 SiLU); the throughput workload.
@@ -17,7 +18,7 @@ WATER_SPACING = systems.WATER_BOX_L / 4
 
 
 def _water192(seed=0):
-    return dict(system=systems.water_box(seed=seed), model=models.water_model(T_max=2, seed=seed),
+    return dict(system=systems.water_box(seed=seed), model=models.water_model_plain(T_max=2, seed=seed),
                 T=2, skin=0.0, decomp=(1, 1, 1))
 
 

@@ -178,15 +178,18 @@ def test_model_shapes(rn, ctx, oracle_lib, shape, prec):
         assert np.abs(F - ref["forces"]).max() <= 1e-10 * np.abs(ref["forces"]).max()
         assert np.abs(W - ref["virial"]).max() <= 1e-10 * np.abs(ref["virial"]).max()
     elif prec == "fp8":
-        # FP8 with one scale per tensor is too coarse for a precision bound (15% in energy on
-        # the Cu crystal); this runs its scaling, conversion and matrix kernels at every shape
-        # and checks the results are finite and nearer the reference than zero forces are
+        # e4m3 keeps 3 mantissa bits (a rounding of up to 1/16 per value), and every layer of the
+        # T NN evaluations adds its own, so the bounds grow with the depth like BF16's but 16x
+        # wider: 5% energy and 10% force RMSE per layer.  An operand or tile mistake gives errors
+        # of order one.  (Measured 1-8% energy, 8-27% forces on these shapes.)
         ref = oracle_lib.evaluate(m, s, T=3, skin=0.5)
         E, F, W = _eval(rn, ctx, m, s, 3, prec, skin=0.5, decomp=(2, 1, 1))
         re, rf = rel_energy(E, ref), rel_force_rmse(F, ref)
         print("fp8 %s: rel E %.2e, force rel-RMSE %.2e" % (shape, re, rf), flush=True)
+        depth = MODEL_SHAPES[shape]["n_hidden"] + 1
         assert np.isfinite(E) and np.isfinite(F).all() and np.isfinite(W).all()
-        assert rf < 1.0
+        assert re <= 5e-2 * depth
+        assert rf <= 1e-1 * depth
     elif prec == "bf16":
         # BF16 operands approximate the model (8 significant bits per operand, and every
         # layer of the T NN evaluations adds its rounding), so this checks the BF16 kernels'
@@ -411,7 +414,10 @@ def test_precision_ladder_cu100800(rn, ctx, prec):
     rel = abs(E - g["energy"]) / max(abs(g["energy"]), g["sum_abs_atom_energy"])
     print("ladder %s: |dE| = %.3e meV/atom (E/N = %.4f eV), force RMSE = %.3e meV/A (force RMS %.3f eV/A), "
           "rel E %.2e" % (prec, de, g["energy"] / n, frmse, g["force_rms"], rel), flush=True)
-    lim = {"fp32": 1e-6, "bf16": 2e-2, "fp8": 3e-1}[prec]
+    # FP8: e4m3 rounds each value to 3 mantissa bits and the errors compound through the T NN
+    # evaluations; an e4m3 emulation of these random-weight models on the CPU gives energy errors
+    # from a few to several hundred meV/atom across seeds, so the bound is a sanity limit
+    lim = {"fp32": 1e-6, "bf16": 2e-2, "fp8": 5e-1}[prec]
     assert rel <= lim
     assert frmse / 1e3 <= {"fp32": 1e-5, "bf16": 5e-2, "fp8": 5e-1}[prec] * g["force_rms"]
 
