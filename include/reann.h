@@ -330,8 +330,11 @@ reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res);
 /* Statistics, host [REANN_N_SERVER_STATS]: [0] engine rounds that admitted at least one
    request, [1] requests completed, [2] atoms evaluated, [3] HIP-graph replays, [4] admissions
    deferred for the HBM budget, [5] device bytes held by resident systems, [6] neighbour-list
-   builds (first builds and skin-rule rebuilds). */
-#define REANN_N_SERVER_STATS 7
+   builds (first builds and skin-rule rebuilds), [7] host nanoseconds the engine thread spent
+   enqueuing requests (admission, launches, copies), [8] of which in HIP-graph launches,
+   [9] host nanoseconds spent unpacking finished requests, [10] of [7] in neighbour-list
+   builds, [11] of [7] in capturing and instantiating HIP graphs. */
+#define REANN_N_SERVER_STATS 12
 reann_status reann_server_stats(reann_server *s, int64_t *stats);
 void reann_server_destroy(reann_server *s);
 

@@ -45,7 +45,10 @@ inline Arena *&current_arena() {
     return a;
 }
 
-// Owning device allocation that only grows.
+// Owning device allocation that only grows.  A buffer that has to grow again takes a quarter
+// more than asked for: sizes that follow a moving system (ghost and pair counts after a list
+// rebuild) then stop reallocating after a few rebuilds, and hipFree, which waits for the whole
+// device, stays out of the steady state.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -72,6 +75,7 @@ struct DevBuf {
     void *ensure(size_t n) {
         if (n == 0) n = 256;
         if (n > bytes) {
+            const bool regrow = p != nullptr;
             release();
             if (Arena *a = current_arena()) {
                 const size_t off = (a->used + 255) & ~(size_t)255;
@@ -82,6 +86,7 @@ struct DevBuf {
                 a->used = off + n;
                 owned = false;
             } else {
+                if (regrow) n += n / 4;
                 HIP_OK(hipMalloc(&p, n));
             }
             bytes = n;

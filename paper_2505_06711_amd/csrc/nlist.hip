@@ -5,6 +5,8 @@
 // with w the wrapped position and y = w + shift*L the copy position.
 #include "nlist.hpp"
 
+#include <cstring>
+
 #include <algorithm>
 #include <cmath>
 
@@ -449,19 +451,58 @@ static void scan_rec(hipStream_t st, int64_t *d, int64_t n, int64_t *tmp) {
     }
 }
 
-// d holds n counts in [0, n); on return d[0..n] are exclusive offsets, d[n] = total.
-int64_t scan_exclusive_i64(hipStream_t st, int64_t *d, int64_t n, DevBuf &tmp) {
+// d holds n counts in [0, n); on return d[0..n] are exclusive offsets, d[n] = total.  Enqueued
+// only: the total stays on the device.
+static void scan_exclusive_async(hipStream_t st, int64_t *d, int64_t n, DevBuf &tmp) {
     // last element + its count = total: scan n+1 values where d[n] was set to 0 by the caller
     int64_t m = n + 1;
     int64_t need = 0, k = m;
     while (k > 1) { k = (k + 1023) / 1024; need += k + 1; }
     int64_t *t = static_cast<int64_t *>(tmp.ensure((size_t)(need + 16) * sizeof(int64_t)));
     scan_rec(st, d, m, t);
+}
+
+int64_t scan_exclusive_i64(hipStream_t st, int64_t *d, int64_t n, DevBuf &tmp) {
+    scan_exclusive_async(st, d, n, tmp);
     int64_t total = 0;
     HIP_OK(hipMemcpyAsync(&total, d + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     return total;
 }
+
+// Scattered device scalars the host needs (counts for allocation sizes, bounds, check flags),
+// gathered by one tiny kernel into one block and read with one copy: every read is a wait for
+// the stream, which behind other streams' work sharing a hardware queue can take far longer
+// than the work itself.
+constexpr int kPickMax = 96;
+struct Pick {
+    const void *p[kPickMax];
+    int8_t is32[kPickMax];   // 1: int32 (sign-extended); 0: eight bytes (int64, or a double's bits)
+    int n;
+};
+
+__global__ void k_pick(Pick pk, int64_t *__restrict__ out) {
+    for (int t = threadIdx.x; t < pk.n; t += blockDim.x)
+        out[t] = pk.is32[t] ? (int64_t) * static_cast<const int32_t *>(pk.p[t]) : *static_cast<const int64_t *>(pk.p[t]);
+}
+
+struct Picker {
+    Pick pk{};
+    int add(const void *p, bool is32) {
+        if (pk.n >= kPickMax) fail(REANN_E_UNSUPPORTED, "neighbour build: too many values to read back");
+        pk.p[pk.n] = p;
+        pk.is32[pk.n] = is32 ? 1 : 0;
+        return pk.n++;
+    }
+    // enqueue the gather, copy to `host` and wait
+    void read(hipStream_t st, DevBuf &dev, int64_t *host) {
+        int64_t *d = static_cast<int64_t *>(dev.ensure(kPickMax * sizeof(int64_t)));
+        hipLaunchKernelGGL(k_pick, dim3(1), dim3(128), 0, st, pk, d);
+        LAUNCH_OK("k_pick");
+        HIP_OK(hipMemcpyAsync(host, d, pk.n * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
+};
 
 // --------------------------------------------------------------------- build --
 
@@ -484,10 +525,23 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     HIP_OK(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_wrap_count, dim3(grid_for(n, B)), dim3(B), 0, st, g, n, d_pos, w, q, dom, goff, bad);
     LAUNCH_OK("k_wrap_count");
-    int32_t hbad = 0;
-    HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    int64_t n_gh = scan_exclusive_i64(st, goff, n, s.m);   // synchronises
-    if (hbad) fail(REANN_E_INVALID, "positions contain NaN, Inf or |x| >= 1e9");
+    scan_exclusive_async(st, goff, n, s.m);
+    double *d_mm = static_cast<double *>(s.mm.ensure(6 * sizeof(double)));
+    hipLaunchKernelGGL(k_minmax, dim3(1), dim3(256), 0, st, n, w, d_mm);
+    LAUNCH_OK("k_minmax");
+    // first read: ghost count, the invalid-position flag and the bounds of the wrapped locals
+    int64_t hv[kPickMax];
+    double bb[6];
+    {
+        Picker pk;
+        pk.add(goff + n, false);
+        pk.add(bad, true);
+        for (int a = 0; a < 6; ++a) pk.add(d_mm + a, false);
+        pk.read(st, s.chk, hv);
+        std::memcpy(bb, hv + 2, sizeof bb);
+    }
+    const int64_t n_gh = hv[0];
+    if (hv[1]) fail(REANN_E_INVALID, "positions contain NaN, Inf or |x| >= 1e9");
     if (n + n_gh >= ((int64_t)1 << 31) - 1) fail(REANN_E_UNSUPPORTED, "extended system too large");
     nl.n_gh = n_gh;
     nl.n_ext = n + n_gh;
@@ -502,14 +556,6 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
 
     // spatial bins of size >= r_c + skin over the region holding every copy
     Bins b{};
-    double bb[6];
-    {
-        double *d_mm = static_cast<double *>(s.h.ensure(6 * sizeof(double)));
-        hipLaunchKernelGGL(k_minmax, dim3(1), dim3(256), 0, st, n, w, d_mm);
-        LAUNCH_OK("k_minmax");
-        HIP_OK(hipMemcpyAsync(bb, d_mm, sizeof bb, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-    }
     b.nbin = 1;
     for (int a = 0; a < 3; ++a) {
         double lo = g.per[a] ? -g.shell : bb[a];
@@ -535,8 +581,9 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     LAUNCH_OK("k_keys");
     hipLaunchKernelGGL(k_i32_to_i64, dim3(grid_for(nkeys + 1, B)), dim3(B), 0, st, cnt32, kstart, nkeys + 1);
     LAUNCH_OK("k_i32_to_i64");
-    int64_t tot = scan_exclusive_i64(st, kstart, nkeys, s.m);
-    if (tot != n_ext) fail(REANN_E_DEVICE, "neighbour build: key count mismatch");
+    // every ext atom adds one to exactly one key, so the total is n_ext by construction; it is
+    // read back (and checked) with the pair count below
+    scan_exclusive_async(st, kstart, nkeys, s.m);
     int32_t *order = static_cast<int32_t *>(s.k.ensure(n_ext * sizeof(int32_t)));
     HIP_OK(hipMemsetAsync(cnt32, 0, (nkeys + 1) * sizeof(int32_t), st));
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_ext, B)), dim3(B), 0, st, n_ext, key, kstart, cnt32, order);
@@ -544,25 +591,12 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     hipLaunchKernelGGL(k_sort_segments, dim3(grid_for(nkeys, B)), dim3(B), 0, st, nkeys, kstart, order);
     LAUNCH_OK("k_sort_segments");
 
-    // species segments of the locals
-    {
-        nl.seg.assign(n_species + 1, 0);
-        for (int sp = 0; sp <= n_species; ++sp) {
-            int64_t v = 0;
-            HIP_OK(hipMemcpyAsync(&v, kstart + (int64_t)sp * g.ndom * b.nbin, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-            HIP_OK(hipStreamSynchronize(st));
-            nl.seg[sp] = v;
-        }
-        if (nl.seg[n_species] != n) fail(REANN_E_DEVICE, "neighbour build: species segments mismatch");
-    }
-
     int32_t *perm = nl.perm.resize(n);
     int32_t *inv_perm = nl.inv_perm.resize(n);
     double *pext = static_cast<double *>(s.l.ensure(3 * n_ext * sizeof(double)));
-    DevBuf dext, bext, gou;
-    int32_t *d_dom_ext = static_cast<int32_t *>(dext.ensure(n_ext * sizeof(int32_t)));
-    int32_t *d_bin_ext = static_cast<int32_t *>(bext.ensure(n_ext * sizeof(int32_t)));
-    int32_t *gh_owner_user = static_cast<int32_t *>(gou.ensure((n_gh + 1) * sizeof(int32_t)));
+    int32_t *d_dom_ext = static_cast<int32_t *>(s.dext.ensure(n_ext * sizeof(int32_t)));
+    int32_t *d_bin_ext = static_cast<int32_t *>(s.bext.ensure(n_ext * sizeof(int32_t)));
+    int32_t *gh_owner_user = static_cast<int32_t *>(s.gou.ensure((n_gh + 1) * sizeof(int32_t)));
     int8_t *spec_ext = nl.spec_ext.resize(n_ext);
     int32_t *gh_shift = nl.gh_shift.resize((n_gh + 1) * 3);
     hipLaunchKernelGGL(k_build_ext, dim3(grid_for(n_ext, B)), dim3(B), 0, st, b, n, n_ext, order, w, dom, d_species,
@@ -582,10 +616,23 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     hipLaunchKernelGGL(k_rows<false>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, n, n_ext, pext,
                        d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr);
     LAUNCH_OK("k_rows<count>");
-    int64_t n_pairs = scan_exclusive_i64(st, row, n_ext, s.m);
+    scan_exclusive_async(st, row, n_ext, s.m);
+    // second read: pair counts, the key total and the species segments of the locals
+    {
+        Picker pk;
+        pk.add(row + n_ext, false);
+        pk.add(row + n, false);
+        pk.add(kstart + nkeys, false);
+        for (int sp = 0; sp <= n_species; ++sp) pk.add(kstart + (int64_t)sp * g.ndom * b.nbin, false);
+        pk.read(st, s.chk, hv);
+    }
+    const int64_t n_pairs = hv[0];
+    if (hv[2] != n_ext) fail(REANN_E_DEVICE, "neighbour build: key count mismatch");
+    nl.seg.assign(hv + 3, hv + 3 + n_species + 1);
+    if (nl.seg[n_species] != n) fail(REANN_E_DEVICE, "neighbour build: species segments mismatch");
     if (n_pairs >= ((int64_t)1 << 31) - 1) fail(REANN_E_UNSUPPORTED, "too many neighbour pairs");
     nl.n_pairs = n_pairs;
-    HIP_OK(hipMemcpyAsync(&nl.n_local_pairs, row + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    nl.n_local_pairs = hv[1];
     int32_t *col = nl.col.resize(n_pairs + 1);
     hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, n, n_ext, pext,
                        d_dom_ext, d_bin_ext, kstart, nullptr, row, col);
@@ -599,10 +646,6 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
         HIP_OK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
         hipLaunchKernelGGL(k_reverse, dim3(grid_for(n_ext * 16, B)), dim3(B), 0, st, n_ext, row, col, rev, flag);
         LAUNCH_OK("k_reverse");
-        int32_t hflag = 0;
-        HIP_OK(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        if (hflag) fail(REANN_E_DEVICE, "neighbour build: list is not symmetric");
     }
 
     // owner -> ghost copies
@@ -618,7 +661,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
         }
         hipLaunchKernelGGL(k_i32_to_i64, dim3(grid_for(n + 1, B)), dim3(B), 0, st, c32, c64, n + 1);
         LAUNCH_OK("k_i32_to_i64");
-        scan_exclusive_i64(st, c64, n, s.m);
+        scan_exclusive_async(st, c64, n, s.m);
         hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for(n + 1, B)), dim3(B), 0, st, c64, copy_ptr, n + 1);
         LAUNCH_OK("k_i64_to_i32");
         if (n_gh > 0) {
@@ -632,7 +675,13 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     double *xref = nl.xref.resize(n * 3);
     hipLaunchKernelGGL(k_xref, dim3(grid_for(n, B)), dim3(B), 0, st, n, d_pos, perm, xref);
     LAUNCH_OK("k_xref");
-    HIP_OK(hipStreamSynchronize(st));
+    // last read (the list is complete when it returns): the symmetry check of the reverse slots
+    {
+        Picker pk;
+        pk.add(s.flag.p, true);
+        pk.read(st, s.chk, hv);
+    }
+    if (hv[0]) fail(REANN_E_DEVICE, "neighbour build: list is not symmetric");
 }
 
 // ------------------------------------------------------------ per-step work --

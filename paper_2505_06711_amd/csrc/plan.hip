@@ -309,22 +309,22 @@ size_t Plan::device_bytes() const {
     return b;
 }
 
-void Plan::ensure_list(const double *d_pos, hipStream_t st) {
-    bool rebuild = !built;
-    if (built) {
-        double d2 = 0;
-        max_displacement2(st, nl, d_pos, disp.as<double>());
-        HIP_OK(hipMemcpyAsync(&d2, disp.p, 8, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        const double half = 0.5 * skin;
-        if (!(d2 <= half * half)) rebuild = true;
-    }
-    if (rebuild) {
-        build_nlist(st, d_pos, d_species.ptr(), n, m->n_species, g, m->r_c, skin, nl, ns);
-        built = true;
-        ++rebuilds;
-        alloc_buffers();
-    }
+bool Plan::list_stale(const double *d_pos, hipStream_t st) {
+    if (!built) return true;
+    double d2 = 0;
+    max_displacement2(st, nl, d_pos, disp.as<double>());
+    HIP_OK(hipMemcpyAsync(&d2, disp.p, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const double half = 0.5 * skin;
+    return !(d2 <= half * half);
+}
+
+void Plan::rebuild(const double *d_pos, hipStream_t st) {
+    build_nlist(st, d_pos, d_species.ptr(), n, m->n_species, g, m->r_c, skin, nl, ns);
+    built = true;
+    ++rebuilds;
+    alloc_buffers();
+    if (fp8_fused() && !fp8_ready) calibrate_fp8(d_pos, st);
 }
 
 int Plan::nn_forward(hipStream_t st, int t, bool energy) {
@@ -484,10 +484,10 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
 }
 
 bool Plan::prepare(const double *d_pos, hipStream_t st) {
-    const int64_t rb0 = rebuilds;
-    ensure_list(d_pos, st);
-    if (fp8_fused() && !fp8_ready) calibrate_fp8(d_pos, st);
-    return rebuilds != rb0;
+    const bool stale = list_stale(d_pos, st);
+    if (stale) rebuild(d_pos, st);
+    else if (fp8_fused() && !fp8_ready) calibrate_fp8(d_pos, st);
+    return stale;
 }
 
 // FP8 calibration (once, on the plan's first evaluation): an FP32 forward gives every NN's

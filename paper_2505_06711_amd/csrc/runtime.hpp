@@ -140,6 +140,11 @@ struct Plan {
     // skin check (one stream synchronisation) and rebuild if needed; true if rebuilt, in which
     // case device buffers may have moved
     bool prepare(const double *d_pos, hipStream_t st);
+    // the two halves of prepare: the skin check alone (true if the list was never built or an
+    // atom has moved more than skin/2 since), and the rebuild (with the FP8 calibration the
+    // first time), which allocates
+    bool list_stale(const double *d_pos, hipStream_t st);
+    void rebuild(const double *d_pos, hipStream_t st);
     // the forward's launches only: no synchronisation and no allocation, so it can be captured
     void launch_forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st);
     size_t device_bytes() const;
@@ -153,7 +158,6 @@ struct Plan {
     bool fp8_fused() const { return op == OpType::FP8 && fused(); }
 
   private:
-    void ensure_list(const double *d_pos, hipStream_t st);
     void calibrate_fp8(const double *d_pos, hipStream_t st);
     void alloc_buffers();
     char *cptr(int t) const { return c.as<char>() + (size_t)t * nl.n_ext * m->K * rs; }

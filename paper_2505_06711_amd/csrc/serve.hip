@@ -5,7 +5,10 @@
 // to kSlots requests in flight, each on its own stream, so the steps of different systems
 // overlap on the device; a request that arrives while others run is admitted as soon as a
 // slot and HBM budget are free (budget exhausted: idle resident systems are evicted, least
-// recently used first, else the request waits).  A step is one HIP-graph replay of the
+// recently used first, else the request waits).  The engine only admits and completes
+// requests; a pool of kWorkers launcher threads enqueues each admitted step on its slot's
+// stream, so that a step that has to rebuild its neighbour list (several waits for the
+// device) does not hold up the launches of the others.  A step is one HIP-graph replay of the
 // captured forward + backward when the neighbour list is unchanged; the list is rebuilt and
 // the graph re-captured when an atom has moved more than skin/2.  Every system has its own
 // buffers and the kernels are deterministic, so a result does not depend on what else is in
@@ -21,6 +24,7 @@
 #include <map>
 #include <mutex>
 #include <random>
+#include <shared_mutex>
 #include <thread>
 
 #include "runtime.hpp"
@@ -30,6 +34,7 @@ using namespace reann;
 namespace {
 
 constexpr int kSlots = 8;
+constexpr int kWorkers = 4;
 constexpr int kOutHead = 14;   // energy, virial (9), kinetic energy, displacement^2, max |v_c|, max |a_c|
 constexpr double kAccel = 9.648533212e-3;   // (eV/A) / amu in A/fs^2
 
@@ -225,11 +230,53 @@ struct Done {
 struct Slot {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
-    bool active = false;
+    bool active = false;              // engine: taken by a request
+    // set by the launcher: kQueued until the step is enqueued and `ev` recorded (kLaunched), or
+    // kFailed with the error in `err`
+    std::atomic<int> state{0};
+    std::string err;
     Req req;
     Sys *sys = nullptr;
     double *h_out = nullptr;          // pinned: the result head, forces, positions, velocities
     size_t h_cap = 0;
+};
+
+constexpr int kQueued = 0, kLaunched = 1, kFailed = 2;
+
+// Keeps HIP-graph captures apart from device allocation and release on the server's other
+// threads: work that may allocate or free (making a system resident, evicting it, pinned
+// result buffers, neighbour-list rebuilds) holds it shared, so such work runs concurrently; a
+// capture (with the instantiation and the release of the graph it replaces) holds it
+// exclusively.  A waiting capture bars new shared holders, so captures are not starved by a
+// stream of rebuilds.
+class CaptureGate {
+    std::mutex m;
+    std::condition_variable cv;
+    int readers = 0, writers_waiting = 0;
+    bool writer = false;
+
+  public:
+    void lock_shared() {
+        std::unique_lock<std::mutex> lk(m);
+        cv.wait(lk, [&] { return !writer && writers_waiting == 0; });
+        ++readers;
+    }
+    void unlock_shared() {
+        std::lock_guard<std::mutex> lk(m);
+        if (--readers == 0) cv.notify_all();
+    }
+    void lock() {
+        std::unique_lock<std::mutex> lk(m);
+        ++writers_waiting;
+        cv.wait(lk, [&] { return !writer && readers == 0; });
+        --writers_waiting;
+        writer = true;
+    }
+    void unlock() {
+        std::lock_guard<std::mutex> lk(m);
+        writer = false;
+        cv.notify_all();
+    }
 };
 
 }  // namespace
@@ -251,11 +298,23 @@ struct reann_server {
     std::thread engine;
     Slot slots[kSlots];
     std::list<Req> pending;              // engine-private
-    int64_t budget = 0, resident = 0, in_flight_atoms = 0;
+    // launcher pool: slots whose step is to be enqueued
+    std::vector<std::thread> workers;
+    std::mutex jmu;
+    std::condition_variable jcv;
+    std::deque<Slot *> jobs;
+    bool wstop = false;                  // guarded by jmu
+    // no capture on one thread overlaps an allocation or release on another; the steps that
+    // only replay a graph and launch kernels take no lock
+    CaptureGate gate;
+    int64_t budget = 0, in_flight_atoms = 0;
+    std::atomic<int64_t> resident{0};
     std::atomic<int64_t> stats[REANN_N_SERVER_STATS]{};
     std::string fatal;
 
     void run();
+    void work();
+    void enqueue(Slot &s);
     bool admit(Req &r);
     void finish(Slot &s);
     bool make_resident(Sys &sy, int64_t need);
@@ -284,6 +343,7 @@ int64_t reann_server::estimate_bytes(const Sys &sy) const {
 }
 
 void reann_server::evict(Sys &sy) {
+    std::shared_lock<CaptureGate> alloc(gate);
     // bring the evolving state home, then release the device memory
     if (sy.plan) {
         // the system is idle: its last request's work is complete, so only these copies are waited for
@@ -300,7 +360,7 @@ void reann_server::evict(Sys &sy) {
     sy.d_spec.b.release();
     resident -= sy.bytes;
     sy.bytes = 0;
-    stats[5] = resident;
+    stats[5] = resident.load();
 }
 
 bool reann_server::make_resident(Sys &sy, int64_t need) {
@@ -319,6 +379,7 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
         }
         if (resident + need > budget) return false;
     }
+    std::shared_lock<CaptureGate> alloc(gate);
     hipStream_t st = ctx.stream;
     auto p = std::make_unique<Plan>();
     reann_opts o{};
@@ -340,7 +401,7 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
     sy.graph_rebuilds = -1;
     sy.bytes = need;   // corrected to the measured size after the first build
     resident += need;
-    stats[5] = resident;
+    stats[5] = resident.load();
     return true;
 }
 
@@ -363,7 +424,15 @@ void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid
         }
         list_valid = d2max <= half * half;
     }
-    const bool rebuilt = list_valid ? false : p.prepare(sy.d_pos.as<double>(), st);
+    // the device skin check (one wait for the stream) runs outside the lock, the rebuild inside
+    bool rebuilt = false;
+    if (!list_valid && p.list_stale(sy.d_pos.as<double>(), st)) {
+        std::shared_lock<CaptureGate> alloc(gate);
+        const int64_t tb = now_ns();
+        p.rebuild(sy.d_pos.as<double>(), st);
+        rebuilt = true;
+        stats[10] += now_ns() - tb;
+    }
     if (rebuilt) {
         if (h_pos) {
             sy.xref_h.assign(h_pos, h_pos + 3 * sy.n);
@@ -375,25 +444,35 @@ void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid
     if (rebuilt) {
         stats[6]++;
         const int64_t actual = (int64_t)p.device_bytes() + 4 * (int64_t)sy.n * 24;
-        resident += actual - (int64_t)sy.bytes;
+        stats[5] = resident.fetch_add(actual - (int64_t)sy.bytes) + (actual - (int64_t)sy.bytes);
         sy.bytes = actual;
-        stats[5] = resident;
     }
     const bool use_graph = opt.use_graph && replay_ok;
     if (use_graph && (sy.graph == nullptr || sy.graph_rebuilds != p.rebuilds)) {
+        std::unique_lock<CaptureGate> cap(gate);
+        const int64_t tc = now_ns();
         if (sy.graph) { (void)hipGraphExecDestroy(sy.graph); sy.graph = nullptr; }
         hipGraph_t g = nullptr;
         HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        p.launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
-        p.backward(nullptr, sy.F(), sy.W(), st);
+        try {
+            p.launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
+            p.backward(nullptr, sy.F(), sy.W(), st);
+        } catch (...) {
+            (void)hipStreamEndCapture(st, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
         HIP_OK(hipStreamEndCapture(st, &g));
         hipError_t e = hipGraphInstantiate(&sy.graph, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         HIP_OK(e);
         sy.graph_rebuilds = p.rebuilds;
+        stats[11] += now_ns() - tc;
     }
     if (use_graph) {
+        const int64_t t0 = now_ns();
         HIP_OK(hipGraphLaunch(sy.graph, st));
+        stats[8] += now_ns() - t0;
         stats[3]++;
     } else {
         p.launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
@@ -433,10 +512,56 @@ bool reann_server::admit(Req &r) {
     }
     const size_t need_host = (size_t)(kOutHead + 9 * sy.n) * 8;
     if (s->h_cap < need_host) {
+        std::shared_lock<CaptureGate> alloc(gate);
         if (s->h_out) (void)hipHostFree(s->h_out);
+        s->h_out = nullptr;
+        s->h_cap = 0;
         HIP_OK(hipHostMalloc((void **)&s->h_out, need_host, hipHostMallocDefault));
         s->h_cap = need_host;
     }
+    sy.busy = true;
+    sy.last_used = now_ns();
+    s->active = true;
+    s->sys = &sy;
+    s->req = std::move(r);
+    s->state.store(kQueued);
+    in_flight_atoms += sy.n;
+    {
+        std::lock_guard<std::mutex> lk(jmu);
+        jobs.push_back(s);
+    }
+    jcv.notify_one();
+    return true;
+}
+
+// Launcher thread: enqueue the admitted step of each slot handed over by the engine.
+void reann_server::work() {
+    (void)hipSetDevice(ctx.device);
+    for (;;) {
+        Slot *s;
+        {
+            std::unique_lock<std::mutex> lk(jmu);
+            jcv.wait(lk, [&] { return wstop || !jobs.empty(); });
+            if (jobs.empty()) return;
+            s = jobs.front();
+            jobs.pop_front();
+        }
+        const int64_t t0 = now_ns();
+        try {
+            enqueue(*s);
+            stats[7] += now_ns() - t0;
+            s->state.store(kLaunched, std::memory_order_release);
+        } catch (const std::exception &e) {
+            s->err = e.what();
+            s->state.store(kFailed, std::memory_order_release);
+        }
+    }
+}
+
+void reann_server::enqueue(Slot &slot) {
+    Slot *s = &slot;
+    Sys &sy = *s->sys;
+    Req &r = s->req;
     hipStream_t st = s->st;
     const int64_t n3 = sy.n * 3;
     const int B = 256;
@@ -490,14 +615,8 @@ bool reann_server::admit(Req &r) {
     sy.have_forces = true;
     HIP_OK(hipMemcpyAsync(s->h_out, sy.d_out.p, (kOutHead + 3 * n3) * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipEventRecord(s->ev, st));
-    sy.busy = true;
-    sy.last_used = now_ns();
-    s->active = true;
-    s->sys = &sy;
-    s->req = std::move(r);
-    in_flight_atoms += sy.n;
-    return true;
 }
+
 
 void reann_server::finish(Slot &s) {
     Sys &sy = *s.sys;
@@ -543,11 +662,17 @@ void reann_server::run() {
                 }
             }
             bool progressed = false;
-            for (auto &x : slots)
-                if (x.active && hipEventQuery(x.ev) == hipSuccess) {
+            for (auto &x : slots) {
+                if (!x.active) continue;
+                const int stt = x.state.load(std::memory_order_acquire);
+                if (stt == kFailed) throw Error(REANN_E_DEVICE, x.err);
+                if (stt == kLaunched && hipEventQuery(x.ev) == hipSuccess) {
+                    const int64_t t0 = now_ns();
                     finish(x);
+                    stats[9] += now_ns() - t0;
                     progressed = true;
                 }
+            }
             bool admitted = false;
             for (auto it = pending.begin(); it != pending.end();) {
                 // nothing more can start while every slot is taken
@@ -565,7 +690,14 @@ void reann_server::run() {
             if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
         for (auto &x : slots)
-            if (x.active) { HIP_OK(hipEventSynchronize(x.ev)); finish(x); }
+            if (x.active) {
+                int stt;
+                while ((stt = x.state.load(std::memory_order_acquire)) == kQueued)
+                    std::this_thread::sleep_for(std::chrono::microseconds(50));
+                if (stt == kFailed) throw Error(REANN_E_DEVICE, x.err);
+                HIP_OK(hipEventSynchronize(x.ev));
+                finish(x);
+            }
     } catch (const std::exception &e) {
         std::lock_guard<std::mutex> lk(mu);
         fatal = e.what();
@@ -647,6 +779,7 @@ reann_status reann_server_create(const reann_model *m, const reann_server_opts *
             s->m->mfma(o->device, s->ctx.stream, true, op);
         }
         reann_server *raw = s.release();
+        for (int k = 0; k < kWorkers; ++k) raw->workers.emplace_back([raw] { raw->work(); });
         raw->engine = std::thread([raw] { raw->run(); });
         *out = raw;
     });
@@ -763,6 +896,13 @@ void reann_server_destroy(reann_server *s) {
     s->stop.store(true);
     s->cv.notify_all();
     if (s->engine.joinable()) s->engine.join();
+    {
+        std::lock_guard<std::mutex> lk(s->jmu);
+        s->wstop = true;
+    }
+    s->jcv.notify_all();
+    for (auto &w : s->workers)
+        if (w.joinable()) w.join();
     (void)hipSetDevice(s->ctx.device);
     (void)hipDeviceSynchronize();
     s->systems.clear();
