@@ -36,7 +36,9 @@ class _Model(C.Structure):
                 ("n_hidden", C.c_int32), ("hidden", C.c_int32), ("r_c", C.c_double),
                 ("ang_scale", C.c_double), ("energy_scale", C.c_double),
                 ("centres", C.c_void_p), ("alphas", C.c_void_p), ("c0", C.c_void_p),
-                ("msg", C.c_void_p), ("en", C.c_void_p)]
+                ("msg", C.c_void_p), ("en", C.c_void_p), ("form", C.c_int32)]
+
+FORMS = {"reann": 0, "radial": 1}   # message forms of reann_oracle.c (readings R1-R5, R10)
 
 
 def _load():
@@ -102,7 +104,8 @@ def _model_struct(model):
     if keep[3].size == 0:
         keep[3] = np.zeros(1)
     mm = _Model(model.n_species, model.L, model.K, model.T_max, model.n_hidden, model.hidden, model.r_c,
-                model.ang_scale, model.energy_scale, *[_p(a) for a in keep])
+                model.ang_scale, model.energy_scale, *[_p(a) for a in keep],
+                FORMS[getattr(model, "form", "reann")])
     return mm, keep
 
 
@@ -145,12 +148,7 @@ def evaluate(model, system: dict, T: int, skin: float = 0.0, decomp=(1, 1, 1), n
     spec = np.ascontiguousarray(system["species"], dtype=np.int32)
     n = pos.shape[0]
     K, NL = model.K, n_lambda(model.L)
-    keep = [np.ascontiguousarray(a, dtype=np.float64) for a in
-            (model.centres, model.alphas, model.c0, model.msg_blob, model.energy_blob)]
-    if keep[3].size == 0:
-        keep[3] = np.zeros(1)
-    mm = _Model(model.n_species, model.L, K, model.T_max, model.n_hidden, model.hidden, model.r_c,
-                model.ang_scale, model.energy_scale, *[_p(a) for a in keep])
+    mm, keep = _model_struct(model)
     E = np.zeros(1)
     Ei = np.zeros(n)
     F = np.zeros((n, 3)) if forces else None

@@ -41,6 +41,13 @@
  *      ghosts of a subdomain are all copies (j,n) other than its own locals whose position
  *      lies within shell = r_c + skin + 1e-6 A of the subdomain box on every split or
  *      periodic axis.  Non-periodic axes are not split (P = 1) and not wrapped.
+ *   R10 a second message form on the same exchange (Sec. 2.2, the paragraph on other
+ *      MPNNs that aggregate messages over neighbours, invariant ones such as SchNet among
+ *      them): the "radial" form takes L = 0 and uses the orbital sum itself as the K
+ *      features, x_i[m] = S_i[0][m] = sum_j c_j[m] R_m(r_ij) f_c(r_ij) (linear in the
+ *      neighbours' messages, a per-channel Gaussian filter), and updates messages with a
+ *      residual, c_i^{t+1} = c_i^t + M^t_{s_i}(x_i^t); E_i = energy_scale * NN^E_{s_i}(x_i^{T-1}).
+ *      Its adjoint carries dE/dc^{t+1} into dE/dc^t through the residual.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no contraction anywhere, so the
  * neighbour predicate is exactly the expression above).
@@ -57,6 +64,9 @@
 #define OM_EINVAL (-1)
 #define OM_ENOMEM (-3)
 
+#define OM_FORM_REANN 0
+#define OM_FORM_RADIAL 1   /* reading R10 */
+
 typedef struct {
     int32_t n_species, L, K, T_max, n_hidden, hidden;
     double r_c, ang_scale, energy_scale;
@@ -65,12 +75,15 @@ typedef struct {
     const double *c0;      /* [n_species][K] */
     const double *msg;     /* message NNs, see om_mlp_offset */
     const double *en;      /* energy NNs */
+    int32_t form;          /* OM_FORM_REANN (Eqs. (1)-(2)) or OM_FORM_RADIAL (reading R10) */
 } om_model;
 
 /* ---------------------------------------------------------------- helpers -- */
 
 static int om_nlambda(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
 static int om_nfeat(int L, int K) { return (L + 1) * K * (K + 1) / 2; }
+/* features per atom: the paired density of Eq. (1), or the K orbital sums of the radial form */
+static int om_model_nfeat(const om_model *m) { return m->form == OM_FORM_RADIAL ? m->K : om_nfeat(m->L, m->K); }
 
 static double om_fact(int n) { double f = 1.0; for (int k = 2; k <= n; ++k) f *= k; return f; }
 
@@ -100,12 +113,12 @@ static int64_t om_mlp_size(int F, int H, int nh, int dout) {
 }
 
 static const double *om_msg_params(const om_model *m, int t, int s) {
-    int F = om_nfeat(m->L, m->K);
+    int F = om_model_nfeat(m);
     return m->msg + ((int64_t)t * m->n_species + s) * om_mlp_size(F, m->hidden, m->n_hidden, m->K);
 }
 
 static const double *om_en_params(const om_model *m, int s) {
-    int F = om_nfeat(m->L, m->K);
+    int F = om_model_nfeat(m);
     return m->en + (int64_t)s * om_mlp_size(F, m->hidden, m->n_hidden, 1);
 }
 
@@ -203,6 +216,18 @@ static void om_density_vjp(const om_lambda *q, int L, int K, const double *S, co
                     Sbar[k * K + b] += rb * q->w[k] * S[k * K + a];
                 }
             }
+}
+
+/* The NN input of an atom from its orbital sums: the density of Eq. (1), or for the radial
+   form (reading R10) the K sums of lambda = 0 themselves; and the adjoint of that map. */
+static void om_features(const om_model *m, const om_lambda *q, const double *S, double *rho) {
+    if (m->form == OM_FORM_RADIAL) { memcpy(rho, S, sizeof(double) * m->K); return; }
+    om_density(q, m->L, m->K, S, rho);
+}
+static void om_features_vjp(const om_model *m, const om_lambda *q, const double *S, const double *rhobar,
+                            double *Sbar) {
+    if (m->form == OM_FORM_RADIAL) { memcpy(Sbar, rhobar, sizeof(double) * m->K); return; }
+    om_density_vjp(q, m->L, m->K, S, rhobar, Sbar);
 }
 
 /* Cutoff (reading R3) and its derivative. */
@@ -582,8 +607,10 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #endif
+    if (m->form != OM_FORM_REANN && !(m->form == OM_FORM_RADIAL && m->L == 0)) return OM_EINVAL;
+    const int radial = m->form == OM_FORM_RADIAL;
     om_ctx C; C.m = m; om_lambda_init(m->L, &C.q);
-    C.K = m->K; C.F = om_nfeat(m->L, m->K); C.NL = C.q.n;
+    C.K = m->K; C.F = om_model_nfeat(m); C.NL = C.q.n;
     const int K = C.K, F = C.F, NL = C.NL, H = m->hidden, nh = m->n_hidden;
     if (F > 1024) return OM_EINVAL;
 
@@ -623,8 +650,11 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
 #pragma omp parallel for schedule(dynamic, 64)
             for (int64_t i = 0; i < Dp->n_loc; ++i) {
                 double rho[1024];
-                om_density(&C.q, m->L, K, S[p][t] + i * NL * K, rho);
-                om_mlp_forward(om_msg_params(m, t, Dp->spec[i]), F, H, nh, K, rho, cglob + Dp->gid[i] * K);
+                om_features(m, &C.q, S[p][t] + i * NL * K, rho);
+                double *ci = cglob + Dp->gid[i] * K;
+                om_mlp_forward(om_msg_params(m, t, Dp->spec[i]), F, H, nh, K, rho, ci);
+                if (radial)   /* residual update (reading R10) */
+                    for (int k = 0; k < K; ++k) ci[k] += c[p][t][i * K + k];
             }
         }
         for (int p = 0; p < np; ++p) {
@@ -638,8 +668,10 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
                 for (int64_t e = Dp->n_loc; e < Dp->n_ext; ++e) {
                     double Sg[64 * 35], rho[1024];
                     om_edge_sum(&C, Dp, e, c[p][t], Sg);
-                    om_density(&C.q, m->L, K, Sg, rho);
+                    om_features(m, &C.q, Sg, rho);
                     om_mlp_forward(om_msg_params(m, t, Dp->spec[e]), F, H, nh, K, rho, c[p][t + 1] + e * K);
+                    if (radial)
+                        for (int k = 0; k < K; ++k) c[p][t + 1][e * K + k] += c[p][t][e * K + k];
                 }
             }
         }
@@ -650,7 +682,7 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
 #pragma omp parallel for schedule(dynamic, 64)
         for (int64_t i = 0; i < Dp->n_loc; ++i) {
             double rho[1024], y;
-            om_density(&C.q, m->L, K, S[p][T - 1] + i * NL * K, rho);
+            om_features(m, &C.q, S[p][T - 1] + i * NL * K, rho);
             om_mlp_forward(om_en_params(m, Dp->spec[i]), F, H, nh, 1, rho, &y);
             Eat[Dp->gid[i]] = m->energy_scale * y;
         }
@@ -673,6 +705,8 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
         double **Sbar = calloc(np, sizeof(double *)), **Fext = calloc(np, sizeof(double *));
         double **cbar = calloc(np, sizeof(double *));
         double *cbglob = calloc((size_t)n * K, sizeof(double));
+        /* radial form: dE/dc^{t+1} of every atom, carried into dE/dc^t by the residual */
+        double *cbnext = calloc((size_t)n * K, sizeof(double));
         double Wtot[9] = { 0 };
         for (int p = 0; p < np; ++p) {
             Sbar[p] = calloc((size_t)D[p].n_loc * NL * K + 1, sizeof(double));
@@ -682,9 +716,9 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
 #pragma omp parallel for schedule(dynamic, 64)
             for (int64_t i = 0; i < Dp->n_loc; ++i) {
                 double rho[1024], rhobar[1024], ybar = m->energy_scale;
-                om_density(&C.q, m->L, K, S[p][T - 1] + i * NL * K, rho);
+                om_features(m, &C.q, S[p][T - 1] + i * NL * K, rho);
                 om_mlp_vjp(om_en_params(m, Dp->spec[i]), F, H, nh, 1, rho, &ybar, rhobar);
-                om_density_vjp(&C.q, m->L, K, S[p][T - 1] + i * NL * K, rhobar, Sbar[p] + i * NL * K);
+                om_features_vjp(m, &C.q, S[p][T - 1] + i * NL * K, rhobar, Sbar[p] + i * NL * K);
             }
         }
         for (int t = T - 1; t >= 0; --t) {
@@ -728,14 +762,20 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
             for (int p = 0; p < np; ++p)
                 for (int64_t e = 0; e < D[p].n_ext; ++e)
                     for (int k = 0; k < K; ++k) cbglob[D[p].gid[e] * K + k] += cbar[p][e * K + k];
+            if (radial) {
+                /* c^t also reaches the energy through c^{t+1} = c^t + M(x^t) when t < T-1 */
+                if (t < T - 1)
+                    for (int64_t x = 0; x < n * K; ++x) cbglob[x] += cbnext[x];
+                memcpy(cbnext, cbglob, sizeof(double) * n * K);
+            }
             for (int p = 0; p < np; ++p) {
                 om_domain *Dp = &D[p];
 #pragma omp parallel for schedule(dynamic, 64)
                 for (int64_t i = 0; i < Dp->n_loc; ++i) {
                     double rho[1024], rhobar[1024];
-                    om_density(&C.q, m->L, K, S[p][t - 1] + i * NL * K, rho);
+                    om_features(m, &C.q, S[p][t - 1] + i * NL * K, rho);
                     om_mlp_vjp(om_msg_params(m, t - 1, Dp->spec[i]), F, H, nh, K, rho, cbglob + Dp->gid[i] * K, rhobar);
-                    om_density_vjp(&C.q, m->L, K, S[p][t - 1] + i * NL * K, rhobar, Sbar[p] + i * NL * K);
+                    om_features_vjp(m, &C.q, S[p][t - 1] + i * NL * K, rhobar, Sbar[p] + i * NL * K);
                 }
             }
         }
@@ -747,7 +787,7 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
         }
         if (virial) memcpy(virial, Wtot, sizeof(Wtot));
         for (int p = 0; p < np; ++p) { free(Sbar[p]); free(Fext[p]); free(cbar[p]); }
-        free(Sbar); free(Fext); free(cbar); free(cbglob);
+        free(Sbar); free(Fext); free(cbar); free(cbglob); free(cbnext);
     }
 
     for (int p = 0; p < np; ++p) {
@@ -802,6 +842,7 @@ int oracle_eval_halo(const om_model *m, int64_t n, const double *pos, const int3
         skin < 0.0 || m->hidden > 1024 || m->n_hidden > 7 || m->n_hidden < 0)
         return OM_EINVAL;
     for (int64_t i = 0; i < n; ++i) if (species[i] < 0 || species[i] >= m->n_species) return OM_EINVAL;
+    if (m->form != OM_FORM_REANN) return OM_EINVAL;   /* the ablation is kept to the paper's form */
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #endif
@@ -840,7 +881,7 @@ int oracle_eval_halo(const om_model *m, int64_t n, const double *pos, const int3
                 om_edge_sum(&C, &D, e, c[t], S[t] + e * NL * K);
                 if (t < T - 1) {
                     double rho[1024];
-                    om_density(&C.q, m->L, K, S[t] + e * NL * K, rho);
+                    om_features(m, &C.q, S[t] + e * NL * K, rho);
                     om_mlp_forward(om_msg_params(m, t, D.spec[e]), F, H, nh, K, rho, c[t + 1] + e * K);
                 }
             }
@@ -858,7 +899,7 @@ int oracle_eval_halo(const om_model *m, int64_t n, const double *pos, const int3
         }
         for (int64_t i = 0; i < D.n_loc; ++i) {
             double rho[1024], y;
-            om_density(&C.q, m->L, K, S[T - 1] + i * NL * K, rho);
+            om_features(m, &C.q, S[T - 1] + i * NL * K, rho);
             om_mlp_forward(om_en_params(m, D.spec[i]), F, H, nh, 1, rho, &y);
             Eat[D.gid[i]] = m->energy_scale * y;
         }
@@ -868,9 +909,9 @@ int oracle_eval_halo(const om_model *m, int64_t n, const double *pos, const int3
             double *cbar = calloc((size_t)ne * K + 1, sizeof(double));
             for (int64_t i = 0; i < D.n_loc; ++i) {
                 double rho[1024], rhobar[1024], ybar = m->energy_scale;
-                om_density(&C.q, m->L, K, S[T - 1] + i * NL * K, rho);
+                om_features(m, &C.q, S[T - 1] + i * NL * K, rho);
                 om_mlp_vjp(om_en_params(m, D.spec[i]), F, H, nh, 1, rho, &ybar, rhobar);
-                om_density_vjp(&C.q, m->L, K, S[T - 1] + i * NL * K, rhobar, Sbar + i * NL * K);
+                om_features_vjp(m, &C.q, S[T - 1] + i * NL * K, rhobar, Sbar + i * NL * K);
             }
             for (int t = T - 1; t >= 0; --t) {
                 const int top = T - 1 - t;
@@ -892,9 +933,9 @@ int oracle_eval_halo(const om_model *m, int64_t n, const double *pos, const int3
                 for (int64_t e = 0; e < ne; ++e) {
                     if (lev[e] > T - t) continue;
                     double rho[1024], rhobar[1024];
-                    om_density(&C.q, m->L, K, S[t - 1] + e * NL * K, rho);
+                    om_features(m, &C.q, S[t - 1] + e * NL * K, rho);
                     om_mlp_vjp(om_msg_params(m, t - 1, D.spec[e]), F, H, nh, K, rho, cbar + e * K, rhobar);
-                    om_density_vjp(&C.q, m->L, K, S[t - 1] + e * NL * K, rhobar, Sbar + e * NL * K);
+                    om_features_vjp(m, &C.q, S[t - 1] + e * NL * K, rhobar, Sbar + e * NL * K);
                 }
             }
             if (forces)                                /* copies' forces summed onto their owners */

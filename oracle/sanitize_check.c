@@ -6,7 +6,8 @@
  * export, whole-system, decomposed, naive-decomposition and extended-halo evaluations, with
  * forces, virial and the per-layer debug outputs) on a small periodic box whose side is shorter
  * than twice the list cutoff (so many periodic images appear), then checks that the decomposed
- * and halo results equal the whole-system one.  Exits non-zero on any failure; the sanitizers
+ * and halo results equal the whole-system one; then the same whole and decomposed evaluations of
+ * the radial message form.  Exits non-zero on any failure; the sanitizers
  * abort on any memory or undefined-behaviour error.
  */
 #include <math.h>
@@ -19,6 +20,7 @@ typedef struct {
     int32_t n_species, L, K, T_max, n_hidden, hidden;
     double r_c, ang_scale, energy_scale;
     const double *centres, *alphas, *c0, *msg, *en;
+    int32_t form;
 } model_t;
 
 int64_t oracle_neighbors(int64_t n, const double *pos, const double *cell, const int32_t *pbc, double rcut,
@@ -66,7 +68,7 @@ int main(void) {
     double *msg = malloc(sizeof(double) * (TM - 1) * NS * nn_msg), *en = malloc(sizeof(double) * NS * nn_en);
     for (int k = 0; k < (TM - 1) * NS * nn_msg; ++k) msg[k] = (urand() - 0.5) * 0.6;
     for (int k = 0; k < NS * nn_en; ++k) en[k] = (urand() - 0.5) * 0.6;
-    model_t m = { NS, L, K, TM, NH, HID, 4.0, 0.25, 1.0, centres, alphas, c0, msg, en };
+    model_t m = { NS, L, K, TM, NH, HID, 4.0, 0.25, 1.0, centres, alphas, c0, msg, en, 0 };
     const double skin = 0.5;
     int32_t whole[3] = { 1, 1, 1 }, split[3] = { 2, 1, 2 };
 
@@ -91,8 +93,24 @@ int main(void) {
     }
     printf("pairs %lld  E whole %.12f  split %.12f  naive %.12f  halo %.12f  max|dF| %.2e %.2e\n", (long long)cnt,
            E0, E1, E2, E3, dF1, dF3);
-    free(msg); free(en); free(row); free(jj); free(sh);
     int bad = fabs(E1 - E0) > 1e-10 * fabs(E0) || fabs(E3 - E0) > 1e-10 * fabs(E0) || dF1 > 1e-9 * fmax ||
               dF3 > 1e-9 * fmax;
+
+    /* the radial form: L = 0, F = K features, residual updates */
+    const int FR = K, rn_msg = HID * FR + HID + K * HID + K, rn_en = HID * FR + HID + HID + 1;
+    model_t mr = { NS, 0, K, TM, NH, HID, 4.0, 0.25, 1.0, centres, alphas, c0, msg, en, 1 };
+    (void)rn_msg; (void)rn_en;   /* smaller than the REANN blobs above, which they reuse */
+    double Er0, Eri[N], Fr0[3 * N], Wr0[9], Sr[TM * N * K], cr[TM * N * K], Er1, Fr1[3 * N], Wr1[9], Er2;
+    if (oracle_eval(&mr, N, pos, spec, cell, pbc, skin, TM, whole, 0, 2, &Er0, Eri, Fr0, Wr0, Sr, cr)) return 1;
+    if (oracle_eval(&mr, N, pos, spec, cell, pbc, skin, TM, split, 0, 2, &Er1, NULL, Fr1, Wr1, NULL, NULL)) return 1;
+    if (oracle_eval(&mr, N, pos, spec, cell, pbc, skin, TM, split, 1, 2, &Er2, NULL, NULL, NULL, NULL, NULL)) return 1;
+    double frmax = 0, dFr = 0;
+    for (int k = 0; k < 3 * N; ++k) {
+        frmax = frmax > fabs(Fr0[k]) ? frmax : fabs(Fr0[k]);
+        dFr = fabs(Fr1[k] - Fr0[k]) > dFr ? fabs(Fr1[k] - Fr0[k]) : dFr;
+    }
+    printf("radial form: E whole %.12f  split %.12f  naive %.12f  max|dF| %.2e\n", Er0, Er1, Er2, dFr);
+    bad = bad || fabs(Er1 - Er0) > 1e-10 * fabs(Er0) || dFr > 1e-9 * frmax;
+    free(msg); free(en); free(row); free(jj); free(sh);
     return bad ? 2 : 0;
 }

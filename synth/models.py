@@ -19,6 +19,10 @@ Hyper-parameters (Sec. 2.1, Eq. (1)-(2)):
     ang_scale  factor applied to the displacement in the angular part
     energy_scale factor applied to the energy NN output
 
+Message forms: "reann" (Eqs. (1)-(2): paired density features) and "radial" (a second,
+invariant form on the same exchange: L = 0, the K orbital sums are the features, and
+messages are updated with a residual c^{t+1} = c^t + M(x^t)); F = K for "radial".
+
 Flat parameter layout (float64), shared as a data format only:
     one atomic NN with dims [d0, d1, ..., dn] is, for k = 1..n, the row-major
     weight W_k [d_k, d_{k-1}] followed by the bias b_k [d_k];
@@ -38,8 +42,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 
-def n_features(L: int, K: int) -> int:
-    return (L + 1) * K * (K + 1) // 2
+def n_features(L: int, K: int, form: str = "reann") -> int:
+    return K if form == "radial" else (L + 1) * K * (K + 1) // 2
 
 
 def mlp_dims(F: int, hidden: int, n_hidden: int, out: int) -> list[int]:
@@ -67,6 +71,7 @@ class ModelParams:
     ang_scale: float = 1.0
     energy_scale: float = 1.0
     meta: dict = field(default_factory=dict)
+    form: str = "reann"
 
     @property
     def n_species(self) -> int:
@@ -74,17 +79,19 @@ class ModelParams:
 
     @property
     def F(self) -> int:
-        return n_features(self.L, self.K)
+        return n_features(self.L, self.K, self.form)
 
 
 def make_model(elements, L=2, K=8, r_c=5.0, width=0.5, centre_range=None, n_hidden=2,
                hidden=64, T_max=2, seed=0, bias_std=0.0, c0_std=1.0, ang_scale=1.0,
-               energy_scale=1.0, w1_scale=1.0) -> ModelParams:
+               energy_scale=1.0, w1_scale=1.0, form="reann") -> ModelParams:
     """Draw a model.  Centres are linspace(lo, hi, K) with (lo, hi) = centre_range
     (default (0, r_c)); every exponent is 1/(2 width^2)."""
     rng = np.random.default_rng(seed)
     ns = len(elements)
-    F = n_features(L, K)
+    if form not in ("reann", "radial") or (form == "radial" and L != 0):
+        raise ValueError("form 'radial' takes L = 0; forms: 'reann', 'radial'")
+    F = n_features(L, K, form)
     lo, hi = centre_range if centre_range is not None else (0.0, r_c)
     centres = np.linspace(lo, hi, K)
     alphas = np.full(K, 1.0 / (2.0 * width * width))
@@ -109,7 +116,7 @@ def make_model(elements, L=2, K=8, r_c=5.0, width=0.5, centre_range=None, n_hidd
                        msg_blob=np.ascontiguousarray(msg_blob, dtype=np.float64),
                        energy_blob=np.ascontiguousarray(np.concatenate(en), dtype=np.float64),
                        ang_scale=float(ang_scale), energy_scale=float(energy_scale),
-                       meta=dict(seed=seed, width=width, bias_std=bias_std, w1_scale=w1_scale))
+                       meta=dict(seed=seed, width=width, bias_std=bias_std, w1_scale=w1_scale), form=form)
 
 
 def unpack_mlp(blob: np.ndarray, dims: list[int], index: int):
@@ -162,3 +169,21 @@ def serving_model(T_max=3, seed=0, **kw) -> ModelParams:
     kw = {**dict(bias_std=1.0, w1_scale=2.0, ang_scale=1.0 / 5.0), **kw}
     return make_model(["H", "O", "Cu"], L=2, K=12, r_c=5.0, width=0.5, n_hidden=3,
                       hidden=128, T_max=T_max, seed=seed, **kw)
+
+
+def cu_model_radial(T_max=3, seed=0, **kw) -> ModelParams:
+    """The Cu model's sizes in the radial message form: L = 0, 12 Gaussians centred uniformly
+    on [0, 6] A, width 0.5 A, r_c = 6 A, three hidden layers of 128 SiLU units, F = K = 12
+    features, residual message updates, element (Cu,)."""
+    kw = {**dict(bias_std=1.0, w1_scale=1.0), **kw}
+    return make_model(["Cu"], L=0, K=12, r_c=6.0, width=0.5, n_hidden=3, hidden=128,
+                      T_max=T_max, seed=seed, form="radial", **kw)
+
+
+def water_model_radial(T_max=3, seed=0, **kw) -> ModelParams:
+    """The water model's sizes in the radial message form: L = 0, 8 Gaussians centred
+    uniformly on [0, 5] A, width 0.5 A, r_c = 5 A, two hidden layers of 64 SiLU units,
+    F = K = 8 features, residual message updates, elements (H, O)."""
+    kw = {**dict(bias_std=1.0, w1_scale=1.0), **kw}
+    return make_model(["H", "O"], L=0, K=8, r_c=5.0, width=0.5, n_hidden=2, hidden=64,
+                      T_max=T_max, seed=seed, form="radial", **kw)

@@ -30,9 +30,14 @@ MUTATIONS = {
     "radial gradient not projected on d / r": ("A[l] * radial * d[k] / r);", "A[l] * radial * d[k]);"),
     "message adjoint without the cutoff": ("cb += s * A[l] * R * fc;", "cb += s * A[l] * R;"),
     "energy scale missing in the backward": ("                double rho[1024], rhobar[1024], ybar = m->energy_scale;\n"
-                                             "                om_density(&C.q, m->L, K, S[p][T - 1]",
+                                             "                om_features(m, &C.q, S[p][T - 1]",
                                              "                double rho[1024], rhobar[1024], ybar = 1.0;\n"
-                                             "                om_density(&C.q, m->L, K, S[p][T - 1]"),
+                                             "                om_features(m, &C.q, S[p][T - 1]"),
+    "radial form without the residual update": ("ci[k] += c[p][t][i * K + k];", "ci[k] += 0.0;"),
+    "radial adjoint without the residual": ("for (int64_t x = 0; x < n * K; ++x) cbglob[x] += cbnext[x];",
+                                            "for (int64_t x = 0; x < n * K; ++x) cbglob[x] += 0.0 * cbnext[x];"),
+    "radial features squared": ("{ memcpy(rho, S, sizeof(double) * m->K); return; }",
+                                "{ for (int k = 0; k < m->K; ++k) rho[k] = S[k] * fabs(S[k]); return; }"),
     "halo one cutoff short": ("rc = om_domain_build(&g, species, p, rcut, T * rcut, 1, &D);",
                               "rc = om_domain_build(&g, species, p, rcut, (T - 1) * rcut, 1, &D);"),
 }
@@ -51,7 +56,8 @@ def test_a_pin_catches_the_planted_mistake(tmp_path, name):
                            "-o", str(lib), str(mut), "-lm"])
     env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_radial.py")], cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=900)
     tail = (r.stdout + r.stderr)[-600:]
     assert r.returncode == 1, "no pin failed for the planted mistake %r:\n%s" % (name, tail)
