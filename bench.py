@@ -465,6 +465,28 @@ def precision_ladder(rn, torch, ctx, w, name, steps=20, warmup=3):
                 rungs=rungs)
 
 
+def message_forms(rn, torch, ctx, w, name, reann_ms, steps=10, warmup=2, Ts=(1, 2, 3, 4)):
+    """The second message form on the same exchange (the radial form: L = 0, the K orbital sums
+    as features, residual message updates) on the same system, list and skin: ms per
+    energy+force step at T = 3 in FP32 and BF16, and its cost against T in FP32."""
+    import synth
+    m = synth.models.cu_model_radial(T_max=max(Ts), seed=0) if name == "cu100800" else None
+    if m is None:
+        return None
+    n = len(w["system"]["pos"])
+    model = rn.Model(m)
+    rows = []
+    for prec in ("fp32", "bf16"):
+        ms = time_steps(rn, torch, ctx, model, w, 3, prec, steps, warmup)[0]
+        rows.append(dict(precision=prec, T=3, ms_per_step=round(ms, 4), atom_steps_per_s=round(n / (ms * 1e-3), 1)))
+        print("forms radial %s %.3f ms" % (prec, ms), file=sys.stderr, flush=True)
+    wr = dict(w, model=m)
+    sw = tsweep(rn, torch, ctx, model, wr, name + " (radial form)", "fp32", Ts, steps, warmup)
+    return dict(workload=describe(name, wr), form="radial: L = 0, F = K = %d features, residual updates" % m.K,
+                model=dict(K=m.K, n_hidden=m.n_hidden, hidden=m.hidden, r_c=m.r_c), rows=rows,
+                reann_form_fp32_ms_per_step=round(reann_ms, 4), tsweep=sw)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -604,6 +626,9 @@ def main():
         out["decomposed_water"] = decomposed_water(rn, torch, ctx)
         print("bench: halo ablation", file=sys.stderr, flush=True)
         out["halo_ablation"] = halo_ablation(rn, torch, ctx, out["decomposed_water"]["tsweep"]["rows"])
+        print("bench: message forms", file=sys.stderr, flush=True)
+        out["message_forms"] = message_forms(rn, torch, ctx, w, a.workload, ms_per_step if a.precision == "fp32"
+                                             else float("nan"))
     if not a.no_serve:
         print("bench: MD-amortised run", file=sys.stderr, flush=True)
         out["md_amortised"] = md_amortised(rn, w, a.precision)

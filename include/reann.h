@@ -88,18 +88,30 @@ const char *reann_last_error(void);
  *                           b_1 [d1], W_2, b_2, ...
  *   msg                     (T_max - 1) * n_species message NNs (out = K), ordered t-major
  *   en                      n_species energy NNs (out = 1); E_i = energy_scale * NN(rho_i^{T-1})
- * Supported (L, K): (2, 8), (2, 12), (1, 4), (2, 4); n_hidden 1..4; hidden <= 256. */
+ *   form                    REANN_FORM_REANN: the above (Eqs. (1)-(2)).  REANN_FORM_RADIAL: a
+ *                           second message form on the same per-layer exchange (Sec. 2.2, the
+ *                           paragraph on other MPNNs that aggregate messages over neighbours):
+ *                           L = 0, the K orbital sums themselves are the features,
+ *                           x_i[m] = sum_j c_j[m] R_m(r_ij) f_c(r_ij) (F = K), and messages are
+ *                           updated with a residual, c_i^{t+1} = c_i^t + NN^t(x_i^t);
+ *                           E_i = energy_scale * NN(x_i^{T-1}).  FP64, FP32 and BF16 only.
+ * Supported (L, K): (2, 8), (2, 12), (1, 4), (2, 4) with REANN_FORM_REANN; (0, 8), (0, 12) with
+ * REANN_FORM_RADIAL; n_hidden 1..4; hidden <= 256. */
+#define REANN_FORM_REANN 0
+#define REANN_FORM_RADIAL 1
 typedef struct {
     int32_t n_species, L, K, T_max, n_hidden, hidden;
     double r_c, ang_scale, energy_scale;
     const double *centres, *alphas, *c0, *msg, *en;
+    int32_t form;
 } reann_model_desc;
 
 reann_status reann_model_create(const reann_model_desc *desc, reann_model **out);
 /* The same model from files.  spec_json_path: a JSON object with the members
  *   "format": "reann-model", "version": 1, n_species, L, K, T_max, n_hidden, hidden, r_c,
- *   ang_scale, energy_scale (numbers) and "weights": path of the weight file (relative paths
- *   are taken from the spec's directory); other members (e.g. element names) are ignored.
+ *   ang_scale, energy_scale (numbers), optionally "form": "reann" (the default) or "radial",
+ *   and "weights": path of the weight file (relative paths are taken from the spec's
+ *   directory); other members (e.g. element names) are ignored.
  * The weight file is raw little-endian FP64: centres[K], alphas[K], c0[n_species][K], msg,
  * en, laid out as in reann_model_desc; its size must match the dimensions exactly.
  * REANN_E_INVALID for an unreadable or malformed spec or weight file. */

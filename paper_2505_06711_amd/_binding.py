@@ -33,7 +33,10 @@ class _ModelDesc(C.Structure):
                 ("n_hidden", C.c_int32), ("hidden", C.c_int32), ("r_c", C.c_double),
                 ("ang_scale", C.c_double), ("energy_scale", C.c_double),
                 ("centres", C.c_void_p), ("alphas", C.c_void_p), ("c0", C.c_void_p),
-                ("msg", C.c_void_p), ("en", C.c_void_p)]
+                ("msg", C.c_void_p), ("en", C.c_void_p), ("form", C.c_int32)]
+
+
+FORMS = {"reann": 0, "radial": 1}   # REANN_FORM_REANN, REANN_FORM_RADIAL
 
 
 class _Opts(C.Structure):
@@ -165,8 +168,10 @@ class Model:
         self.params = params
         self._keep = [_f64(params.centres), _f64(params.alphas), _f64(params.c0),
                       _f64(params.msg_blob if params.msg_blob.size else np.zeros(1)), _f64(params.energy_blob)]
+        self.form = getattr(params, "form", "reann")
         d = _ModelDesc(params.n_species, params.L, params.K, params.T_max, params.n_hidden, params.hidden,
-                       params.r_c, params.ang_scale, params.energy_scale, *[_p(a) for a in self._keep])
+                       params.r_c, params.ang_scale, params.energy_scale, *[_p(a) for a in self._keep],
+                       FORMS[self.form])
         h = _vp()
         check(lib.reann_model_create(C.byref(d), C.byref(h)))
         self.handle = h
@@ -186,6 +191,7 @@ class Model:
         self._keep = []
         spec = json.load(open(spec_json_path))
         self.r_c, self.T_max, self.K, self.L = float(spec["r_c"]), int(spec["T_max"]), int(spec["K"]), int(spec["L"])
+        self.form = spec.get("form", "reann")
         _LIVE["model"].add(self)
         return self
 
@@ -204,7 +210,7 @@ class Model:
         spec = dict(format="reann-model", version=1, n_species=int(p.n_species), L=int(p.L), K=int(p.K),
                     T_max=int(p.T_max), n_hidden=int(p.n_hidden), hidden=int(p.hidden), r_c=float(p.r_c),
                     ang_scale=float(p.ang_scale), energy_scale=float(p.energy_scale),
-                    elements=list(getattr(p, "elements", [])), weights=weights_name)
+                    form=getattr(p, "form", "reann"), elements=list(getattr(p, "elements", [])), weights=weights_name)
         with open(spec_json_path, "w") as f:
             json.dump(spec, f, indent=1)
 

@@ -91,7 +91,11 @@ reann_status reann_model_create(const reann_model_desc *d, reann_model **out) {
         REQUIRE(d && out, "NULL argument");
         REQUIRE(d->n_species >= 1 && d->n_species <= 64, "n_species must be in [1, 64]");
         REQUIRE(d->L >= 0 && d->K >= 1, "bad L or K");
-        const bool lk_ok = (d->L == 2 && (d->K == 8 || d->K == 12 || d->K == 4)) || (d->L == 1 && d->K == 4);
+        REQUIRE(d->form == REANN_FORM_REANN || d->form == REANN_FORM_RADIAL, "unknown message form");
+        const bool radial = d->form == REANN_FORM_RADIAL;
+        REQUIRE(radial == (d->L == 0), "the radial form takes L = 0, the REANN form L >= 1");
+        const bool lk_ok = radial ? (d->K == 8 || d->K == 12)
+                                  : ((d->L == 2 && (d->K == 8 || d->K == 12 || d->K == 4)) || (d->L == 1 && d->K == 4));
         if (!lk_ok) fail(REANN_E_UNSUPPORTED, "no kernels compiled for this (L, K)");
         REQUIRE(d->T_max >= 1 && d->T_max <= 16, "T_max must be in [1, 16]");
         REQUIRE(d->n_hidden >= 1 && d->n_hidden <= 4, "n_hidden must be in [1, 4]");
@@ -104,7 +108,8 @@ reann_status reann_model_create(const reann_model_desc *d, reann_model **out) {
         Model &M = m->impl;
         M.n_species = d->n_species; M.L = d->L; M.K = d->K; M.T_max = d->T_max;
         M.nh = d->n_hidden; M.H = d->hidden;
-        M.F = n_feat(d->L, d->K); M.NL = n_lambda(d->L);
+        M.form = d->form;
+        M.F = radial ? d->K : n_feat(d->L, d->K); M.NL = n_lambda(d->L);
         M.r_c = d->r_c; M.ang_scale = d->ang_scale; M.energy_scale = d->energy_scale;
         M.centres.assign(d->centres, d->centres + d->K);
         M.alphas.assign(d->alphas, d->alphas + d->K);
@@ -221,6 +226,12 @@ reann_status reann_model_load(const char *spec_json_path, reann_model **out) {
         d.n_species = integer("n_species"); d.L = integer("L"); d.K = integer("K"); d.T_max = integer("T_max");
         d.n_hidden = integer("n_hidden"); d.hidden = integer("hidden");
         d.r_c = num("r_c"); d.ang_scale = num("ang_scale"); d.energy_scale = num("energy_scale");
+        d.form = REANN_FORM_REANN;
+        if (kv.count("form")) {
+            const std::string &fm = kv.at("form");
+            if (fm == "radial") d.form = REANN_FORM_RADIAL;
+            else if (fm != "reann") fail(REANN_E_INVALID, "model spec: \"form\" must be \"reann\" or \"radial\"");
+        }
         REQUIRE(d.n_species >= 1 && d.n_species <= 64 && d.K >= 1 && d.K <= 64 && d.L >= 0 && d.L <= 4 &&
                     d.T_max >= 1 && d.T_max <= 16 && d.n_hidden >= 1 && d.n_hidden <= 4 && d.hidden >= 1 &&
                     d.hidden <= 256,
@@ -230,7 +241,7 @@ reann_status reann_model_load(const char *spec_json_path, reann_model **out) {
         const std::string sp(spec_json_path);
         const size_t slash = sp.find_last_of('/');
         if (!wpath.empty() && wpath[0] != '/' && slash != std::string::npos) wpath = sp.substr(0, slash + 1) + wpath;
-        const int F = n_feat(d.L, d.K);
+        const int F = d.form == REANN_FORM_RADIAL ? d.K : n_feat(d.L, d.K);
         const size_t nmsg = (size_t)(d.T_max - 1) * d.n_species * nn_doubles(F, d.hidden, d.n_hidden, d.K);
         const size_t nen = (size_t)d.n_species * nn_doubles(F, d.hidden, d.n_hidden, 1);
         const size_t total = 2 * (size_t)d.K + (size_t)d.n_species * d.K + nmsg + nen;

@@ -569,6 +569,8 @@ __global__ __launch_bounds__(256) void k_adj_gather(EdgeArgs a, CutList cl, cons
         else if ((L) == 2 && (K) == 12) { CALL(2, 12); }                           \
         else if ((L) == 1 && (K) == 4) { CALL(1, 4); }                             \
         else if ((L) == 2 && (K) == 4) { CALL(2, 4); }                             \
+        else if ((L) == 0 && (K) == 12) { CALL(0, 12); }                           \
+        else if ((L) == 0 && (K) == 8) { CALL(0, 8); }                             \
         else fail(REANN_E_UNSUPPORTED, "no edge kernel compiled for this (L, K)"); \
     } while (0)
 

@@ -485,6 +485,7 @@ constexpr int pair_split(int K) {
 
 // Forward of one element's NN over rows [0, rows): C = out_layer(SiLU(... SiLU(rho W_0^T + b_0) ...))
 // with rho the density of S.  NCB = H / 64 column blocks per wave; (L, K) fix the density.
+// L = 0 is the radial message form: its features are the K orbital sums S[0] themselves.
 template <OpType OP, int NCB, int L, int K>
 __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
     using T = typename Fuse<OP>::T;
@@ -516,8 +517,15 @@ __global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
     // zero padded to Fk columns.  One task per wave (lanes 0..31 take the tile's rows): the
     // orders l < L whole, and order L (the most components) split in two halves of its pairs,
     // so that no wave runs divergent code and the longest task is about half of order L.
-    static_assert(L == 1 || L == 2, "density tasks are laid out for L = 1, 2");
-    if (lane < BM) {
+    // The radial form (L = 0) copies the sums.
+    static_assert(L <= 2, "density tasks are laid out for L <= 2");
+    if constexpr (L == 0) {
+        for (int it = tid; it < BM * K; it += 256) {
+            const int r = it / K, f = it % K;
+            const int64_t row = min(m0 + r, p.rows - 1);
+            X[r * ldx + f] = to_op<OP>(p.S[row * K + f], OP == OpType::FP8 ? p.xinv[f] : 1.0f);
+        }
+    } else if (lane < BM) {
         constexpr int AS = pair_split(K);
         if (wave == 0) density_part<OP, L, K, 0, 0, (L == 1 ? K : K)>(p, X, ldx, m0, lane);
         if constexpr (L == 2) {
@@ -690,6 +698,14 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
             for (int r = 0; r < 4; ++r) Rb[(16 * rb + 4 * lg + r) * ldr + col] = acc[rb][cb][r];
         }
     __syncthreads();
+    // the radial form (L = 0): dE/dS = dE/dx
+    if constexpr (L == 0) {
+        for (int it = tid; it < BM * K; it += 256) {
+            const int r = it / K, f = it % K;
+            if (m0 + r < p.rows) p.C[(m0 + r) * K + f] = Rb[r * ldr + f];
+        }
+        return;
+    }
     // density adjoint: dE/dS[lambda][a] = w_lambda sum_b M_l[a][b] S[lambda][b] for lambda of
     // order l, with M_l the symmetric matrix of dE/drho[l] (doubled on the diagonal); one
     // thread per (row, lambda), S read from global
@@ -804,8 +820,8 @@ static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout, int NLK) {
 void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
     if (p.rows <= 0) return;
     const int NLK = p.dc.lstart[p.L + 1] * p.K;
-    if (!fused_nn_ok(op, p.F, p.H, p.nh, p.dout, NLK) || p.F != (p.L + 1) * p.K * (p.K + 1) / 2 ||
-        (p.dout != p.K && p.dout != 1))
+    const int Fwant = p.L == 0 ? p.K : (p.L + 1) * p.K * (p.K + 1) / 2;   // L = 0: the radial form
+    if (!fused_nn_ok(op, p.F, p.H, p.nh, p.dout, NLK) || p.F != Fwant || (p.dout != p.K && p.dout != 1))
         fail(REANN_E_DEVICE, "mlp_fused: unsupported layer shape");
     const size_t smem = fused_smem(op, fwd, p.F, p.H, p.dout, NLK);
     const dim3 grid((unsigned)((p.rows + kFuseBM - 1) / kFuseBM));
@@ -821,6 +837,8 @@ void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
     else if (p.L == 2 && p.K == 12) { NC_(OPV, 2, 12) }                                 \
     else if (p.L == 1 && p.K == 4) { NC_(OPV, 1, 4) }                                   \
     else if (p.L == 2 && p.K == 4) { NC_(OPV, 2, 4) }                                   \
+    else if (p.L == 0 && p.K == 12) { NC_(OPV, 0, 12) }                                 \
+    else if (p.L == 0 && p.K == 8) { NC_(OPV, 0, 8) }                                   \
     else fail(REANN_E_UNSUPPORTED, "mlp_fused: no kernel compiled for this (L, K)");
     if (op == OpType::F32) { ALL_(OpType::F32) }
     else if (op == OpType::BF16) { ALL_(OpType::BF16) }

@@ -432,4 +432,26 @@ void zero(hipStream_t st, void *p, size_t bytes) {
     LAUNCH_OK("k_zero");
 }
 
+// dst[t] += src[t] (and copy: dst[t] = src[t]) for t < count, in the working type; kernels, so
+// that the step can be captured in a HIP graph.
+template <typename R, bool ADD>
+__global__ void k_axpy1(int64_t count, R *__restrict__ dst, const R *__restrict__ src) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) dst[t] = ADD ? dst[t] + src[t] : src[t];
+}
+
+void add_into(hipStream_t st, bool fp64, int64_t count, void *dst, const void *src) {
+    if (count <= 0) return;
+    if (fp64) hipLaunchKernelGGL((k_axpy1<double, true>), dim3(grid_for(count, 256)), dim3(256), 0, st, count, (double *)dst, (const double *)src);
+    else hipLaunchKernelGGL((k_axpy1<float, true>), dim3(grid_for(count, 256)), dim3(256), 0, st, count, (float *)dst, (const float *)src);
+    LAUNCH_OK("k_axpy1");
+}
+
+void copy_into(hipStream_t st, bool fp64, int64_t count, void *dst, const void *src) {
+    if (count <= 0) return;
+    if (fp64) hipLaunchKernelGGL((k_axpy1<double, false>), dim3(grid_for(count, 256)), dim3(256), 0, st, count, (double *)dst, (const double *)src);
+    else hipLaunchKernelGGL((k_axpy1<float, false>), dim3(grid_for(count, 256)), dim3(256), 0, st, count, (float *)dst, (const float *)src);
+    LAUNCH_OK("k_axpy1");
+}
+
 }  // namespace reann

@@ -51,5 +51,8 @@ void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const 
 void forces_out(hipStream_t st, bool fp64, int64_t n, const void *F, const int32_t *perm, const double *g,
                 double *forces_user, const double *W, double *virial_out);
 void zero(hipStream_t st, void *p, size_t bytes);
+// dst += src, and dst = src, over `count` elements of the working type (FP64 or FP32)
+void add_into(hipStream_t st, bool fp64, int64_t count, void *dst, const void *src);
+void copy_into(hipStream_t st, bool fp64, int64_t count, void *dst, const void *src);
 
 }  // namespace reann

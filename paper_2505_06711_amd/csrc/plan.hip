@@ -179,6 +179,8 @@ void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const doubl
         fail(REANN_E_INVALID, "unknown precision");
     fp64 = prec == REANN_FP64;
     op = prec == REANN_BF16 ? OpType::BF16 : (prec == REANN_FP8 ? OpType::FP8 : OpType::F32);
+    if (op == OpType::FP8 && m->form == REANN_FORM_RADIAL)
+        fail(REANN_E_UNSUPPORTED, "the radial message form runs in FP64, FP32 or BF16");
     rs = fp64 ? 8 : 4;
     skin = opt ? opt->skin : 0.0;
     if (!(skin >= 0.0) || !std::isfinite(skin)) fail(REANN_E_INVALID, "skin must be >= 0");
@@ -269,7 +271,7 @@ void Plan::alloc_buffers() {
     p4.ensure(ne * 32);
     c.ensure((size_t)T * ne * K * rs);
     S.ensure((size_t)T * n * NL * K * rs);
-    if (!fused()) rho.ensure((size_t)T * n * F * rs);
+    if (!fused() && !radial()) rho.ensure((size_t)T * n * F * rs);
     Z.ensure((size_t)T * nh * n * H * rs);
     if (!fused()) Hh.ensure((size_t)2 * n * H * rs);
     y.ensure((size_t)n * K * rs);
@@ -277,7 +279,8 @@ void Plan::alloc_buffers() {
     Eat.ensure((size_t)n * 8);
     Epart.ensure((size_t)(grid_for(n, 256) + 1) * 8);
     Sbar.ensure((size_t)n * NL * K * rs);
-    if (!fused()) rhobar.ensure((size_t)n * F * rs);
+    if (!fused() && !radial()) rhobar.ensure((size_t)n * F * rs);
+    if (radial()) cbar_next.ensure((size_t)n * K * rs);
     if (!fused()) {
         const int wmax = F > H ? F : H;
         gA.ensure((size_t)n * wmax * rs);
@@ -301,7 +304,7 @@ size_t Plan::device_bytes() const {
     size_t b = 0;
     for (const DevBuf *d : {&p4, &c, &S, &rho, &Z, &Hh, &y, &ybar, &Eat, &Epart, &Sbar, &rhobar, &gA, &gB,
                             &cbar, &F, &Wpart, &Wacc, &disp, &col2, &fslot, &cpos, &rslot, &nloc, &ngh, &erec, &fp8s,
-                            &fp8tmp})
+                            &fp8tmp, &cbar_next})
         b += d->bytes;
     b += nl.perm.bytes() + nl.inv_perm.bytes() + nl.q.bytes() + nl.gh_owner.bytes() + nl.gh_shift.bytes() +
          nl.copy_ptr.bytes() + nl.copy_idx.bytes() + nl.row.bytes() + nl.col.bytes() + nl.rev.bytes() + nl.spec_ext.bytes() +
@@ -339,7 +342,7 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
         if (rows <= 0) continue;
         const int64_t nn_index = energy ? s : (int64_t)t * m->n_species + s;
         const char *p = blob + (size_t)nn_index * lay.size * rs;
-        const char *A = rhoptr(t) + (size_t)a * F * rs;
+        const char *A = featptr(t) + (size_t)a * F * rs;
         int lda = F;
         const bool f8 = fp8_fused();
         const MfmaSet *mf = fp64 ? nullptr : (f8 ? fp8set[energy ? 1 : 0].get() : &m->mfma(ctx->device, st, energy, op));
@@ -467,7 +470,8 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
             ldin = H;
             cur ^= 1;
         }
-        char *rb = rhobar.as<char>() + (size_t)a * F * rs;
+        // radial form: dE/dx is dE/dS (F = K, S is [n][1][K])
+        char *rb = (radial() ? Sbar.as<char>() : rhobar.as<char>()) + (size_t)a * F * rs;
         if (fp64) {
             dense(st, fp64, EPI_NONE, false, rows, lay.dout[0], F, gin, ldin, p + lay.w_off[0] * rs, nullptr, nullptr, 0,
                   rb, F);
@@ -610,12 +614,16 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
     for (int t = 0; t < T; ++t) {
         edge_forward(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sptr(t));
         mark(st, PH_EDGE_FWD, 1);
-        if (!fused()) {   // the fused NN kernels contract S themselves
+        if (!fused() && !radial()) {   // the fused NN kernels contract S themselves
             density(st, fp64, m->L, K, n, dc, Sptr(t), rhoptr(t));
             mark(st, PH_DENSITY, 1);
         }
         if (t < T - 1) {
             mark(st, PH_NN_FWD, nn_forward(st, t, false));
+            if (radial()) {   // c^{t+1} = c^t + NN(x^t) for the locals
+                add_into(st, fp64, n * K, cptr(t + 1), cptr(t));
+                mark(st, PH_OTHER);
+            }
             ghost_gather(st, fp64, n, nl.n_gh, K, nl.gh_owner.ptr(), cptr(t + 1));
             mark(st, PH_GHOST);
         }
@@ -641,7 +649,7 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     zero(st, this->F.p, (size_t)nl.n_ext * 3 * rs);
     mark(st, PH_OTHER);
     mark(st, PH_NN_BWD, nn_vjp(st, T - 1, true, ybar.as<char>(), 1));
-    if (!fused()) {
+    if (!fused() && !radial()) {
         density_vjp(st, fp64, m->L, K, n, dc, Sptr(T - 1), rhobar.p, Sbar.p);
         mark(st, PH_DENSITY_ADJ, 1);
     }
@@ -657,8 +665,13 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
         if (t > 0) {
             ghost_reduce(st, fp64, n, K, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), cbar.p);
             mark(st, PH_GHOST);
+            if (radial()) {   // c^t also reaches E through c^{t+1} = c^t + NN(x^t) (t < T - 1)
+                if (t < T - 1) add_into(st, fp64, n * K, cbar.p, cbar_next.p);
+                if (t > 1) copy_into(st, fp64, n * K, cbar_next.p, cbar.p);
+                mark(st, PH_OTHER);
+            }
             mark(st, PH_NN_BWD, nn_vjp(st, t - 1, false, cbar.as<char>(), K));
-            if (!fused()) {
+            if (!fused() && !radial()) {
                 density_vjp(st, fp64, m->L, K, n, dc, Sptr(t - 1), rhobar.p, Sbar.p);
                 mark(st, PH_DENSITY_ADJ, 1);
             }

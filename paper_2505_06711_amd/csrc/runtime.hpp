@@ -52,6 +52,7 @@ inline uint64_t next_model_id() {
 struct Model {
     const uint64_t id = next_model_id();
     int n_species, L, K, T_max, nh, H, F, NL;
+    int form = REANN_FORM_REANN;   // REANN_FORM_RADIAL: F = K features, residual message updates
     double r_c, ang_scale, energy_scale;
     std::vector<double> centres, alphas, c0, msg, en;
     NNLayout msg_nn, en_nn;
@@ -107,6 +108,7 @@ struct Plan {
     int64_t rebuilds = 0;
     // layer buffers
     DevBuf p4, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, Wacc, disp, one;
+    DevBuf cbar_next;                // radial form: dE/dc^{t+1} of the locals, carried by the residual
     DevBuf col2, fslot, cpos, rslot, nloc, ngh;   // in-cutoff compaction of the list for the current step
     DevBuf erec;                     // per-slot edge records of the adjoint
     DevBuf fp8s, fp8tmp;      // per-call activation scale for FP8 products
@@ -163,6 +165,10 @@ struct Plan {
     char *cptr(int t) const { return c.as<char>() + (size_t)t * nl.n_ext * m->K * rs; }
     char *Sptr(int t) const { return S.as<char>() + (size_t)t * n * m->NL * m->K * rs; }
     char *rhoptr(int t) const { return rho.as<char>() + (size_t)t * n * m->F * rs; }
+    bool radial() const { return m->form == REANN_FORM_RADIAL; }
+    // the atomic NNs' input at layer t: the density, or for the radial form the sums S[0]
+    // themselves (S is [n][1][K] there, the same layout as [n][F])
+    char *featptr(int t) const { return radial() ? Sptr(t) : rhoptr(t); }
     char *Zptr(int t, int k) const { return Z.as<char>() + ((size_t)t * m->nh + k) * n * m->H * rs; }
     // hidden activations of the per-layer (unfused) path: two buffers used in turn
     char *Hptr(int, int k) const { return Hh.as<char>() + (size_t)(k & 1) * n * m->H * rs; }

@@ -58,3 +58,29 @@ def test_load_rejects_bad_files(b, tmp_path):
     open(spec, "w").write("K = 12\n"); _expect_error(b, spec, "JSON")
     # no such file
     _expect_error(b, str(tmp_path / "missing.json"), "cannot open")
+
+
+def test_radial_form_save_then_load(b, tmp_path):
+    """The second message form's models: F = K features in the weight file, the form kept."""
+    p = models.water_model_radial(T_max=3, seed=5)
+    spec = str(tmp_path / "radial.json")
+    b.Model(p).save(spec)
+    d = json.load(open(spec))
+    assert d["form"] == "radial" and d["L"] == 0
+    w = np.fromfile(str(tmp_path / d["weights"]), dtype="<f8")
+    assert w.size == 2 * p.K + p.c0.size + p.msg_blob.size + p.energy_blob.size
+    m = b.Model.load(spec)
+    assert m.form == "radial" and (m.K, m.L) == (p.K, 0)
+    d["form"] = "spherical"
+    json.dump(d, open(spec, "w")); _expect_error(b, spec, "form")
+
+
+def test_form_and_L_must_agree(b):
+    p = models.water_model_radial(T_max=2, seed=6)
+    p.form = "reann"            # L = 0 is not a REANN model here
+    with pytest.raises(b.ReannError):
+        b.Model(p)
+    q = models.water_model(T_max=2, seed=6)
+    q.form = "radial"           # the radial form takes L = 0
+    with pytest.raises(b.ReannError):
+        b.Model(q)
