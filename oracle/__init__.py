@@ -38,7 +38,7 @@ class _Model(C.Structure):
                 ("centres", C.c_void_p), ("alphas", C.c_void_p), ("c0", C.c_void_p),
                 ("msg", C.c_void_p), ("en", C.c_void_p), ("form", C.c_int32)]
 
-FORMS = {"reann": 0, "radial": 1}   # message forms of reann_oracle.c (readings R1-R5, R10)
+FORMS = {"reann": 0, "radial": 1}   # message forms of reann_oracle.c (readings R1-R5, R14)
 
 
 def _load():

@@ -41,7 +41,7 @@
  *      ghosts of a subdomain are all copies (j,n) other than its own locals whose position
  *      lies within shell = r_c + skin + 1e-6 A of the subdomain box on every split or
  *      periodic axis.  Non-periodic axes are not split (P = 1) and not wrapped.
- *   R10 a second message form on the same exchange (Sec. 2.2, the paragraph on other
+ *   R14 a second message form on the same exchange (Sec. 2.2, the paragraph on other
  *      MPNNs that aggregate messages over neighbours, invariant ones such as SchNet among
  *      them): the "radial" form takes L = 0 and uses the orbital sum itself as the K
  *      features, x_i[m] = S_i[0][m] = sum_j c_j[m] R_m(r_ij) f_c(r_ij) (linear in the
@@ -65,7 +65,7 @@
 #define OM_ENOMEM (-3)
 
 #define OM_FORM_REANN 0
-#define OM_FORM_RADIAL 1   /* reading R10 */
+#define OM_FORM_RADIAL 1   /* reading R14 */
 
 typedef struct {
     int32_t n_species, L, K, T_max, n_hidden, hidden;
@@ -75,7 +75,7 @@ typedef struct {
     const double *c0;      /* [n_species][K] */
     const double *msg;     /* message NNs, see om_mlp_offset */
     const double *en;      /* energy NNs */
-    int32_t form;          /* OM_FORM_REANN (Eqs. (1)-(2)) or OM_FORM_RADIAL (reading R10) */
+    int32_t form;          /* OM_FORM_REANN (Eqs. (1)-(2)) or OM_FORM_RADIAL (reading R14) */
 } om_model;
 
 /* ---------------------------------------------------------------- helpers -- */
@@ -219,7 +219,7 @@ static void om_density_vjp(const om_lambda *q, int L, int K, const double *S, co
 }
 
 /* The NN input of an atom from its orbital sums: the density of Eq. (1), or for the radial
-   form (reading R10) the K sums of lambda = 0 themselves; and the adjoint of that map. */
+   form (reading R14) the K sums of lambda = 0 themselves; and the adjoint of that map. */
 static void om_features(const om_model *m, const om_lambda *q, const double *S, double *rho) {
     if (m->form == OM_FORM_RADIAL) { memcpy(rho, S, sizeof(double) * m->K); return; }
     om_density(q, m->L, m->K, S, rho);
@@ -653,7 +653,7 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
                 om_features(m, &C.q, S[p][t] + i * NL * K, rho);
                 double *ci = cglob + Dp->gid[i] * K;
                 om_mlp_forward(om_msg_params(m, t, Dp->spec[i]), F, H, nh, K, rho, ci);
-                if (radial)   /* residual update (reading R10) */
+                if (radial)   /* residual update (reading R14) */
                     for (int k = 0; k < K; ++k) ci[k] += c[p][t][i * K + k];
             }
         }

@@ -149,3 +149,34 @@ def test_radial_cu100800_fp32_against_oracle(rn, ctx, oracle_lib):
     m = models.cu_model_radial(T_max=3, seed=0)
     ref = oracle_lib.evaluate(m, w["system"], T=3, skin=w["skin"])
     check_fp32(*_eval(rn, ctx, m, w["system"], 3, "fp32", skin=w["skin"]), ref, "cu100800")
+
+
+def test_radial_md_decomposed_equals_whole_fp64(rn):
+    """The MD driver with the radial form: 20 velocity-Verlet steps (1 fs, skin 0.3 A, so the
+    list is rebuilt on the way) of a 648-atom water box split 2x2x2 equal the whole-system run
+    in FP64."""
+    import time
+    s = systems.water_box(grid=(6, 6, 6), spacing=systems.WATER_BOX_L / 4, seed=81)
+    m = models.water_model_radial(T_max=3, seed=81)
+    v0 = systems.maxwell_boltzmann(s["species"], ["H", "O"], 300.0, seed=10)
+    runs = {}
+    for dec in ((1, 1, 1), (2, 2, 2)):
+        srv = rn.Server(rn.Model(m), T=3, precision="fp64", skin=0.3, use_graph=True, decomp=dec)
+        srv.set_masses([systems.MASS_AMU[e] for e in ("H", "O")])
+        sid = srv.add_system(s, v0)
+        traj = []
+        for _ in range(20):
+            t = srv.submit_vv(sid, 1.0)
+            t0 = time.time()
+            while (r := srv.poll(t, sid, positions=True, velocities=True)) is None:
+                assert time.time() - t0 < 60.0
+                time.sleep(0.0002)
+            traj.append((r["energy"], r["positions"], r["velocities"]))
+        runs[dec] = (traj, srv.stats()["list_builds"])
+        srv.close()
+    L = np.diag(s["cell"]).max()
+    for x, y in zip(runs[(1, 1, 1)][0], runs[(2, 2, 2)][0]):
+        assert abs(x[0] - y[0]) <= 1e-12 * abs(x[0])
+        assert np.abs(x[1] - y[1]).max() <= 1e-12 * L
+        assert np.abs(x[2] - y[2]).max() <= 1e-12 * np.abs(x[2]).max()
+    assert runs[(2, 2, 2)][1] >= 2
