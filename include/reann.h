@@ -201,7 +201,8 @@ reann_status reann_energy_forces_noalloc(reann_ctx *ctx, const reann_model *m, c
  *                        if not NULL, d_atom_energy (device FP64 [n]).  Enqueued on hip_stream
  *                        (NULL = HIP's null stream, which is also PyTorch's default stream);
  *                        synchronises that stream once per call for the skin check, and
- *                        rebuilds the neighbour list when an atom has moved more than skin/2.
+ *                        rebuilds the neighbour list when an atom has moved more than skin/2
+ *                        (unless the plan's list policy leaves that to the caller, below).
  *   reann_plan_backward: gradient of E w.r.t. positions after a forward: d_grad_energy is a
  *                        device FP64 scalar g (NULL = 1); writes d_forces = -g dE/dx (device FP64
  *                        [n][3]) and, if not NULL, d_virial = g W (device FP64 [9]).  Enqueued
@@ -215,6 +216,22 @@ reann_status reann_plan_forward(reann_plan *p, const double *d_pos, double *d_en
 reann_status reann_plan_backward(reann_plan *p, const double *d_grad_energy, double *d_forces, double *d_virial,
                                  void *hip_stream);
 void reann_plan_free(reann_plan *p);
+
+/* Neighbour-list upkeep of a plan (Sec. 2.2: one list for r_c + skin, reused while every atom
+ * stays within skin/2 of where it was built).
+ *   reann_plan_set_list_policy: auto_check = 1 (the default): every reann_plan_forward checks
+ *     the skin rule (one stream synchronisation) and rebuilds the list when needed.
+ *     auto_check = 0: forwards use the current list as it is and make no host synchronisation
+ *     and no device allocation, so a forward + backward can be captured in a HIP graph and
+ *     replayed; the caller keeps the list valid with reann_plan_update_list (for instance every
+ *     few MD steps, or when its own bound on the displacement since the last build reaches
+ *     skin/2).  A forward before any list has been built returns REANN_E_STATE.
+ *   reann_plan_update_list: the skin check at positions d_pos (device FP64 [n][3]) on
+ *     hip_stream, and a rebuild when it fails or no list exists; synchronises that stream.
+ *     rebuilt (host int32, may be NULL) is set to 1 after a rebuild, else 0.  A rebuild may
+ *     move the plan's device buffers, so a graph captured before it must be captured again. */
+reann_status reann_plan_set_list_policy(reann_plan *p, int32_t auto_check);
+reann_status reann_plan_update_list(reann_plan *p, const double *d_pos, void *hip_stream, int32_t *rebuilt);
 
 /* Weights of the atomic energies in the plan's energy: E = sum_i w_i E_i, and the backward
  * gives the gradient of that weighted sum (forces, virial).  w: host [n] in caller order,

@@ -84,6 +84,8 @@ _SIGS = {
     "reann_plan_get": (_i32, [_vp, _i32, _i32, _vp]),
     "reann_plan_set_timing": (_i32, [_vp, _i32]),
     "reann_plan_generation": (_i32, [_vp, C.POINTER(C.c_uint64)]),
+    "reann_plan_set_list_policy": (_i32, [_vp, _i32]),
+    "reann_plan_update_list": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_int32)]),
     "reann_plan_set_energy_weights": (_i32, [_vp, _vp]),
     "reann_plan_timing": (_i32, [_vp, _vp, _vp, C.POINTER(_i64)]),
     "reann_server_create": (_i32, [_vp, C.POINTER(_ServerOpts), C.POINTER(_vp)]),
@@ -356,6 +358,20 @@ class Plan:
             _require_device_f64(virial, (3, 3))
             w = virial.data_ptr()
         check(load().reann_plan_backward(self.handle, g, forces.data_ptr(), w, self._stream(stream)))
+
+    def set_list_policy(self, auto_check: bool):
+        """True (the default): every forward checks the skin rule and rebuilds when needed (one
+        stream synchronisation).  False: forwards use the list as it is, with no host
+        synchronisation or allocation, so forward + backward can be captured in a graph; keep
+        the list valid with ``update_list``."""
+        check(load().reann_plan_set_list_policy(self.handle, int(bool(auto_check))))
+
+    def update_list(self, pos, stream=None) -> bool:
+        """Skin check at ``pos`` (device FP64 [n, 3]) and a rebuild if needed; True if rebuilt
+        (a graph captured earlier must then be captured again)."""
+        r = C.c_int32(0)
+        check(load().reann_plan_update_list(self.handle, pos.data_ptr(), self._stream(stream), C.byref(r)))
+        return bool(r.value)
 
     def set_energy_weights(self, w=None):
         """E = sum_i w_i E_i (w: [n] in caller order; None = all 1); the backward follows."""

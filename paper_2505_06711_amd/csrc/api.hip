@@ -602,6 +602,23 @@ reann_status reann_plan_get(reann_plan *p, int32_t what, int32_t t, double *host
     });
 }
 
+reann_status reann_plan_set_list_policy(reann_plan *p, int32_t auto_check) {
+    return guarded([&] {
+        REQUIRE(p, "NULL argument");
+        REQUIRE(auto_check == 0 || auto_check == 1, "auto_check must be 0 or 1");
+        p->impl.auto_list = auto_check != 0;
+    });
+}
+
+reann_status reann_plan_update_list(reann_plan *p, const double *d_pos, void *hip_stream, int32_t *rebuilt) {
+    return guarded([&] {
+        REQUIRE(p && d_pos, "NULL argument");
+        HIP_OK(hipSetDevice(p->impl.ctx->device));
+        const bool r = p->impl.prepare(d_pos, (hipStream_t)hip_stream);
+        if (rebuilt) *rebuilt = r ? 1 : 0;
+    });
+}
+
 reann_status reann_plan_set_energy_weights(reann_plan *p, const double *w) {
     return guarded([&] {
         REQUIRE(p, "NULL argument");

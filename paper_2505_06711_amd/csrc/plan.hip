@@ -594,7 +594,7 @@ void Plan::calibrate_fp8(const double *d_pos, hipStream_t st) {
 
 void Plan::forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st) {
     mark(st, -1);
-    const bool rebuilt = prepare(d_pos, st);
+    const bool rebuilt = auto_list ? prepare(d_pos, st) : false;
     mark(st, PH_NLIST, rebuilt ? 1 : 0);
     launch_forward(d_pos, d_energy, d_atom_energy, st);
 }

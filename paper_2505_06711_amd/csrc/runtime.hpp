@@ -142,6 +142,8 @@ struct Plan {
     // skin check (one stream synchronisation) and rebuild if needed; true if rebuilt, in which
     // case device buffers may have moved
     bool prepare(const double *d_pos, hipStream_t st);
+    // false: forwards neither check the skin rule nor rebuild (reann_plan_set_list_policy)
+    bool auto_list = true;
     // the two halves of prepare: the skin check alone (true if the list was never built or an
     // atom has moved more than skin/2 since), and the rebuild (with the FP8 calibration the
     // first time), which allocates
