@@ -334,14 +334,14 @@ def serve_bench(rn, seconds=4.0, n_systems=256, seed=0):
     return out
 
 
-def time_steps(rn, torch, ctx, model, w, T, precision, steps, warmup, want_forces=False):
+def time_steps(rn, torch, ctx, model, w, T, precision, steps, warmup, want_forces=False, exchange="messages"):
     """ms per energy+force step of `w` at T (device-resident positions), and optionally the
     energy and forces of the last step (caller atom order)."""
     s = w["system"]
     pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
     E = torch.zeros((), dtype=torch.float64, device="cuda")
     F = torch.zeros_like(pos)
-    plan = rn.Plan(ctx, model, s, T=T, precision=precision, decomp=w["decomp"], skin=w["skin"])
+    plan = rn.Plan(ctx, model, s, T=T, precision=precision, decomp=w["decomp"], skin=w["skin"], exchange=exchange)
     for _ in range(1 + warmup):
         plan.forward(pos, E)
         plan.backward(F)
@@ -487,6 +487,39 @@ def message_forms(rn, torch, ctx, w, name, reann_ms, steps=10, warmup=2, Ts=(1, 
                 reann_form_fp32_ms_per_step=round(reann_ms, 4), tsweep=sw)
 
 
+def node_feature_exchange(rn, torch, ctx, w, name, steps=10, warmup=2, Ts=(1, 2, 3)):
+    """The communication the paper contrasts its scheme with (end of Sec. 2.2): exchanging node
+    features (here each ghost's orbital sums S^t, NL K values) and running the message NNs for
+    every ghost in every subdomain, against exchanging messages (K values) and running the NNs
+    for locals only.  Same results; ms per energy+force step on the Cu crystal against T, and
+    on the 1.2M-atom water box split 2x2x2 at T = 3, FP32."""
+    import synth
+    out = {}
+    cases = [(name, w, Ts)]
+    if name == "cu100800":
+        cases.append(("water1207296", synth.workload("water1207296"), (3,)))
+    for wname, ww, ts in cases:
+        m = ww["model"]
+        model = rn.Model(m)
+        n = len(ww["system"]["pos"])
+        info = rn.build_neighbors(ctx, ww["system"], m.r_c, ww["skin"], ww["decomp"]).info()
+        nl_ = (m.L + 1) * (m.L + 2) * (m.L + 3) // 6
+        rows = []
+        for T in ts:
+            r = dict(T=T)
+            for ex in ("messages", "node_features"):
+                ms = time_steps(rn, torch, ctx, model, ww, T, "fp32", steps, warmup, exchange=ex)[0]
+                r[ex + "_ms_per_step"] = round(ms, 4)
+                print("exchange %s %s T=%d %.3f ms" % (wname, ex, T, ms), file=sys.stderr, flush=True)
+            r["node_over_messages"] = round(r["node_features_ms_per_step"] / r["messages_ms_per_step"], 3)
+            rows.append(r)
+        out[wname] = dict(workload=describe(wname, ww), n_atoms=n, ghosts=info["n_ghosts"],
+                          message_nn_rows_per_layer=dict(messages=n, node_features=n + info["n_ghosts"]),
+                          values_exchanged_per_ghost_per_layer=dict(messages=m.K, node_features=nl_ * m.K),
+                          rows=rows)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -626,6 +659,8 @@ def main():
         out["decomposed_water"] = decomposed_water(rn, torch, ctx)
         print("bench: halo ablation", file=sys.stderr, flush=True)
         out["halo_ablation"] = halo_ablation(rn, torch, ctx, out["decomposed_water"]["tsweep"]["rows"])
+        print("bench: node-feature exchange", file=sys.stderr, flush=True)
+        out["node_feature_exchange"] = node_feature_exchange(rn, torch, ctx, w, a.workload)
         print("bench: message forms", file=sys.stderr, flush=True)
         out["message_forms"] = message_forms(rn, torch, ctx, w, a.workload, ms_per_step if a.precision == "fp32"
                                              else float("nan"))

@@ -129,12 +129,23 @@ void reann_model_free(reann_model *m);
 reann_status reann_ctx_create(int32_t device, void *hip_stream, reann_ctx **out);
 void reann_ctx_free(reann_ctx *ctx);
 
-/* Options of an evaluation.  Zero-initialised = FP32, whole system, no skin. */
+/* Options of an evaluation.  Zero-initialised = FP32, whole system, no skin, message
+ * exchange.
+ * exchange: what the subdomains exchange between MP layers.  REANN_EXCHANGE_MESSAGES (the
+ *   paper's scheme, Sec. 2.2): ghosts receive their owners' messages c^{t+1} and send back the
+ *   message adjoints.  REANN_EXCHANGE_NODE_FEATURES (the alternative the end of Sec. 2.2
+ *   contrasts with it, node-feature communication): ghosts receive their owners' orbital
+ *   sums S^t (NL K values instead of K), every subdomain evaluates the message NN for its
+ *   ghosts as well as its locals, and the adjoints sent back are dE/dS^t.  Same results, more
+ *   work and wider exchanges; FP64, FP32 and BF16 only. */
+#define REANN_EXCHANGE_MESSAGES 0
+#define REANN_EXCHANGE_NODE_FEATURES 1
 typedef struct {
     int32_t precision;   /* REANN_FP64 / FP32 / BF16 / FP8                                 */
     int32_t decomp[3];   /* subdomains per axis; {0,0,0} or {1,1,1} = whole system          */
     double skin;         /* neighbour-list skin (A); the list is rebuilt when an atom has
                             moved more than skin/2 since the last build                    */
+    int32_t exchange;    /* REANN_EXCHANGE_MESSAGES or REANN_EXCHANGE_NODE_FEATURES          */
 } reann_opts;
 
 /* ------------------------------------------------------------- neighbours --

@@ -40,7 +40,10 @@ FORMS = {"reann": 0, "radial": 1}   # REANN_FORM_REANN, REANN_FORM_RADIAL
 
 
 class _Opts(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("decomp", C.c_int32 * 3), ("skin", C.c_double)]
+    _fields_ = [("precision", C.c_int32), ("decomp", C.c_int32 * 3), ("skin", C.c_double), ("exchange", C.c_int32)]
+
+
+EXCHANGES = {"messages": 0, "node_features": 1}   # REANN_EXCHANGE_MESSAGES, REANN_EXCHANGE_NODE_FEATURES
 
 
 class _ServerOpts(C.Structure):
@@ -152,12 +155,13 @@ def _i32a(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
-def _opts(precision="fp32", decomp=(1, 1, 1), skin=0.0) -> _Opts:
+def _opts(precision="fp32", decomp=(1, 1, 1), skin=0.0, exchange="messages") -> _Opts:
     o = _Opts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     for a in range(3):
         o.decomp[a] = int(decomp[a])
     o.skin = float(skin)
+    o.exchange = EXCHANGES[exchange] if isinstance(exchange, str) else int(exchange)
     return o
 
 
@@ -289,9 +293,10 @@ def build_neighbors(ctx: Context, system: dict, r_c: float, skin: float = 0.0, d
 
 
 def energy_forces(ctx: Context, model: Model, system: dict, T: int, precision="fp32", decomp=(1, 1, 1),
-                  skin: float = 0.0, forces: bool = True, noalloc: bool = False):
+                  skin: float = 0.0, forces: bool = True, noalloc: bool = False, exchange="messages"):
     """Host-pointer evaluation: returns (E, F[n,3] or None, W[3,3] or None).  noalloc=True
-    calls reann_energy_forces_noalloc (no device allocation; bounded system size)."""
+    calls reann_energy_forces_noalloc (no device allocation; bounded system size).  exchange:
+    "messages" (the paper's per-layer exchange) or "node_features" (see reann_opts)."""
     pos = _f64(system["pos"])
     spec = _i32a(system["species"])
     cell = _f64(system["cell"], (9,))
@@ -300,7 +305,7 @@ def energy_forces(ctx: Context, model: Model, system: dict, T: int, precision="f
     E = np.zeros(1)
     F = np.zeros((n, 3)) if forces else None
     W = np.zeros(9) if forces else None
-    o = _opts(precision, decomp, skin)
+    o = _opts(precision, decomp, skin, exchange)
     fn = load().reann_energy_forces_noalloc if noalloc else load().reann_energy_forces
     check(fn(ctx.handle, model.handle, _p(pos), _p(spec), n, _p(cell), _p(pbc), float(model.r_c), int(T),
              C.byref(o), _p(E), _p(F), _p(W)))
@@ -312,7 +317,7 @@ class Plan:
     tensors on the context's GPU; the stream defaults to torch's current stream."""
 
     def __init__(self, ctx: Context, model: Model, system: dict, T: int, precision="fp32", decomp=(1, 1, 1),
-                 skin: float = 0.0):
+                 skin: float = 0.0, exchange="messages"):
         lib = load()
         self.ctx, self.model = ctx, model
         spec = _i32a(system["species"])
@@ -320,7 +325,7 @@ class Plan:
         pbc = _i32a(system["pbc"])
         self.n = spec.shape[0]
         self.T = T
-        o = _opts(precision, decomp, skin)
+        o = _opts(precision, decomp, skin, exchange)
         h = _vp()
         check(lib.reann_plan_create(ctx.handle, model.handle, _p(spec), self.n, _p(cell), _p(pbc), int(T),
                                     C.byref(o), C.byref(h)))

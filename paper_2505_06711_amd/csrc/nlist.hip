@@ -165,10 +165,12 @@ __device__ inline int bin_of(const Bins &b, const double *y) {
     return (c[0] * b.nb[1] + c[1]) * b.nb[2] + c[2];
 }
 
-// Key of a pre-ext element: locals (slot = species) then ghosts (slot = n_species).
+// Key of a pre-ext element: locals (slot = species) then ghosts (slot = n_species, or with
+// ghosts_by_species n_species + the owner's species).
 __global__ void k_keys(Bins b, int ndom, int n_species, int64_t n, int64_t n_gh, const double *__restrict__ w,
                        const int32_t *__restrict__ dom, const int32_t *__restrict__ species, const double *__restrict__ g_pos,
-                       const int32_t *__restrict__ g_dom, int64_t *__restrict__ key, int32_t *__restrict__ count) {
+                       const int32_t *__restrict__ g_dom, const int32_t *__restrict__ g_owner, int ghosts_by_species,
+                       int64_t *__restrict__ key, int32_t *__restrict__ count) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n + n_gh) return;
     int slot, p;
@@ -177,7 +179,9 @@ __global__ void k_keys(Bins b, int ndom, int n_species, int64_t n, int64_t n_gh,
         slot = species[e]; p = dom[e]; bn = bin_of(b, w + 3 * e);
     } else {
         int64_t gi = e - n;
-        slot = n_species; p = g_dom[gi]; bn = bin_of(b, g_pos + 3 * gi);
+        slot = n_species + (ghosts_by_species ? species[g_owner[gi]] : 0);
+        p = g_dom[gi];
+        bn = bin_of(b, g_pos + 3 * gi);
     }
     int64_t k = ((int64_t)slot * ndom + p) * b.nbin + bn;
     key[e] = k;
@@ -326,7 +330,7 @@ __global__ void k_ghost_owner(int64_t n_gh, const int32_t *__restrict__ owner_us
 // Candidate scan over the 27 bins around atom x of its subdomain.  Locals see every
 // ext atom of the subdomain; ghosts see only locals.
 template <bool FILL>
-__global__ void k_rows(Bins b, Geom g, int n_species, int64_t n, int64_t n_ext, const double *__restrict__ pext,
+__global__ void k_rows(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t n, int64_t n_ext, const double *__restrict__ pext,
                        const int32_t *__restrict__ dom_ext, const int32_t *__restrict__ bin_ext,
                        const int64_t *__restrict__ kstart, int64_t *__restrict__ rowcnt, const int64_t *__restrict__ row,
                        int32_t *__restrict__ col) {
@@ -336,7 +340,7 @@ __global__ void k_rows(Bins b, Geom g, int n_species, int64_t n, int64_t n_ext, 
     const int p = dom_ext[x];
     const int bx = bin_ext[x];
     const int c2 = bx % b.nb[2], c1 = (bx / b.nb[2]) % b.nb[1], c0 = bx / (b.nb[2] * b.nb[1]);
-    const int nslot = (x < n) ? n_species + 1 : n_species;
+    const int nslot = (x < n) ? n_species + n_ghost_slots : n_species;
     int64_t cnt = 0, o = FILL ? row[x] : 0;
     for (int d0 = -1; d0 <= 1; ++d0) {
         int a0 = c0 + d0;
@@ -474,7 +478,7 @@ int64_t scan_exclusive_i64(hipStream_t st, int64_t *d, int64_t n, DevBuf &tmp) {
 // gathered by one tiny kernel into one block and read with one copy: every read is a wait for
 // the stream, which behind other streams' work sharing a hardware queue can take far longer
 // than the work itself.
-constexpr int kPickMax = 96;
+constexpr int kPickMax = 160;
 struct Pick {
     const void *p[kPickMax];
     int8_t is32[kPickMax];   // 1: int32 (sign-extended); 0: eight bytes (int64, or a double's bits)
@@ -507,7 +511,7 @@ struct Picker {
 // --------------------------------------------------------------------- build --
 
 void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, int64_t n, int n_species,
-                 const Geom &g, double r_c, double skin, NList &nl, NListScratch &s) {
+                 const Geom &g, double r_c, double skin, NList &nl, NListScratch &s, bool ghosts_by_species) {
     if (n <= 0) fail(REANN_E_INVALID, "n must be > 0");
     if (n >= (int64_t)1 << 30) fail(REANN_E_UNSUPPORTED, "too many atoms");
     const int B = 256;
@@ -569,7 +573,8 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
         b.bs[a] = nb > 1 ? ext / nb : 1.0;
         b.nbin *= nb;
     }
-    const int64_t nkeys = (int64_t)(n_species + 1) * g.ndom * b.nbin;
+    const int nghs = ghosts_by_species ? n_species : 1;   // ghost key slots
+    const int64_t nkeys = (int64_t)(n_species + nghs) * g.ndom * b.nbin;
     if (nkeys > ((int64_t)1 << 28)) fail(REANN_E_UNSUPPORTED, "bin table too large");
 
     int64_t *key = static_cast<int64_t *>(s.h.ensure(n_ext * sizeof(int64_t)));
@@ -577,7 +582,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     int64_t *kstart = static_cast<int64_t *>(s.j.ensure((nkeys + 1) * sizeof(int64_t)));
     HIP_OK(hipMemsetAsync(cnt32, 0, (nkeys + 1) * sizeof(int32_t), st));
     hipLaunchKernelGGL(k_keys, dim3(grid_for(n_ext, B)), dim3(B), 0, st, b, g.ndom, n_species, n, n_gh, w, dom,
-                       d_species, g_pos, g_dom, key, cnt32);
+                       d_species, g_pos, g_dom, g_owner, ghosts_by_species ? 1 : 0, key, cnt32);
     LAUNCH_OK("k_keys");
     hipLaunchKernelGGL(k_i32_to_i64, dim3(grid_for(nkeys + 1, B)), dim3(B), 0, st, cnt32, kstart, nkeys + 1);
     LAUNCH_OK("k_i32_to_i64");
@@ -613,7 +618,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     // rows: count, scan, fill
     int64_t *row = nl.row.resize(n_ext + 1);
     HIP_OK(hipMemsetAsync(row + n_ext, 0, sizeof(int64_t), st));
-    hipLaunchKernelGGL(k_rows<false>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, n, n_ext, pext,
+    hipLaunchKernelGGL(k_rows<false>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n, n_ext, pext,
                        d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr);
     LAUNCH_OK("k_rows<count>");
     scan_exclusive_async(st, row, n_ext, s.m);
@@ -624,17 +629,28 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
         pk.add(row + n, false);
         pk.add(kstart + nkeys, false);
         for (int sp = 0; sp <= n_species; ++sp) pk.add(kstart + (int64_t)sp * g.ndom * b.nbin, false);
+        if (ghosts_by_species)
+            for (int sp = 1; sp <= n_species; ++sp) pk.add(kstart + (int64_t)(n_species + sp) * g.ndom * b.nbin, false);
         pk.read(st, s.chk, hv);
     }
     const int64_t n_pairs = hv[0];
     if (hv[2] != n_ext) fail(REANN_E_DEVICE, "neighbour build: key count mismatch");
     nl.seg.assign(hv + 3, hv + 3 + n_species + 1);
+    // ghost species segments: [gseg[s], gseg[s+1]) are the ghosts of element s (ghosts_by_species),
+    // else one segment of every ghost
+    if (ghosts_by_species) {
+        nl.gseg.assign(1, n);
+        nl.gseg.insert(nl.gseg.end(), hv + 3 + n_species + 1, hv + 3 + 2 * n_species + 1);
+    } else {
+        nl.gseg = {n, n_ext};
+    }
+    if (nl.gseg.back() != n_ext) fail(REANN_E_DEVICE, "neighbour build: ghost segments mismatch");
     if (nl.seg[n_species] != n) fail(REANN_E_DEVICE, "neighbour build: species segments mismatch");
     if (n_pairs >= ((int64_t)1 << 31) - 1) fail(REANN_E_UNSUPPORTED, "too many neighbour pairs");
     nl.n_pairs = n_pairs;
     nl.n_local_pairs = hv[1];
     int32_t *col = nl.col.resize(n_pairs + 1);
-    hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, n, n_ext, pext,
+    hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n, n_ext, pext,
                        d_dom_ext, d_bin_ext, kstart, nullptr, row, col);
     LAUNCH_OK("k_rows<fill>");
     // rows ascending, then the reverse slot of every entry

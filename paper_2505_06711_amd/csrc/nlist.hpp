@@ -20,7 +20,8 @@ struct Geom {
 
 // Extended-atom layout: [0, n) are the local atoms of all subdomains, ordered by
 // (species, subdomain, spatial bin, caller index); [n, n_ext) are the ghost copies,
-// ordered by (subdomain, spatial bin, generation order).  Rows of locals list every
+// ordered by (subdomain, spatial bin, generation order), or with ghosts_by_species by
+// (species, subdomain, spatial bin, generation order).  Rows of locals list every
 // ext atom of the same subdomain within r_c + skin; rows of ghosts list only the
 // locals of their subdomain within r_c + skin (used by the atomics-free backward).
 // Every row is sorted ascending, so its locals come before its ghosts.
@@ -30,6 +31,7 @@ struct NList {
     int n_species = 0;
     double skin = 0, r_c = 0;
     std::vector<int64_t> seg;    // host: species segments over the locals, [n_species + 1]
+    std::vector<int64_t> gseg;   // host: species segments over the ghosts ([n, n_ext) if not by species)
     DArr<int32_t> perm;          // [n]   local -> caller index
     DArr<int32_t> inv_perm;      // [n]   caller -> local index
     DArr<int32_t> q;             // [n*3] integer wrap per axis, caller order: w = x - q L
@@ -53,7 +55,7 @@ void geom_init(Geom &g, const double cell[9], const int32_t pbc[3], const int32_
 
 // d_pos: device FP64 [n][3] (caller order); d_species: device int32 [n].
 void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, int64_t n, int n_species,
-                 const Geom &g, double r_c, double skin, NList &nl, NListScratch &s);
+                 const Geom &g, double r_c, double skin, NList &nl, NListScratch &s, bool ghosts_by_species = false);
 
 // Exclusive scan of n int64 values in place; returns the total (synchronises).
 int64_t scan_exclusive_i64(hipStream_t st, int64_t *d, int64_t n, DevBuf &tmp);

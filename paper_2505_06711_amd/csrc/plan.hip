@@ -181,6 +181,11 @@ void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const doubl
     op = prec == REANN_BF16 ? OpType::BF16 : (prec == REANN_FP8 ? OpType::FP8 : OpType::F32);
     if (op == OpType::FP8 && m->form == REANN_FORM_RADIAL)
         fail(REANN_E_UNSUPPORTED, "the radial message form runs in FP64, FP32 or BF16");
+    const int exch = opt ? opt->exchange : REANN_EXCHANGE_MESSAGES;
+    if (exch != REANN_EXCHANGE_MESSAGES && exch != REANN_EXCHANGE_NODE_FEATURES)
+        fail(REANN_E_INVALID, "unknown exchange");
+    nodefeat = exch == REANN_EXCHANGE_NODE_FEATURES;
+    if (nodefeat && op == OpType::FP8) fail(REANN_E_UNSUPPORTED, "node-feature exchange runs in FP64, FP32 or BF16");
     rs = fp64 ? 8 : 4;
     skin = opt ? opt->skin : 0.0;
     if (!(skin >= 0.0) || !std::isfinite(skin)) fail(REANN_E_INVALID, "skin must be >= 0");
@@ -217,7 +222,8 @@ bool Plan::same_system(const Model *mm, const int32_t *spec, int64_t nn, const d
     if (mm != m || mm->id != model_id || nn != n || TT != T) return false;
     const int pr = opt ? opt->precision : REANN_FP32;
     const double sk = opt ? opt->skin : 0.0;
-    if (pr != prec || sk != skin) return false;
+    const bool nf = opt && opt->exchange == REANN_EXCHANGE_NODE_FEATURES;
+    if (pr != prec || sk != skin || nf != nodefeat) return false;
     for (int a = 0; a < 3; ++a) {
         const int pa = (opt && opt->decomp[a] > 0) ? opt->decomp[a] : 1;
         if (pa != P[a] || (pbc_[a] != 0) != (pbc[a] != 0)) return false;
@@ -269,22 +275,23 @@ void Plan::alloc_buffers() {
     const int K = m->K, NL = m->NL, F = m->F, H = m->H, nh = m->nh;
     const int64_t ne = nl.n_ext;
     p4.ensure(ne * 32);
+    const int64_t ns = nS();
     c.ensure((size_t)T * ne * K * rs);
-    S.ensure((size_t)T * n * NL * K * rs);
-    if (!fused() && !radial()) rho.ensure((size_t)T * n * F * rs);
-    Z.ensure((size_t)T * nh * n * H * rs);
-    if (!fused()) Hh.ensure((size_t)2 * n * H * rs);
+    S.ensure((size_t)T * ns * NL * K * rs);
+    if (!fused() && !radial()) rho.ensure((size_t)T * ns * F * rs);
+    Z.ensure((size_t)T * nh * ns * H * rs);
+    if (!fused()) Hh.ensure((size_t)2 * ns * H * rs);
     y.ensure((size_t)n * K * rs);
     ybar.ensure((size_t)n * rs);
     Eat.ensure((size_t)n * 8);
     Epart.ensure((size_t)(grid_for(n, 256) + 1) * 8);
-    Sbar.ensure((size_t)n * NL * K * rs);
-    if (!fused() && !radial()) rhobar.ensure((size_t)n * F * rs);
-    if (radial()) cbar_next.ensure((size_t)n * K * rs);
+    Sbar.ensure((size_t)ns * NL * K * rs);
+    if (!fused() && !radial()) rhobar.ensure((size_t)ns * F * rs);
+    if (radial()) cbar_next.ensure((size_t)ns * K * rs);
     if (!fused()) {
         const int wmax = F > H ? F : H;
-        gA.ensure((size_t)n * wmax * rs);
-        gB.ensure((size_t)n * wmax * rs);
+        gA.ensure((size_t)ns * wmax * rs);
+        gB.ensure((size_t)ns * wmax * rs);
     }
     cbar.ensure((size_t)ne * K * rs);
     this->F.ensure((size_t)ne * 3 * rs);
@@ -323,11 +330,20 @@ bool Plan::list_stale(const double *d_pos, hipStream_t st) {
 }
 
 void Plan::rebuild(const double *d_pos, hipStream_t st) {
-    build_nlist(st, d_pos, d_species.ptr(), n, m->n_species, g, m->r_c, skin, nl, ns);
+    build_nlist(st, d_pos, d_species.ptr(), n, m->n_species, g, m->r_c, skin, nl, ns, nodefeat);
     built = true;
     ++rebuilds;
     alloc_buffers();
     if (fp8_fused() && !fp8_ready) calibrate_fp8(d_pos, st);
+}
+
+int Plan::nn_ranges(int s, bool energy, int64_t (&a)[2], int64_t (&rows)[2]) const {
+    a[0] = nl.seg[s];
+    rows[0] = nl.seg[s + 1] - nl.seg[s];
+    if (energy || !nodefeat) return 1;
+    a[1] = nl.gseg[s];
+    rows[1] = nl.gseg[s + 1] - nl.gseg[s];
+    return 2;
 }
 
 int Plan::nn_forward(hipStream_t st, int t, bool energy) {
@@ -338,7 +354,10 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
     const int F = m->F, H = m->H, nh = m->nh, K = m->K;
     int nfused = 0;
     for (int s = 0; s < m->n_species; ++s) {
-        const int64_t a = nl.seg[s], rows = nl.seg[s + 1] - nl.seg[s];
+      int64_t ra[2], rn[2];
+      const int nr = nn_ranges(s, energy, ra, rn);
+      for (int q = 0; q < nr; ++q) {
+        const int64_t a = ra[q], rows = rn[q];
         if (rows <= 0) continue;
         const int64_t nn_index = energy ? s : (int64_t)t * m->n_species + s;
         const char *p = blob + (size_t)nn_index * lay.size * rs;
@@ -403,6 +422,7 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
         } else
             out_layer_fwd(st, rows, H, dout, (const float *)A, lda, (const float *)(p + lay.w_off[nh] * rs),
                           (const float *)(p + lay.b_off[nh] * rs), (float *)out, dout);
+      }
     }
     return nfused;
 }
@@ -417,7 +437,10 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
     const int F = m->F, H = m->H, nh = m->nh;
     int nfused = 0;
     for (int s = 0; s < m->n_species; ++s) {
-        const int64_t a = nl.seg[s], rows = nl.seg[s + 1] - nl.seg[s];
+      int64_t ra[2], rn[2];
+      const int nr = nn_ranges(s, energy, ra, rn);
+      for (int q = 0; q < nr; ++q) {
+        const int64_t a = ra[q], rows = rn[q];
         if (rows <= 0) continue;
         const int64_t nn_index = energy ? s : (int64_t)t * m->n_species + s;
         const char *p = blob + (size_t)nn_index * lay.size * rs;
@@ -483,6 +506,7 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
                       mf->ld_bwd[qi], nullptr, nullptr, 0, (float *)rb, F, fp8s.as<float>(),
                       mf->scales.as<float>() + mf->sc_bwd[qi]);
         }
+      }
     }
     return nfused;
 }
@@ -614,18 +638,27 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
     for (int t = 0; t < T; ++t) {
         edge_forward(st, fp64, m->L, K, ea, cl, ec, cptr(t), Sptr(t));
         mark(st, PH_EDGE_FWD, 1);
+        // node-feature exchange: the ghosts' orbital sums come from their owners, and the
+        // message NN then runs over the ghosts as well
+        const bool ghost_nn = nodefeat && t < T - 1;
+        if (ghost_nn) {
+            ghost_gather(st, fp64, n, nl.n_gh, m->NL * K, nl.gh_owner.ptr(), Sptr(t));
+            mark(st, PH_GHOST);
+        }
         if (!fused() && !radial()) {   // the fused NN kernels contract S themselves
-            density(st, fp64, m->L, K, n, dc, Sptr(t), rhoptr(t));
+            density(st, fp64, m->L, K, ghost_nn ? nl.n_ext : n, dc, Sptr(t), rhoptr(t));
             mark(st, PH_DENSITY, 1);
         }
         if (t < T - 1) {
             mark(st, PH_NN_FWD, nn_forward(st, t, false));
-            if (radial()) {   // c^{t+1} = c^t + NN(x^t) for the locals
-                add_into(st, fp64, n * K, cptr(t + 1), cptr(t));
+            if (radial()) {   // c^{t+1} = c^t + NN(x^t) for the rows the NN ran over
+                add_into(st, fp64, nS() * K, cptr(t + 1), cptr(t));
                 mark(st, PH_OTHER);
             }
-            ghost_gather(st, fp64, n, nl.n_gh, K, nl.gh_owner.ptr(), cptr(t + 1));
-            mark(st, PH_GHOST);
+            if (!nodefeat) {
+                ghost_gather(st, fp64, n, nl.n_gh, K, nl.gh_owner.ptr(), cptr(t + 1));
+                mark(st, PH_GHOST);
+            }
         }
     }
     mark(st, PH_NN_FWD, nn_forward(st, T - 1, true));
@@ -663,17 +696,26 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
         edge_adjoint_gather(st, fp64, K, ea, cl, t > 0, t == T - 1, erec.p, this->F.p, cbar.p);
         mark(st, PH_ADJ_GATHER, 1);
         if (t > 0) {
-            ghost_reduce(st, fp64, n, K, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), cbar.p);
-            mark(st, PH_GHOST);
+            // message exchange: the ghosts' message adjoints go back to their owners here;
+            // node-feature exchange: the ghosts keep theirs (their message NN ran locally) and
+            // the adjoints of their orbital sums go back after the NN's VJP
+            if (!nodefeat) {
+                ghost_reduce(st, fp64, n, K, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), cbar.p);
+                mark(st, PH_GHOST);
+            }
             if (radial()) {   // c^t also reaches E through c^{t+1} = c^t + NN(x^t) (t < T - 1)
-                if (t < T - 1) add_into(st, fp64, n * K, cbar.p, cbar_next.p);
-                if (t > 1) copy_into(st, fp64, n * K, cbar_next.p, cbar.p);
+                if (t < T - 1) add_into(st, fp64, nS() * K, cbar.p, cbar_next.p);
+                if (t > 1) copy_into(st, fp64, nS() * K, cbar_next.p, cbar.p);
                 mark(st, PH_OTHER);
             }
             mark(st, PH_NN_BWD, nn_vjp(st, t - 1, false, cbar.as<char>(), K));
             if (!fused() && !radial()) {
-                density_vjp(st, fp64, m->L, K, n, dc, Sptr(t - 1), rhobar.p, Sbar.p);
+                density_vjp(st, fp64, m->L, K, nS(), dc, Sptr(t - 1), rhobar.p, Sbar.p);
                 mark(st, PH_DENSITY_ADJ, 1);
+            }
+            if (nodefeat) {   // the ghosts' dE/dS^{t-1} summed onto their owners
+                ghost_reduce(st, fp64, n, m->NL * K, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), Sbar.p);
+                mark(st, PH_GHOST);
             }
         }
     }

@@ -165,15 +165,21 @@ struct Plan {
     void calibrate_fp8(const double *d_pos, hipStream_t st);
     void alloc_buffers();
     char *cptr(int t) const { return c.as<char>() + (size_t)t * nl.n_ext * m->K * rs; }
-    char *Sptr(int t) const { return S.as<char>() + (size_t)t * n * m->NL * m->K * rs; }
-    char *rhoptr(int t) const { return rho.as<char>() + (size_t)t * n * m->F * rs; }
+    char *Sptr(int t) const { return S.as<char>() + (size_t)t * nS() * m->NL * m->K * rs; }
+    char *rhoptr(int t) const { return rho.as<char>() + (size_t)t * nS() * m->F * rs; }
     bool radial() const { return m->form == REANN_FORM_RADIAL; }
+    // node-feature exchange: ghosts carry their own S^t, Z and NN results for the message NNs
+    bool nodefeat = false;
+    int64_t nS() const { return nodefeat ? nl.n_ext : n; }   // rows of the per-layer NN buffers
     // the atomic NNs' input at layer t: the density, or for the radial form the sums S[0]
     // themselves (S is [n][1][K] there, the same layout as [n][F])
     char *featptr(int t) const { return radial() ? Sptr(t) : rhoptr(t); }
-    char *Zptr(int t, int k) const { return Z.as<char>() + ((size_t)t * m->nh + k) * n * m->H * rs; }
+    char *Zptr(int t, int k) const { return Z.as<char>() + ((size_t)t * m->nh + k) * nS() * m->H * rs; }
     // hidden activations of the per-layer (unfused) path: two buffers used in turn
-    char *Hptr(int, int k) const { return Hh.as<char>() + (size_t)(k & 1) * n * m->H * rs; }
+    char *Hptr(int, int k) const { return Hh.as<char>() + (size_t)(k & 1) * nS() * m->H * rs; }
+    // row ranges (first row, count) an NN of element s runs over: its locals, and for the
+    // message NNs under node-feature exchange its ghosts too
+    int nn_ranges(int s, bool energy, int64_t (&a)[2], int64_t (&rows)[2]) const;
     bool fused() const;
     // both return the launches of the fused NN kernel (0 on the per-layer path)
     int nn_forward(hipStream_t st, int t, bool energy);
