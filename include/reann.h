@@ -156,7 +156,10 @@ typedef struct {
  *   d = (w_j + shift*L) - w_i,  fma(dz,dz, fma(dy,dy, dx*dx)) < (r_c+skin)^2   (FP64),
  * where w is the position wrapped into [0, L) on periodic axes by
  *   w = x - floor(x/L)*L, then +L if negative, then -L if >= L.
- * pos: host [n][3].  The result stays on the device; export it with reann_nlist_export. */
+ * pos: host [n][3].  The result stays on the device; export it with reann_nlist_export.
+ * Every list build (here and inside evaluations and plans) returns REANN_E_INVALID for
+ * non-finite positions, |x| >= 1e9, or two copies closer than 1e-6 A (the direction of such
+ * a pair, and so its force, is undefined). */
 reann_status reann_build_neighbors(reann_ctx *ctx, const double *pos, int64_t n, const double cell[9],
                                    const int32_t pbc[3], double r_c, double skin, const int32_t decomp[3],
                                    reann_nlist **out);

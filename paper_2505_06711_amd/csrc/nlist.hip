@@ -333,7 +333,7 @@ template <bool FILL>
 __global__ void k_rows(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t n, int64_t n_ext, const double *__restrict__ pext,
                        const int32_t *__restrict__ dom_ext, const int32_t *__restrict__ bin_ext,
                        const int64_t *__restrict__ kstart, int64_t *__restrict__ rowcnt, const int64_t *__restrict__ row,
-                       int32_t *__restrict__ col) {
+                       int32_t *__restrict__ col, int32_t *__restrict__ coincident) {
     int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n_ext) return;
     const double xi = pext[x], yi = pext[n_ext + x], zi = pext[2 * n_ext + x];
@@ -361,6 +361,8 @@ __global__ void k_rows(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t
                         if (d2 < g.rc2) {
                             if (FILL) col[o++] = (int32_t)e;
                             else ++cnt;
+                            // two copies closer than 1e-6 A: the pair direction is undefined
+                            if (!FILL && d2 < 1e-12) atomicOr(coincident, 1);
                         }
                     }
                 }
@@ -618,8 +620,10 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     // rows: count, scan, fill
     int64_t *row = nl.row.resize(n_ext + 1);
     HIP_OK(hipMemsetAsync(row + n_ext, 0, sizeof(int64_t), st));
+    int32_t *coinc = static_cast<int32_t *>(s.coinc.ensure(64));
+    HIP_OK(hipMemsetAsync(coinc, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_rows<false>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n, n_ext, pext,
-                       d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr);
+                       d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr, coinc);
     LAUNCH_OK("k_rows<count>");
     scan_exclusive_async(st, row, n_ext, s.m);
     // second read: pair counts, the key total and the species segments of the locals
@@ -628,6 +632,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
         pk.add(row + n_ext, false);
         pk.add(row + n, false);
         pk.add(kstart + nkeys, false);
+        pk.add(coinc, true);
         for (int sp = 0; sp <= n_species; ++sp) pk.add(kstart + (int64_t)sp * g.ndom * b.nbin, false);
         if (ghosts_by_species)
             for (int sp = 1; sp <= n_species; ++sp) pk.add(kstart + (int64_t)(n_species + sp) * g.ndom * b.nbin, false);
@@ -635,12 +640,13 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     }
     const int64_t n_pairs = hv[0];
     if (hv[2] != n_ext) fail(REANN_E_DEVICE, "neighbour build: key count mismatch");
-    nl.seg.assign(hv + 3, hv + 3 + n_species + 1);
+    if (hv[3]) fail(REANN_E_INVALID, "two atoms (or an atom and a periodic copy) closer than 1e-6 A");
+    nl.seg.assign(hv + 4, hv + 4 + n_species + 1);
     // ghost species segments: [gseg[s], gseg[s+1]) are the ghosts of element s (ghosts_by_species),
     // else one segment of every ghost
     if (ghosts_by_species) {
         nl.gseg.assign(1, n);
-        nl.gseg.insert(nl.gseg.end(), hv + 3 + n_species + 1, hv + 3 + 2 * n_species + 1);
+        nl.gseg.insert(nl.gseg.end(), hv + 4 + n_species + 1, hv + 4 + 2 * n_species + 1);
     } else {
         nl.gseg = {n, n_ext};
     }
@@ -651,7 +657,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     nl.n_local_pairs = hv[1];
     int32_t *col = nl.col.resize(n_pairs + 1);
     hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n, n_ext, pext,
-                       d_dom_ext, d_bin_ext, kstart, nullptr, row, col);
+                       d_dom_ext, d_bin_ext, kstart, nullptr, row, col, nullptr);
     LAUNCH_OK("k_rows<fill>");
     // rows ascending, then the reverse slot of every entry
     hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n_ext, 4)), dim3(256), 0, st, n_ext, row, col);

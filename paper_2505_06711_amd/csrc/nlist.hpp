@@ -48,7 +48,7 @@ struct NList {
 
 // Scratch reused between builds.
 struct NListScratch {
-    DevBuf a, b, c, d, e, f, g, h, i, j, k, l, m, flag, mm, chk, dext, bext, gou;
+    DevBuf a, b, c, d, e, f, g, h, i, j, k, l, m, flag, mm, chk, dext, bext, gou, coinc;
 };
 
 void geom_init(Geom &g, const double cell[9], const int32_t pbc[3], const int32_t P[3], double r_c, double skin);

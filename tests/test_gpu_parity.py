@@ -580,3 +580,19 @@ def test_autograd_backward_after_another_forward_is_refused(rn, ctx, oracle_lib)
     ref = oracle_lib.evaluate(m, dict(s, pos=moved), T=2)
     np.testing.assert_allclose(-p2.grad.cpu().numpy(), ref["forces"], rtol=0,
                                atol=1e-10 * np.abs(ref["forces"]).max())
+
+
+@pytest.mark.parametrize("pbc", [(0, 0, 0), (1, 1, 1)])
+def test_coincident_atoms_are_refused(rn, ctx, pbc):
+    """Two atoms at the same place (within 1e-6 A) make the pair direction undefined; the list
+    build refuses them with REANN_E_INVALID instead of returning NaN forces."""
+    s = dict(pos=np.array([[1.0, 2.0, 3.0], [1.0, 2.0, 3.0 + 1e-8], [3.0, 2.0, 3.0]]),
+             species=np.array([0, 1, 0], np.int32), cell=np.eye(3) * 12.0, pbc=np.array(pbc, np.int32),
+             elements=["H", "O"])
+    m = models.water_model(T_max=2, seed=52)
+    with pytest.raises(rn.ReannError) as e:
+        _eval(rn, ctx, m, s, 2, "fp32")
+    assert e.value.status == -1
+    s["pos"][1, 2] = 3.0 + 1e-3      # 1e-3 A apart: a valid (if extreme) pair
+    E, F, W = _eval(rn, ctx, m, s, 2, "fp64")
+    assert np.isfinite(E) and np.isfinite(F).all()
