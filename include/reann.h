@@ -299,9 +299,12 @@ reann_status reann_plan_timing(reann_plan *p, double *ms, int64_t *launches, int
  * other requests are in flight.
  *   hbm_budget_bytes  device memory the resident systems may use (0 = 3/4 of free memory);
  *                     reann_system_add returns REANN_E_CAPACITY for a system that can never fit.
- *   max_batch_atoms   atoms evaluated together in one batched step (0 = 262144).
- *   precision, T, skin as in reann_opts.  use_graph != 0 replays a captured HIP graph for the
- *   batched step when the batch shape repeats.
+ *   max_batch_atoms   cap on the total atoms of the requests in flight at once (0 = 262144);
+ *                     a request that would exceed it waits (a lone request always runs).
+ *                     Requests are not packed into shared launches: each runs its own
+ *                     system's kernels on its own stream, up to 8 at a time.
+ *   precision, T, skin as in reann_opts.  use_graph != 0 replays each system's captured HIP
+ *   graph of the forward + backward while its neighbour list is unchanged.
  *   thermostat_K, thermostat_tau_fs: both > 0 ends every REANN_REQ_VV_STEP with a Berendsen
  *   velocity rescaling (Berendsen et al., J. Chem. Phys. 81, 3684 (1984)) toward
  *   thermostat_K with time constant thermostat_tau_fs: v *= sqrt(1 + (dt / tau)(T0 / T - 1)),
@@ -368,13 +371,19 @@ reann_status reann_system_add(reann_server *s, const int32_t *species, int64_t n
                               const int32_t pbc[3], const double *pos, const double *vel, uint64_t *sys_id);
 reann_status reann_submit(reann_server *s, const reann_request *req, uint64_t *ticket);
 /* Non-blocking: REANN_PENDING while running, REANN_OK when res is filled (the ticket is then
-   released), or a negative status. */
+   released), or a negative status.  A request that fails for its inputs (e.g. REANN_E_INVALID
+   from the neighbour build when the step brought two atoms within 1e-6 A) fails alone: its
+   system's device state is dropped, later requests for that system return REANN_E_STATE, and
+   the server keeps serving the others.  A device error fails every request and the server.
+   Test hook: with the environment variable REANN_SERVER_FAULT_TICKET=k set when the server is
+   created, request ticket k is refused as if its inputs were invalid. */
 reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res);
 /* Statistics, host [REANN_N_SERVER_STATS]: [0] engine rounds that admitted at least one
    request, [1] requests completed, [2] atoms evaluated, [3] HIP-graph replays, [4] admissions
    deferred for the HBM budget, [5] device bytes held by resident systems, [6] neighbour-list
-   builds (first builds and skin-rule rebuilds), [7] host nanoseconds the engine thread spent
-   enqueuing requests (admission, launches, copies), [8] of which in HIP-graph launches,
+   builds (first builds and skin-rule rebuilds), [7] host nanoseconds the launcher threads spent
+   enqueuing steps (launches, list checks and rebuilds, copies; summed over the threads), [8] of
+   which in HIP-graph launches,
    [9] host nanoseconds spent unpacking finished requests, [10] of [7] in neighbour-list
    builds, [11] of [7] in capturing and instantiating HIP graphs. */
 #define REANN_N_SERVER_STATS 12

@@ -15,6 +15,8 @@
 
 #include "runtime.hpp"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 namespace reann {
 
 NNLayout nn_layout(int F, int H, int nh, int out) {
@@ -232,7 +234,16 @@ bool Plan::same_system(const Model *mm, const int32_t *spec, int64_t nn, const d
     return std::memcmp(spec, species.data(), nn * sizeof(int32_t)) == 0;
 }
 
+// Phase names for the trace markers (the order of the Phase enumeration).
+static const char *const kPhaseName[REANN_N_PHASES] = {"reann: nlist",      "reann: edge forward", "reann: density",
+                                                        "reann: NN forward", "reann: ghost exchange", "reann: NN adjoint",
+                                                        "reann: density adjoint", "reann: edge adjoint (centre)",
+                                                        "reann: edge adjoint (gather)", "reann: other"};
+
 void Plan::mark(hipStream_t st, int phase, int nlaunch) {
+    // a host-side trace marker at the end of every phase's launches (rocprofv3 --marker-trace
+    // shows them beside the kernels); no cost without a tracing tool
+    if (phase >= 0 && phase < REANN_N_PHASES) roctxMarkA(kPhaseName[phase]);
     if (!timing) return;
     if (nev == ev.size()) {
         hipEvent_t e;
@@ -616,7 +627,18 @@ void Plan::calibrate_fp8(const double *d_pos, hipStream_t st) {
     fp8_ready = true;
 }
 
+namespace {
+// A host-side trace range over a scope (closed on every exit, exceptions included).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+}  // namespace
+
 void Plan::forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st) {
+    TraceRange range("reann: forward");
     mark(st, -1);
     const bool rebuilt = auto_list ? prepare(d_pos, st) : false;
     mark(st, PH_NLIST, rebuilt ? 1 : 0);
@@ -672,6 +694,7 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
 
 void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipStream_t st) {
     if (!have_forward) fail(REANN_E_STATE, "backward called before forward");
+    TraceRange range("reann: backward");
     const int K = m->K;
     EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), p4.as<double4>()};
     const CutList cl = cutlist();

@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <list>
@@ -206,6 +207,9 @@ struct Sys {
     size_t bytes = 0;
     int64_t last_used = 0;
     bool busy = false;
+    // set when a request of this system failed for its inputs: its device state was dropped
+    // (it may have been half updated), and later requests for it fail with REANN_E_STATE
+    std::string failed;
     ~Sys() {
         if (graph) (void)hipGraphExecDestroy(graph);
     }
@@ -235,13 +239,17 @@ struct Slot {
     // kFailed with the error in `err`
     std::atomic<int> state{0};
     std::string err;
+    reann_status err_code = REANN_E_DEVICE;
     Req req;
     Sys *sys = nullptr;
     double *h_out = nullptr;          // pinned: the result head, forces, positions, velocities
     size_t h_cap = 0;
 };
 
-constexpr int kQueued = 0, kLaunched = 1, kFailed = 2;
+// slot states: the launcher has the step (queued), enqueued it (launched), hit a device error
+// (failed: fatal for the server), or refused it for its inputs (rejected: only that request
+// fails, and its system is set aside)
+constexpr int kQueued = 0, kLaunched = 1, kFailed = 2, kRejected = 3;
 
 // Keeps HIP-graph captures apart from device allocation and release on the server's other
 // threads: work that may allocate or free (making a system resident, evicting it, pinned
@@ -309,16 +317,20 @@ struct reann_server {
     CaptureGate gate;
     int64_t budget = 0, in_flight_atoms = 0;
     std::atomic<int64_t> resident{0};
+    // test hook: the request with this ticket is refused as if its inputs were invalid
+    // (environment variable REANN_SERVER_FAULT_TICKET at server creation; -1 = none)
+    int64_t fault_ticket = -1;
     std::atomic<int64_t> stats[REANN_N_SERVER_STATS]{};
     std::string fatal;
 
     void run();
     void work();
     void enqueue(Slot &s);
+    void reject(Slot &s);
     bool admit(Req &r);
     void finish(Slot &s);
     bool make_resident(Sys &sy, int64_t need);
-    void evict(Sys &sy);
+    void evict(Sys &sy, bool copy_back = true);
     int64_t estimate_bytes(const Sys &sy) const;
     void launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid = false, const double *h_pos = nullptr);
 };
@@ -342,10 +354,10 @@ int64_t reann_server::estimate_bytes(const Sys &sy) const {
     return (int64_t)(b * 1.2) + (1 << 20);
 }
 
-void reann_server::evict(Sys &sy) {
+void reann_server::evict(Sys &sy, bool copy_back) {
     std::shared_lock<CaptureGate> alloc(gate);
     // bring the evolving state home, then release the device memory
-    if (sy.plan) {
+    if (sy.plan && copy_back) {
         // the system is idle: its last request's work is complete, so only these copies are waited for
         hipStream_t st = ctx.stream;
         HIP_OK(hipMemcpyAsync(sy.pos.data(), sy.d_pos.p, sy.n * 24, hipMemcpyDeviceToHost, st));
@@ -488,6 +500,16 @@ bool reann_server::admit(Req &r) {
     }
     Sys &sy = *syp;
     if (sy.busy) return false;
+    if (!sy.failed.empty()) {
+        Done d;
+        d.status = REANN_E_STATE;
+        d.error = "the system failed in an earlier request: " + sy.failed;
+        d.t_submit = r.t_submit;
+        d.t_done = now_ns();
+        std::lock_guard<std::mutex> lk(mu);
+        results[r.ticket] = std::move(d);
+        return true;   // consumed
+    }
     Slot *s = nullptr;
     for (auto &x : slots)
         if (!x.active) { s = &x; break; }
@@ -551,17 +573,45 @@ void reann_server::work() {
             enqueue(*s);
             stats[7] += now_ns() - t0;
             s->state.store(kLaunched, std::memory_order_release);
+        } catch (const Error &e) {
+            s->err = e.what();
+            s->err_code = e.code;
+            const bool device = e.code == REANN_E_DEVICE || e.code == REANN_E_NOMEM;
+            s->state.store(device ? kFailed : kRejected, std::memory_order_release);
         } catch (const std::exception &e) {
             s->err = e.what();
+            s->err_code = REANN_E_DEVICE;
             s->state.store(kFailed, std::memory_order_release);
         }
     }
+}
+
+// A request its launcher refused for its inputs (an invalid configuration found by the list
+// build, for instance): that request fails with the launcher's status, its system's device
+// state is dropped without a copy back, and the server goes on serving the others.
+void reann_server::reject(Slot &s) {
+    Sys &sy = *s.sys;
+    HIP_OK(hipStreamSynchronize(s.st));   // whatever the step enqueued before it stopped ends first
+    sy.failed = s.err;
+    evict(sy, false);
+    Done d;
+    d.status = s.err_code;
+    d.error = s.err;
+    d.t_submit = s.req.t_submit;
+    d.t_done = now_ns();
+    s.active = false;
+    sy.busy = false;
+    in_flight_atoms -= sy.n;
+    std::lock_guard<std::mutex> lk(mu);
+    results[s.req.ticket] = std::move(d);
 }
 
 void reann_server::enqueue(Slot &slot) {
     Slot *s = &slot;
     Sys &sy = *s->sys;
     Req &r = s->req;
+    if (fault_ticket >= 0 && (int64_t)r.ticket == fault_ticket)
+        fail(REANN_E_INVALID, "fault injected for this request (REANN_SERVER_FAULT_TICKET)");
     hipStream_t st = s->st;
     const int64_t n3 = sy.n * 3;
     const int B = 256;
@@ -666,6 +716,11 @@ void reann_server::run() {
                 if (!x.active) continue;
                 const int stt = x.state.load(std::memory_order_acquire);
                 if (stt == kFailed) throw Error(REANN_E_DEVICE, x.err);
+                if (stt == kRejected) {
+                    reject(x);
+                    progressed = true;
+                    continue;
+                }
                 if (stt == kLaunched && hipEventQuery(x.ev) == hipSuccess) {
                     const int64_t t0 = now_ns();
                     finish(x);
@@ -695,6 +750,10 @@ void reann_server::run() {
                 while ((stt = x.state.load(std::memory_order_acquire)) == kQueued)
                     std::this_thread::sleep_for(std::chrono::microseconds(50));
                 if (stt == kFailed) throw Error(REANN_E_DEVICE, x.err);
+                if (stt == kRejected) {
+                    reject(x);
+                    continue;
+                }
                 HIP_OK(hipEventSynchronize(x.ev));
                 finish(x);
             }
@@ -780,6 +839,7 @@ reann_status reann_server_create(const reann_model *m, const reann_server_opts *
             s->m->mfma(o->device, s->ctx.stream, false, op);
             s->m->mfma(o->device, s->ctx.stream, true, op);
         }
+        if (const char *ft = std::getenv("REANN_SERVER_FAULT_TICKET")) s->fault_ticket = std::atoll(ft);
         reann_server *raw = s.release();
         for (int k = 0; k < kWorkers; ++k) raw->workers.emplace_back([raw] { raw->work(); });
         raw->engine = std::thread([raw] { raw->run(); });

@@ -257,3 +257,63 @@ def test_eval_request_reports_no_kinetic_energy(rn, model_params):
     r = wait(srv, srv.submit_eval(sid, s["pos"]), sid)
     assert r["kinetic"] == 0.0
     srv.close()
+
+
+def test_injected_fault_fails_one_request_and_the_server_keeps_serving(rn, monkeypatch):
+    """A request refused for its inputs fails alone (here forced through the server's test hook
+    REANN_SERVER_FAULT_TICKET): its system is set aside (later requests get REANN_E_STATE), and
+    the other systems' requests complete and match a server without the fault."""
+    import time
+    m = rn.Model(models.serving_model(T_max=3, seed=7))
+    systems_ = mix(90, [120, 256, 180])
+
+    def run(fault):
+        if fault:
+            monkeypatch.setenv("REANN_SERVER_FAULT_TICKET", "2")
+        srv = rn.Server(m, T=3, precision="fp32", skin=0.5, use_graph=True)
+        monkeypatch.delenv("REANN_SERVER_FAULT_TICKET", raising=False)
+        ids = [srv.add_system(s) for s in systems_]
+        tickets = [(srv.submit_eval(sid, s["pos"]), sid) for sid, s in zip(ids, systems_)]   # tickets 1, 2, 3
+        out = {}
+        for t, sid in tickets:
+            t0 = time.time()
+            while True:
+                try:
+                    r = srv.poll(t, sid)
+                except rn.ReannError as e:
+                    r = e
+                if r is not None:
+                    break
+                assert time.time() - t0 < 60
+                time.sleep(0.0005)
+            out[t] = r
+        # a second round: the failed system is refused, the others still serve
+        again = {}
+        for sid, s in zip(ids, systems_):
+            t = srv.submit_eval(sid, s["pos"])
+            t0 = time.time()
+            while True:
+                try:
+                    r = srv.poll(t, sid)
+                except rn.ReannError as e:
+                    r = e
+                if r is not None:
+                    break
+                assert time.time() - t0 < 60
+                time.sleep(0.0005)
+            again[sid] = r
+        srv.close()
+        return ids, out, again
+
+    ids, ok, ok2 = run(False)
+    ids_f, bad, bad2 = run(True)
+    assert isinstance(bad[2], rn.ReannError) and bad[2].status == -1 and "injected" in str(bad[2])
+    for t in (1, 3):
+        assert not isinstance(bad[t], Exception)
+        assert bad[t]["energy"] == ok[t]["energy"]
+        np.testing.assert_array_equal(bad[t]["forces"], ok[t]["forces"])
+    failed_sid = ids_f[1]
+    assert isinstance(bad2[failed_sid], rn.ReannError) and bad2[failed_sid].status == -7
+    for k in (0, 2):
+        assert not isinstance(bad2[ids_f[k]], Exception)
+        assert bad2[ids_f[k]]["energy"] == ok2[ids[k]]["energy"]
