@@ -38,7 +38,7 @@ class _Model(C.Structure):
                 ("centres", C.c_void_p), ("alphas", C.c_void_p), ("c0", C.c_void_p),
                 ("msg", C.c_void_p), ("en", C.c_void_p), ("form", C.c_int32)]
 
-FORMS = {"reann": 0, "radial": 1}   # message forms of reann_oracle.c (readings R1-R5, R14)
+FORMS = {"reann": 0, "radial": 1, "diag": 2}   # forms of reann_oracle.c (readings R1-R5, R14, R15)
 
 
 def _load():

@@ -48,6 +48,8 @@
  *      neighbours' messages, a per-channel Gaussian filter), and updates messages with a
  *      residual, c_i^{t+1} = c_i^t + M^t_{s_i}(x_i^t); E_i = energy_scale * NN^E_{s_i}(x_i^{T-1}).
  *      Its adjoint carries dE/dc^{t+1} into dE/dc^t through the residual.
+ *   R15 the literal reading of Eq. (1) (the "diag" form): only the squares,
+ *      rho[l,a] = sum_{|lambda|=l} l!/lambda! S[lambda,a]^2, F = (L+1) K; everything else as R1-R5.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no contraction anywhere, so the
  * neighbour predicate is exactly the expression above).
@@ -66,6 +68,7 @@
 
 #define OM_FORM_REANN 0
 #define OM_FORM_RADIAL 1   /* reading R14 */
+#define OM_FORM_DIAG 2     /* reading R15 */
 
 typedef struct {
     int32_t n_species, L, K, T_max, n_hidden, hidden;
@@ -83,7 +86,11 @@ typedef struct {
 static int om_nlambda(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
 static int om_nfeat(int L, int K) { return (L + 1) * K * (K + 1) / 2; }
 /* features per atom: the paired density of Eq. (1), or the K orbital sums of the radial form */
-static int om_model_nfeat(const om_model *m) { return m->form == OM_FORM_RADIAL ? m->K : om_nfeat(m->L, m->K); }
+static int om_model_nfeat(const om_model *m) {
+    if (m->form == OM_FORM_RADIAL) return m->K;
+    if (m->form == OM_FORM_DIAG) return (m->L + 1) * m->K;
+    return om_nfeat(m->L, m->K);
+}
 
 static double om_fact(int n) { double f = 1.0; for (int k = 2; k <= n; ++k) f *= k; return f; }
 
@@ -221,13 +228,30 @@ static void om_density_vjp(const om_lambda *q, int L, int K, const double *S, co
 /* The NN input of an atom from its orbital sums: the density of Eq. (1), or for the radial
    form (reading R14) the K sums of lambda = 0 themselves; and the adjoint of that map. */
 static void om_features(const om_model *m, const om_lambda *q, const double *S, double *rho) {
-    if (m->form == OM_FORM_RADIAL) { memcpy(rho, S, sizeof(double) * m->K); return; }
-    om_density(q, m->L, m->K, S, rho);
+    const int K = m->K;
+    if (m->form == OM_FORM_RADIAL) { memcpy(rho, S, sizeof(double) * K); return; }
+    if (m->form == OM_FORM_DIAG) {   /* reading R15: the squares of Eq. (1) */
+        for (int l = 0; l <= m->L; ++l)
+            for (int a = 0; a < K; ++a) {
+                double s = 0.0;
+                for (int k = 0; k < q->n; ++k)
+                    if (q->l[k] == l) s += q->w[k] * S[k * K + a] * S[k * K + a];
+                rho[l * K + a] = s;
+            }
+        return;
+    }
+    om_density(q, m->L, K, S, rho);
 }
 static void om_features_vjp(const om_model *m, const om_lambda *q, const double *S, const double *rhobar,
                             double *Sbar) {
-    if (m->form == OM_FORM_RADIAL) { memcpy(Sbar, rhobar, sizeof(double) * m->K); return; }
-    om_density_vjp(q, m->L, m->K, S, rhobar, Sbar);
+    const int K = m->K;
+    if (m->form == OM_FORM_RADIAL) { memcpy(Sbar, rhobar, sizeof(double) * K); return; }
+    if (m->form == OM_FORM_DIAG) {
+        for (int k = 0; k < q->n; ++k)
+            for (int a = 0; a < K; ++a) Sbar[k * K + a] = 2.0 * q->w[k] * S[k * K + a] * rhobar[q->l[k] * K + a];
+        return;
+    }
+    om_density_vjp(q, m->L, K, S, rhobar, Sbar);
 }
 
 /* Cutoff (reading R3) and its derivative. */
@@ -607,7 +631,8 @@ int oracle_eval(const om_model *m, int64_t n, const double *pos, const int32_t *
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #endif
-    if (m->form != OM_FORM_REANN && !(m->form == OM_FORM_RADIAL && m->L == 0)) return OM_EINVAL;
+    if (m->form != OM_FORM_REANN && m->form != OM_FORM_DIAG && !(m->form == OM_FORM_RADIAL && m->L == 0))
+        return OM_EINVAL;
     const int radial = m->form == OM_FORM_RADIAL;
     om_ctx C; C.m = m; om_lambda_init(m->L, &C.q);
     C.K = m->K; C.F = om_model_nfeat(m); C.NL = C.q.n;

@@ -19,9 +19,10 @@ Hyper-parameters (Sec. 2.1, Eq. (1)-(2)):
     ang_scale  factor applied to the displacement in the angular part
     energy_scale factor applied to the energy NN output
 
-Message forms: "reann" (Eqs. (1)-(2): paired density features) and "radial" (a second,
-invariant form on the same exchange: L = 0, the K orbital sums are the features, and
-messages are updated with a residual c^{t+1} = c^t + M(x^t)); F = K for "radial".
+Message forms: "reann" (Eqs. (1)-(2): paired density features), "diag" (the literal reading of
+Eq. (1): only the squares, F = (L+1) K) and "radial" (a second, invariant form on the same
+exchange: L = 0, the K orbital sums are the features, and messages are updated with a
+residual c^{t+1} = c^t + M(x^t)); F = K for "radial".
 
 Flat parameter layout (float64), shared as a data format only:
     one atomic NN with dims [d0, d1, ..., dn] is, for k = 1..n, the row-major
@@ -43,7 +44,11 @@ import numpy as np
 
 
 def n_features(L: int, K: int, form: str = "reann") -> int:
-    return K if form == "radial" else (L + 1) * K * (K + 1) // 2
+    if form == "radial":
+        return K
+    if form == "diag":
+        return (L + 1) * K
+    return (L + 1) * K * (K + 1) // 2
 
 
 def mlp_dims(F: int, hidden: int, n_hidden: int, out: int) -> list[int]:
@@ -89,8 +94,8 @@ def make_model(elements, L=2, K=8, r_c=5.0, width=0.5, centre_range=None, n_hidd
     (default (0, r_c)); every exponent is 1/(2 width^2)."""
     rng = np.random.default_rng(seed)
     ns = len(elements)
-    if form not in ("reann", "radial") or (form == "radial" and L != 0):
-        raise ValueError("form 'radial' takes L = 0; forms: 'reann', 'radial'")
+    if form not in ("reann", "radial", "diag") or (form == "radial" and L != 0):
+        raise ValueError("form 'radial' takes L = 0; forms: 'reann', 'radial', 'diag'")
     F = n_features(L, K, form)
     lo, hi = centre_range if centre_range is not None else (0.0, r_c)
     centres = np.linspace(lo, hi, K)

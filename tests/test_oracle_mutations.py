@@ -36,8 +36,12 @@ MUTATIONS = {
     "radial form without the residual update": ("ci[k] += c[p][t][i * K + k];", "ci[k] += 0.0;"),
     "radial adjoint without the residual": ("for (int64_t x = 0; x < n * K; ++x) cbglob[x] += cbnext[x];",
                                             "for (int64_t x = 0; x < n * K; ++x) cbglob[x] += 0.0 * cbnext[x];"),
-    "radial features squared": ("{ memcpy(rho, S, sizeof(double) * m->K); return; }",
-                                "{ for (int k = 0; k < m->K; ++k) rho[k] = S[k] * fabs(S[k]); return; }"),
+    "radial features squared": ("{ memcpy(rho, S, sizeof(double) * K); return; }",
+                                "{ for (int k = 0; k < K; ++k) rho[k] = S[k] * fabs(S[k]); return; }"),
+    "diag features without the multinomial weights": ("if (q->l[k] == l) s += q->w[k] * S[k * K + a] * S[k * K + a];",
+                                                      "if (q->l[k] == l) s += S[k * K + a] * S[k * K + a];"),
+    "diag adjoint without the factor 2": ("Sbar[k * K + a] = 2.0 * q->w[k] * S[k * K + a]",
+                                          "Sbar[k * K + a] = q->w[k] * S[k * K + a]"),
     "halo one cutoff short": ("rc = om_domain_build(&g, species, p, rcut, T * rcut, 1, &D);",
                               "rc = om_domain_build(&g, species, p, rcut, (T - 1) * rcut, 1, &D);"),
 }
@@ -57,7 +61,8 @@ def test_a_pin_catches_the_planted_mistake(tmp_path, name):
     env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_radial.py")], cwd=ROOT, env=env,
+                        os.path.join(ROOT, "tests", "test_oracle_radial.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_diag.py")], cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=900)
     tail = (r.stdout + r.stderr)[-600:]
     assert r.returncode == 1, "no pin failed for the planted mistake %r:\n%s" % (name, tail)
