@@ -95,10 +95,15 @@ const char *reann_last_error(void);
  *                           x_i[m] = sum_j c_j[m] R_m(r_ij) f_c(r_ij) (F = K), and messages are
  *                           updated with a residual, c_i^{t+1} = c_i^t + NN^t(x_i^t);
  *                           E_i = energy_scale * NN(x_i^{T-1}).  FP64, FP32 and BF16 only.
- * Supported (L, K): (2, 8), (2, 12), (1, 4), (2, 4) with REANN_FORM_REANN; (0, 8), (0, 12) with
- * REANN_FORM_RADIAL; n_hidden 1..4; hidden <= 256. */
+ *                           REANN_FORM_DIAG: the literal reading of Eq. (1), only the squares,
+ *                           rho[l,a] = sum_{|lambda|=l} l!/lambda! S[lambda,a]^2 (F = (L+1) K),
+ *                           otherwise as REANN_FORM_REANN; runs on the per-layer NN kernels;
+ *                           FP64, FP32 and BF16 only.
+ * Supported (L, K): (2, 8), (2, 12), (1, 4), (2, 4) with REANN_FORM_REANN and REANN_FORM_DIAG;
+ * (0, 8), (0, 12) with REANN_FORM_RADIAL; n_hidden 1..4; hidden <= 256. */
 #define REANN_FORM_REANN 0
 #define REANN_FORM_RADIAL 1
+#define REANN_FORM_DIAG 2
 typedef struct {
     int32_t n_species, L, K, T_max, n_hidden, hidden;
     double r_c, ang_scale, energy_scale;
@@ -109,7 +114,7 @@ typedef struct {
 reann_status reann_model_create(const reann_model_desc *desc, reann_model **out);
 /* The same model from files.  spec_json_path: a JSON object with the members
  *   "format": "reann-model", "version": 1, n_species, L, K, T_max, n_hidden, hidden, r_c,
- *   ang_scale, energy_scale (numbers), optionally "form": "reann" (the default) or "radial",
+ *   ang_scale, energy_scale (numbers), optionally "form": "reann" (the default), "radial" or "diag",
  *   and "weights": path of the weight file (relative paths are taken from the spec's
  *   directory); other members (e.g. element names) are ignored.
  * The weight file is raw little-endian FP64: centres[K], alphas[K], c0[n_species][K], msg,

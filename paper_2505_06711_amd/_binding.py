@@ -36,7 +36,7 @@ class _ModelDesc(C.Structure):
                 ("msg", C.c_void_p), ("en", C.c_void_p), ("form", C.c_int32)]
 
 
-FORMS = {"reann": 0, "radial": 1}   # REANN_FORM_REANN, REANN_FORM_RADIAL
+FORMS = {"reann": 0, "radial": 1, "diag": 2}   # REANN_FORM_REANN, REANN_FORM_RADIAL, REANN_FORM_DIAG
 
 
 class _Opts(C.Structure):

@@ -91,9 +91,10 @@ reann_status reann_model_create(const reann_model_desc *d, reann_model **out) {
         REQUIRE(d && out, "NULL argument");
         REQUIRE(d->n_species >= 1 && d->n_species <= 64, "n_species must be in [1, 64]");
         REQUIRE(d->L >= 0 && d->K >= 1, "bad L or K");
-        REQUIRE(d->form == REANN_FORM_REANN || d->form == REANN_FORM_RADIAL, "unknown message form");
+        REQUIRE(d->form == REANN_FORM_REANN || d->form == REANN_FORM_RADIAL || d->form == REANN_FORM_DIAG,
+                "unknown message form");
         const bool radial = d->form == REANN_FORM_RADIAL;
-        REQUIRE(radial == (d->L == 0), "the radial form takes L = 0, the REANN form L >= 1");
+        REQUIRE(radial == (d->L == 0), "the radial form takes L = 0, the other forms L >= 1");
         const bool lk_ok = radial ? (d->K == 8 || d->K == 12)
                                   : ((d->L == 2 && (d->K == 8 || d->K == 12 || d->K == 4)) || (d->L == 1 && d->K == 4));
         if (!lk_ok) fail(REANN_E_UNSUPPORTED, "no kernels compiled for this (L, K)");
@@ -109,7 +110,8 @@ reann_status reann_model_create(const reann_model_desc *d, reann_model **out) {
         M.n_species = d->n_species; M.L = d->L; M.K = d->K; M.T_max = d->T_max;
         M.nh = d->n_hidden; M.H = d->hidden;
         M.form = d->form;
-        M.F = radial ? d->K : n_feat(d->L, d->K); M.NL = n_lambda(d->L);
+        M.F = radial ? d->K : (d->form == REANN_FORM_DIAG ? (d->L + 1) * d->K : n_feat(d->L, d->K));
+        M.NL = n_lambda(d->L);
         M.r_c = d->r_c; M.ang_scale = d->ang_scale; M.energy_scale = d->energy_scale;
         M.centres.assign(d->centres, d->centres + d->K);
         M.alphas.assign(d->alphas, d->alphas + d->K);
@@ -230,7 +232,8 @@ reann_status reann_model_load(const char *spec_json_path, reann_model **out) {
         if (kv.count("form")) {
             const std::string &fm = kv.at("form");
             if (fm == "radial") d.form = REANN_FORM_RADIAL;
-            else if (fm != "reann") fail(REANN_E_INVALID, "model spec: \"form\" must be \"reann\" or \"radial\"");
+            else if (fm == "diag") d.form = REANN_FORM_DIAG;
+            else if (fm != "reann") fail(REANN_E_INVALID, "model spec: \"form\" must be \"reann\", \"radial\" or \"diag\"");
         }
         REQUIRE(d.n_species >= 1 && d.n_species <= 64 && d.K >= 1 && d.K <= 64 && d.L >= 0 && d.L <= 4 &&
                     d.T_max >= 1 && d.T_max <= 16 && d.n_hidden >= 1 && d.n_hidden <= 4 && d.hidden >= 1 &&
@@ -241,7 +244,7 @@ reann_status reann_model_load(const char *spec_json_path, reann_model **out) {
         const std::string sp(spec_json_path);
         const size_t slash = sp.find_last_of('/');
         if (!wpath.empty() && wpath[0] != '/' && slash != std::string::npos) wpath = sp.substr(0, slash + 1) + wpath;
-        const int F = d.form == REANN_FORM_RADIAL ? d.K : n_feat(d.L, d.K);
+        const int F = d.form == REANN_FORM_RADIAL ? d.K : (d.form == REANN_FORM_DIAG ? (d.L + 1) * d.K : n_feat(d.L, d.K));
         const size_t nmsg = (size_t)(d.T_max - 1) * d.n_species * nn_doubles(F, d.hidden, d.n_hidden, d.K);
         const size_t nen = (size_t)d.n_species * nn_doubles(F, d.hidden, d.n_hidden, 1);
         const size_t total = 2 * (size_t)d.K + (size_t)d.n_species * d.K + nmsg + nen;

@@ -92,6 +92,55 @@ __global__ void k_density_vjp(int64_t n, int L, DensityConsts dc, const R *__res
     }
 }
 
+// The literal reading of Eq. (1): only the squares, rho[l][a] = sum_{|lambda|=l} w_lambda
+// S[lambda][a]^2 (F = (L+1) K); one thread per feature.
+template <typename R>
+__global__ void k_density_sq(int64_t n, int L, int K, DensityConsts dc, const R *__restrict__ S, R *__restrict__ rho) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int F = (L + 1) * K, NL = dc.lstart[L + 1];
+    if (t >= n * F) return;
+    const int64_t i = t / F;
+    const int l = (int)(t % F) / K, a = (int)(t % K);
+    R s = R(0);
+    for (int k = dc.lstart[l]; k < dc.lstart[l + 1]; ++k) {
+        const R v = S[(i * NL + k) * K + a];
+        s += R(dc.w[k]) * v * v;
+    }
+    rho[t] = s;
+}
+
+// its adjoint: Sbar[lambda][a] = 2 w_lambda S[lambda][a] rhobar[l(lambda)][a]; one thread per value
+template <typename R>
+__global__ void k_density_sq_vjp(int64_t n, int L, int K, DensityConsts dc, const R *__restrict__ S,
+                                 const R *__restrict__ rb, R *__restrict__ Sbar) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int NL = dc.lstart[L + 1];
+    if (t >= n * NL * K) return;
+    const int64_t i = t / (NL * K);
+    const int k = (int)(t % (NL * K)) / K, a = (int)(t % K);
+    int l = 0;
+    while (dc.lstart[l + 1] <= k) ++l;
+    Sbar[t] = R(2) * R(dc.w[k]) * S[t] * rb[i * (L + 1) * K + l * K + a];
+}
+
+void density_sq(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S,
+                void *rho) {
+    const int64_t tot = n * (L + 1) * K;
+    if (tot == 0) return;
+    if (fp64) hipLaunchKernelGGL(k_density_sq<double>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const double *)S, (double *)rho);
+    else hipLaunchKernelGGL(k_density_sq<float>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const float *)S, (float *)rho);
+    LAUNCH_OK("k_density_sq");
+}
+
+void density_sq_vjp(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S,
+                    const void *rhobar, void *Sbar) {
+    const int64_t tot = n * dc.lstart[L + 1] * K;
+    if (tot == 0) return;
+    if (fp64) hipLaunchKernelGGL(k_density_sq_vjp<double>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const double *)S, (const double *)rhobar, (double *)Sbar);
+    else hipLaunchKernelGGL(k_density_sq_vjp<float>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, L, K, dc, (const float *)S, (const float *)rhobar, (float *)Sbar);
+    LAUNCH_OK("k_density_sq_vjp");
+}
+
 #define REANN_K_DISPATCH(K, CALL)                                                      \
     do {                                                                               \
         if ((K) == 8) { CALL(8); }                                                     \

@@ -14,6 +14,10 @@ struct DensityConsts {
 // rho[i][f], f = (l, a, b >= a), from S[i][NL][K]; rows [0, n).
 void density(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S, void *rho);
 // Sbar[i][lambda][a] from rhobar[i][F] and S (overwrites Sbar).
+// The literal reading of Eq. (1) (only the squares, rho[i][l K + a], F = (L+1) K) and its adjoint.
+void density_sq(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S, void *rho);
+void density_sq_vjp(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S,
+                    const void *rhobar, void *Sbar);
 void density_vjp(hipStream_t st, bool fp64, int L, int K, int64_t n, const DensityConsts &dc, const void *S,
                  const void *rhobar, void *Sbar);
 

@@ -181,8 +181,8 @@ void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const doubl
         fail(REANN_E_INVALID, "unknown precision");
     fp64 = prec == REANN_FP64;
     op = prec == REANN_BF16 ? OpType::BF16 : (prec == REANN_FP8 ? OpType::FP8 : OpType::F32);
-    if (op == OpType::FP8 && m->form == REANN_FORM_RADIAL)
-        fail(REANN_E_UNSUPPORTED, "the radial message form runs in FP64, FP32 or BF16");
+    if (op == OpType::FP8 && m->form != REANN_FORM_REANN)
+        fail(REANN_E_UNSUPPORTED, "this message form runs in FP64, FP32 or BF16");
     const int exch = opt ? opt->exchange : REANN_EXCHANGE_MESSAGES;
     if (exch != REANN_EXCHANGE_MESSAGES && exch != REANN_EXCHANGE_NODE_FEATURES)
         fail(REANN_E_INVALID, "unknown exchange");
@@ -278,7 +278,8 @@ int64_t Plan::collect_timing(double *ms, int64_t *nlaunch) {
 
 // whether both atomic NNs run as fused kernels (FP32 or BF16 operands, supported widths)
 bool Plan::fused() const {
-    return !fp64 && fused_nn_ok(op, m->F, m->H, m->nh, m->K, m->NL * m->K) &&
+    // the fused kernels form the paired density (or, at L = 0, take the radial form's sums)
+    return !fp64 && m->form != REANN_FORM_DIAG && fused_nn_ok(op, m->F, m->H, m->nh, m->K, m->NL * m->K) &&
            fused_nn_ok(op, m->F, m->H, m->nh, 1, m->NL * m->K);
 }
 
@@ -668,7 +669,10 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
             mark(st, PH_GHOST);
         }
         if (!fused() && !radial()) {   // the fused NN kernels contract S themselves
-            density(st, fp64, m->L, K, ghost_nn ? nl.n_ext : n, dc, Sptr(t), rhoptr(t));
+            if (m->form == REANN_FORM_DIAG)
+                density_sq(st, fp64, m->L, K, ghost_nn ? nl.n_ext : n, dc, Sptr(t), rhoptr(t));
+            else
+                density(st, fp64, m->L, K, ghost_nn ? nl.n_ext : n, dc, Sptr(t), rhoptr(t));
             mark(st, PH_DENSITY, 1);
         }
         if (t < T - 1) {
@@ -706,7 +710,8 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     mark(st, PH_OTHER);
     mark(st, PH_NN_BWD, nn_vjp(st, T - 1, true, ybar.as<char>(), 1));
     if (!fused() && !radial()) {
-        density_vjp(st, fp64, m->L, K, n, dc, Sptr(T - 1), rhobar.p, Sbar.p);
+        if (m->form == REANN_FORM_DIAG) density_sq_vjp(st, fp64, m->L, K, n, dc, Sptr(T - 1), rhobar.p, Sbar.p);
+        else density_vjp(st, fp64, m->L, K, n, dc, Sptr(T - 1), rhobar.p, Sbar.p);
         mark(st, PH_DENSITY_ADJ, 1);
     }
     // the centre role's per-block virial partials of the T layers side by side, summed once
@@ -733,7 +738,10 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
             }
             mark(st, PH_NN_BWD, nn_vjp(st, t - 1, false, cbar.as<char>(), K));
             if (!fused() && !radial()) {
-                density_vjp(st, fp64, m->L, K, nS(), dc, Sptr(t - 1), rhobar.p, Sbar.p);
+                if (m->form == REANN_FORM_DIAG)
+                    density_sq_vjp(st, fp64, m->L, K, nS(), dc, Sptr(t - 1), rhobar.p, Sbar.p);
+                else
+                    density_vjp(st, fp64, m->L, K, nS(), dc, Sptr(t - 1), rhobar.p, Sbar.p);
                 mark(st, PH_DENSITY_ADJ, 1);
             }
             if (nodefeat) {   // the ghosts' dE/dS^{t-1} summed onto their owners

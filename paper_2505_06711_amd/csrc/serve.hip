@@ -803,8 +803,8 @@ reann_status reann_server_create(const reann_model *m, const reann_server_opts *
         if (o->T < 1 || o->T > m->impl.T_max) fail(REANN_E_INVALID, "T must be in [1, T_max]");
         if (!(o->skin >= 0) || !std::isfinite(o->skin)) fail(REANN_E_INVALID, "skin must be >= 0");
         if (o->precision < REANN_FP64 || o->precision > REANN_FP8) fail(REANN_E_INVALID, "unknown precision");
-        if (o->precision == REANN_FP8 && m->impl.form == REANN_FORM_RADIAL)
-            fail(REANN_E_UNSUPPORTED, "the radial message form runs in FP64, FP32 or BF16");
+        if (o->precision == REANN_FP8 && m->impl.form != REANN_FORM_REANN)
+            fail(REANN_E_UNSUPPORTED, "this message form runs in FP64, FP32 or BF16");
         if (!(o->thermostat_K >= 0) || !(o->thermostat_tau_fs >= 0) || !std::isfinite(o->thermostat_K) ||
             !std::isfinite(o->thermostat_tau_fs))
             fail(REANN_E_INVALID, "thermostat temperature and time constant must be finite and >= 0");

@@ -192,3 +192,20 @@ def water_model_radial(T_max=3, seed=0, **kw) -> ModelParams:
     kw = {**dict(bias_std=1.0, w1_scale=1.0), **kw}
     return make_model(["H", "O"], L=0, K=8, r_c=5.0, width=0.5, n_hidden=2, hidden=64,
                       T_max=T_max, seed=seed, form="radial", **kw)
+
+
+def cu_model_diag(T_max=3, seed=0, **kw) -> ModelParams:
+    """The Cu model's sizes with the literal Eq. (1) features (squares only, F = (L+1) K = 36).
+    Squares of sums without the cross terms grow faster from layer to layer, so the first
+    layer's weight scale is 0.3 (force RMS of order 1 eV/A, like the other presets)."""
+    kw = {**dict(bias_std=1.0, w1_scale=0.3, ang_scale=1.0 / 6.0), **kw}
+    return make_model(["Cu"], L=2, K=12, r_c=6.0, width=0.5, n_hidden=3, hidden=128,
+                      T_max=T_max, seed=seed, form="diag", **kw)
+
+
+def water_model_diag(T_max=3, seed=0, **kw) -> ModelParams:
+    """The water model's sizes with the literal Eq. (1) features (F = (L+1) K = 24); first-layer
+    weight scale 1 (force RMS of order 1 eV/A)."""
+    kw = {**dict(bias_std=1.0, w1_scale=1.0, ang_scale=1.0 / 5.0), **kw}
+    return make_model(["H", "O"], L=2, K=8, r_c=5.0, width=0.5, n_hidden=2, hidden=64,
+                      T_max=T_max, seed=seed, form="diag", **kw)

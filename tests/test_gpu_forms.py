@@ -47,7 +47,7 @@ def check_fp64(E, F, W, ref):
 def check_fp32(E, F, W, ref, tag):
     re, rf = rel_energy(E, ref), rel_force_rmse(F, ref)
     fmax, wmax = np.abs(ref["forces"]).max(), np.abs(ref["virial"]).max()
-    print("radial fp32 %s: rel E %.2e, force rel-RMSE %.2e, max component %.2e, virial %.2e" %
+    print("fp32 %s: rel E %.2e, force rel-RMSE %.2e, max component %.2e, virial %.2e" %
           (tag, re, rf, np.abs(F - ref["forces"]).max() / fmax, np.abs(W - ref["virial"]).max() / wmax), flush=True)
     assert re <= 1e-6
     assert rf <= 1e-5
@@ -180,3 +180,39 @@ def test_radial_md_decomposed_equals_whole_fp64(rn):
         assert np.abs(x[1] - y[1]).max() <= 1e-12 * L
         assert np.abs(x[2] - y[2]).max() <= 1e-12 * np.abs(x[2]).max()
     assert runs[(2, 2, 2)][1] >= 2
+
+
+# ---- the literal reading of Eq. (1): only the squares (the "diag" form), on the per-layer path --
+
+@pytest.mark.parametrize("T", [1, 2, 3])
+@pytest.mark.parametrize("decomp", [(1, 1, 1), (2, 2, 1)])
+def test_diag_fp64_water(rn, ctx, oracle_lib, T, decomp):
+    s = systems.water_box(seed=110)
+    m = models.water_model_diag(T_max=3, seed=110)
+    ref = oracle_lib.evaluate(m, s, T=T, skin=0.5)
+    check_fp64(*_eval(rn, ctx, m, s, T, "fp64", skin=0.5, decomp=decomp), ref)
+
+
+@pytest.mark.parametrize("case", ["water", "cu"])
+def test_diag_fp32(rn, ctx, oracle_lib, case):
+    if case == "water":
+        s, m, skin = systems.water_box(seed=111), models.water_model_diag(T_max=3, seed=111), 0.5
+    else:
+        s, m, skin = systems.fcc_crystal((5, 5, 4), seed=112), models.cu_model_diag(T_max=3, seed=112), 1.0
+    ref = oracle_lib.evaluate(m, s, T=3, skin=skin)
+    check_fp32(*_eval(rn, ctx, m, s, 3, "fp32", skin=skin, decomp=(2, 1, 1)), ref, "diag " + case)
+
+
+def test_diag_bf16(rn, ctx, oracle_lib):
+    s = systems.water_box(seed=113)
+    m = models.water_model_diag(T_max=3, seed=113)
+    ref = oracle_lib.evaluate(m, s, T=3, skin=0.5)
+    E, F, W = _eval(rn, ctx, m, s, 3, "bf16", skin=0.5)
+    re, rf = rel_energy(E, ref), rel_force_rmse(F, ref)
+    print("diag bf16: rel E %.2e, force rel-RMSE %.2e" % (re, rf), flush=True)
+    assert re <= 3e-2 and rf <= 6e-2
+
+
+def test_diag_fp8_is_refused(rn, ctx):
+    with pytest.raises(rn.ReannError):
+        _eval(rn, ctx, models.water_model_diag(T_max=2, seed=114), systems.water_box(seed=114), 2, "fp8")

@@ -84,3 +84,14 @@ def test_form_and_L_must_agree(b):
     q.form = "radial"           # the radial form takes L = 0
     with pytest.raises(b.ReannError):
         b.Model(q)
+
+
+def test_diag_form_save_then_load(b, tmp_path):
+    p = models.water_model(T_max=2, seed=7, form="diag")
+    spec = str(tmp_path / "diag.json")
+    b.Model(p).save(spec)
+    d = json.load(open(spec))
+    assert d["form"] == "diag"
+    w = np.fromfile(str(tmp_path / d["weights"]), dtype="<f8")
+    assert w.size == 2 * p.K + p.c0.size + p.msg_blob.size + p.energy_blob.size
+    assert b.Model.load(spec).form == "diag"
