@@ -390,8 +390,9 @@ reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res);
    enqueuing steps (launches, list checks and rebuilds, copies; summed over the threads), [8] of
    which in HIP-graph launches,
    [9] host nanoseconds spent unpacking finished requests, [10] of [7] in neighbour-list
-   builds, [11] of [7] in capturing and instantiating HIP graphs. */
-#define REANN_N_SERVER_STATS 12
+   builds, [11] of [7] in capturing and instantiating HIP graphs, [12] skin checks on the
+   device (steps whose displacement bound did not show the list valid), [13] of [7] in them. */
+#define REANN_N_SERVER_STATS 14
 reann_status reann_server_stats(reann_server *s, int64_t *stats);
 void reann_server_destroy(reann_server *s);
 

@@ -517,7 +517,8 @@ class Server:
 
     def stats(self) -> dict:
         keys = ("admission_rounds", "completed", "atoms", "graph_replays", "deferred", "resident_bytes",
-                "list_builds", "enqueue_ns", "graph_launch_ns", "finish_ns", "list_build_ns", "graph_capture_ns")
+                "list_builds", "enqueue_ns", "graph_launch_ns", "finish_ns", "list_build_ns", "graph_capture_ns",
+                "skin_checks", "skin_check_ns")
         out = np.zeros(len(keys), np.int64)
         check(load().reann_server_stats(self.handle, _p(out)))
         return dict(zip(keys, out.tolist()))

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kKeBlock) void k_ke_part(int64_t n3, const int32_t 
 }
 
 __global__ __launch_bounds__(kKeBlock) void k_ke_final(int64_t n, int nb, double dt, double T0, double tau,
-                                                        int kind, double r1, double s_chi2,
+                                                        int kind, const double *__restrict__ rng,
                                                         double *__restrict__ aux, double *__restrict__ head) {
     __shared__ double sh[3][kKeBlock];
     const double *part = aux + kAuxKe;
@@ -131,6 +131,7 @@ __global__ __launch_bounds__(kKeBlock) void k_ke_final(int64_t n, int nb, double
         if (T0 > 0.0 && tau > 0.0 && K > 0.0) {
             const double nf = 3.0 * (double)n;
             if (kind == REANN_THERMO_CSVR) {
+                const double r1 = rng[0], s_chi2 = rng[1];
                 const double K0 = 0.5 * nf * kBoltzmann * T0, c = exp(-dt / tau);
                 const double Kn = K + (1.0 - c) * (K0 * (r1 * r1 + s_chi2) / nf - K) +
                                   2.0 * r1 * sqrt(c * (1.0 - c) * K * K0 / nf);
@@ -202,16 +203,30 @@ struct Sys {
     double *V() { return d_out.as<double>() + kOutHead + 6 * n; }
     std::mt19937_64 rng;   // CSVR draws
     DArr<int32_t> d_spec;
-    hipGraphExec_t graph = nullptr;
-    int64_t graph_rebuilds = -1;   // plan rebuild count the graph was captured for
+    // pinned host buffers while resident: the step's results (d_out copied back) and the CSVR
+    // draws of the step (copied to d_rng)
+    double *h_res = nullptr, *h_rng = nullptr;
+    DevBuf d_rng;
+    // the step after the positions are in place as one HIP graph, captured for a request kind,
+    // a time step and a neighbour-list build
+    hipGraphExec_t tail = nullptr;
+    int64_t tail_rebuilds = -1;
+    bool tail_vv = false;
+    double tail_dt = 0.0;
     size_t bytes = 0;
     int64_t last_used = 0;
     bool busy = false;
     // set when a request of this system failed for its inputs: its device state was dropped
     // (it may have been half updated), and later requests for it fail with REANN_E_STATE
     std::string failed;
+    void free_host() {
+        if (h_res) (void)hipHostFree(h_res);
+        if (h_rng) (void)hipHostFree(h_rng);
+        h_res = h_rng = nullptr;
+    }
     ~Sys() {
-        if (graph) (void)hipGraphExecDestroy(graph);
+        if (tail) (void)hipGraphExecDestroy(tail);
+        free_host();
     }
 };
 
@@ -242,8 +257,6 @@ struct Slot {
     reann_status err_code = REANN_E_DEVICE;
     Req req;
     Sys *sys = nullptr;
-    double *h_out = nullptr;          // pinned: the result head, forces, positions, velocities
-    size_t h_cap = 0;
 };
 
 // slot states: the launcher has the step (queued), enqueued it (launched), hit a device error
@@ -332,7 +345,9 @@ struct reann_server {
     bool make_resident(Sys &sy, int64_t need);
     void evict(Sys &sy, bool copy_back = true);
     int64_t estimate_bytes(const Sys &sy) const;
-    void launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid = false, const double *h_pos = nullptr);
+    bool update_list(Slot &s, Sys &sy, bool list_valid, const double *h_pos);
+    void enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt);
+    void launch_tail(Slot &s, Sys &sy, bool vv, double dt);
 };
 
 int64_t reann_server::estimate_bytes(const Sys &sy) const {
@@ -366,7 +381,9 @@ void reann_server::evict(Sys &sy, bool copy_back) {
         HIP_OK(hipStreamSynchronize(st));
     }
     sy.xref_ok = false;
-    if (sy.graph) { (void)hipGraphExecDestroy(sy.graph); sy.graph = nullptr; }
+    if (sy.tail) { (void)hipGraphExecDestroy(sy.tail); sy.tail = nullptr; }
+    sy.free_host();
+    sy.d_rng.release();
     sy.plan.reset();
     sy.d_pos.release(); sy.d_vel.release(); sy.d_Fold.release(); sy.d_out.release(); sy.d_aux.release();
     sy.d_spec.b.release();
@@ -402,6 +419,10 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
     sy.d_pos.ensure(sy.n * 24); sy.d_vel.ensure(sy.n * 24); sy.d_Fold.ensure(sy.n * 24);
     sy.d_out.ensure((kOutHead + 9 * sy.n) * 8);
     sy.d_aux.ensure((size_t)(kAuxKe + 3 * grid_for(sy.n * 3, kKeBlock)) * 8);
+    sy.d_rng.ensure(16);
+    sy.free_host();
+    HIP_OK(hipHostMalloc((void **)&sy.h_res, (size_t)(kOutHead + 9 * sy.n) * 8, hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void **)&sy.h_rng, 16, hipHostMallocDefault));
     sy.motion_known = false;
     int32_t *ds = sy.d_spec.resize(sy.n);
     HIP_OK(hipMemcpyAsync(ds, sy.species.data(), sy.n * 4, hipMemcpyHostToDevice, st));
@@ -410,22 +431,22 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
     HIP_OK(hipMemcpyAsync(sy.d_Fold.p, sy.forces.data(), sy.n * 24, hipMemcpyHostToDevice, st));
     HIP_OK(hipStreamSynchronize(st));
     sy.plan = std::move(p);
-    sy.graph_rebuilds = -1;
+    sy.tail_rebuilds = -1;
     sy.bytes = need;   // corrected to the measured size after the first build
     resident += need;
     stats[5] = resident.load();
     return true;
 }
 
-// Enqueue one step of `sy` on slot `s` (positions for EVAL already staged in d_pos; h_pos: the
-// same positions on the host, for EVAL requests).
-void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid, const double *h_pos) {
+// Neighbour-list upkeep of a step (positions already in place on the device; h_pos: the same
+// positions on the host for EVAL requests).  The skin check on the device waits for the stream;
+// it is skipped when the caller has shown the list valid (velocity-Verlet motion bounds), and
+// for EVAL requests it runs on the host against the host copy of the positions the list was
+// built from (the same rule: rebuild when an atom has moved more than skin/2).  Returns whether
+// the list was rebuilt.
+bool reann_server::update_list(Slot &s, Sys &sy, bool list_valid, const double *h_pos) {
     hipStream_t st = s.st;
     Plan &p = *sy.plan;
-    // The skin check on the device waits for it.  It is skipped when the caller has shown the
-    // list valid (velocity-Verlet motion bounds), and for EVAL requests it runs on the host
-    // against the host copy of the positions the list was built from (the same rule: rebuild
-    // when an atom has moved more than skin/2).
     if (!list_valid && h_pos && sy.xref_ok && p.built) {
         const double half = 0.5 * opt.skin;
         double d2max = 0.0;
@@ -436,60 +457,100 @@ void reann_server::launch_step(Slot &s, Sys &sy, bool replay_ok, bool list_valid
         }
         list_valid = d2max <= half * half;
     }
-    // the device skin check (one wait for the stream) runs outside the lock, the rebuild inside
-    bool rebuilt = false;
-    if (!list_valid && p.list_stale(sy.d_pos.as<double>(), st)) {
+    // the device skin check (one wait for the stream) runs outside the gate, the rebuild inside
+    bool stale = false;
+    if (!list_valid) {
+        const int64_t tk = now_ns();
+        stale = p.list_stale(sy.d_pos.as<double>(), st);
+        stats[12]++;
+        stats[13] += now_ns() - tk;
+    }
+    if (!stale) return false;
+    {
         std::shared_lock<CaptureGate> alloc(gate);
         const int64_t tb = now_ns();
         p.rebuild(sy.d_pos.as<double>(), st);
-        rebuilt = true;
         stats[10] += now_ns() - tb;
     }
-    if (rebuilt) {
-        if (h_pos) {
-            sy.xref_h.assign(h_pos, h_pos + 3 * sy.n);
-            sy.xref_ok = true;
-        } else {
-            sy.xref_ok = false;
-        }
+    if (h_pos) {
+        sy.xref_h.assign(h_pos, h_pos + 3 * sy.n);
+        sy.xref_ok = true;
+    } else {
+        sy.xref_ok = false;
     }
-    if (rebuilt) {
-        stats[6]++;
-        const int64_t actual = (int64_t)p.device_bytes() + 4 * (int64_t)sy.n * 24;
-        stats[5] = resident.fetch_add(actual - (int64_t)sy.bytes) + (actual - (int64_t)sy.bytes);
-        sy.bytes = actual;
+    stats[6]++;
+    const int64_t actual = (int64_t)p.device_bytes() + 4 * (int64_t)sy.n * 24;
+    stats[5] = resident.fetch_add(actual - (int64_t)sy.bytes) + (actual - (int64_t)sy.bytes);
+    sy.bytes = actual;
+    return true;
+}
+
+// The step once the positions are in place: the forward and backward (E, F, W), then for a
+// velocity-Verlet step the kick, the largest displacement since the list build, the kinetic
+// energy and the thermostat (its draws read from d_rng), then the result vectors and their copy
+// to the system's pinned buffer.  Enqueued only (no synchronisation, no allocation).
+void reann_server::enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt) {
+    Plan &p = *sy.plan;
+    const int64_t n3 = sy.n * 3;
+    const int B = 256;
+    p.launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
+    p.backward(nullptr, sy.F(), sy.W(), st);
+    if (vv) {
+        hipLaunchKernelGGL(k_vv_kick, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, dt, sy.d_spec.ptr(),
+                           d_minv.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.F());
+        LAUNCH_OK("k_vv_kick");
+        const int nb = grid_for(n3, kKeBlock);
+        double *aux = sy.d_aux.as<double>();
+        max_displacement2(st, p.nl, sy.d_pos.as<double>(), aux + kAuxDisp);
+        hipLaunchKernelGGL(k_ke_part, dim3(nb), dim3(kKeBlock), 0, st, n3, sy.d_spec.ptr(), d_minv.as<double>(),
+                           sy.d_vel.as<double>(), sy.F(), aux + kAuxKe);
+        LAUNCH_OK("k_ke_part");
+        hipLaunchKernelGGL(k_ke_final, dim3(1), dim3(kKeBlock), 0, st, sy.n, nb, dt, opt.thermostat_K,
+                           opt.thermostat_tau_fs, (int)opt.thermostat, sy.d_rng.as<double>(), aux, sy.KE());
+        LAUNCH_OK("k_ke_final");
     }
-    const bool use_graph = opt.use_graph && replay_ok;
-    if (use_graph && (sy.graph == nullptr || sy.graph_rebuilds != p.rebuilds)) {
+    hipLaunchKernelGGL(k_vv_post, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.F(), sy.d_Fold.as<double>(),
+                       sy.d_pos.as<double>(), sy.P(), sy.d_vel.as<double>(), sy.V(), sy.d_aux.as<double>(),
+                       vv ? 1 : 0);
+    LAUNCH_OK("k_vv_post");
+    HIP_OK(hipMemcpyAsync(sy.h_res, sy.d_out.p, (kOutHead + 3 * n3) * 8, hipMemcpyDeviceToHost, st));
+}
+
+// enqueue_tail as one HIP-graph replay (use_graph): captured for the request kind, time step and
+// list build it was made for, and captured again when one of them changes.
+void reann_server::launch_tail(Slot &s, Sys &sy, bool vv, double dt) {
+    hipStream_t st = s.st;
+    if (!opt.use_graph) {
+        enqueue_tail(st, sy, vv, dt);
+        return;
+    }
+    Plan &p = *sy.plan;
+    if (!sy.tail || sy.tail_rebuilds != p.rebuilds || sy.tail_vv != vv || (vv && sy.tail_dt != dt)) {
         std::unique_lock<CaptureGate> cap(gate);
         const int64_t tc = now_ns();
-        if (sy.graph) { (void)hipGraphExecDestroy(sy.graph); sy.graph = nullptr; }
+        if (sy.tail) { (void)hipGraphExecDestroy(sy.tail); sy.tail = nullptr; }
         hipGraph_t g = nullptr;
         HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         try {
-            p.launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
-            p.backward(nullptr, sy.F(), sy.W(), st);
+            enqueue_tail(st, sy, vv, dt);
         } catch (...) {
             (void)hipStreamEndCapture(st, &g);
             if (g) (void)hipGraphDestroy(g);
             throw;
         }
         HIP_OK(hipStreamEndCapture(st, &g));
-        hipError_t e = hipGraphInstantiate(&sy.graph, g, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&sy.tail, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         HIP_OK(e);
-        sy.graph_rebuilds = p.rebuilds;
+        sy.tail_rebuilds = p.rebuilds;
+        sy.tail_vv = vv;
+        sy.tail_dt = dt;
         stats[11] += now_ns() - tc;
     }
-    if (use_graph) {
-        const int64_t t0 = now_ns();
-        HIP_OK(hipGraphLaunch(sy.graph, st));
-        stats[8] += now_ns() - t0;
-        stats[3]++;
-    } else {
-        p.launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
-        p.backward(nullptr, sy.F(), sy.W(), st);
-    }
+    const int64_t t0 = now_ns();
+    HIP_OK(hipGraphLaunch(sy.tail, st));
+    stats[8] += now_ns() - t0;
+    stats[3]++;
 }
 
 bool reann_server::admit(Req &r) {
@@ -531,15 +592,6 @@ bool reann_server::admit(Req &r) {
             stats[4]++;
             return false;
         }
-    }
-    const size_t need_host = (size_t)(kOutHead + 9 * sy.n) * 8;
-    if (s->h_cap < need_host) {
-        std::shared_lock<CaptureGate> alloc(gate);
-        if (s->h_out) (void)hipHostFree(s->h_out);
-        s->h_out = nullptr;
-        s->h_cap = 0;
-        HIP_OK(hipHostMalloc((void **)&s->h_out, need_host, hipHostMallocDefault));
-        s->h_cap = need_host;
     }
     sy.busy = true;
     sy.last_used = now_ns();
@@ -615,10 +667,12 @@ void reann_server::enqueue(Slot &slot) {
     hipStream_t st = s->st;
     const int64_t n3 = sy.n * 3;
     const int B = 256;
-    bool vv = r.kind == REANN_REQ_VV_STEP;
+    const bool vv = r.kind == REANN_REQ_VV_STEP;
     if (vv && !sy.have_forces) {
         // forces at the current positions first (once per system)
-        launch_step(*s, sy, false);
+        update_list(*s, sy, false, nullptr);
+        sy.plan->launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
+        sy.plan->backward(nullptr, sy.F(), sy.W(), st);
         hipLaunchKernelGGL(k_copy_d, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.F(), sy.d_Fold.as<double>());
         LAUNCH_OK("k_copy_d");
         sy.have_forces = true;
@@ -635,35 +689,20 @@ void reann_server::enqueue(Slot &slot) {
         hipLaunchKernelGGL(k_vv_drift, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, r.dt, sy.d_spec.ptr(),
                            d_minv.as<double>(), sy.d_pos.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>());
         LAUNCH_OK("k_vv_drift");
+        // CSVR: one normal and one chi-square (N_f - 1 degrees of freedom) per step from the
+        // system's stream; drawn every step so that the stream does not depend on the thermostat.
+        // The previous step of this system has completed, so its copy of h_rng has been made.
+        std::normal_distribution<double> nd(0.0, 1.0);
+        std::gamma_distribution<double> gd(0.5 * (3.0 * (double)sy.n - 1.0), 2.0);
+        sy.h_rng[0] = nd(sy.rng);
+        sy.h_rng[1] = sy.n * 3 > 1 ? gd(sy.rng) : 0.0;
+        HIP_OK(hipMemcpyAsync(sy.d_rng.p, sy.h_rng, 16, hipMemcpyHostToDevice, st));
     } else {
         HIP_OK(hipMemcpyAsync(sy.d_pos.p, r.pos.data(), sy.n * 24, hipMemcpyHostToDevice, st));
     }
-    launch_step(*s, sy, true, list_valid, vv ? nullptr : r.pos.data());
-    if (vv) {
-        hipLaunchKernelGGL(k_vv_kick, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, r.dt, sy.d_spec.ptr(),
-                           d_minv.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.F());
-        LAUNCH_OK("k_vv_kick");
-        const int nb = grid_for(n3, kKeBlock);
-        double *aux = sy.d_aux.as<double>();
-        max_displacement2(st, sy.plan->nl, sy.d_pos.as<double>(), aux + kAuxDisp);
-        hipLaunchKernelGGL(k_ke_part, dim3(nb), dim3(kKeBlock), 0, st, n3, sy.d_spec.ptr(), d_minv.as<double>(),
-                           sy.d_vel.as<double>(), sy.F(), aux + kAuxKe);
-        LAUNCH_OK("k_ke_part");
-        // CSVR: one normal and one chi-square (N_f - 1 degrees of freedom) per step from the
-        // system's stream; drawn every step so that the stream does not depend on the thermostat
-        std::normal_distribution<double> nd(0.0, 1.0);
-        std::gamma_distribution<double> gd(0.5 * (3.0 * (double)sy.n - 1.0), 2.0);
-        const double r1 = nd(sy.rng), s_chi2 = sy.n * 3 > 1 ? gd(sy.rng) : 0.0;
-        hipLaunchKernelGGL(k_ke_final, dim3(1), dim3(kKeBlock), 0, st, sy.n, nb, r.dt, opt.thermostat_K,
-                           opt.thermostat_tau_fs, (int)opt.thermostat, r1, s_chi2, aux, sy.KE());
-        LAUNCH_OK("k_ke_final");
-    }
-    hipLaunchKernelGGL(k_vv_post, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.F(), sy.d_Fold.as<double>(),
-                       sy.d_pos.as<double>(), sy.P(), sy.d_vel.as<double>(), sy.V(), sy.d_aux.as<double>(),
-                       vv ? 1 : 0);
-    LAUNCH_OK("k_vv_post");
+    update_list(*s, sy, list_valid, vv ? nullptr : r.pos.data());
+    launch_tail(*s, sy, vv, r.dt);
     sy.have_forces = true;
-    HIP_OK(hipMemcpyAsync(s->h_out, sy.d_out.p, (kOutHead + 3 * n3) * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipEventRecord(s->ev, st));
 }
 
@@ -672,19 +711,19 @@ void reann_server::finish(Slot &s) {
     Sys &sy = *s.sys;
     const int64_t n3 = sy.n * 3;
     Done d;
-    d.energy = s.h_out[0];
-    std::memcpy(d.virial, s.h_out + 1, 72);
+    d.energy = sy.h_res[0];
+    std::memcpy(d.virial, sy.h_res + 1, 72);
     const bool vv = s.req.kind == REANN_REQ_VV_STEP;
-    d.kinetic = vv ? s.h_out[10] : 0.0;
+    d.kinetic = vv ? sy.h_res[10] : 0.0;
     sy.motion_known = vv;
     if (vv) {
-        sy.disp = std::sqrt(s.h_out[11]);
-        sy.vmax = s.h_out[12];
-        sy.amax = s.h_out[13];
+        sy.disp = std::sqrt(sy.h_res[11]);
+        sy.vmax = sy.h_res[12];
+        sy.amax = sy.h_res[13];
     }
-    d.forces.assign(s.h_out + kOutHead, s.h_out + kOutHead + n3);
-    d.positions.assign(s.h_out + kOutHead + n3, s.h_out + kOutHead + 2 * n3);
-    d.velocities.assign(s.h_out + kOutHead + 2 * n3, s.h_out + kOutHead + 3 * n3);
+    d.forces.assign(sy.h_res + kOutHead, sy.h_res + kOutHead + n3);
+    d.positions.assign(sy.h_res + kOutHead + n3, sy.h_res + kOutHead + 2 * n3);
+    d.velocities.assign(sy.h_res + kOutHead + 2 * n3, sy.h_res + kOutHead + 3 * n3);
     d.t_submit = s.req.t_submit;
     d.t_done = now_ns();
     sy.busy = false;
@@ -969,7 +1008,6 @@ void reann_server_destroy(reann_server *s) {
     (void)hipDeviceSynchronize();
     s->systems.clear();
     for (auto &x : s->slots) {
-        if (x.h_out) (void)hipHostFree(x.h_out);
         (void)hipEventDestroy(x.ev);
         (void)hipStreamDestroy(x.st);
     }
