@@ -308,8 +308,10 @@ reann_status reann_plan_timing(reann_plan *p, double *ms, int64_t *launches, int
  *                     a request that would exceed it waits (a lone request always runs).
  *                     Requests are not packed into shared launches: each runs its own
  *                     system's kernels on its own stream, up to 8 at a time.
- *   precision, T, skin as in reann_opts.  use_graph != 0 replays each system's captured HIP
- *   graph of the forward + backward while its neighbour list is unchanged.
+ *   precision, T, skin as in reann_opts.  use_graph != 0 replays, once the step's positions are
+ *   in place and its list checked, one captured HIP graph per system (forward, backward, the
+ *   rest of a velocity-Verlet step, the result copy), captured again when the list is rebuilt
+ *   or the request kind, time step or skipped outputs change.
  *   thermostat_K, thermostat_tau_fs: both > 0 ends every REANN_REQ_VV_STEP with a Berendsen
  *   velocity rescaling (Berendsen et al., J. Chem. Phys. 81, 3684 (1984)) toward
  *   thermostat_K with time constant thermostat_tau_fs: v *= sqrt(1 + (dt / tau)(T0 / T - 1)),
@@ -349,11 +351,20 @@ typedef struct {
 #define REANN_REQ_EVAL 0      /* evaluate E, F, W at the given positions (pos required)        */
 #define REANN_REQ_VV_STEP 1   /* one velocity-Verlet step of dt_fs (pos ignored), then E, F, W  */
 
+/* Result vectors a request may leave on the device (reann_request.skip_outputs, or-ed). */
+#define REANN_OUT_FORCES 1
+#define REANN_OUT_POSITIONS 2
+#define REANN_OUT_VELOCITIES 4
+
 typedef struct {
     uint64_t sys_id;
     int32_t kind;
     double dt_fs;
     const double *pos;        /* host [n][3] for REANN_REQ_EVAL, copied by reann_submit */
+    int32_t skip_outputs;     /* REANN_OUT_* vectors not copied back to the host (0 = all three
+                                 come back); energy, virial and kinetic energy always do.  A
+                                 dynamics run that reads vectors only now and then skips them on
+                                 the other steps.  Other bits: REANN_E_INVALID.              */
 } reann_request;
 
 typedef struct {
@@ -376,7 +387,8 @@ reann_status reann_system_add(reann_server *s, const int32_t *species, int64_t n
                               const int32_t pbc[3], const double *pos, const double *vel, uint64_t *sys_id);
 reann_status reann_submit(reann_server *s, const reann_request *req, uint64_t *ticket);
 /* Non-blocking: REANN_PENDING while running, REANN_OK when res is filled (the ticket is then
-   released), or a negative status.  A request that fails for its inputs (e.g. REANN_E_INVALID
+   released), or a negative status.  A non-NULL res->forces, positions or velocities for a vector
+   the request skipped returns REANN_E_INVALID and keeps the result for another poll.  A request that fails for its inputs (e.g. REANN_E_INVALID
    from the neighbour build when the step brought two atoms within 1e-6 A) fails alone: its
    system's device state is dropped, later requests for that system return REANN_E_STATE, and
    the server keeps serving the others.  A device error fails every request and the server.
@@ -391,8 +403,10 @@ reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res);
    which in HIP-graph launches,
    [9] host nanoseconds spent unpacking finished requests, [10] of [7] in neighbour-list
    builds, [11] of [7] in capturing and instantiating HIP graphs, [12] skin checks on the
-   device (steps whose displacement bound did not show the list valid), [13] of [7] in them. */
-#define REANN_N_SERVER_STATS 14
+   device (steps whose list the previous step's prediction or the displacement bound did not
+   decide), [13] of [7] in them, [14] velocity-Verlet steps whose list the previous step's
+   prediction decided (it computes the displacement that the next drift of the same dt gives). */
+#define REANN_N_SERVER_STATS 15
 reann_status reann_server_stats(reann_server *s, int64_t *stats);
 void reann_server_destroy(reann_server *s);
 

@@ -19,6 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libreann.so")
 FP64, FP32, BF16, FP8 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp8": FP8}
 REQ_EVAL, REQ_VV_STEP = 0, 1
+OUTPUTS = {"forces": 1, "positions": 2, "velocities": 4}   # REANN_OUT_*
+# reann_server_stats, in order (REANN_N_SERVER_STATS entries)
+SERVER_STATS = ("admission_rounds", "completed", "atoms", "graph_replays", "deferred", "resident_bytes",
+                "list_builds", "enqueue_ns", "graph_launch_ns", "finish_ns", "list_build_ns", "graph_capture_ns",
+                "skin_checks", "skin_check_ns", "predicted_list_decisions")
 OK, PENDING = 0, 1
 
 
@@ -54,7 +59,8 @@ class _ServerOpts(C.Structure):
 
 
 class _Request(C.Structure):
-    _fields_ = [("sys_id", C.c_uint64), ("kind", C.c_int32), ("dt_fs", C.c_double), ("pos", C.c_void_p)]
+    _fields_ = [("sys_id", C.c_uint64), ("kind", C.c_int32), ("dt_fs", C.c_double), ("pos", C.c_void_p),
+                ("skip_outputs", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -460,6 +466,7 @@ class Server:
         self.handle = h
         self.model = model
         self.n_atoms = {}
+        self._poll_bufs = {}
         _LIVE["server"].add(self)
 
     def set_masses(self, masses_amu):
@@ -478,11 +485,15 @@ class Server:
         self.n_atoms[sid.value] = pos.shape[0]
         return sid.value
 
-    def _submit(self, sys_id, kind, dt=0.0, pos=None) -> int:
+    def _submit(self, sys_id, kind, dt=0.0, pos=None, skip=()) -> int:
         r = _Request()
         r.sys_id = int(sys_id)
         r.kind = int(kind)
         r.dt_fs = float(dt)
+        bad = set(skip) - set(OUTPUTS)
+        if bad:
+            raise ValueError("unknown outputs %s (known: %s)" % (sorted(bad), sorted(OUTPUTS)))
+        r.skip_outputs = sum(OUTPUTS[k] for k in set(skip))
         keep = None
         if pos is not None:
             keep = _f64(pos)
@@ -491,37 +502,41 @@ class Server:
         check(load().reann_submit(self.handle, C.byref(r), C.byref(t)))
         return t.value
 
-    def submit_eval(self, sys_id: int, pos) -> int:
-        return self._submit(sys_id, REQ_EVAL, pos=pos)
+    def submit_eval(self, sys_id: int, pos, skip=()) -> int:
+        """skip: names in OUTPUTS of result vectors left on the device."""
+        return self._submit(sys_id, REQ_EVAL, pos=pos, skip=skip)
 
-    def submit_vv(self, sys_id: int, dt_fs: float) -> int:
-        return self._submit(sys_id, REQ_VV_STEP, dt=dt_fs)
+    def submit_vv(self, sys_id: int, dt_fs: float, skip=()) -> int:
+        """skip: names in OUTPUTS of result vectors left on the device."""
+        return self._submit(sys_id, REQ_VV_STEP, dt=dt_fs, skip=skip)
 
     def poll(self, ticket: int, sys_id: int, forces: bool = True, positions: bool = False, velocities: bool = False):
         """None while pending; else a dict with energy, virial, forces, positions, velocities,
         kinetic (eV, velocity-Verlet steps), latency_s."""
         n = self.n_atoms[sys_id]
         res = _Result()
-        F = np.zeros((n, 3)) if forces else None
-        P = np.zeros((n, 3)) if positions else None
-        V = np.zeros((n, 3)) if velocities else None
+        # the output arrays of a ticket are made once and kept while it is pending
+        key = (ticket, forces, positions, velocities)
+        bufs = self._poll_bufs.get(ticket)
+        if bufs is None or bufs[0] != key:
+            bufs = (key,) + tuple(np.empty((n, 3)) if w else None for w in (forces, positions, velocities))
+            self._poll_bufs[ticket] = bufs
+        _, F, P, V = bufs
         res.forces = None if F is None else F.ctypes.data
         res.positions = None if P is None else P.ctypes.data
         res.velocities = None if V is None else V.ctypes.data
         st = load().reann_poll(self.handle, C.c_uint64(ticket), C.byref(res))
         if st == PENDING:
             return None
+        self._poll_bufs.pop(ticket, None)
         check(st)
         return dict(energy=res.energy, virial=np.array(res.virial[:]).reshape(3, 3), forces=F, positions=P,
                     velocities=V, kinetic=res.kinetic, latency_s=(res.t_done_ns - res.t_submit_ns) * 1e-9, t_done_ns=res.t_done_ns)
 
     def stats(self) -> dict:
-        keys = ("admission_rounds", "completed", "atoms", "graph_replays", "deferred", "resident_bytes",
-                "list_builds", "enqueue_ns", "graph_launch_ns", "finish_ns", "list_build_ns", "graph_capture_ns",
-                "skin_checks", "skin_check_ns")
-        out = np.zeros(len(keys), np.int64)
+        out = np.zeros(len(SERVER_STATS), np.int64)
         check(load().reann_server_stats(self.handle, _p(out)))
-        return dict(zip(keys, out.tolist()))
+        return dict(zip(SERVER_STATS, out.tolist()))
 
     def close(self):
         if _can_free(self):

@@ -96,6 +96,22 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// A pinned host word that device-to-host copies write (a device-side check read later, once
+// the stream has been waited for anyway).
+struct PinnedWord {
+    int32_t *p = nullptr;
+    PinnedWord() = default;
+    PinnedWord(const PinnedWord &) = delete;
+    PinnedWord &operator=(const PinnedWord &) = delete;
+    ~PinnedWord() {
+        if (p) (void)hipHostFree(p);
+    }
+    int32_t *get() {
+        if (!p) HIP_OK(hipHostMalloc((void **)&p, 64, hipHostMallocDefault));
+        return p;
+    }
+};
+
 template <class T> struct DArr {
     DevBuf b;
     size_t n = 0;

@@ -513,7 +513,8 @@ struct Picker {
 // --------------------------------------------------------------------- build --
 
 void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, int64_t n, int n_species,
-                 const Geom &g, double r_c, double skin, NList &nl, NListScratch &s, bool ghosts_by_species) {
+                 const Geom &g, double r_c, double skin, NList &nl, NListScratch &s, bool ghosts_by_species,
+                 bool defer_check) {
     if (n <= 0) fail(REANN_E_INVALID, "n must be > 0");
     if (n >= (int64_t)1 << 30) fail(REANN_E_UNSUPPORTED, "too many atoms");
     const int B = 256;
@@ -546,6 +547,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
         pk.read(st, s.chk, hv);
         std::memcpy(bb, hv + 2, sizeof bb);
     }
+    check_deferred(s);   // a previous build's deferred check (the wait above covered its copy)
     const int64_t n_gh = hv[0];
     if (hv[1]) fail(REANN_E_INVALID, "positions contain NaN, Inf or |x| >= 1e9");
     if (n + n_gh >= ((int64_t)1 << 31) - 1) fail(REANN_E_UNSUPPORTED, "extended system too large");
@@ -698,12 +700,23 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     hipLaunchKernelGGL(k_xref, dim3(grid_for(n, B)), dim3(B), 0, st, n, d_pos, perm, xref);
     LAUNCH_OK("k_xref");
     // last read (the list is complete when it returns): the symmetry check of the reverse slots
+    if (defer_check) {
+        HIP_OK(hipMemcpyAsync(s.sym.get(), s.flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        s.sym_pending = true;
+        return;
+    }
     {
         Picker pk;
         pk.add(s.flag.p, true);
         pk.read(st, s.chk, hv);
     }
     if (hv[0]) fail(REANN_E_DEVICE, "neighbour build: list is not symmetric");
+}
+
+void check_deferred(NListScratch &s) {
+    if (!s.sym_pending) return;
+    s.sym_pending = false;
+    if (*s.sym.get()) fail(REANN_E_DEVICE, "neighbour build: list is not symmetric");
 }
 
 // ------------------------------------------------------------ per-step work --
@@ -773,14 +786,17 @@ __global__ void k_maxdisp_final(int nb, const double *__restrict__ part, double 
     if (threadIdx.x == 0) *out = sm[0];
 }
 
-// d_out must hold 1 + 1024 doubles (result, then per-block partials).
-void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_out) {
+// d_part must hold 1024 doubles (per-block partials); the result goes to d_result[0].
+void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_part, double *d_result) {
     const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nl.n + 255) / 256));
-    hipLaunchKernelGGL(k_maxdisp_part, dim3(nb), dim3(256), 0, st, nl.n, d_pos, nl.perm.ptr(), nl.xref.ptr(),
-                       d_out + 1);
+    hipLaunchKernelGGL(k_maxdisp_part, dim3(nb), dim3(256), 0, st, nl.n, d_pos, nl.perm.ptr(), nl.xref.ptr(), d_part);
     LAUNCH_OK("k_maxdisp_part");
-    hipLaunchKernelGGL(k_maxdisp_final, dim3(1), dim3(256), 0, st, nb, d_out + 1, d_out);
+    hipLaunchKernelGGL(k_maxdisp_final, dim3(1), dim3(256), 0, st, nb, d_part, d_result);
     LAUNCH_OK("k_maxdisp_final");
+}
+
+void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_out) {
+    max_displacement2(st, nl, d_pos, d_out + 1, d_out);
 }
 
 }  // namespace reann

@@ -49,13 +49,21 @@ struct NList {
 // Scratch reused between builds.
 struct NListScratch {
     DevBuf a, b, c, d, e, f, g, h, i, j, k, l, m, flag, mm, chk, dext, bext, gou, coinc;
+    PinnedWord sym;             // deferred symmetry check: the flag, copied back
+    bool sym_pending = false;
 };
 
 void geom_init(Geom &g, const double cell[9], const int32_t pbc[3], const int32_t P[3], double r_c, double skin);
 
-// d_pos: device FP64 [n][3] (caller order); d_species: device int32 [n].
+// d_pos: device FP64 [n][3] (caller order); d_species: device int32 [n].  The build reads its
+// counts back in two waits; a third waits for the end of the build and checks that every entry
+// has its reverse.  defer_check: that last check is copied back with the build instead, and
+// read by check_deferred after the caller has waited for the stream for other reasons.
 void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, int64_t n, int n_species,
-                 const Geom &g, double r_c, double skin, NList &nl, NListScratch &s, bool ghosts_by_species = false);
+                 const Geom &g, double r_c, double skin, NList &nl, NListScratch &s, bool ghosts_by_species = false,
+                 bool defer_check = false);
+// REANN_E_DEVICE if a deferred check failed (the stream of the build must have been waited for).
+void check_deferred(NListScratch &s);
 
 // Exclusive scan of n int64 values in place; returns the total (synchronises).
 int64_t scan_exclusive_i64(hipStream_t st, int64_t *d, int64_t n, DevBuf &tmp);
@@ -68,5 +76,7 @@ void refresh_positions(hipStream_t st, const NList &nl, const double *d_pos, dou
 
 // max_i |x_i - xref_i|^2 over locals -> d_out[0]; d_out holds 1 + 1024 doubles (partials after it).
 void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_out);
+// The same with the partials (1024 doubles) and the result apart.
+void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_part, double *d_result);
 
 }  // namespace reann

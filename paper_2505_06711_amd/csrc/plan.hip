@@ -337,12 +337,13 @@ bool Plan::list_stale(const double *d_pos, hipStream_t st) {
     max_displacement2(st, nl, d_pos, disp.as<double>());
     HIP_OK(hipMemcpyAsync(&d2, disp.p, 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    check_deferred();
     const double half = 0.5 * skin;
     return !(d2 <= half * half);
 }
 
-void Plan::rebuild(const double *d_pos, hipStream_t st) {
-    build_nlist(st, d_pos, d_species.ptr(), n, m->n_species, g, m->r_c, skin, nl, ns, nodefeat);
+void Plan::rebuild(const double *d_pos, hipStream_t st, bool defer_check) {
+    build_nlist(st, d_pos, d_species.ptr(), n, m->n_species, g, m->r_c, skin, nl, ns, nodefeat, defer_check);
     built = true;
     ++rebuilds;
     alloc_buffers();

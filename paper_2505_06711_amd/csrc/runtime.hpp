@@ -148,7 +148,10 @@ struct Plan {
     // atom has moved more than skin/2 since), and the rebuild (with the FP8 calibration the
     // first time), which allocates
     bool list_stale(const double *d_pos, hipStream_t st);
-    void rebuild(const double *d_pos, hipStream_t st);
+    // defer_check: the list's last consistency check is read by check_deferred (after the
+    // caller's next wait for the stream) instead of by a wait here
+    void rebuild(const double *d_pos, hipStream_t st, bool defer_check = false);
+    void check_deferred() { reann::check_deferred(ns); }
     // the forward's launches only: no synchronisation and no allocation, so it can be captured
     void launch_forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st);
     size_t device_bytes() const;

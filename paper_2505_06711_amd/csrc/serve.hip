@@ -36,7 +36,9 @@ namespace {
 
 constexpr int kSlots = 8;
 constexpr int kWorkers = 4;
-constexpr int kOutHead = 14;   // energy, virial (9), kinetic energy, displacement^2, max |v_c|, max |a_c|
+// energy, virial (9), kinetic energy, displacement^2, max |v_c|, max |a_c|, the displacement^2
+// that the next drift of the same dt will give, one spare
+constexpr int kOutHead = 16;
 constexpr double kAccel = 9.648533212e-3;   // (eV/A) / amu in A/fs^2
 
 int64_t now_ns() {
@@ -44,12 +46,28 @@ int64_t now_ns() {
         .count();
 }
 
+// The drift of one position component; the same function predicts it a step ahead, so the
+// prediction and the drift agree to the last bit.
+__device__ inline double drift(double x, double v, double F, double minv, double dt) {
+    const double a = F * minv * kAccel;
+    return x + v * dt + 0.5 * a * dt * dt;
+}
+
 __global__ void k_vv_drift(int64_t n, double dt, const int32_t *__restrict__ spec, const double *__restrict__ minv,
                            double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ F) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * 3) return;
-    const double a = F[t] * minv[spec[t / 3]] * kAccel;
-    x[t] = x[t] + v[t] * dt + 0.5 * a * dt * dt;
+    x[t] = drift(x[t], v[t], F[t], minv[spec[t / 3]], dt);
+}
+
+// The positions the next drift of dt will give (from the velocities and forces the step ends
+// with), for its displacement since the list was built.
+__global__ void k_vv_predict(int64_t n, double dt, const int32_t *__restrict__ spec, const double *__restrict__ minv,
+                             const double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ F,
+                             double *__restrict__ xp) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * 3) return;
+    xp[t] = drift(x[t], v[t], F[t], minv[spec[t / 3]], dt);
 }
 
 __global__ void k_vv_kick(int64_t n, double dt, const int32_t *__restrict__ spec, const double *__restrict__ minv,
@@ -73,7 +91,8 @@ constexpr int kKeBlock = 256;
 // applies), the squared largest displacement since the list was built (aux[1], from
 // max_displacement2), lambda max|v_c| and max|a_c|.
 constexpr int kAuxDisp = 1;      // max_displacement2 output and its partials (<= 1025 values)
-constexpr int kAuxKe = 1100;     // kinetic partials, 3 per block
+constexpr int kAuxPred = 1100;   // partials of the predicted displacement (<= 1024 values)
+constexpr int kAuxKe = 2200;     // kinetic partials, 3 per block
 
 __global__ __launch_bounds__(kKeBlock) void k_ke_part(int64_t n3, const int32_t *__restrict__ spec,
                                                        const double *__restrict__ minv, const double *__restrict__ v,
@@ -182,7 +201,7 @@ struct Sys {
     bool have_forces = false;               // forces of the current positions are known
     // residency
     std::unique_ptr<Plan> plan;
-    // d_out = [E, W (9), K, d^2, vmax, amax, F (3n), positions (3n), velocities (3n)]: the step
+    // d_out = [E, W (9), K, d^2, vmax, amax, d_next^2, 0, F (3n), positions (3n), velocities (3n)]: the step
     // writes E, W and F in place, the motion figures, positions and velocities are written after
     // it, and one device-to-host copy returns the lot
     DevBuf d_pos, d_vel, d_Fold, d_out, d_aux;   // d_aux: [lambda, displacement scratch, kinetic partials]
@@ -191,6 +210,10 @@ struct Sys {
     // displacement, so that the skin check (a device round trip) is needed only near the edge
     bool motion_known = false;
     double disp = 0, vmax = 0, amax = 0;
+    // the displacement (since the list build) the next drift gives if it takes pred_dt
+    bool pred_known = false;
+    double pred = 0, pred_dt = 0;
+    DevBuf d_pred;   // the predicted positions
     // caller positions the neighbour list was last built from, when that build came from an
     // EVAL request (host positions): later EVAL requests check the skin rule on the host
     std::vector<double> xref_h;
@@ -212,6 +235,7 @@ struct Sys {
     hipGraphExec_t tail = nullptr;
     int64_t tail_rebuilds = -1;
     bool tail_vv = false;
+    int32_t tail_skip = 0;
     double tail_dt = 0.0;
     size_t bytes = 0;
     int64_t last_used = 0;
@@ -234,6 +258,7 @@ struct Req {
     uint64_t ticket = 0, sys = 0;
     int32_t kind = REANN_REQ_EVAL;
     double dt = 0;
+    int32_t skip = 0;   // REANN_OUT_* vectors not brought back
     std::vector<double> pos;
     int64_t t_submit = 0;
 };
@@ -241,6 +266,7 @@ struct Req {
 struct Done {
     double energy = 0, virial[9]{}, kinetic = 0;
     std::vector<double> forces, positions, velocities;
+    int32_t skip = 0;
     int64_t t_submit = 0, t_done = 0;
     reann_status status = REANN_OK;
     std::string error;
@@ -345,9 +371,9 @@ struct reann_server {
     bool make_resident(Sys &sy, int64_t need);
     void evict(Sys &sy, bool copy_back = true);
     int64_t estimate_bytes(const Sys &sy) const;
-    bool update_list(Slot &s, Sys &sy, bool list_valid, const double *h_pos);
-    void enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt);
-    void launch_tail(Slot &s, Sys &sy, bool vv, double dt);
+    bool update_list(Slot &s, Sys &sy, bool list_valid, const double *h_pos, bool stale_known = false);
+    void enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt, int32_t skip);
+    void launch_tail(Slot &s, Sys &sy, bool vv, double dt, int32_t skip);
 };
 
 int64_t reann_server::estimate_bytes(const Sys &sy) const {
@@ -384,6 +410,7 @@ void reann_server::evict(Sys &sy, bool copy_back) {
     if (sy.tail) { (void)hipGraphExecDestroy(sy.tail); sy.tail = nullptr; }
     sy.free_host();
     sy.d_rng.release();
+    sy.d_pred.release();
     sy.plan.reset();
     sy.d_pos.release(); sy.d_vel.release(); sy.d_Fold.release(); sy.d_out.release(); sy.d_aux.release();
     sy.d_spec.b.release();
@@ -420,10 +447,11 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
     sy.d_out.ensure((kOutHead + 9 * sy.n) * 8);
     sy.d_aux.ensure((size_t)(kAuxKe + 3 * grid_for(sy.n * 3, kKeBlock)) * 8);
     sy.d_rng.ensure(16);
+    sy.d_pred.ensure(sy.n * 24);
     sy.free_host();
     HIP_OK(hipHostMalloc((void **)&sy.h_res, (size_t)(kOutHead + 9 * sy.n) * 8, hipHostMallocDefault));
     HIP_OK(hipHostMalloc((void **)&sy.h_rng, 16, hipHostMallocDefault));
-    sy.motion_known = false;
+    sy.motion_known = sy.pred_known = false;
     int32_t *ds = sy.d_spec.resize(sy.n);
     HIP_OK(hipMemcpyAsync(ds, sy.species.data(), sy.n * 4, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(sy.d_pos.p, sy.pos.data(), sy.n * 24, hipMemcpyHostToDevice, st));
@@ -442,9 +470,10 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
 // positions on the host for EVAL requests).  The skin check on the device waits for the stream;
 // it is skipped when the caller has shown the list valid (velocity-Verlet motion bounds), and
 // for EVAL requests it runs on the host against the host copy of the positions the list was
-// built from (the same rule: rebuild when an atom has moved more than skin/2).  Returns whether
-// the list was rebuilt.
-bool reann_server::update_list(Slot &s, Sys &sy, bool list_valid, const double *h_pos) {
+// built from (the same rule: rebuild when an atom has moved more than skin/2).  stale_known: the
+// caller has shown the list stale (a predicted drift), so it is rebuilt without a check.
+// Returns whether the list was rebuilt.
+bool reann_server::update_list(Slot &s, Sys &sy, bool list_valid, const double *h_pos, bool stale_known) {
     hipStream_t st = s.st;
     Plan &p = *sy.plan;
     if (!list_valid && h_pos && sy.xref_ok && p.built) {
@@ -458,8 +487,8 @@ bool reann_server::update_list(Slot &s, Sys &sy, bool list_valid, const double *
         list_valid = d2max <= half * half;
     }
     // the device skin check (one wait for the stream) runs outside the gate, the rebuild inside
-    bool stale = false;
-    if (!list_valid) {
+    bool stale = stale_known;
+    if (!list_valid && !stale) {
         const int64_t tk = now_ns();
         stale = p.list_stale(sy.d_pos.as<double>(), st);
         stats[12]++;
@@ -469,7 +498,7 @@ bool reann_server::update_list(Slot &s, Sys &sy, bool list_valid, const double *
     {
         std::shared_lock<CaptureGate> alloc(gate);
         const int64_t tb = now_ns();
-        p.rebuild(sy.d_pos.as<double>(), st);
+        p.rebuild(sy.d_pos.as<double>(), st, true);   // its last check is read when the step ends
         stats[10] += now_ns() - tb;
     }
     if (h_pos) {
@@ -487,9 +516,10 @@ bool reann_server::update_list(Slot &s, Sys &sy, bool list_valid, const double *
 
 // The step once the positions are in place: the forward and backward (E, F, W), then for a
 // velocity-Verlet step the kick, the largest displacement since the list build, the kinetic
-// energy and the thermostat (its draws read from d_rng), then the result vectors and their copy
-// to the system's pinned buffer.  Enqueued only (no synchronisation, no allocation).
-void reann_server::enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt) {
+// energy and the thermostat (its draws read from d_rng), then the result vectors and the copy of
+// the head and of the vectors not in `skip` to the system's pinned buffer.  Enqueued only (no
+// synchronisation, no allocation).
+void reann_server::enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt, int32_t skip) {
     Plan &p = *sy.plan;
     const int64_t n3 = sy.n * 3;
     const int B = 256;
@@ -513,26 +543,47 @@ void reann_server::enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt) {
                        sy.d_pos.as<double>(), sy.P(), sy.d_vel.as<double>(), sy.V(), sy.d_aux.as<double>(),
                        vv ? 1 : 0);
     LAUNCH_OK("k_vv_post");
-    HIP_OK(hipMemcpyAsync(sy.h_res, sy.d_out.p, (kOutHead + 3 * n3) * 8, hipMemcpyDeviceToHost, st));
+    if (vv) {
+        // the displacement the next drift of dt will give, from the final velocities and forces
+        hipLaunchKernelGGL(k_vv_predict, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, dt, sy.d_spec.ptr(),
+                           d_minv.as<double>(), sy.d_pos.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(),
+                           sy.d_pred.as<double>());
+        LAUNCH_OK("k_vv_predict");
+        max_displacement2(st, p.nl, sy.d_pred.as<double>(), sy.d_aux.as<double>() + kAuxPred, sy.d_out.as<double>() + 14);
+    }
+    // the head, then each wanted vector, contiguous runs in one copy
+    const int64_t seg[4] = {0, kOutHead, kOutHead + n3, kOutHead + 2 * n3};
+    const int64_t end[4] = {kOutHead, kOutHead + n3, kOutHead + 2 * n3, kOutHead + 3 * n3};
+    const bool want[4] = {true, !(skip & REANN_OUT_FORCES), !(skip & REANN_OUT_POSITIONS),
+                          !(skip & REANN_OUT_VELOCITIES)};
+    for (int k = 0; k < 4;) {
+        if (!want[k]) { ++k; continue; }
+        int e = k;
+        while (e + 1 < 4 && want[e + 1]) ++e;
+        HIP_OK(hipMemcpyAsync(sy.h_res + seg[k], sy.d_out.as<double>() + seg[k], (end[e] - seg[k]) * 8,
+                              hipMemcpyDeviceToHost, st));
+        k = e + 1;
+    }
 }
 
-// enqueue_tail as one HIP-graph replay (use_graph): captured for the request kind, time step and
-// list build it was made for, and captured again when one of them changes.
-void reann_server::launch_tail(Slot &s, Sys &sy, bool vv, double dt) {
+// enqueue_tail as one HIP-graph replay (use_graph): captured for the request kind, time step,
+// vectors wanted and list build it was made for, and captured again when one of them changes.
+void reann_server::launch_tail(Slot &s, Sys &sy, bool vv, double dt, int32_t skip) {
     hipStream_t st = s.st;
     if (!opt.use_graph) {
-        enqueue_tail(st, sy, vv, dt);
+        enqueue_tail(st, sy, vv, dt, skip);
         return;
     }
     Plan &p = *sy.plan;
-    if (!sy.tail || sy.tail_rebuilds != p.rebuilds || sy.tail_vv != vv || (vv && sy.tail_dt != dt)) {
+    if (!sy.tail || sy.tail_rebuilds != p.rebuilds || sy.tail_vv != vv || sy.tail_skip != skip ||
+        (vv && sy.tail_dt != dt)) {
         std::unique_lock<CaptureGate> cap(gate);
         const int64_t tc = now_ns();
         if (sy.tail) { (void)hipGraphExecDestroy(sy.tail); sy.tail = nullptr; }
         hipGraph_t g = nullptr;
         HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         try {
-            enqueue_tail(st, sy, vv, dt);
+            enqueue_tail(st, sy, vv, dt, skip);
         } catch (...) {
             (void)hipStreamEndCapture(st, &g);
             if (g) (void)hipGraphDestroy(g);
@@ -544,6 +595,7 @@ void reann_server::launch_tail(Slot &s, Sys &sy, bool vv, double dt) {
         HIP_OK(e);
         sy.tail_rebuilds = p.rebuilds;
         sy.tail_vv = vv;
+        sy.tail_skip = skip;
         sy.tail_dt = dt;
         stats[11] += now_ns() - tc;
     }
@@ -677,11 +729,17 @@ void reann_server::enqueue(Slot &slot) {
         LAUNCH_OK("k_copy_d");
         sy.have_forces = true;
     }
-    // velocity-Verlet step with the motion of the previous step known: the drift moves atom
-    // component c by v_c dt + a_c dt^2 / 2, so no atom gets further than
-    // disp + sqrt(3) (dt max|v_c| + dt^2 max|a_c| / 2) from where the list was built
-    bool list_valid = false;
-    if (vv && sy.motion_known) {
+    // After a velocity-Verlet step the previous step has already found the displacement this
+    // drift gives when dt is unchanged: the list is then known valid or known stale, with no
+    // check on the device.  With another dt the motion of the previous step bounds it: the drift
+    // moves atom component c by v_c dt + a_c dt^2 / 2, so no atom gets further than
+    // disp + sqrt(3) (dt max|v_c| + dt^2 max|a_c| / 2) from where the list was built.
+    bool list_valid = false, stale_known = false;
+    if (vv && sy.pred_known && r.dt == sy.pred_dt) {
+        list_valid = sy.pred < 0.5 * opt.skin * (1.0 - 1e-9);
+        stale_known = !list_valid;
+        stats[14]++;
+    } else if (vv && sy.motion_known) {
         const double bound = sy.disp + 1.7320508075688772 * (r.dt * sy.vmax + 0.5 * r.dt * r.dt * sy.amax);
         list_valid = bound < 0.5 * opt.skin * (1.0 - 1e-9);
     }
@@ -700,8 +758,8 @@ void reann_server::enqueue(Slot &slot) {
     } else {
         HIP_OK(hipMemcpyAsync(sy.d_pos.p, r.pos.data(), sy.n * 24, hipMemcpyHostToDevice, st));
     }
-    update_list(*s, sy, list_valid, vv ? nullptr : r.pos.data());
-    launch_tail(*s, sy, vv, r.dt);
+    update_list(*s, sy, list_valid, vv ? nullptr : r.pos.data(), stale_known);
+    launch_tail(*s, sy, vv, r.dt, r.skip);
     sy.have_forces = true;
     HIP_OK(hipEventRecord(s->ev, st));
 }
@@ -709,21 +767,26 @@ void reann_server::enqueue(Slot &slot) {
 
 void reann_server::finish(Slot &s) {
     Sys &sy = *s.sys;
+    sy.plan->check_deferred();   // an inconsistent list is a device error: the server stops
     const int64_t n3 = sy.n * 3;
     Done d;
     d.energy = sy.h_res[0];
     std::memcpy(d.virial, sy.h_res + 1, 72);
     const bool vv = s.req.kind == REANN_REQ_VV_STEP;
     d.kinetic = vv ? sy.h_res[10] : 0.0;
-    sy.motion_known = vv;
+    sy.motion_known = sy.pred_known = vv;
     if (vv) {
         sy.disp = std::sqrt(sy.h_res[11]);
         sy.vmax = sy.h_res[12];
         sy.amax = sy.h_res[13];
+        sy.pred = std::sqrt(sy.h_res[14]);   // NaN (a blown-up system) reads as stale
+        sy.pred_dt = s.req.dt;
     }
-    d.forces.assign(sy.h_res + kOutHead, sy.h_res + kOutHead + n3);
-    d.positions.assign(sy.h_res + kOutHead + n3, sy.h_res + kOutHead + 2 * n3);
-    d.velocities.assign(sy.h_res + kOutHead + 2 * n3, sy.h_res + kOutHead + 3 * n3);
+    d.skip = s.req.skip;
+    if (!(d.skip & REANN_OUT_FORCES)) d.forces.assign(sy.h_res + kOutHead, sy.h_res + kOutHead + n3);
+    if (!(d.skip & REANN_OUT_POSITIONS)) d.positions.assign(sy.h_res + kOutHead + n3, sy.h_res + kOutHead + 2 * n3);
+    if (!(d.skip & REANN_OUT_VELOCITIES))
+        d.velocities.assign(sy.h_res + kOutHead + 2 * n3, sy.h_res + kOutHead + 3 * n3);
     d.t_submit = s.req.t_submit;
     d.t_done = now_ns();
     sy.busy = false;
@@ -936,6 +999,9 @@ reann_status reann_submit(reann_server *s, const reann_request *req, uint64_t *t
         r.sys = req->sys_id;
         r.kind = req->kind;
         r.dt = req->dt_fs;
+        if (req->skip_outputs & ~(REANN_OUT_FORCES | REANN_OUT_POSITIONS | REANN_OUT_VELOCITIES))
+            fail(REANN_E_INVALID, "unknown REANN_OUT_* bits in skip_outputs");
+        r.skip = req->skip_outputs;
         std::lock_guard<std::mutex> lk(s->mu);
         if (!s->fatal.empty()) fail(REANN_E_DEVICE, s->fatal);
         auto it = s->systems.find(req->sys_id);
@@ -968,6 +1034,12 @@ reann_status reann_poll(reann_server *s, uint64_t ticket, reann_result *res) {
     auto it = s->results.find(ticket);
     if (it == s->results.end()) return REANN_PENDING;
     Done &d = it->second;
+    if (d.status == REANN_OK && ((res->forces && (d.skip & REANN_OUT_FORCES)) ||
+                                 (res->positions && (d.skip & REANN_OUT_POSITIONS)) ||
+                                 (res->velocities && (d.skip & REANN_OUT_VELOCITIES)))) {
+        set_last_error("the result holds no vector that the request skipped (skip_outputs)");
+        return REANN_E_INVALID;
+    }
     res->status = d.status;
     res->energy = d.energy;
     std::memcpy(res->virial, d.virial, sizeof d.virial);

@@ -63,3 +63,44 @@ def test_null_arguments_rejected(lib):
     L.reann_plan_free(None)
     L.reann_nlist_free(None)
     L.reann_server_destroy(None)
+
+
+def test_struct_layouts_and_constants_match_the_header(tmp_path):
+    """The binding's ctypes structures and constants against the header, as a C compiler lays
+    them out: every field's offset and every struct's size, and the REANN_* values the binding
+    mirrors."""
+    import shutil
+    import subprocess
+    from paper_2505_06711_amd import _binding as b
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    structs = {"reann_model_desc": b._ModelDesc, "reann_opts": b._Opts, "reann_server_opts": b._ServerOpts,
+               "reann_request": b._Request, "reann_result": b._Result}
+    consts = {"REANN_REQ_EVAL": b.REQ_EVAL, "REANN_REQ_VV_STEP": b.REQ_VV_STEP,
+              "REANN_OUT_FORCES": b.OUTPUTS["forces"], "REANN_OUT_POSITIONS": b.OUTPUTS["positions"],
+              "REANN_OUT_VELOCITIES": b.OUTPUTS["velocities"],
+              "REANN_FORM_REANN": b.FORMS["reann"], "REANN_FORM_RADIAL": b.FORMS["radial"],
+              "REANN_FORM_DIAG": b.FORMS["diag"], "REANN_EXCHANGE_MESSAGES": b.EXCHANGES["messages"],
+              "REANN_EXCHANGE_NODE_FEATURES": b.EXCHANGES["node_features"],
+              "REANN_N_SERVER_STATS": len(b.SERVER_STATS)}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "reann.h"', "int main(void) {"]
+    for sn, cls in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (sn, sn))
+        for f in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (sn, f[0], sn, f[0]))
+    for cn in consts:
+        lines.append('printf("%s %%lld\\n", (long long)(%s));' % (cn, cn))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                         text=True).stdout.splitlines())
+    for sn, cls in structs.items():
+        assert int(got["%s size" % sn]) == C.sizeof(cls), sn
+        for f in cls._fields_:
+            assert int(got["%s.%s" % (sn, f[0])]) == getattr(cls, f[0]).offset, (sn, f[0])
+    for cn, v in consts.items():
+        assert int(got[cn]) == v, cn

@@ -250,6 +250,65 @@ def test_berendsen_thermostat_pulls_toward_target(rn, model_params):
     assert T_th[-1] < 0.25 * T_nve[-1]
 
 
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_skipped_outputs_change_nothing_but_the_copy(rn, model_params, use_graph):
+    # two copies of one system at constant energy follow the same trajectory whether or not the
+    # steps bring their vectors back; a poll that asks for a skipped vector is refused and the
+    # result stays for a poll that does not
+    from paper_2505_06711_amd._binding import ReannError
+    s = mix(11, [900])[0]
+    srv = rn.Server(rn.Model(model_params), T=3, precision="fp32", skin=0.5, use_graph=use_graph)
+    srv.set_masses(MASSES)
+    v = systems.maxwell_boltzmann(s["species"], ["H", "O", "Cu"], 600.0, seed=2)
+    a, b = srv.add_system(s, v), srv.add_system(s, v)
+    full = dict(forces=True, positions=True, velocities=True)
+    for k in range(24):
+        skip = () if k % 8 == 7 else (("forces", "positions", "velocities") if k % 2 else ("positions",))
+        ta, tb = srv.submit_vv(a, 0.5, skip=skip), srv.submit_vv(b, 0.5)
+        rb = wait(srv, tb, b, **full)
+        want = {n: n not in skip for n in ("forces", "positions", "velocities")}
+        if skip:
+            with pytest.raises(ReannError):
+                wait(srv, ta, a, **full)
+        ra = wait(srv, ta, a, **want)
+        assert ra["energy"] == rb["energy"] and ra["kinetic"] == rb["kinetic"]
+        np.testing.assert_array_equal(ra["virial"], rb["virial"])
+        for n, w in want.items():
+            if w:
+                np.testing.assert_array_equal(ra[n], rb[n])
+    assert srv.stats()["list_builds"] > 2          # rebuilds happened along the way
+    import ctypes as C
+    from paper_2505_06711_amd._binding import _Request, load
+    r = _Request(sys_id=a, kind=1, dt_fs=0.5, skip_outputs=8)
+    assert load().reann_submit(srv.handle, C.byref(r), C.byref(C.c_uint64())) == -1   # unknown bit
+    srv.close()
+
+
+def test_lists_stay_valid_when_the_previous_step_decides_them(rn, model_params):
+    # velocity Verlet at a constant dt with a thin skin, so that lists are rebuilt often and
+    # each step's list is decided by the displacement the previous step predicted for it: every
+    # step's energy and forces (FP64) equal a fresh evaluation at the same positions with a
+    # list built for them, to rounding.  A list kept one step too long would miss pairs that
+    # came within the cutoff.
+    s = mix(21, [700])[0]
+    model = rn.Model(model_params)
+    ctx = rn.Context(0)
+    srv = rn.Server(model, T=3, precision="fp64", skin=0.3, use_graph=True)
+    srv.set_masses(MASSES)
+    v = systems.maxwell_boltzmann(s["species"], ["H", "O", "Cu"], 1500.0, seed=4)
+    sid = srv.add_system(s, v)
+    for k in range(40):
+        r = wait(srv, srv.submit_vv(sid, 1.0), sid, forces=True, positions=True)
+        E, F, W = rn.energy_forces(ctx, model, dict(s, pos=r["positions"]), T=3, precision="fp64", skin=0.3)
+        assert r["energy"] == pytest.approx(E, rel=1e-11, abs=1e-11), k
+        np.testing.assert_allclose(r["forces"], F, rtol=0, atol=1e-10 * np.abs(F).max())
+    st = srv.stats()
+    assert st["list_builds"] >= 4, st
+    assert st["predicted_list_decisions"] >= 38, st
+    assert st["skin_checks"] <= 2, st
+    srv.close()
+
+
 def test_eval_request_reports_no_kinetic_energy(rn, model_params):
     s = mix(7, [200])[0]
     srv = rn.Server(rn.Model(model_params), T=2, precision="fp32", skin=1.0)
