@@ -786,17 +786,14 @@ __global__ void k_maxdisp_final(int nb, const double *__restrict__ part, double 
     if (threadIdx.x == 0) *out = sm[0];
 }
 
-// d_part must hold 1024 doubles (per-block partials); the result goes to d_result[0].
-void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_part, double *d_result) {
-    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nl.n + 255) / 256));
-    hipLaunchKernelGGL(k_maxdisp_part, dim3(nb), dim3(256), 0, st, nl.n, d_pos, nl.perm.ptr(), nl.xref.ptr(), d_part);
-    LAUNCH_OK("k_maxdisp_part");
-    hipLaunchKernelGGL(k_maxdisp_final, dim3(1), dim3(256), 0, st, nb, d_part, d_result);
-    LAUNCH_OK("k_maxdisp_final");
-}
-
+// d_out must hold 1 + 1024 doubles (result, then per-block partials).
 void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_out) {
-    max_displacement2(st, nl, d_pos, d_out + 1, d_out);
+    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nl.n + 255) / 256));
+    hipLaunchKernelGGL(k_maxdisp_part, dim3(nb), dim3(256), 0, st, nl.n, d_pos, nl.perm.ptr(), nl.xref.ptr(),
+                       d_out + 1);
+    LAUNCH_OK("k_maxdisp_part");
+    hipLaunchKernelGGL(k_maxdisp_final, dim3(1), dim3(256), 0, st, nb, d_out + 1, d_out);
+    LAUNCH_OK("k_maxdisp_final");
 }
 
 }  // namespace reann

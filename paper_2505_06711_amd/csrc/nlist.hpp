@@ -76,7 +76,5 @@ void refresh_positions(hipStream_t st, const NList &nl, const double *d_pos, dou
 
 // max_i |x_i - xref_i|^2 over locals -> d_out[0]; d_out holds 1 + 1024 doubles (partials after it).
 void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_out);
-// The same with the partials (1024 doubles) and the result apart.
-void max_displacement2(hipStream_t st, const NList &nl, const double *d_pos, double *d_part, double *d_result);
 
 }  // namespace reann

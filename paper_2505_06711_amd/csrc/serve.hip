@@ -60,19 +60,12 @@ __global__ void k_vv_drift(int64_t n, double dt, const int32_t *__restrict__ spe
     x[t] = drift(x[t], v[t], F[t], minv[spec[t / 3]], dt);
 }
 
-// The positions the next drift of dt will give (from the velocities and forces the step ends
-// with), for its displacement since the list was built.
-__global__ void k_vv_predict(int64_t n, double dt, const int32_t *__restrict__ spec, const double *__restrict__ minv,
-                             const double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ F,
-                             double *__restrict__ xp) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * 3) return;
-    xp[t] = drift(x[t], v[t], F[t], minv[spec[t / 3]], dt);
-}
-
+// The kick; the first thread also clears the two displacement maxima that k_vv_post raises.
 __global__ void k_vv_kick(int64_t n, double dt, const int32_t *__restrict__ spec, const double *__restrict__ minv,
-                          double *__restrict__ v, const double *__restrict__ Fold, const double *__restrict__ Fnew) {
+                          double *__restrict__ v, const double *__restrict__ Fold, const double *__restrict__ Fnew,
+                          unsigned long long *__restrict__ dmax) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) dmax[0] = dmax[3] = 0ull;
     if (t >= n * 3) return;
     v[t] = v[t] + 0.5 * (Fold[t] + Fnew[t]) * minv[spec[t / 3]] * kAccel * dt;
 }
@@ -88,11 +81,8 @@ constexpr int kKeBlock = 256;
 // with T = 2 K / (3 n k_B); CSVR, lambda^2 = K' / K with K' the kinetic energy resampled from the
 // host-drawn normal r1 and chi-square s (see include/reann.h).  It writes aux[0] = lambda and,
 // to the result head, lambda^2 K (eV: the kinetic energy after the rescaling that k_vv_post
-// applies), the squared largest displacement since the list was built (aux[1], from
-// max_displacement2), lambda max|v_c| and max|a_c|.
-constexpr int kAuxDisp = 1;      // max_displacement2 output and its partials (<= 1025 values)
-constexpr int kAuxPred = 1100;   // partials of the predicted displacement (<= 1024 values)
-constexpr int kAuxKe = 2200;     // kinetic partials, 3 per block
+// applies), lambda max|v_c| and max|a_c|.
+constexpr int kAuxKe = 16;       // kinetic partials, 3 per block
 
 __global__ __launch_bounds__(kKeBlock) void k_ke_part(int64_t n3, const int32_t *__restrict__ spec,
                                                        const double *__restrict__ minv, const double *__restrict__ v,
@@ -163,27 +153,67 @@ __global__ __launch_bounds__(kKeBlock) void k_ke_final(int64_t n, int nb, double
         const double lam = sqrt(lam2);
         aux[0] = lam;
         head[0] = lam2 * K;
-        head[1] = aux[kAuxDisp];
         head[2] = lam * sh[1][0];
         head[3] = sh[2][0];
     }
 }
 
-// After a step: the new forces become the old ones, the positions and velocities go to the
-// output block, and (velocity-Verlet steps, scale_v) the velocities first take the factor aux[0].
-__global__ void k_vv_post(int64_t n3, const double *__restrict__ F, double *__restrict__ Fold,
-                          const double *__restrict__ x, double *__restrict__ xout, double *__restrict__ v,
-                          double *__restrict__ vout, const double *__restrict__ aux, int scale_v) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n3) return;
-    Fold[t] = F[t];
-    xout[t] = x[t];
-    double vt = v[t];
-    if (scale_v) {
-        vt *= aux[0];
-        v[t] = vt;
+// The bits of a non-negative double (or a NaN) as an unsigned integer: their order is the
+// order of the values, with every NaN above +inf, so an integer atomic max takes the largest
+// value (a NaN, from a blown-up system, counts as too far) in any order of arrival.
+__device__ inline unsigned long long order_bits(double v) { return (unsigned long long)__double_as_longlong(v); }
+__device__ inline double nan_max2(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// After a step, one thread per atom: the new forces become the old ones, the positions and
+// velocities go to the output block.  A velocity-Verlet step (vv) first rescales the velocities
+// by aux[0] and raises dmax[0] to the squared largest displacement of an atom since the list
+// was built (xref, in the list's local order) and dmax[3] to the same after the drift of dt
+// that the next step would make (drift() on the final velocities and forces).
+__global__ __launch_bounds__(256) void k_vv_post(int64_t n, double dt, const int32_t *__restrict__ spec,
+                                                 const double *__restrict__ minv, const double *__restrict__ F,
+                                                 double *__restrict__ Fold, const double *__restrict__ x,
+                                                 double *__restrict__ xout, double *__restrict__ v,
+                                                 double *__restrict__ vout, const double *__restrict__ aux, int vv,
+                                                 const int32_t *__restrict__ inv_perm, const double *__restrict__ xref,
+                                                 unsigned long long *__restrict__ dmax) {
+    __shared__ double sh[2][256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double d2 = 0.0, p2 = 0.0;
+    if (i < n) {
+        const double lam = vv ? aux[0] : 1.0, mi = vv ? minv[spec[i]] : 0.0;
+        const int64_t l = vv ? inv_perm[i] : 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t t = 3 * i + c;
+            const double f = F[t], xc = x[t];
+            Fold[t] = f;
+            xout[t] = xc;
+            double vt = v[t];
+            if (vv) {
+                vt *= lam;
+                v[t] = vt;
+                const double r = xref[3 * l + c], dx = xc - r, dp = drift(xc, vt, f, mi, dt) - r;
+                d2 += dx * dx;
+                p2 += dp * dp;
+            }
+            vout[t] = vt;
+        }
     }
-    vout[t] = vt;
+    if (!vv) return;   // uniform over the grid
+    sh[0][threadIdx.x] = d2;
+    sh[1][threadIdx.x] = p2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sh[0][threadIdx.x] = nan_max2(sh[0][threadIdx.x], sh[0][threadIdx.x + h]);
+            sh[1][threadIdx.x] = nan_max2(sh[1][threadIdx.x], sh[1][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(dmax, order_bits(sh[0][0]));
+        atomicMax(dmax + 3, order_bits(sh[1][0]));
+    }
 }
 
 __global__ void k_copy_d(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
@@ -213,7 +243,6 @@ struct Sys {
     // the displacement (since the list build) the next drift gives if it takes pred_dt
     bool pred_known = false;
     double pred = 0, pred_dt = 0;
-    DevBuf d_pred;   // the predicted positions
     // caller positions the neighbour list was last built from, when that build came from an
     // EVAL request (host positions): later EVAL requests check the skin rule on the host
     std::vector<double> xref_h;
@@ -410,7 +439,6 @@ void reann_server::evict(Sys &sy, bool copy_back) {
     if (sy.tail) { (void)hipGraphExecDestroy(sy.tail); sy.tail = nullptr; }
     sy.free_host();
     sy.d_rng.release();
-    sy.d_pred.release();
     sy.plan.reset();
     sy.d_pos.release(); sy.d_vel.release(); sy.d_Fold.release(); sy.d_out.release(); sy.d_aux.release();
     sy.d_spec.b.release();
@@ -447,7 +475,6 @@ bool reann_server::make_resident(Sys &sy, int64_t need) {
     sy.d_out.ensure((kOutHead + 9 * sy.n) * 8);
     sy.d_aux.ensure((size_t)(kAuxKe + 3 * grid_for(sy.n * 3, kKeBlock)) * 8);
     sy.d_rng.ensure(16);
-    sy.d_pred.ensure(sy.n * 24);
     sy.free_host();
     HIP_OK(hipHostMalloc((void **)&sy.h_res, (size_t)(kOutHead + 9 * sy.n) * 8, hipHostMallocDefault));
     HIP_OK(hipHostMalloc((void **)&sy.h_rng, 16, hipHostMallocDefault));
@@ -525,13 +552,15 @@ void reann_server::enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt, int
     const int B = 256;
     p.launch_forward(sy.d_pos.as<double>(), sy.E(), nullptr, st);
     p.backward(nullptr, sy.F(), sy.W(), st);
+    // the squared displacements since the list build, now (head[11]) and after the next drift of
+    // dt (head[14]), raised by k_vv_post as integer maxima
+    unsigned long long *dmax = reinterpret_cast<unsigned long long *>(sy.d_out.as<double>() + 11);
     if (vv) {
         hipLaunchKernelGGL(k_vv_kick, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, dt, sy.d_spec.ptr(),
-                           d_minv.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.F());
+                           d_minv.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.F(), dmax);
         LAUNCH_OK("k_vv_kick");
         const int nb = grid_for(n3, kKeBlock);
         double *aux = sy.d_aux.as<double>();
-        max_displacement2(st, p.nl, sy.d_pos.as<double>(), aux + kAuxDisp);
         hipLaunchKernelGGL(k_ke_part, dim3(nb), dim3(kKeBlock), 0, st, n3, sy.d_spec.ptr(), d_minv.as<double>(),
                            sy.d_vel.as<double>(), sy.F(), aux + kAuxKe);
         LAUNCH_OK("k_ke_part");
@@ -539,18 +568,11 @@ void reann_server::enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt, int
                            opt.thermostat_tau_fs, (int)opt.thermostat, sy.d_rng.as<double>(), aux, sy.KE());
         LAUNCH_OK("k_ke_final");
     }
-    hipLaunchKernelGGL(k_vv_post, dim3(grid_for(n3, B)), dim3(B), 0, st, n3, sy.F(), sy.d_Fold.as<double>(),
-                       sy.d_pos.as<double>(), sy.P(), sy.d_vel.as<double>(), sy.V(), sy.d_aux.as<double>(),
-                       vv ? 1 : 0);
+    hipLaunchKernelGGL(k_vv_post, dim3(grid_for(sy.n, B)), dim3(B), 0, st, sy.n, dt, sy.d_spec.ptr(),
+                       d_minv.as<double>(), sy.F(), sy.d_Fold.as<double>(), sy.d_pos.as<double>(), sy.P(),
+                       sy.d_vel.as<double>(), sy.V(), sy.d_aux.as<double>(), vv ? 1 : 0, p.nl.inv_perm.ptr(),
+                       p.nl.xref.ptr(), dmax);
     LAUNCH_OK("k_vv_post");
-    if (vv) {
-        // the displacement the next drift of dt will give, from the final velocities and forces
-        hipLaunchKernelGGL(k_vv_predict, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, dt, sy.d_spec.ptr(),
-                           d_minv.as<double>(), sy.d_pos.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(),
-                           sy.d_pred.as<double>());
-        LAUNCH_OK("k_vv_predict");
-        max_displacement2(st, p.nl, sy.d_pred.as<double>(), sy.d_aux.as<double>() + kAuxPred, sy.d_out.as<double>() + 14);
-    }
     // the head, then each wanted vector, contiguous runs in one copy
     const int64_t seg[4] = {0, kOutHead, kOutHead + n3, kOutHead + 2 * n3};
     const int64_t end[4] = {kOutHead, kOutHead + n3, kOutHead + 2 * n3, kOutHead + 3 * n3};
