@@ -231,13 +231,14 @@ struct Sys {
     bool have_forces = false;               // forces of the current positions are known
     // residency
     std::unique_ptr<Plan> plan;
-    // d_out = [E, W (9), K, d^2, vmax, amax, d_next^2, 0, F (3n), positions (3n), velocities (3n)]: the step
-    // writes E, W and F in place, the motion figures, positions and velocities are written after
-    // it, and one device-to-host copy returns the lot
-    DevBuf d_pos, d_vel, d_Fold, d_out, d_aux;   // d_aux: [lambda, displacement scratch, kinetic partials]
+    // d_out = [E, W (9), K, d^2, vmax, amax, d_next^2, 0, F (3n), positions (3n), velocities (3n)]:
+    // the step writes E, W and F in place and the motion figures, positions and velocities after
+    // it; the head and the wanted vectors are copied back to h_res
+    DevBuf d_pos, d_vel, d_Fold, d_out, d_aux;   // d_aux: [lambda, ..., kinetic partials from kAuxKe]
     // motion after the last velocity-Verlet step (largest displacement since the list was
-    // built, largest velocity and acceleration components): bound the next step's
-    // displacement, so that the skin check (a device round trip) is needed only near the edge
+    // built, largest velocity and acceleration components): bound the next step's displacement
+    // when its dt differs from the one predicted for, so that the skin check (a device round
+    // trip) is needed only near the edge
     bool motion_known = false;
     double disp = 0, vmax = 0, amax = 0;
     // the displacement (since the list build) the next drift gives if it takes pred_dt
@@ -260,7 +261,7 @@ struct Sys {
     double *h_res = nullptr, *h_rng = nullptr;
     DevBuf d_rng;
     // the step after the positions are in place as one HIP graph, captured for a request kind,
-    // a time step and a neighbour-list build
+    // a time step, the vectors skipped and a neighbour-list build
     hipGraphExec_t tail = nullptr;
     int64_t tail_rebuilds = -1;
     bool tail_vv = false;
