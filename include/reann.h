@@ -219,9 +219,12 @@ reann_status reann_energy_forces_noalloc(reann_ctx *ctx, const reann_model *m, c
  *   reann_plan_forward:  d_pos device FP64 [n][3]; writes d_energy (device FP64 scalar) and,
  *                        if not NULL, d_atom_energy (device FP64 [n]).  Enqueued on hip_stream
  *                        (NULL = HIP's null stream, which is also PyTorch's default stream);
- *                        synchronises that stream once per call for the skin check, and
- *                        rebuilds the neighbour list when an atom has moved more than skin/2
- *                        (unless the plan's list policy leaves that to the caller, below).
+ *                        checks the skin rule on that stream and rebuilds the neighbour list
+ *                        when an atom has moved more than skin/2 (unless the plan's list
+ *                        policy leaves that to the caller, below).  On a built list the
+ *                        forward is queued behind the check and the call waits for the check
+ *                        alone (the forward runs meanwhile); after a rebuild the forward is
+ *                        queued again, so the outputs are those of the rebuilt list.
  *   reann_plan_backward: gradient of E w.r.t. positions after a forward: d_grad_energy is a
  *                        device FP64 scalar g (NULL = 1); writes d_forces = -g dE/dx (device FP64
  *                        [n][3]) and, if not NULL, d_virial = g W (device FP64 [9]).  Enqueued
@@ -239,7 +242,7 @@ void reann_plan_free(reann_plan *p);
 /* Neighbour-list upkeep of a plan (Sec. 2.2: one list for r_c + skin, reused while every atom
  * stays within skin/2 of where it was built).
  *   reann_plan_set_list_policy: auto_check = 1 (the default): every reann_plan_forward checks
- *     the skin rule (one stream synchronisation) and rebuilds the list when needed.
+ *     the skin rule (one wait for the check) and rebuilds the list when needed.
  *     auto_check = 0: forwards use the current list as it is and make no host synchronisation
  *     and no device allocation, so a forward + backward can be captured in a HIP graph and
  *     replayed; the caller keeps the list valid with reann_plan_update_list (for instance every

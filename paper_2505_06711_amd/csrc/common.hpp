@@ -110,6 +110,7 @@ struct PinnedWord {
         if (!p) HIP_OK(hipHostMalloc((void **)&p, 64, hipHostMallocDefault));
         return p;
     }
+    double *get_double() { return reinterpret_cast<double *>(get()); }   // the 64 bytes as doubles
 };
 
 template <class T> struct DArr {

@@ -166,6 +166,7 @@ DensityConsts Model::density_consts() const {
 Plan::~Plan() {
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
+    if (check_ev) (void)hipEventDestroy(check_ev);
 }
 
 void Plan::init(Ctx *c_, Model *mm, const int32_t *spec, int64_t nn, const double cell_[9], const int32_t pbc_[3],
@@ -642,6 +643,28 @@ struct TraceRange {
 void Plan::forward(const double *d_pos, double *d_energy, double *d_atom_energy, hipStream_t st) {
     TraceRange range("reann: forward");
     mark(st, -1);
+    if (auto_list && built && !(fp8_fused() && !fp8_ready)) {
+        // The skin check goes to the device with the forward on the list it checks behind it,
+        // and its answer is read while that forward runs, so the device does not wait for the
+        // host between the check and the forward.  A stale list is rebuilt and the forward
+        // enqueued again: its outputs are written again, in stream order.  (On a stale list
+        // the first forward only misses pairs; every index it uses is the old list's own.)
+        max_displacement2(st, nl, d_pos, disp.as<double>());
+        double *h = check_host.get_double();
+        HIP_OK(hipMemcpyAsync(h, disp.p, 8, hipMemcpyDeviceToHost, st));
+        if (!check_ev) HIP_OK(hipEventCreateWithFlags(&check_ev, hipEventDisableTiming));
+        HIP_OK(hipEventRecord(check_ev, st));
+        mark(st, PH_NLIST, 0);
+        launch_forward(d_pos, d_energy, d_atom_energy, st);
+        HIP_OK(hipEventSynchronize(check_ev));
+        check_deferred();
+        const double half = 0.5 * skin;
+        if (*h <= half * half) return;
+        rebuild(d_pos, st);
+        mark(st, PH_NLIST, 1);
+        launch_forward(d_pos, d_energy, d_atom_energy, st);
+        return;
+    }
     const bool rebuilt = auto_list ? prepare(d_pos, st) : false;
     mark(st, PH_NLIST, rebuilt ? 1 : 0);
     launch_forward(d_pos, d_energy, d_atom_energy, st);

@@ -144,6 +144,10 @@ struct Plan {
     bool prepare(const double *d_pos, hipStream_t st);
     // false: forwards neither check the skin rule nor rebuild (reann_plan_set_list_policy)
     bool auto_list = true;
+    // the skin check of a forward on a built list: its result copied to the host, and the
+    // event after the copy
+    PinnedWord check_host;
+    hipEvent_t check_ev = nullptr;
     // the two halves of prepare: the skin check alone (true if the list was never built or an
     // atom has moved more than skin/2 since), and the rebuild (with the FP8 calibration the
     // first time), which allocates

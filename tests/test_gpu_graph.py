@@ -99,3 +99,50 @@ def test_forward_without_a_list_is_refused(rn):
     E = torch.zeros((), dtype=torch.float64, device="cuda")
     with pytest.raises(rn.ReannError):
         plan.forward(pos, E)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_automatic_list_policy_keeps_and_rebuilds(rn, oracle_lib, prec):
+    """The plan's default policy: each forward checks the skin rule on the device, with the
+    forward on the checked list queued behind the check, and rebuilds and repeats the forward
+    when the list is stale.  Positions move below and beyond skin/2 in turn; every step is
+    checked against the FP64 oracle at the same positions (FP64: 1e-10; FP32: the path's
+    bounds), and the rebuilds happen exactly when an atom has moved more than skin/2 since the
+    last build."""
+    import torch
+    s = systems.water_box(seed=91)
+    m = models.water_model(T_max=3, seed=91)
+    ctx = rn.Context(0)
+    model = rn.Model(m)
+    skin = 0.6
+    plan = rn.Plan(ctx, model, s, T=3, precision=prec, skin=skin)
+    plan.set_timing(True)         # its per-phase counts include the list builds
+    E = torch.zeros((), dtype=torch.float64, device="cuda")
+    F = torch.zeros((len(s["pos"]), 3), dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(3)
+    ref_pos = s["pos"].copy()     # positions of the last build
+    x = s["pos"].copy()
+    builds = 0
+    for k in range(8):
+        if k > 0:
+            x = x + rng.uniform(-1, 1, x.shape) * (0.02 if k % 3 else 0.4)   # every third step jumps
+        moved = np.sqrt(((x - ref_pos) ** 2).sum(1)).max()
+        stale = k == 0 or moved > 0.5 * skin
+        if stale:
+            ref_pos = x.copy()
+            builds += 1
+        pos = torch.tensor(x, dtype=torch.float64, device="cuda")
+        g0 = plan.generation()
+        plan.forward(pos, E)
+        plan.backward(F)
+        torch.cuda.synchronize()
+        ref = oracle_lib.evaluate(m, dict(s, pos=x), T=3, skin=skin)
+        Ek, Fk = float(E), F.cpu().numpy()
+        if prec == "fp64":
+            assert abs(Ek - ref["energy"]) <= 1e-10 * abs(ref["energy"]), k
+            np.testing.assert_allclose(Fk, ref["forces"], rtol=0, atol=1e-10 * np.abs(ref["forces"]).max())
+        else:
+            assert abs(Ek - ref["energy"]) <= 1e-6 * abs(ref["energy"]), k
+            np.testing.assert_allclose(Fk, ref["forces"], rtol=0, atol=1e-5 * np.abs(ref["forces"]).max())
+        assert plan.generation() > g0
+    assert plan.timing()["launches"]["nlist"] == builds >= 3
