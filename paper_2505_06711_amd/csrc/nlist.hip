@@ -390,15 +390,41 @@ __global__ void k_i64_to_i32(const int64_t *__restrict__ a, int32_t *__restrict_
     if (i < n) b[i] = (int32_t)a[i];
 }
 
-__global__ void k_minmax(int64_t n, const double *__restrict__ w, double *__restrict__ out) {
-    // single block: deterministic min/max of the three coordinates
+// Bounds of the wrapped positions (needed along open axes only): per-block minima and maxima of
+// the three coordinates over a grid-strided share of the atoms (stride = blocks x 256), then
+// one block combines the blocks' values.  Min and max do not depend on the order.
+constexpr int kMinmaxBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_minmax_part(int64_t n, const double *__restrict__ w, double *__restrict__ part) {
     __shared__ double smin[3][256], smax[3][256];
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         for (int a = 0; a < 3; ++a) {
             double v = w[3 * i + a];
             mn[a] = fmin(mn[a], v);
             mx[a] = fmax(mx[a], v);
+        }
+    for (int a = 0; a < 3; ++a) { smin[a][threadIdx.x] = mn[a]; smax[a][threadIdx.x] = mx[a]; }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < 3; ++a) {
+                smin[a][threadIdx.x] = fmin(smin[a][threadIdx.x], smin[a][threadIdx.x + s]);
+                smax[a][threadIdx.x] = fmax(smax[a][threadIdx.x], smax[a][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) { part[6 * blockIdx.x + a] = smin[a][0]; part[6 * blockIdx.x + 3 + a] = smax[a][0]; }
+}
+
+__global__ __launch_bounds__(256) void k_minmax(int nb, const double *__restrict__ part, double *__restrict__ out) {
+    __shared__ double smin[3][256], smax[3][256];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fmin(mn[a], part[6 * b + a]);
+            mx[a] = fmax(mx[a], part[6 * b + 3 + a]);
         }
     for (int a = 0; a < 3; ++a) { smin[a][threadIdx.x] = mn[a]; smax[a][threadIdx.x] = mx[a]; }
     __syncthreads();
@@ -533,19 +559,27 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     hipLaunchKernelGGL(k_wrap_count, dim3(grid_for(n, B)), dim3(B), 0, st, g, n, d_pos, w, q, dom, goff, bad);
     LAUNCH_OK("k_wrap_count");
     scan_exclusive_async(st, goff, n, s.m);
-    double *d_mm = static_cast<double *>(s.mm.ensure(6 * sizeof(double)));
-    hipLaunchKernelGGL(k_minmax, dim3(1), dim3(256), 0, st, n, w, d_mm);
-    LAUNCH_OK("k_minmax");
-    // first read: ghost count, the invalid-position flag and the bounds of the wrapped locals
+    // the bounds of the wrapped locals set the bins along open axes only
+    const bool open_axis = !(g.per[0] && g.per[1] && g.per[2]);
+    double *d_mm = static_cast<double *>(s.mm.ensure((6 + 6 * kMinmaxBlocks) * sizeof(double)));
+    if (open_axis) {
+        const int nb = (int)std::min<int64_t>(kMinmaxBlocks, (n + 255) / 256);
+        hipLaunchKernelGGL(k_minmax_part, dim3(nb), dim3(256), 0, st, n, w, d_mm + 6);
+        LAUNCH_OK("k_minmax_part");
+        hipLaunchKernelGGL(k_minmax, dim3(1), dim3(256), 0, st, nb, d_mm + 6, d_mm);
+        LAUNCH_OK("k_minmax");
+    }
+    // first read: ghost count, the invalid-position flag and (open axes) the bounds
     int64_t hv[kPickMax];
-    double bb[6];
+    double bb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     {
         Picker pk;
         pk.add(goff + n, false);
         pk.add(bad, true);
-        for (int a = 0; a < 6; ++a) pk.add(d_mm + a, false);
+        if (open_axis)
+            for (int a = 0; a < 6; ++a) pk.add(d_mm + a, false);
         pk.read(st, s.chk, hv);
-        std::memcpy(bb, hv + 2, sizeof bb);
+        if (open_axis) std::memcpy(bb, hv + 2, sizeof bb);
     }
     check_deferred(s);   // a previous build's deferred check (the wait above covered its copy)
     const int64_t n_gh = hv[0];
