@@ -639,6 +639,20 @@ def main():
         torch.cuda.synchronize()
         tb.append((time.perf_counter() - t1) * 1e3)
     nlist_ms = float(np.median(tb))
+    # the plan's own rebuild (its buffers kept): the caller-kept list policy, and a rigid shift
+    # of the whole system by 0.6 of the skin and back, so that each update rebuilds
+    plan.set_list_policy(False)
+    shift = torch.zeros_like(pos)
+    shift[:, 0] = 0.6 * w["skin"]
+    tr = []
+    for k in range(4):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rebuilt = plan.update_list(pos + shift if k % 2 == 0 else pos)
+        tr.append((time.perf_counter() - t1) * 1e3)
+        assert rebuilt
+    plan.set_list_policy(True)
+    rebuild_ms = float(np.median(tr))
 
     # the host-pointer entry point on the same system: positions in and forces / virial out
     # over PCIe each call (reported beside the device-resident rate, never as `value`)
@@ -659,7 +673,7 @@ def main():
                            first_step_s=round(t_build, 3), wall_s=round(wall, 3)),
                step_ms=dict(median=round(float(np.median(per_step)), 4),
                             iqr=round(float(np.percentile(per_step, 75) - np.percentile(per_step, 25)), 4)),
-               nlist_build_ms=round(nlist_ms, 3),
+               nlist_build_ms=round(nlist_ms, 3), nlist_rebuild_ms=round(rebuild_ms, 3),
                phase_ms_per_step={k: round(v, 4) for k, v in ms.items()},
                host_pointer_path=dict(ms_per_call=round(host_ms, 3), atom_steps_per_s=round(n / (host_ms * 1e-3), 1),
                                       note="reann_energy_forces with host buffers: PCIe copies included"),

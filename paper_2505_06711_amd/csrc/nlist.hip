@@ -227,40 +227,6 @@ __global__ void k_sort_segments32(int64_t nseg, const int32_t *__restrict__ star
     }
 }
 
-// Sort every row of the list ascending.  One wave per row: each entry's rank is the number
-// of smaller entries of the row (columns of a row are distinct), taken against an LDS copy;
-// a row longer than kSortLds is sorted by one lane instead.
-constexpr int kSortLds = 2048;
-
-__global__ __launch_bounds__(256) void k_sort_rows(int64_t nrow, const int64_t *__restrict__ row,
-                                                   int32_t *__restrict__ col) {
-    __shared__ int32_t sv[4][kSortLds];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t x = (int64_t)blockIdx.x * 4 + w;
-    const bool valid = x < nrow;
-    const int64_t lo = valid ? row[x] : 0;
-    const int m = valid ? (int)(row[x + 1] - lo) : 0;
-    const bool in_lds = m <= kSortLds;
-    if (in_lds)
-        for (int e = lane; e < m; e += 64) sv[w][e] = col[lo + e];
-    __syncthreads();
-    if (in_lds) {
-        for (int e = lane; e < m; e += 64) {
-            const int32_t v = sv[w][e];
-            int rank = 0;
-            for (int q = 0; q < m; ++q) rank += sv[w][q] < v;
-            col[lo + rank] = v;
-        }
-    } else if (lane == 0) {
-        for (int64_t i = lo + 1; i < lo + m; ++i) {
-            const int32_t v = col[i];
-            int64_t j = i - 1;
-            while (j >= lo && col[j] > v) { col[j + 1] = col[j]; --j; }
-            col[j + 1] = v;
-        }
-    }
-}
-
 // rev[f] for the entry f = (x -> j) of a sorted list: the slot of (j -> x) in row j (binary
 // search).  Every entry has one: rows of locals list every ext atom in range, rows of ghosts
 // every local in range, and a row of a ghost only holds locals.  Sets *bad when one is missing.
@@ -342,17 +308,19 @@ __global__ void k_rows(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t
     const int c2 = bx % b.nb[2], c1 = (bx / b.nb[2]) % b.nb[1], c0 = bx / (b.nb[2] * b.nb[1]);
     const int nslot = (x < n) ? n_species + n_ghost_slots : n_species;
     int64_t cnt = 0, o = FILL ? row[x] : 0;
-    for (int d0 = -1; d0 <= 1; ++d0) {
-        int a0 = c0 + d0;
-        if (a0 < 0 || a0 >= b.nb[0]) continue;
-        for (int d1 = -1; d1 <= 1; ++d1) {
-            int a1 = c1 + d1;
-            if (a1 < 0 || a1 >= b.nb[1]) continue;
-            for (int d2 = -1; d2 <= 1; ++d2) {
-                int a2 = c2 + d2;
-                if (a2 < 0 || a2 >= b.nb[2]) continue;
-                int64_t bn = ((int64_t)a0 * b.nb[1] + a1) * b.nb[2] + a2;
-                for (int slot = 0; slot < nslot; ++slot) {
+    // keys in increasing order (slot, then the stencil's bins by index): ext atoms are numbered
+    // in key order, so a row comes out with its columns ascending
+    for (int slot = 0; slot < nslot; ++slot) {
+        for (int d0 = -1; d0 <= 1; ++d0) {
+            int a0 = c0 + d0;
+            if (a0 < 0 || a0 >= b.nb[0]) continue;
+            for (int d1 = -1; d1 <= 1; ++d1) {
+                int a1 = c1 + d1;
+                if (a1 < 0 || a1 >= b.nb[1]) continue;
+                for (int d2 = -1; d2 <= 1; ++d2) {
+                    int a2 = c2 + d2;
+                    if (a2 < 0 || a2 >= b.nb[2]) continue;
+                    int64_t bn = ((int64_t)a0 * b.nb[1] + a1) * b.nb[2] + a2;
                     int64_t k = ((int64_t)slot * g.ndom + p) * b.nbin + bn;
                     for (int64_t e = kstart[k]; e < kstart[k + 1]; ++e) {
                         if (e == x) continue;
@@ -695,9 +663,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n, n_ext, pext,
                        d_dom_ext, d_bin_ext, kstart, nullptr, row, col, nullptr);
     LAUNCH_OK("k_rows<fill>");
-    // rows ascending, then the reverse slot of every entry
-    hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n_ext, 4)), dim3(256), 0, st, n_ext, row, col);
-    LAUNCH_OK("k_sort_rows");
+    // the rows are ascending as filled; the reverse slot of every entry
     {
         int32_t *rev = nl.rev.resize(n_pairs + 1);
         int32_t *flag = static_cast<int32_t *>(s.flag.ensure(64));
