@@ -167,7 +167,7 @@ def cpu_baseline(workload_name, T, max_seconds=30.0):
     w = synth.workload(workload_name)
     s = w["system"]
     n = len(s["pos"])
-    sample = "full %s system, one energy+force+virial evaluation" % workload_name
+    sample = "full %s system, one energy+force+virial evaluation (its neighbour search included)" % workload_name
     # bound the CPU work: on hosts far slower than expected fall back to an FCC sub-box of
     # the same lattice, density and model
     if workload_name == "cu100800" and threads < 4:
