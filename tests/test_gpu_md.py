@@ -112,6 +112,48 @@ def test_vv_step_matches_host_fp64_with_oracle_forces(rn, oracle_lib):
     assert abs(r["kinetic"] - K1) <= 1e-12 * K1
 
 
+def test_md_cu100800_fp32_against_host_steps_with_oracle_forces(rn, oracle_lib):
+    """The full 100,800-atom Cu workload as the MD-amortised bench runs it (FP32, T = 3,
+    r_c = 6 A + 1 A skin, 1 fs, 300 K, through the server): three velocity-Verlet steps against
+    the same steps on the host in FP64, driven by the oracle's forces at each host position.
+    FP32 forces hold to 1e-5 of the largest component, so after three steps the positions
+    agree to far below 1e-6 A, the velocities to 1e-5 of the largest, the energy at the last
+    positions to 1e-6 relative."""
+    import synth
+    w = synth.workload("cu100800")
+    m, s = w["model"], w["system"]
+    dt, steps = 1.0, 3
+    v0 = systems.maxwell_boltzmann(s["species"], m.elements, 300.0, seed=7)
+    srv = rn.Server(rn.Model(m), T=3, precision="fp32", skin=w["skin"], use_graph=True)
+    srv.set_masses([systems.MASS_AMU[e] for e in m.elements])
+    sid = srv.add_system(s, v0)
+    for k in range(steps):
+        last = k == steps - 1
+        r = wait(srv, srv.submit_vv(sid, dt), sid, forces=last, positions=last, velocities=last)
+    srv.close()
+    minv = 1.0 / np.array([systems.MASS_AMU[m.elements[k]] for k in s["species"]])[:, None]
+    x, v = s["pos"].copy(), v0.copy()
+    ref = oracle_lib.evaluate(m, s, T=3, skin=w["skin"])
+    a = ref["forces"] * minv * KACCEL
+    for k in range(steps):
+        x = x + v * dt + 0.5 * a * dt * dt
+        ref = oracle_lib.evaluate(m, dict(s, pos=x), T=3, skin=w["skin"])
+        a1 = ref["forces"] * minv * KACCEL
+        v = v + 0.5 * (a + a1) * dt
+        a = a1
+    ex = np.abs(r["positions"] - x).max()
+    ev = np.abs(r["velocities"] - v).max() / np.abs(v).max()
+    fmax = np.abs(ref["forces"]).max()
+    ef = np.abs(r["forces"] - ref["forces"]).max() / fmax
+    den = max(abs(ref["energy"]), np.abs(ref["atom_energy"]).sum())
+    print("cu100800 MD, %d FP32 steps vs host FP64 with oracle forces: positions %.2e A, velocities %.2e, "
+          "forces %.2e, E %.2e" % (steps, ex, ev, ef, abs(r["energy"] - ref["energy"]) / den), flush=True)
+    assert ex <= 1e-6
+    assert ev <= 1e-5
+    assert ef <= 1e-5
+    assert abs(r["energy"] - ref["energy"]) <= 1e-6 * den
+
+
 def _kinetic_series(rn, thermostat, steps, warm, seed=0):
     s = systems.remap_species(systems.fcc_crystal((4, 4, 4), seed=82), ELEMENTS)
     # a nearly free crystal (energy scale 1e-4): the kinetic energy is then set by the
