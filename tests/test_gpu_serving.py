@@ -106,6 +106,42 @@ def test_bf16_server_against_fp64_oracle(rn, model_params, oracle_lib):
     srv.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_serving_mix_systems_against_fp64_oracle(rn, oracle_lib, prec):
+    """Systems of the serving workload itself (its model, its 256-system mix with seed 0: the
+    smallest, the largest, and quartiles, water boxes and FCC crystals), evaluated together in
+    one server, against the FP64 oracle.  FP32: the path's bounds (energy 1e-6 relative, every
+    force component 1e-5 of the largest); BF16: the sanity limits of the BF16 test above, with
+    the errors printed in meV/atom and meV/A."""
+    m = models.serving_model(T_max=3, seed=0)
+    mix = systems.serving_mix(256, seed=0, elements=m.elements)
+    order = np.argsort([len(x["pos"]) for x in mix])
+    pick = sorted(set(int(order[q]) for q in (0, 1, 64, 128, 192, 254, 255)))
+    srv = rn.Server(rn.Model(m), T=3, precision=prec, skin=1.0, use_graph=True)
+    ids = {k: srv.add_system(mix[k]) for k in pick}
+    tickets = {k: srv.submit_eval(ids[k], mix[k]["pos"]) for k in pick}   # all in flight together
+    for k in pick:
+        r = wait(srv, tickets[k], ids[k])
+        ref = oracle_lib.evaluate(m, mix[k], T=3, skin=1.0)
+        n = len(mix[k]["pos"])
+        de = abs(r["energy"] - ref["energy"])
+        den = max(abs(ref["energy"]), np.abs(ref["atom_energy"]).sum())
+        fmax = np.abs(ref["forces"]).max()
+        frms = np.sqrt((ref["forces"] ** 2).mean())
+        frmse = np.sqrt(((r["forces"] - ref["forces"]) ** 2).mean())
+        print("serving mix system %d (%d atoms, %s) %s: |dE| = %.3g meV/atom (rel %.2e), force RMSE = %.3g meV/A "
+              "(max component %.2e of the largest)" % (k, n, "water" if k % 2 == 0 else "fcc", prec, de / n * 1e3,
+                                                       de / den, frmse * 1e3, np.abs(r["forces"] - ref["forces"]).max() / fmax),
+              flush=True)
+        if prec == "fp32":
+            assert de <= 1e-6 * den
+            assert np.abs(r["forces"] - ref["forces"]).max() <= 1e-5 * fmax
+        else:
+            assert de / n <= 2e-2 * np.abs(ref["atom_energy"]).mean()
+            assert frmse <= 5e-2 * frms
+    srv.close()
+
+
 # Other model shapes through the server (its graphs capture the same kernels as the plan
 # path): K = 8 and K = 4 edge passes, one and two hidden layers, and a hidden width that the
 # fused NN kernels do not take (the per-layer path).
