@@ -202,16 +202,37 @@ __global__ void k_scatter(int64_t m, const int64_t *__restrict__ key, const int6
     order[pos] = (int32_t)e;
 }
 
-// Sort each segment [start[k], start[k+1]) ascending (insertion sort; segments are small).
-__global__ void k_sort_segments(int64_t nseg, const int64_t *__restrict__ start, int32_t *__restrict__ v) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nseg) return;
-    int64_t a = start[k], e = start[k + 1];
-    for (int64_t i = a + 1; i < e; ++i) {
-        int32_t x = v[i];
-        int64_t j = i - 1;
-        while (j >= a && v[j] > x) { v[j + 1] = v[j]; --j; }
-        v[j + 1] = x;
+// Sort each segment [start[k], start[k+1]) of distinct values ascending.  One wave per
+// segment: every value's rank is the number of smaller values in the segment, taken against
+// an LDS copy; a segment longer than kSegLds is sorted by one lane (insertion sort) instead.
+constexpr int kSegLds = 1024;
+
+__global__ __launch_bounds__(256) void k_sort_segments(int64_t nseg, const int64_t *__restrict__ start,
+                                                       int32_t *__restrict__ v) {
+    __shared__ int32_t sv[4][kSegLds];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * 4 + w;
+    const bool valid = k < nseg;
+    const int64_t a = valid ? start[k] : 0;
+    const int m = valid ? (int)(start[k + 1] - a) : 0;
+    const bool in_lds = m <= kSegLds;
+    if (in_lds)
+        for (int e = lane; e < m; e += 64) sv[w][e] = v[a + e];
+    __syncthreads();
+    if (in_lds) {
+        for (int e = lane; e < m; e += 64) {
+            const int32_t x = sv[w][e];
+            int rank = 0;
+            for (int q = 0; q < m; ++q) rank += sv[w][q] < x;
+            v[a + rank] = x;
+        }
+    } else if (lane == 0) {
+        for (int64_t i = a + 1; i < a + m; ++i) {
+            const int32_t x = v[i];
+            int64_t j = i - 1;
+            while (j >= a && v[j] > x) { v[j + 1] = v[j]; --j; }
+            v[j + 1] = x;
+        }
     }
 }
 
@@ -299,7 +320,8 @@ template <bool FILL>
 __global__ void k_rows(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t n, int64_t n_ext, const double *__restrict__ pext,
                        const int32_t *__restrict__ dom_ext, const int32_t *__restrict__ bin_ext,
                        const int64_t *__restrict__ kstart, int64_t *__restrict__ rowcnt, const int64_t *__restrict__ row,
-                       int32_t *__restrict__ col, int32_t *__restrict__ coincident) {
+                       int32_t *__restrict__ col, int32_t *__restrict__ coincident, uint32_t *__restrict__ mask,
+                       int32_t *__restrict__ ncand, int cap_words) {
     int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n_ext) return;
     const double xi = pext[x], yi = pext[n_ext + x], zi = pext[2 * n_ext + x];
@@ -307,9 +329,16 @@ __global__ void k_rows(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t
     const int bx = bin_ext[x];
     const int c2 = bx % b.nb[2], c1 = (bx / b.nb[2]) % b.nb[1], c0 = bx / (b.nb[2] * b.nb[1]);
     const int nslot = (x < n) ? n_species + n_ghost_slots : n_species;
-    int64_t cnt = 0, o = FILL ? row[x] : 0;
+    const int64_t cap_bits = (int64_t)cap_words * 32;
+    uint32_t *mrow = mask + x * cap_words;
+    // the fill replays the count pass's hits from its bits when they fitted, else it measures
+    // the distances again
+    const bool replay = FILL && ncand[x] <= cap_bits;
+    int64_t cnt = 0, o = FILL ? row[x] : 0, ci = 0;
+    uint32_t word = 0;
     // keys in increasing order (slot, then the stencil's bins by index): ext atoms are numbered
-    // in key order, so a row comes out with its columns ascending
+    // in key order, so a row comes out with its columns ascending; ci numbers the candidates in
+    // this order
     for (int slot = 0; slot < nslot; ++slot) {
         for (int d0 = -1; d0 <= 1; ++d0) {
             int a0 = c0 + d0;
@@ -322,22 +351,42 @@ __global__ void k_rows(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t
                     if (a2 < 0 || a2 >= b.nb[2]) continue;
                     int64_t bn = ((int64_t)a0 * b.nb[1] + a1) * b.nb[2] + a2;
                     int64_t k = ((int64_t)slot * g.ndom + p) * b.nbin + bn;
-                    for (int64_t e = kstart[k]; e < kstart[k + 1]; ++e) {
-                        if (e == x) continue;
-                        double dx = pext[e] - xi, dy = pext[n_ext + e] - yi, dz = pext[2 * n_ext + e] - zi;
-                        double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                        if (d2 < g.rc2) {
-                            if (FILL) col[o++] = (int32_t)e;
-                            else ++cnt;
+                    for (int64_t e = kstart[k]; e < kstart[k + 1]; ++e, ++ci) {
+                        if (replay) {
+                            if ((ci & 31) == 0) word = mrow[ci >> 5];
+                            if ((word >> (ci & 31)) & 1u) col[o++] = (int32_t)e;
+                            continue;
+                        }
+                        bool hit = false;
+                        if (e != x) {
+                            double dx = pext[e] - xi, dy = pext[n_ext + e] - yi, dz = pext[2 * n_ext + e] - zi;
+                            double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                            hit = d2 < g.rc2;
                             // two copies closer than 1e-6 A: the pair direction is undefined
                             if (!FILL && d2 < 1e-12) atomicOr(coincident, 1);
+                        }
+                        if (FILL) {
+                            if (hit) col[o++] = (int32_t)e;
+                        } else {
+                            if (hit) {
+                                ++cnt;
+                                word |= 1u << (ci & 31);
+                            }
+                            if ((ci & 31) == 31) {
+                                if ((ci >> 5) < cap_words) mrow[ci >> 5] = word;
+                                word = 0;
+                            }
                         }
                     }
                 }
             }
         }
     }
-    if (!FILL) rowcnt[x] = cnt;
+    if (!FILL) {
+        if ((ci & 31) != 0 && (ci >> 5) < cap_words) mrow[ci >> 5] = word;   // the last, partial word
+        rowcnt[x] = cnt;
+        ncand[x] = ci < INT32_MAX ? (int32_t)ci : INT32_MAX;
+    }
 }
 
 __global__ void k_copy_count(int64_t n_gh, const int32_t *__restrict__ owner, int32_t *__restrict__ cnt) {
@@ -599,7 +648,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     HIP_OK(hipMemsetAsync(cnt32, 0, (nkeys + 1) * sizeof(int32_t), st));
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_ext, B)), dim3(B), 0, st, n_ext, key, kstart, cnt32, order);
     LAUNCH_OK("k_scatter");
-    hipLaunchKernelGGL(k_sort_segments, dim3(grid_for(nkeys, B)), dim3(B), 0, st, nkeys, kstart, order);
+    hipLaunchKernelGGL(k_sort_segments, dim3(grid_for(nkeys, 4)), dim3(256), 0, st, nkeys, kstart, order);
     LAUNCH_OK("k_sort_segments");
 
     int32_t *perm = nl.perm.resize(n);
@@ -621,13 +670,20 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
         LAUNCH_OK("k_ghost_owner");
     }
 
-    // rows: count, scan, fill
+    // rows: count (keeping each row's hits as bits over its candidates), scan, fill.  The bits
+    // are kept for up to twice the mean number of candidates of a row (27 bins; a subdomain's
+    // atoms fill about its own share of the bins, so a bin holds about n_ext / nbin atoms); a
+    // row with more is measured again by the fill.
     int64_t *row = nl.row.resize(n_ext + 1);
     HIP_OK(hipMemsetAsync(row + n_ext, 0, sizeof(int64_t), st));
     int32_t *coinc = static_cast<int32_t *>(s.coinc.ensure(64));
     HIP_OK(hipMemsetAsync(coinc, 0, sizeof(int32_t), st));
+    const double mean_cand = 27.0 * (double)n_ext / (double)b.nbin;
+    const int cap_words = (int)std::min<double>(4096.0, std::ceil(2.0 * mean_cand / 32.0) + 2.0);
+    uint32_t *mask = static_cast<uint32_t *>(s.mask.ensure((size_t)n_ext * cap_words * sizeof(uint32_t)));
+    int32_t *ncand = static_cast<int32_t *>(s.ncand.ensure((size_t)n_ext * sizeof(int32_t)));
     hipLaunchKernelGGL(k_rows<false>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n, n_ext, pext,
-                       d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr, coinc);
+                       d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr, coinc, mask, ncand, cap_words);
     LAUNCH_OK("k_rows<count>");
     scan_exclusive_async(st, row, n_ext, s.m);
     // second read: pair counts, the key total and the species segments of the locals
@@ -661,7 +717,7 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     nl.n_local_pairs = hv[1];
     int32_t *col = nl.col.resize(n_pairs + 1);
     hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n, n_ext, pext,
-                       d_dom_ext, d_bin_ext, kstart, nullptr, row, col, nullptr);
+                       d_dom_ext, d_bin_ext, kstart, nullptr, row, col, nullptr, mask, ncand, cap_words);
     LAUNCH_OK("k_rows<fill>");
     // the rows are ascending as filled; the reverse slot of every entry
     {

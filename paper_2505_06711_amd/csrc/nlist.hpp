@@ -48,7 +48,7 @@ struct NList {
 
 // Scratch reused between builds.
 struct NListScratch {
-    DevBuf a, b, c, d, e, f, g, h, i, j, k, l, m, flag, mm, chk, dext, bext, gou, coinc;
+    DevBuf a, b, c, d, e, f, g, h, i, j, k, l, m, flag, mm, chk, dext, bext, gou, coinc, mask, ncand;
     PinnedWord sym;             // deferred symmetry check: the flag, copied back
     bool sym_pending = false;
 };
