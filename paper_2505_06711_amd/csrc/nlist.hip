@@ -248,9 +248,11 @@ __global__ void k_sort_segments32(int64_t nseg, const int32_t *__restrict__ star
     }
 }
 
-// rev[f] for the entry f = (x -> j) of a sorted list: the slot of (j -> x) in row j (binary
-// search).  Every entry has one: rows of locals list every ext atom in range, rows of ghosts
-// every local in range, and a row of a ghost only holds locals.  Sets *bad when one is missing.
+// rev[f] for the entry f = (x -> j) of a sorted list: the slot of (j -> x) in row j.  Every
+// entry has one: rows of locals list every ext atom in range, rows of ghosts every local in
+// range, and a row of a ghost only holds locals.  Each pair is resolved once, from its entry
+// with x < j (a binary search for x in row j), which writes both slots; rev starts at -1, and
+// k_reverse_check then sets *bad if a slot was not written (an entry without its reverse).
 __global__ void k_reverse(int64_t n_ext, const int64_t *__restrict__ row, const int32_t *__restrict__ col,
                           int32_t *__restrict__ rev, int32_t *__restrict__ bad) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,6 +262,7 @@ __global__ void k_reverse(int64_t n_ext, const int64_t *__restrict__ row, const 
     const int64_t hi = row[x + 1];
     for (int64_t f = row[x] + g; f < hi; f += 16) {
         const int32_t j = col[f];
+        if (j < x) continue;   // resolved from (j -> x)
         int64_t a = row[j], b = row[j + 1];
         const int64_t end = b;
         while (a < b) {
@@ -269,11 +272,16 @@ __global__ void k_reverse(int64_t n_ext, const int64_t *__restrict__ row, const 
         }
         if (a < end && col[a] == (int32_t)x) {
             rev[f] = (int32_t)a;
+            rev[a] = (int32_t)f;
         } else {
-            rev[f] = -1;
             atomicOr(bad, 1);
         }
     }
+}
+
+__global__ void k_reverse_check(int64_t n_pairs, const int32_t *__restrict__ rev, int32_t *__restrict__ bad) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < n_pairs && rev[f] < 0) atomicOr(bad, 1);
 }
 
 __global__ void k_build_ext(Bins b, int64_t n, int64_t n_ext, const int32_t *__restrict__ order,
@@ -724,8 +732,13 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
         int32_t *rev = nl.rev.resize(n_pairs + 1);
         int32_t *flag = static_cast<int32_t *>(s.flag.ensure(64));
         HIP_OK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+        HIP_OK(hipMemsetAsync(rev, 0xff, (n_pairs + 1) * sizeof(int32_t), st));   // -1: not resolved
         hipLaunchKernelGGL(k_reverse, dim3(grid_for(n_ext * 16, B)), dim3(B), 0, st, n_ext, row, col, rev, flag);
         LAUNCH_OK("k_reverse");
+        if (n_pairs > 0) {
+            hipLaunchKernelGGL(k_reverse_check, dim3(grid_for(n_pairs, B)), dim3(B), 0, st, n_pairs, rev, flag);
+            LAUNCH_OK("k_reverse_check");
+        }
     }
 
     // owner -> ghost copies
