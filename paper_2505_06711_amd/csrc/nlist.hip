@@ -322,10 +322,87 @@ __global__ void k_ghost_owner(int64_t n_gh, const int32_t *__restrict__ owner_us
     if (g < n_gh) owner[g] = inv_perm[owner_user[g]];
 }
 
-// Candidate scan over the 27 bins around atom x of its subdomain.  Locals see every
-// ext atom of the subdomain; ghosts see only locals.
+// Candidate scan over the 27 bins around atom x of its subdomain.  Locals see every ext atom
+// of the subdomain; ghosts see only locals.  A half-wave (32 lanes) takes a row: the keys in
+// increasing order (slot, then the stencil's bins by index), and each key's atoms 32 at a
+// time, one per lane, so that the atoms' positions are read contiguously.  Ext atoms are
+// numbered in key order, so the row comes out with its columns ascending.  The count pass
+// keeps each 32-atom chunk's hits as one word (up to cap_words chunks per row) and the fill
+// replays them; a row with more chunks is measured again by the fill.
+constexpr int kRowsPerBlk = 8;   // 256 threads, a half-wave per row
+
 template <bool FILL>
-__global__ void k_rows(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t n, int64_t n_ext, const double *__restrict__ pext,
+__global__ __launch_bounds__(256) void k_rows_group(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t n, int64_t n_ext,
+                                              const double *__restrict__ pext, const int32_t *__restrict__ dom_ext,
+                                              const int32_t *__restrict__ bin_ext, const int64_t *__restrict__ kstart,
+                                              int64_t *__restrict__ rowcnt, const int64_t *__restrict__ row,
+                                              int32_t *__restrict__ col, int32_t *__restrict__ coincident,
+                                              uint32_t *__restrict__ mask, int32_t *__restrict__ nchunk, int cap_words) {
+    const int64_t x = (int64_t)blockIdx.x * kRowsPerBlk + (threadIdx.x >> 5);
+    const int lane = threadIdx.x & 31, half = threadIdx.x & 32;
+    if (x >= n_ext) return;   // the whole half-wave
+    const double xi = pext[x], yi = pext[n_ext + x], zi = pext[2 * n_ext + x];
+    const int p = dom_ext[x];
+    const int bx = bin_ext[x];
+    const int c2 = bx % b.nb[2], c1 = (bx / b.nb[2]) % b.nb[1], c0 = bx / (b.nb[2] * b.nb[1]);
+    const int nslot = (x < n) ? n_species + n_ghost_slots : n_species;
+    uint32_t *mrow = mask + x * cap_words;
+    const bool replay = FILL && nchunk[x] <= cap_words;
+    int64_t cnt = 0, o = FILL ? row[x] : 0;
+    int q = 0;   // chunks so far
+    for (int slot = 0; slot < nslot; ++slot) {
+        for (int d0 = -1; d0 <= 1; ++d0) {
+            const int a0 = c0 + d0;
+            if (a0 < 0 || a0 >= b.nb[0]) continue;
+            for (int d1 = -1; d1 <= 1; ++d1) {
+                const int a1 = c1 + d1;
+                if (a1 < 0 || a1 >= b.nb[1]) continue;
+                for (int d2 = -1; d2 <= 1; ++d2) {
+                    const int a2 = c2 + d2;
+                    if (a2 < 0 || a2 >= b.nb[2]) continue;
+                    const int64_t bn = ((int64_t)a0 * b.nb[1] + a1) * b.nb[2] + a2;
+                    const int64_t k = ((int64_t)slot * g.ndom + p) * b.nbin + bn;
+                    const int64_t s0 = kstart[k], s1 = kstart[k + 1];
+                    for (int64_t t0 = s0; t0 < s1; t0 += 32, ++q) {
+                        const int64_t e = t0 + lane;
+                        uint32_t bits;
+                        if (replay) {
+                            bits = mrow[q];
+                        } else {
+                            bool hit = false;
+                            if (e < s1 && e != x) {
+                                const double dx = pext[e] - xi, dy = pext[n_ext + e] - yi, dz = pext[2 * n_ext + e] - zi;
+                                const double dd = fma(dz, dz, fma(dy, dy, dx * dx));
+                                hit = dd < g.rc2;
+                                // two copies closer than 1e-6 A: the pair direction is undefined
+                                if (!FILL && dd < 1e-12) atomicOr(coincident, 1);
+                            }
+                            bits = (uint32_t)(__ballot(hit) >> half);
+                        }
+                        if (FILL) {
+                            if ((bits >> lane) & 1u) col[o + __popc(bits & ((1u << lane) - 1u))] = (int32_t)e;
+                            o += __popc(bits);
+                        } else {
+                            cnt += __popc(bits);
+                            if (lane == 0 && q < cap_words) mrow[q] = bits;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (!FILL && lane == 0) {
+        rowcnt[x] = cnt;
+        nchunk[x] = q;
+    }
+}
+
+// The candidate scan (see k_rows_group) with a thread per row, each taking its candidates one
+// by one: the count pass keeps the hits as bits over the row's candidates (up to 32 cap_words),
+// and the fill replays them.  Suits rows whose keys hold few atoms (several elements, small
+// bins), where most lanes of a group would idle.
+template <bool FILL>
+__global__ void k_rows_thread(Bins b, Geom g, int n_species, int n_ghost_slots, int64_t n, int64_t n_ext, const double *__restrict__ pext,
                        const int32_t *__restrict__ dom_ext, const int32_t *__restrict__ bin_ext,
                        const int64_t *__restrict__ kstart, int64_t *__restrict__ rowcnt, const int64_t *__restrict__ row,
                        int32_t *__restrict__ col, int32_t *__restrict__ coincident, uint32_t *__restrict__ mask,
@@ -678,20 +755,28 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
         LAUNCH_OK("k_ghost_owner");
     }
 
-    // rows: count (keeping each row's hits as bits over its candidates), scan, fill.  The bits
-    // are kept for up to twice the mean number of candidates of a row (27 bins; a subdomain's
-    // atoms fill about its own share of the bins, so a bin holds about n_ext / nbin atoms); a
-    // row with more is measured again by the fill.
+    // rows: count (keeping the hits), scan, fill.  A bin holds about n_ext / nbin atoms (a
+    // subdomain's atoms fill about its own share of the bins), so a row has about
+    // 27 n_ext / nbin candidates; the hits are kept for up to about twice that (as bits per
+    // candidate, or one word per 32-atom chunk of a key).  Keys of 24 or more atoms on average
+    // take a half-wave per row, smaller ones a thread per row.
     int64_t *row = nl.row.resize(n_ext + 1);
     HIP_OK(hipMemsetAsync(row + n_ext, 0, sizeof(int64_t), st));
     int32_t *coinc = static_cast<int32_t *>(s.coinc.ensure(64));
     HIP_OK(hipMemsetAsync(coinc, 0, sizeof(int32_t), st));
-    const double mean_cand = 27.0 * (double)n_ext / (double)b.nbin;
-    const int cap_words = (int)std::min<double>(4096.0, std::ceil(2.0 * mean_cand / 32.0) + 2.0);
+    const double per_bin = (double)n_ext / (double)b.nbin, mean_cand = 27.0 * per_bin;
+    const bool group = per_bin / n_species >= 24.0;
+    const double words = std::ceil(2.0 * mean_cand / 32.0) + 2.0 + (group ? 27.0 * (n_species + nghs) : 0.0);
+    const int cap_words = (int)std::min<double>(4096.0, words);
     uint32_t *mask = static_cast<uint32_t *>(s.mask.ensure((size_t)n_ext * cap_words * sizeof(uint32_t)));
-    int32_t *ncand = static_cast<int32_t *>(s.ncand.ensure((size_t)n_ext * sizeof(int32_t)));
-    hipLaunchKernelGGL(k_rows<false>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n, n_ext, pext,
-                       d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr, coinc, mask, ncand, cap_words);
+    int32_t *nkept = static_cast<int32_t *>(s.ncand.ensure((size_t)n_ext * sizeof(int32_t)));
+    if (group)
+        hipLaunchKernelGGL(k_rows_group<false>, dim3(grid_for(n_ext, kRowsPerBlk)), dim3(256), 0, st, b, g, n_species,
+                           nghs, n, n_ext, pext, d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr, coinc, mask, nkept,
+                           cap_words);
+    else
+        hipLaunchKernelGGL(k_rows_thread<false>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n,
+                           n_ext, pext, d_dom_ext, d_bin_ext, kstart, row, nullptr, nullptr, coinc, mask, nkept, cap_words);
     LAUNCH_OK("k_rows<count>");
     scan_exclusive_async(st, row, n_ext, s.m);
     // second read: pair counts, the key total and the species segments of the locals
@@ -724,8 +809,13 @@ void build_nlist(hipStream_t st, const double *d_pos, const int32_t *d_species, 
     nl.n_pairs = n_pairs;
     nl.n_local_pairs = hv[1];
     int32_t *col = nl.col.resize(n_pairs + 1);
-    hipLaunchKernelGGL(k_rows<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n, n_ext, pext,
-                       d_dom_ext, d_bin_ext, kstart, nullptr, row, col, nullptr, mask, ncand, cap_words);
+    if (group)
+        hipLaunchKernelGGL(k_rows_group<true>, dim3(grid_for(n_ext, kRowsPerBlk)), dim3(256), 0, st, b, g, n_species,
+                           nghs, n, n_ext, pext, d_dom_ext, d_bin_ext, kstart, nullptr, row, col, nullptr, mask, nkept,
+                           cap_words);
+    else
+        hipLaunchKernelGGL(k_rows_thread<true>, dim3(grid_for(n_ext, 128)), dim3(128), 0, st, b, g, n_species, nghs, n,
+                           n_ext, pext, d_dom_ext, d_bin_ext, kstart, nullptr, row, col, nullptr, mask, nkept, cap_words);
     LAUNCH_OK("k_rows<fill>");
     // the rows are ascending as filled; the reverse slot of every entry
     {
