@@ -771,13 +771,15 @@ void reann_server::enqueue(Slot &slot) {
                            d_minv.as<double>(), sy.d_pos.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>());
         LAUNCH_OK("k_vv_drift");
         // CSVR: one normal and one chi-square (N_f - 1 degrees of freedom) per step from the
-        // system's stream; drawn every step so that the stream does not depend on the thermostat.
+        // system's stream, drawn when that thermostat is on (the kernel reads them only then).
         // The previous step of this system has completed, so its copy of h_rng has been made.
-        std::normal_distribution<double> nd(0.0, 1.0);
-        std::gamma_distribution<double> gd(0.5 * (3.0 * (double)sy.n - 1.0), 2.0);
-        sy.h_rng[0] = nd(sy.rng);
-        sy.h_rng[1] = sy.n * 3 > 1 ? gd(sy.rng) : 0.0;
-        HIP_OK(hipMemcpyAsync(sy.d_rng.p, sy.h_rng, 16, hipMemcpyHostToDevice, st));
+        if (opt.thermostat == REANN_THERMO_CSVR && opt.thermostat_K > 0.0 && opt.thermostat_tau_fs > 0.0) {
+            std::normal_distribution<double> nd(0.0, 1.0);
+            std::gamma_distribution<double> gd(0.5 * (3.0 * (double)sy.n - 1.0), 2.0);
+            sy.h_rng[0] = nd(sy.rng);
+            sy.h_rng[1] = sy.n * 3 > 1 ? gd(sy.rng) : 0.0;
+            HIP_OK(hipMemcpyAsync(sy.d_rng.p, sy.h_rng, 16, hipMemcpyHostToDevice, st));
+        }
     } else {
         HIP_OK(hipMemcpyAsync(sy.d_pos.p, r.pos.data(), sy.n * 24, hipMemcpyHostToDevice, st));
     }
