@@ -347,9 +347,13 @@ __global__ __launch_bounds__(256) void k_rows_group(Bins b, Geom g, int n_specie
     const int c2 = bx % b.nb[2], c1 = (bx / b.nb[2]) % b.nb[1], c0 = bx / (b.nb[2] * b.nb[1]);
     const int nslot = (x < n) ? n_species + n_ghost_slots : n_species;
     uint32_t *mrow = mask + x * cap_words;
-    const bool replay = FILL && nchunk[x] <= cap_words;
+    const int nkept = FILL ? nchunk[x] : 0;
+    const bool replay = FILL && nkept <= cap_words;
     int64_t cnt = 0, o = FILL ? row[x] : 0;
     int q = 0;   // chunks so far
+    // replay: the row's words are read 32 at a time, one per lane, and passed round by shuffles
+    uint32_t wbuf = 0;
+    int wbase = -32;
     for (int slot = 0; slot < nslot; ++slot) {
         for (int d0 = -1; d0 <= 1; ++d0) {
             const int a0 = c0 + d0;
@@ -367,7 +371,11 @@ __global__ __launch_bounds__(256) void k_rows_group(Bins b, Geom g, int n_specie
                         const int64_t e = t0 + lane;
                         uint32_t bits;
                         if (replay) {
-                            bits = mrow[q];
+                            if (q >= wbase + 32) {
+                                wbase = q;
+                                wbuf = q + lane < nkept ? mrow[q + lane] : 0u;
+                            }
+                            bits = (uint32_t)__shfl((int)wbuf, q - wbase, 32);
                         } else {
                             bool hit = false;
                             if (e < s1 && e != x) {
