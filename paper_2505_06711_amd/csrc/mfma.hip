@@ -487,13 +487,12 @@ constexpr int pair_split(int K) {
 // with rho the density of S.  NCB = H / 64 column blocks per wave; (L, K) fix the density.
 // L = 0 is the radial message form: its features are the K orbital sums S[0] themselves.
 template <OpType OP, int NCB, int L, int K>
-__global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
+__device__ __forceinline__ void mlp_fwd_body(const FusedNN &p, const int64_t m0) {
     using T = typename Fuse<OP>::T;
     constexpr int BM = kFuseBM, RB = BM / 16;
     constexpr int NLK = n_lambda(L) * K, P = K * (K + 1) / 2;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-    const int64_t m0 = (int64_t)blockIdx.x * BM;
     // layer 0 contracts over F rounded up to the chunk size only (the weight rows are padded
     // further, with zeros, which the product does not need)
     const int F = p.F, H = p.H, Fk = (F + Fuse<OP>::KC - 1) / Fuse<OP>::KC * Fuse<OP>::KC;
@@ -612,14 +611,13 @@ __device__ inline void out_adjoint(const FusedNN &p, const float *wo, const floa
 
 // Adjoint of one element's NN: C = dE/dS from G = dE/d(output), using the stored Z_k.
 template <OpType OP, int NCB, int L, int K>
-__global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
+__device__ __forceinline__ void mlp_bwd_body(const FusedNN &p, const int64_t m0) {
     constexpr int NCBF = (L + 1) * K * (K + 1) / 2 > 128 ? 4 : 2;   // column blocks per wave, first layer
     using T = typename Fuse<OP>::T;
     constexpr int BM = kFuseBM, RB = BM / 16;
     constexpr int NLK = n_lambda(L) * K, P = K * (K + 1) / 2, NL = n_lambda(L);
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-    const int64_t m0 = (int64_t)blockIdx.x * BM;
     const int F = p.F, H = p.H, dout = p.dout;
     const int ldh = H + Fuse<OP>::PAD, ldr = F + 4;
     // LDS from `smem` by offset arithmetic only (see the forward kernel).  Region A holds the
@@ -745,6 +743,32 @@ __global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
     }
 }
 
+// The kernels: one element's rows (blocks of kFuseBM rows), or several segments of the same NN
+// shape in one launch (block b runs segment s for tile0[s] <= b < tile0[s + 1]).
+template <OpType OP, int NCB, int L, int K>
+__global__ __launch_bounds__(256, 4) void k_mlp_fwd(FusedNN p) {
+    mlp_fwd_body<OP, NCB, L, K>(p, (int64_t)blockIdx.x * kFuseBM);
+}
+template <OpType OP, int NCB, int L, int K>
+__global__ __launch_bounds__(256, 4) void k_mlp_bwd(FusedNN p) {
+    mlp_bwd_body<OP, NCB, L, K>(p, (int64_t)blockIdx.x * kFuseBM);
+}
+__device__ __forceinline__ int fused_segment(const FusedMulti &pm) {
+    int s = 0;
+    while (s + 1 < pm.n && (int64_t)blockIdx.x >= pm.tile0[s + 1]) ++s;
+    return s;
+}
+template <OpType OP, int NCB, int L, int K>
+__global__ __launch_bounds__(256, 4) void k_mlp_fwd_multi(FusedMulti pm) {
+    const int s = fused_segment(pm);
+    mlp_fwd_body<OP, NCB, L, K>(pm.seg[s], ((int64_t)blockIdx.x - pm.tile0[s]) * kFuseBM);
+}
+template <OpType OP, int NCB, int L, int K>
+__global__ __launch_bounds__(256, 4) void k_mlp_bwd_multi(FusedMulti pm) {
+    const int s = fused_segment(pm);
+    mlp_bwd_body<OP, NCB, L, K>(pm.seg[s], ((int64_t)blockIdx.x - pm.tile0[s]) * kFuseBM);
+}
+
 bool fused_nn_ok(OpType op, int F, int H, int nh, int dout, int NLK) {
     (void)op;
     return (H == 64 || H == 128) && F >= 1 && F <= kFuseMaxF && nh >= 1 && nh <= kFuseMaxNh &&
@@ -817,18 +841,44 @@ static size_t fused_smem(OpType op, bool fwd, int F, int H, int dout, int NLK) {
     return b + (size_t)dout * H * (dout == 1 ? 8 : 4);   // W_out: FP64 for the energy NN
 }
 
-void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
-    if (p.rows <= 0) return;
+// Launch the fused kernel over nseg segments of the same NN shape: one segment with the
+// per-element kernel, several with the segment-table kernel.
+static void launch_fused(hipStream_t st, OpType op, bool fwd, const FusedNN *segs, int nseg) {
+    const FusedNN &p = segs[0];
     const int NLK = p.dc.lstart[p.L + 1] * p.K;
     const int Fwant = p.L == 0 ? p.K : (p.L + 1) * p.K * (p.K + 1) / 2;   // L = 0: the radial form
     if (!fused_nn_ok(op, p.F, p.H, p.nh, p.dout, NLK) || p.F != Fwant || (p.dout != p.K && p.dout != 1))
         fail(REANN_E_DEVICE, "mlp_fused: unsupported layer shape");
+    FusedMulti pm{};
+    int64_t tiles = 0;
+    if (nseg > 1) {
+        if (nseg > kFuseMaxSeg) fail(REANN_E_DEVICE, "mlp_fused: too many segments");
+        pm.n = nseg;
+        for (int s = 0; s < nseg; ++s) {
+            const FusedNN &q = segs[s];
+            if (q.F != p.F || q.H != p.H || q.nh != p.nh || q.dout != p.dout || q.L != p.L || q.K != p.K)
+                fail(REANN_E_DEVICE, "mlp_fused: segments of different shapes");
+            pm.seg[s] = q;
+            pm.tile0[s] = tiles;
+            tiles += (q.rows + kFuseBM - 1) / kFuseBM;
+        }
+        pm.tile0[nseg] = tiles;
+    } else {
+        tiles = (p.rows + kFuseBM - 1) / kFuseBM;
+    }
+    if (tiles <= 0) return;
     const size_t smem = fused_smem(op, fwd, p.F, p.H, p.dout, NLK);
-    const dim3 grid((unsigned)((p.rows + kFuseBM - 1) / kFuseBM));
+    const dim3 grid((unsigned)tiles);
     const bool h128 = p.H == 128;   // the kernels take H = 64 NCB as a compile-time constant
-#define LK_(OPV, NC, LL, KK)                                                                          \
-    if (fwd) hipLaunchKernelGGL((k_mlp_fwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);        \
-    else hipLaunchKernelGGL((k_mlp_bwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);
+    const bool multi = nseg > 1;
+#define LK_(OPV, NC, LL, KK)                                                                                  \
+    if (fwd) {                                                                                              \
+        if (multi) hipLaunchKernelGGL((k_mlp_fwd_multi<OPV, NC, LL, KK>), grid, dim3(256), smem, st, pm);   \
+        else hipLaunchKernelGGL((k_mlp_fwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);                \
+    } else {                                                                                                \
+        if (multi) hipLaunchKernelGGL((k_mlp_bwd_multi<OPV, NC, LL, KK>), grid, dim3(256), smem, st, pm);   \
+        else hipLaunchKernelGGL((k_mlp_bwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);                \
+    }
 #define NC_(OPV, LL, KK)                       \
     if (h128) { LK_(OPV, 2, LL, KK) }          \
     else { LK_(OPV, 1, LL, KK) }
@@ -845,7 +895,9 @@ void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
     else {
         if (!fwd) fail(REANN_E_DEVICE, "mlp_fused: FP8 runs the forward only (its adjoint takes BF16 operands)");
 #undef LK_
-#define LK_(OPV, NC, LL, KK) hipLaunchKernelGGL((k_mlp_fwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);
+#define LK_(OPV, NC, LL, KK)                                                                                  \
+    if (multi) hipLaunchKernelGGL((k_mlp_fwd_multi<OPV, NC, LL, KK>), grid, dim3(256), smem, st, pm);       \
+    else hipLaunchKernelGGL((k_mlp_fwd<OPV, NC, LL, KK>), grid, dim3(256), smem, st, p);
         ALL_(OpType::FP8)
 #undef LK_
     }
@@ -853,6 +905,21 @@ void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
 #undef NC_
 #undef LK_
     LAUNCH_OK(fwd ? "k_mlp_fwd" : "k_mlp_bwd");
+}
+
+void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p) {
+    if (p.rows <= 0) return;
+    launch_fused(st, op, fwd, &p, 1);
+}
+
+int mlp_fused_segments(hipStream_t st, OpType op, bool fwd, const FusedNN *segs, int nseg) {
+    int launches = 0;
+    for (int s0 = 0; s0 < nseg; s0 += kFuseMaxSeg) {
+        const int k = std::min(kFuseMaxSeg, nseg - s0);
+        launch_fused(st, op, fwd, segs + s0, k);
+        ++launches;
+    }
+    return launches;
 }
 
 }  // namespace reann

@@ -64,6 +64,16 @@ struct FusedNN {
     int ldc;
 };
 
+// Segments of the same NN shape (the elements' rows of one layer, or locals and ghosts) for
+// one launch of the fused kernels.  Kernel arguments stay well under 4 KiB.
+constexpr int kFuseMaxSeg = 4;
+struct FusedMulti {
+    int n;
+    int64_t tile0[kFuseMaxSeg + 1];   // first block of each segment; tile0[n] = total blocks
+    FusedNN seg[kFuseMaxSeg];
+};
+static_assert(sizeof(FusedMulti) < 3072, "kernel arguments");
+
 // Whether the fused kernels take these shapes (every operand type: FP8 runs the forward only,
 // its adjoint takes BF16 operands).
 bool fused_nn_ok(OpType op, int F, int H, int nh, int dout, int NLK);
@@ -77,6 +87,8 @@ void silu_absmax(hipStream_t st, int64_t rows, int H, int ld, const float *Z, fl
 // accumulation) or adjoint (fwd = false: output layer, hidden layers, first layer, density
 // adjoint to dE/dS) of one element's NN.
 void mlp_fused(hipStream_t st, OpType op, bool fwd, const FusedNN &p);
+// The same over nseg segments of one NN shape, kFuseMaxSeg to a launch; returns the launches.
+int mlp_fused_segments(hipStream_t st, OpType op, bool fwd, const FusedNN *segs, int nseg);
 
 inline size_t op_bytes(OpType op) { return op == OpType::F32 ? 4 : (op == OpType::BF16 ? 2 : 1); }
 

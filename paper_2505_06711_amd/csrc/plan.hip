@@ -367,6 +367,7 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
                               : (fp64 ? w.msg64.as<char>() : w.msg32.as<char>());
     const int F = m->F, H = m->H, nh = m->nh, K = m->K;
     int nfused = 0;
+    std::vector<FusedNN> segs;   // the fused kernel's segments, launched together below
     for (int s = 0; s < m->n_species; ++s) {
       int64_t ra[2], rn[2];
       const int nr = nn_ranges(s, energy, ra, rn);
@@ -405,8 +406,7 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
                 f.bout64 = p64 + lay.b_off[nh];
             }
             f.C = (float *)out; f.ldc = dout;
-            mlp_fused(st, op, true, f);
-            ++nfused;
+            segs.push_back(f);
             continue;
         }
         for (int k = 0; k < nh; ++k) {
@@ -438,6 +438,8 @@ int Plan::nn_forward(hipStream_t st, int t, bool energy) {
                           (const float *)(p + lay.b_off[nh] * rs), (float *)out, dout);
       }
     }
+    // the elements' rows (and ghosts') are independent: one launch over all of them
+    if (!segs.empty()) nfused += mlp_fused_segments(st, op, true, segs.data(), (int)segs.size());
     return nfused;
 }
 
@@ -450,6 +452,8 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
                               : (fp64 ? w.msg64.as<char>() : w.msg32.as<char>());
     const int F = m->F, H = m->H, nh = m->nh;
     int nfused = 0;
+    std::vector<FusedNN> segs;   // the fused kernel's segments, launched together below
+    OpType seg_op = op;
     for (int s = 0; s < m->n_species; ++s) {
       int64_t ra[2], rn[2];
       const int nr = nn_ranges(s, energy, ra, rn);
@@ -482,8 +486,8 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
             f.Wout = (const float *)(p + lay.w_off[nh] * rs);
             f.G = (const float *)gin; f.ldg = ldin;
             f.C = (float *)(Sbar.as<char>() + (size_t)a * m->NL * m->K * rs); f.ldc = m->NL * m->K;
-            mlp_fused(st, bop, false, f);
-            ++nfused;
+            segs.push_back(f);
+            seg_op = bop;
             continue;
         }
         for (int k = nh; k >= 1; --k) {
@@ -522,6 +526,7 @@ int Plan::nn_vjp(hipStream_t st, int t, bool energy, const char *gout, int ldg) 
         }
       }
     }
+    if (!segs.empty()) nfused += mlp_fused_segments(st, seg_op, false, segs.data(), (int)segs.size());
     return nfused;
 }
 
