@@ -433,17 +433,24 @@ void out_layer_vjp(hipStream_t st, int64_t rows, int out, int in, const float *G
     LAUNCH_OK("k_out_vjp");
 }
 
+// The backward's start: the energy adjoint of every atom, and (nz > 0) zeros in z[0, nz).
 template <typename R>
 __global__ void k_seed(int64_t n, double scale, const double *__restrict__ g, const int32_t *__restrict__ perm,
-                       const double *__restrict__ w, R *__restrict__ ybar) {
+                       const double *__restrict__ w, R *__restrict__ ybar, int64_t nz, R *__restrict__ z) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) ybar[i] = R(scale * (g ? *g : 1.0) * (w ? w[perm[i]] : 1.0));
+    if (i < nz) z[i] = R(0);
 }
 
 void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const double *g, const int32_t *perm,
-                      const double *w_user, void *ybar) {
-    if (fp64) hipLaunchKernelGGL(k_seed<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, scale, g, perm, w_user, (double *)ybar);
-    else hipLaunchKernelGGL(k_seed<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, scale, g, perm, w_user, (float *)ybar);
+                      const double *w_user, void *ybar, int64_t nzero, void *zero_out) {
+    const int64_t nt = std::max<int64_t>(n, nzero);
+    if (fp64)
+        hipLaunchKernelGGL(k_seed<double>, dim3(grid_for(nt, 256)), dim3(256), 0, st, n, scale, g, perm, w_user,
+                           (double *)ybar, nzero, (double *)zero_out);
+    else
+        hipLaunchKernelGGL(k_seed<float>, dim3(grid_for(nt, 256)), dim3(256), 0, st, n, scale, g, perm, w_user,
+                           (float *)ybar, nzero, (float *)zero_out);
     LAUNCH_OK("k_seed");
 }
 

@@ -48,9 +48,9 @@ int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const vo
 // out[0] = sum of partials[0..nb) (single block, fixed order); if accumulate, out[q] += ...
 void sum_rows(hipStream_t st, const double *partials, int nb, int width, double *out, bool accumulate);
 // ybar[i] = scale * g * w[perm[i]]  (g = device scalar or NULL = 1; w_user = caller-order weights
-// or NULL = 1)
+// or NULL = 1), and zero_out[0, nzero) = 0 in the same launch (working type)
 void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const double *g, const int32_t *perm,
-                      const double *w_user, void *ybar);
+                      const double *w_user, void *ybar, int64_t nzero = 0, void *zero_out = nullptr);
 // forces_user[perm[i]][a] = gscale * F[i][a]; virial_out[q] = gscale * W[q]
 void forces_out(hipStream_t st, bool fp64, int64_t n, const void *F, const int32_t *perm, const double *g,
                 double *forces_user, const double *W, double *virial_out);

@@ -680,7 +680,11 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
     const int K = m->K;
     DeviceWeights &w = m->weights(ctx->device, st);
     refresh_positions(st, nl, d_pos, p4.as<double4>());
-    init_messages(st, fp64, nl.n_ext, K, nl.spec_ext.ptr(), fp64 ? w.c064.p : w.c032.p, cptr(0));
+    // c^0 depends on the element alone and nothing writes it afterwards: set once per list build
+    if (c0_build != rebuilds) {
+        init_messages(st, fp64, nl.n_ext, K, nl.spec_ext.ptr(), fp64 ? w.c064.p : w.c032.p, cptr(0));
+        c0_build = rebuilds;
+    }
     EdgeArgs ea{n, nl.n_ext, nl.row.ptr(), nl.col.ptr(), p4.as<double4>()};
     CutList cl = cutlist();
     compact_cutoff(st, ea, m->r_c, cl);
@@ -734,8 +738,9 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     const EdgeConsts ec = m->edge_consts();
     const DensityConsts dc = m->density_consts();
     mark(st, -1);
-    fill_energy_seed(st, fp64, n, m->energy_scale, d_g, nl.perm.ptr(), have_ew ? d_ew.ptr() : nullptr, ybar.p);
-    zero(st, this->F.p, (size_t)nl.n_ext * 3 * rs);
+    // the energy adjoints, and the force accumulator cleared, in one launch
+    fill_energy_seed(st, fp64, n, m->energy_scale, d_g, nl.perm.ptr(), have_ew ? d_ew.ptr() : nullptr, ybar.p,
+                     nl.n_ext * 3, this->F.p);
     mark(st, PH_OTHER);
     mark(st, PH_NN_BWD, nn_vjp(st, T - 1, true, ybar.as<char>(), 1));
     if (!fused() && !radial()) {

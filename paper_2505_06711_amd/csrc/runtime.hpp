@@ -106,6 +106,7 @@ struct Plan {
     NListScratch ns;
     bool built = false;
     int64_t rebuilds = 0;
+    int64_t c0_build = -1;   // the list build whose ext atoms cptr(0) holds c^0 for
     // layer buffers
     DevBuf p4, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, Wacc, disp, one;
     DevBuf cbar_next;                // radial form: dE/dc^{t+1} of the locals, carried by the residual

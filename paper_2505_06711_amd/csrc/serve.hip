@@ -60,16 +60,6 @@ __global__ void k_vv_drift(int64_t n, double dt, const int32_t *__restrict__ spe
     x[t] = drift(x[t], v[t], F[t], minv[spec[t / 3]], dt);
 }
 
-// The kick; the first thread also clears the two displacement maxima that k_vv_post raises.
-__global__ void k_vv_kick(int64_t n, double dt, const int32_t *__restrict__ spec, const double *__restrict__ minv,
-                          double *__restrict__ v, const double *__restrict__ Fold, const double *__restrict__ Fnew,
-                          unsigned long long *__restrict__ dmax) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) dmax[0] = dmax[3] = 0ull;
-    if (t >= n * 3) return;
-    v[t] = v[t] + 0.5 * (Fold[t] + Fnew[t]) * minv[spec[t / 3]] * kAccel * dt;
-}
-
 constexpr double kBoltzmann = 8.617333262e-5;   // eV / K
 constexpr int kKeBlock = 256;
 
@@ -84,17 +74,24 @@ constexpr int kKeBlock = 256;
 // applies), lambda max|v_c| and max|a_c|.
 constexpr int kAuxKe = 16;       // kinetic partials, 3 per block
 
-__global__ __launch_bounds__(kKeBlock) void k_ke_part(int64_t n3, const int32_t *__restrict__ spec,
-                                                       const double *__restrict__ minv, const double *__restrict__ v,
-                                                       const double *__restrict__ F, double *__restrict__ part) {
+// The kick of a velocity-Verlet step with the new forces F, then the block's kinetic partials
+// of the kicked velocities; the first thread also clears the two displacement maxima that
+// k_vv_post raises.
+__global__ __launch_bounds__(kKeBlock) void k_vv_kick_ke(int64_t n3, double dt, const int32_t *__restrict__ spec,
+                                                          const double *__restrict__ minv, double *__restrict__ v,
+                                                          const double *__restrict__ Fold, const double *__restrict__ F,
+                                                          double *__restrict__ part, unsigned long long *__restrict__ dmax) {
     __shared__ double sh[3][kKeBlock];
     const int64_t t = (int64_t)blockIdx.x * kKeBlock + threadIdx.x;
+    if (t == 0) dmax[0] = dmax[3] = 0ull;
     double s = 0.0, vm = 0.0, am = 0.0;
     if (t < n3) {
         const double mi = minv[spec[t / 3]];
+        const double vt = v[t] + 0.5 * (Fold[t] + F[t]) * mi * kAccel * dt;
+        v[t] = vt;
         if (mi > 0.0) {
-            s = v[t] * v[t] / mi;
-            vm = fabs(v[t]);
+            s = vt * vt / mi;
+            vm = fabs(vt);
             am = fabs(F[t] * mi * kAccel);
         }
     }
@@ -557,14 +554,11 @@ void reann_server::enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt, int
     // dt (head[14]), raised by k_vv_post as integer maxima
     unsigned long long *dmax = reinterpret_cast<unsigned long long *>(sy.d_out.as<double>() + 11);
     if (vv) {
-        hipLaunchKernelGGL(k_vv_kick, dim3(grid_for(n3, B)), dim3(B), 0, st, sy.n, dt, sy.d_spec.ptr(),
-                           d_minv.as<double>(), sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.F(), dmax);
-        LAUNCH_OK("k_vv_kick");
         const int nb = grid_for(n3, kKeBlock);
         double *aux = sy.d_aux.as<double>();
-        hipLaunchKernelGGL(k_ke_part, dim3(nb), dim3(kKeBlock), 0, st, n3, sy.d_spec.ptr(), d_minv.as<double>(),
-                           sy.d_vel.as<double>(), sy.F(), aux + kAuxKe);
-        LAUNCH_OK("k_ke_part");
+        hipLaunchKernelGGL(k_vv_kick_ke, dim3(nb), dim3(kKeBlock), 0, st, n3, dt, sy.d_spec.ptr(), d_minv.as<double>(),
+                           sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.F(), aux + kAuxKe, dmax);
+        LAUNCH_OK("k_vv_kick_ke");
         hipLaunchKernelGGL(k_ke_final, dim3(1), dim3(kKeBlock), 0, st, sy.n, nb, dt, opt.thermostat_K,
                            opt.thermostat_tau_fs, (int)opt.thermostat, sy.d_rng.as<double>(), aux, sy.KE());
         LAUNCH_OK("k_ke_final");
