@@ -454,24 +454,48 @@ void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const 
     LAUNCH_OK("k_seed");
 }
 
+// Blocks [0, 9): virial component q = the sum over the nw rows of Wpart[.][q] (in the order of
+// sum_rows), times g, to Wout (when asked for); the other blocks: forces in caller order, times g.
+__device__ inline double virial_column(const double *__restrict__ part, int nw, int q) {
+    __shared__ double sm[256];
+    double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int r = threadIdx.x;
+    for (; r + 7 * 256 < nw; r += 8 * 256)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s8[u] += part[(int64_t)(r + u * 256) * 9 + q];
+    for (; r < nw; r += 256) s8[0] += part[(int64_t)r * 9 + q];
+    sm[threadIdx.x] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+        __syncthreads();
+    }
+    return sm[0];
+}
+
 template <typename R>
-__global__ void k_forces_out(int64_t n, const R *__restrict__ F, const int32_t *__restrict__ perm,
-                             const double *__restrict__ g, double *__restrict__ out, const double *__restrict__ W,
-                             double *__restrict__ Wout) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_forces_out(int64_t n, const R *__restrict__ F, const int32_t *__restrict__ perm,
+                                                    const double *__restrict__ g, double *__restrict__ out,
+                                                    const double *__restrict__ Wpart, int nw, double *__restrict__ Wout) {
     const double gs = g ? *g : 1.0;
+    if (blockIdx.x < 9) {
+        if (!Wout) return;   // uniform over the block
+        const double w = virial_column(Wpart, nw, (int)blockIdx.x);
+        if (threadIdx.x == 0) Wout[blockIdx.x] = gs * w;
+        return;
+    }
+    const int64_t t = (int64_t)(blockIdx.x - 9) * blockDim.x + threadIdx.x;
     if (t < n * 3) {
         const int64_t i = t / 3, a = t % 3;
         out[(int64_t)perm[i] * 3 + a] = gs * (double)F[t];
     }
-    if (Wout && t < 9) Wout[t] = gs * W[t];
 }
 
 void forces_out(hipStream_t st, bool fp64, int64_t n, const void *F, const int32_t *perm, const double *g,
-                double *forces_user, const double *W, double *virial_out) {
-    const int64_t tot = n * 3 > 9 ? n * 3 : 9;
-    if (fp64) hipLaunchKernelGGL(k_forces_out<double>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, (const double *)F, perm, g, forces_user, W, virial_out);
-    else hipLaunchKernelGGL(k_forces_out<float>, dim3(grid_for(tot, 256)), dim3(256), 0, st, n, (const float *)F, perm, g, forces_user, W, virial_out);
+                double *forces_user, const double *Wpart, int nw, double *virial_out) {
+    const unsigned nb = 9u + (unsigned)grid_for(n * 3, 256);
+    if (fp64) hipLaunchKernelGGL(k_forces_out<double>, dim3(nb), dim3(256), 0, st, n, (const double *)F, perm, g, forces_user, Wpart, nw, virial_out);
+    else hipLaunchKernelGGL(k_forces_out<float>, dim3(nb), dim3(256), 0, st, n, (const float *)F, perm, g, forces_user, Wpart, nw, virial_out);
     LAUNCH_OK("k_forces_out");
 }
 

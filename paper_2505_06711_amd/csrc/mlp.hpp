@@ -51,9 +51,10 @@ void sum_rows(hipStream_t st, const double *partials, int nb, int width, double 
 // or NULL = 1), and zero_out[0, nzero) = 0 in the same launch (working type)
 void fill_energy_seed(hipStream_t st, bool fp64, int64_t n, double scale, const double *g, const int32_t *perm,
                       const double *w_user, void *ybar, int64_t nzero = 0, void *zero_out = nullptr);
-// forces_user[perm[i]][a] = gscale * F[i][a]; virial_out[q] = gscale * W[q]
+// forces_user[perm[i]][a] = gscale * F[i][a]; virial_out[q] = gscale * sum_r Wpart[r][q] over the
+// nw rows of partials (virial_out NULL: not formed); one launch
 void forces_out(hipStream_t st, bool fp64, int64_t n, const void *F, const int32_t *perm, const double *g,
-                double *forces_user, const double *W, double *virial_out);
+                double *forces_user, const double *Wpart, int nw, double *virial_out);
 void zero(hipStream_t st, void *p, size_t bytes);
 // dst += src, and dst = src, over `count` elements of the working type (FP64 or FP32)
 void add_into(hipStream_t st, bool fp64, int64_t count, void *dst, const void *src);

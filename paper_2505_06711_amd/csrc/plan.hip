@@ -309,7 +309,6 @@ void Plan::alloc_buffers() {
     cbar.ensure((size_t)ne * K * rs);
     this->F.ensure((size_t)ne * 3 * rs);
     Wpart.ensure((size_t)T * (edge_backward_blocks(ne) + 1) * 9 * 8);   // per layer, summed once
-    Wacc.ensure(16 * 8);
     disp.ensure(1025 * 8);
     col2.ensure((size_t)(nl.n_pairs + 1) * 4);
     fslot.ensure((size_t)(nl.n_pairs + 1) * 4);
@@ -323,7 +322,7 @@ void Plan::alloc_buffers() {
 size_t Plan::device_bytes() const {
     size_t b = 0;
     for (const DevBuf *d : {&p4, &c, &S, &rho, &Z, &Hh, &y, &ybar, &Eat, &Epart, &Sbar, &rhobar, &gA, &gB,
-                            &cbar, &F, &Wpart, &Wacc, &disp, &col2, &fslot, &cpos, &rslot, &nloc, &ngh, &erec, &fp8s,
+                            &cbar, &F, &Wpart, &disp, &col2, &fslot, &cpos, &rslot, &nloc, &ngh, &erec, &fp8s,
                             &fp8tmp, &cbar_next})
         b += d->bytes;
     b += nl.perm.bytes() + nl.inv_perm.bytes() + nl.q.bytes() + nl.gh_owner.bytes() + nl.gh_shift.bytes() +
@@ -786,9 +785,9 @@ void Plan::backward(const double *d_g, double *d_forces, double *d_virial, hipSt
     }
     ghost_reduce(st, fp64, n, 3, nl.copy_ptr.ptr(), nl.copy_idx.ptr(), this->F.p);
     mark(st, PH_GHOST);
-    sum_rows(st, Wpart.as<double>(), nbw, 9, Wacc.as<double>(), false);
-    // the seed carried g; forces are -dE/dx already scaled
-    forces_out(st, fp64, n, this->F.p, nl.perm.ptr(), nullptr, d_forces, Wacc.as<double>(), d_virial);
+    // the seed carried g; forces are -dE/dx already scaled; the virial partials are summed in the
+    // same launch
+    forces_out(st, fp64, n, this->F.p, nl.perm.ptr(), nullptr, d_forces, Wpart.as<double>(), nbw, d_virial);
     mark(st, PH_OTHER);
     if (timing) ++timed_steps;
 }

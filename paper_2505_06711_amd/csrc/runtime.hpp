@@ -108,7 +108,7 @@ struct Plan {
     int64_t rebuilds = 0;
     int64_t c0_build = -1;   // the list build whose ext atoms cptr(0) holds c^0 for
     // layer buffers
-    DevBuf p4, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, Wacc, disp, one;
+    DevBuf p4, c, S, rho, Z, Hh, y, ybar, Eat, Epart, Sbar, rhobar, gA, gB, cbar, F, Wpart, disp, one;
     DevBuf cbar_next;                // radial form: dE/dc^{t+1} of the locals, carried by the residual
     DevBuf col2, fslot, cpos, rslot, nloc, ngh;   // in-cutoff compaction of the list for the current step
     DevBuf erec;                     // per-slot edge records of the adjoint
