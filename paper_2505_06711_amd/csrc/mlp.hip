@@ -312,6 +312,40 @@ __global__ void k_energy(int64_t n, double scale, const R *__restrict__ y, const
     if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
 }
 
+// The same for a small system in one block, which also forms the total: thread t takes atoms
+// t, t + 256, ... in order, then a tree over the threads.
+template <typename R>
+__global__ __launch_bounds__(kRedBlock) void k_energy_total(int64_t n, double scale, const R *__restrict__ y,
+                                                            const int32_t *__restrict__ perm, const double *__restrict__ w,
+                                                            double *__restrict__ Eat, double *__restrict__ total) {
+    __shared__ double sm[kRedBlock];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kRedBlock) {
+        const double e = scale * (double)y[i];
+        if (Eat) Eat[perm[i]] = e;
+        acc += w ? w[perm[i]] * e : e;
+    }
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kRedBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = sm[0];
+}
+
+void energy_total(hipStream_t st, bool fp64, int64_t n, double scale, const void *y, const int32_t *perm,
+                  const double *w_user, double *Eat_user, double *partials, double *total) {
+    if (n <= kEnergyOneBlock) {
+        if (fp64) hipLaunchKernelGGL(k_energy_total<double>, dim3(1), dim3(kRedBlock), 0, st, n, scale, (const double *)y, perm, w_user, Eat_user, total);
+        else hipLaunchKernelGGL(k_energy_total<float>, dim3(1), dim3(kRedBlock), 0, st, n, scale, (const float *)y, perm, w_user, Eat_user, total);
+        LAUNCH_OK("k_energy_total");
+        return;
+    }
+    const int nb = energy_finalize(st, fp64, n, scale, y, perm, w_user, Eat_user, partials);
+    sum_rows(st, partials, nb, 1, total, false);
+}
+
 int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const void *y, const int32_t *perm,
                     const double *w_user, double *Eat_user, double *partials) {
     const int nb = grid_for(n, kRedBlock);

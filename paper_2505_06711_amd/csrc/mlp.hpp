@@ -45,6 +45,12 @@ void out_layer_vjp(hipStream_t st, int64_t rows, int out, int in, const float *G
 // local order (w_user: caller-order weights, NULL = 1).
 int energy_finalize(hipStream_t st, bool fp64, int64_t n, double scale, const void *y, const int32_t *perm,
                     const double *w_user, double *Eat_user, double *partials);
+// total[0] = sum of w[perm[i]] Eat[perm[i]], with Eat written as above: a system of at most
+// kEnergyOneBlock atoms in one launch (one block, fixed order), a larger one by energy_finalize
+// and sum_rows (partials: grid_for(n, 256) doubles)
+constexpr int64_t kEnergyOneBlock = 8192;
+void energy_total(hipStream_t st, bool fp64, int64_t n, double scale, const void *y, const int32_t *perm,
+                  const double *w_user, double *Eat_user, double *partials, double *total);
 // out[0] = sum of partials[0..nb) (single block, fixed order); if accumulate, out[q] += ...
 void sum_rows(hipStream_t st, const double *partials, int nb, int width, double *out, bool accumulate);
 // ybar[i] = scale * g * w[perm[i]]  (g = device scalar or NULL = 1; w_user = caller-order weights

@@ -720,9 +720,8 @@ void Plan::launch_forward(const double *d_pos, double *d_energy, double *d_atom_
         }
     }
     mark(st, PH_NN_FWD, nn_forward(st, T - 1, true));
-    const int nb = energy_finalize(st, fp64, n, m->energy_scale, y.p, nl.perm.ptr(), have_ew ? d_ew.ptr() : nullptr,
-                                   d_atom_energy, Epart.as<double>());
-    sum_rows(st, Epart.as<double>(), nb, 1, d_energy, false);
+    energy_total(st, fp64, n, m->energy_scale, y.p, nl.perm.ptr(), have_ew ? d_ew.ptr() : nullptr, d_atom_energy,
+                 Epart.as<double>(), d_energy);
     mark(st, PH_OTHER);
     have_forward = true;
     ++generation;
