@@ -110,6 +110,33 @@ __global__ __launch_bounds__(kKeBlock) void k_vv_kick_ke(int64_t n3, double dt, 
     }
 }
 
+// From sum m v^2 (s2, amu A^2/fs^2), max |v_c| and max |a_c|: the kinetic energy, the thermostat's
+// factor lambda (aux[0]) and the result head (see above).
+__device__ inline void ke_thermostat(double s2, double vm, double am, int64_t n, double dt, double T0, double tau,
+                                     int kind, const double *__restrict__ rng, double *__restrict__ aux,
+                                     double *__restrict__ head) {
+    const double K = 0.5 * s2 / kAccel;   // amu A^2 / fs^2 -> eV
+    double lam2 = 1.0;
+    if (T0 > 0.0 && tau > 0.0 && K > 0.0) {
+        const double nf = 3.0 * (double)n;
+        if (kind == REANN_THERMO_CSVR) {
+            const double r1 = rng[0], s_chi2 = rng[1];
+            const double K0 = 0.5 * nf * kBoltzmann * T0, c = exp(-dt / tau);
+            const double Kn = K + (1.0 - c) * (K0 * (r1 * r1 + s_chi2) / nf - K) +
+                              2.0 * r1 * sqrt(c * (1.0 - c) * K * K0 / nf);
+            lam2 = fmax(0.0, Kn / K);
+        } else {
+            const double Tcur = 2.0 * K / (nf * kBoltzmann);
+            lam2 = fmax(0.0, 1.0 + dt / tau * (T0 / Tcur - 1.0));
+        }
+    }
+    const double lam = sqrt(lam2);
+    aux[0] = lam;
+    head[0] = lam2 * K;
+    head[2] = lam * vm;
+    head[3] = am;
+}
+
 __global__ __launch_bounds__(kKeBlock) void k_ke_final(int64_t n, int nb, double dt, double T0, double tau,
                                                         int kind, const double *__restrict__ rng,
                                                         double *__restrict__ aux, double *__restrict__ head) {
@@ -131,28 +158,43 @@ __global__ __launch_bounds__(kKeBlock) void k_ke_final(int64_t n, int nb, double
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double K = 0.5 * sh[0][0] / kAccel;   // amu A^2 / fs^2 -> eV
-        double lam2 = 1.0;
-        if (T0 > 0.0 && tau > 0.0 && K > 0.0) {
-            const double nf = 3.0 * (double)n;
-            if (kind == REANN_THERMO_CSVR) {
-                const double r1 = rng[0], s_chi2 = rng[1];
-                const double K0 = 0.5 * nf * kBoltzmann * T0, c = exp(-dt / tau);
-                const double Kn = K + (1.0 - c) * (K0 * (r1 * r1 + s_chi2) / nf - K) +
-                                  2.0 * r1 * sqrt(c * (1.0 - c) * K * K0 / nf);
-                lam2 = fmax(0.0, Kn / K);
-            } else {
-                const double Tcur = 2.0 * K / (nf * kBoltzmann);
-                lam2 = fmax(0.0, 1.0 + dt / tau * (T0 / Tcur - 1.0));
-            }
+    if (threadIdx.x == 0) ke_thermostat(sh[0][0], sh[1][0], sh[2][0], n, dt, T0, tau, kind, rng, aux, head);
+}
+
+// A system of up to kKeOneBlock / 3 atoms: the kick, the kinetic energy and the thermostat in
+// one block (thread t takes components t, t + kKeBlock, ... in order, then the tree).
+constexpr int64_t kKeOneBlock = 3 * 8192;
+
+__global__ __launch_bounds__(kKeBlock) void k_vv_kick_ke_one(int64_t n3, double dt, const int32_t *__restrict__ spec,
+                                                              const double *__restrict__ minv, double *__restrict__ v,
+                                                              const double *__restrict__ Fold, const double *__restrict__ F,
+                                                              unsigned long long *__restrict__ dmax, double T0, double tau,
+                                                              int kind, const double *__restrict__ rng,
+                                                              double *__restrict__ aux, double *__restrict__ head) {
+    __shared__ double sh[3][kKeBlock];
+    if (threadIdx.x == 0) dmax[0] = dmax[3] = 0ull;
+    double s = 0.0, vm = 0.0, am = 0.0;
+    for (int64_t t = threadIdx.x; t < n3; t += kKeBlock) {
+        const double mi = minv[spec[t / 3]];
+        const double vt = v[t] + 0.5 * (Fold[t] + F[t]) * mi * kAccel * dt;
+        v[t] = vt;
+        if (mi > 0.0) {
+            s += vt * vt / mi;
+            vm = fmax(vm, fabs(vt));
+            am = fmax(am, fabs(F[t] * mi * kAccel));
         }
-        const double lam = sqrt(lam2);
-        aux[0] = lam;
-        head[0] = lam2 * K;
-        head[2] = lam * sh[1][0];
-        head[3] = sh[2][0];
     }
+    sh[0][threadIdx.x] = s; sh[1][threadIdx.x] = vm; sh[2][threadIdx.x] = am;
+    __syncthreads();
+    for (int h = kKeBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + h]);
+            sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ke_thermostat(sh[0][0], sh[1][0], sh[2][0], n3 / 3, dt, T0, tau, kind, rng, aux, head);
 }
 
 // The bits of a non-negative double (or a NaN) as an unsigned integer: their order is the
@@ -553,7 +595,13 @@ void reann_server::enqueue_tail(hipStream_t st, Sys &sy, bool vv, double dt, int
     // the squared displacements since the list build, now (head[11]) and after the next drift of
     // dt (head[14]), raised by k_vv_post as integer maxima
     unsigned long long *dmax = reinterpret_cast<unsigned long long *>(sy.d_out.as<double>() + 11);
-    if (vv) {
+    if (vv && n3 <= kKeOneBlock) {
+        hipLaunchKernelGGL(k_vv_kick_ke_one, dim3(1), dim3(kKeBlock), 0, st, n3, dt, sy.d_spec.ptr(), d_minv.as<double>(),
+                           sy.d_vel.as<double>(), sy.d_Fold.as<double>(), sy.F(), dmax, opt.thermostat_K,
+                           opt.thermostat_tau_fs, (int)opt.thermostat, sy.d_rng.as<double>(), sy.d_aux.as<double>(),
+                           sy.KE());
+        LAUNCH_OK("k_vv_kick_ke_one");
+    } else if (vv) {
         const int nb = grid_for(n3, kKeBlock);
         double *aux = sy.d_aux.as<double>();
         hipLaunchKernelGGL(k_vv_kick_ke, dim3(nb), dim3(kKeBlock), 0, st, n3, dt, sy.d_spec.ptr(), d_minv.as<double>(),
