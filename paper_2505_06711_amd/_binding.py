@@ -512,7 +512,8 @@ class Server:
 
     def poll(self, ticket: int, sys_id: int, forces: bool = True, positions: bool = False, velocities: bool = False):
         """None while pending; else a dict with energy, virial, forces, positions, velocities,
-        kinetic (eV, velocity-Verlet steps), latency_s."""
+        kinetic (eV, velocity-Verlet steps), latency_s.  A vector asked for here must not have
+        been skipped at submit (ReannError otherwise, and the result stays for another poll)."""
         n = self.n_atoms[sys_id]
         res = _Result()
         # the output arrays of a ticket are made once and kept while it is pending
